@@ -1,0 +1,263 @@
+"""Pins for the CPU oracle: it is checked against facts fixed by the paper and
+by mathematics, never against itself.
+
+* hand-derived 1D eigenvalues and a hand-solved n=1 control problem
+  (tests/golden/fd_hand_values.txt);
+* the closed-form constant-coefficient eigenpairs 4/h^2 sin^2(k pi h/2) and
+  the DST-I vectors (Section 3.4);
+* dense n^3 x n^3 brute force with distinct coefficients per mode (catches a
+  transposed mode, a wrong Kronecker order, a dropped term of f);
+* the alpha = 1 sparse identity (no eigensolver involved);
+* alpha = 0 (both fractional powers become the identity, Section 4 remark);
+* an eigenvector-triple design function (rank-1 exact solution);
+* symmetry, positivity and linearity of the solution operator;
+* the canonical-format definitions (Appendix 1) against full-grid evaluation;
+* the slab-streamed error evaluator against a full-grid evaluation.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import brute, fd, solve, tensor
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fd_hand_values.txt")
+
+
+def _golden_lines(kind):
+    with open(GOLDEN) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith(kind + " "):
+                yield line[len(kind) + 1:]
+
+
+def test_golden_fd_eigenvalues():
+    seen = 0
+    for rest in _golden_lines("eig"):
+        lhs, rhs = rest.split(":")
+        parts = lhs.split()
+        n = int(parts[1])
+        a = np.array([float(v) for v in parts[2:]])
+        assert a.shape[0] == n + 1
+        want = np.array([float(v) for v in rhs.split()])
+        lam, V = fd.eig1d(a)
+        np.testing.assert_allclose(lam, want, rtol=1e-13)
+        seen += 1
+    assert seen >= 4
+
+
+def test_golden_control_n1():
+    seen = 0
+    for rest in _golden_lines("control"):
+        lhs, rhs = rest.split(":")
+        head, m2, m3 = lhs.split("|")
+        h = head.split()
+        alpha, beta, gamma = float(h[0]), float(h[1]), float(h[2])
+        a = [np.array([float(v) for v in h[3:]]), np.array([float(v) for v in m2.split()]),
+             np.array([float(v) for v in m3.split()])]
+        one = np.ones((1, 1), order="F")
+        prob = wl.Problem("golden", 1, a, alpha, beta, gamma, 1e-6, np.ones(1), [one, one, one])
+        u = solve.solve_full(prob)
+        np.testing.assert_allclose(u.reshape(-1), [float(rhs)], rtol=1e-14)
+        seen += 1
+    assert seen >= 2
+
+
+def test_paper_literal_boundary_rows():
+    # Section 3.2 prints diagonal entries 2 a_{3/2} and 2 a_{n-1/2} in the first
+    # and last rows (times 1/h^2); the literal-sample reading reproduces them.
+    a = np.array([0.7, 1.3, 2.1, 0.9, 1.6])
+    n = 4
+    d, e = fd.stiffness_tridiag(fd.paper_literal_samples(a))
+    h2 = 1.0 / (n + 1) ** 2
+    assert d[0] == pytest.approx(2 * a[1] / h2, rel=1e-15)
+    assert d[-1] == pytest.approx(2 * a[-2] / h2, rel=1e-15)
+    assert d[1] == pytest.approx((a[1] + a[2]) / h2, rel=1e-15)
+    np.testing.assert_allclose(e, -a[1:-1] / h2, rtol=1e-15)
+
+
+@pytest.mark.parametrize("n,c", [(7, 1.0), (50, 1.7), (257, 0.3)])
+def test_closed_form_constant_coefficient(n, c):
+    lam, V = fd.eig1d(np.full(n + 1, c))
+    lam_cf, V_cf = fd.laplacian_closed_form(n, c)
+    # backward-stable eigensolver: absolute error of order n * eps * ||A||
+    np.testing.assert_allclose(lam, lam_cf, rtol=1e-12, atol=64 * 2.2e-16 * lam_cf.max())
+    # eigenvectors agree up to sign
+    M = np.abs(V.T @ V_cf)
+    np.testing.assert_allclose(M, np.eye(n), atol=1e-10)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_eigen_invariants(seed):
+    rng = np.random.default_rng(seed)
+    n = 300
+    a = 0.1 + 1.8 * rng.random(n + 1)
+    lam, V = fd.eig1d(a)
+    A = fd.stiffness_dense(a)
+    assert np.all(np.diff(lam) > 0)
+    assert lam[0] > 0
+    assert np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-12
+    assert np.linalg.norm(A @ V - V * lam[None, :]) <= 1e-12 * np.linalg.norm(A)
+
+
+def _tiny_problem(n, alpha, beta=0.7, gamma=1.3, rank=2, seed=11):
+    rng = np.random.default_rng(seed)
+    xm = wl.midpoints(n)
+    a = [1.0 + 0.5 * np.sin(2 * np.pi * xm), 0.3 + xm ** 2, 2.0 - np.cos(3 * xm)]
+    w = rng.uniform(0.5, 1.5, rank)
+    Y = [np.asfortranarray(rng.standard_normal((n, rank))) for _ in range(3)]
+    return wl.Problem("tiny", n, a, alpha, beta, gamma, 1e-6, w, Y)
+
+
+@pytest.mark.parametrize("alpha", [0.25, 0.5, 0.9, 1.0])
+def test_dense_brute_force(alpha):
+    prob = _tiny_problem(7, alpha)
+    u = solve.solve_full(prob)
+    ub = brute.dense_solve(prob)
+    assert np.linalg.norm(u - ub) <= 1e-11 * np.linalg.norm(ub)
+    # and the residual of the oracle's answer under the dense operator
+    r = brute.dense_operator_apply(prob, u) - tensor.cp_full(prob.w, prob.Y)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(tensor.cp_full(prob.w, prob.Y))
+
+
+def test_dense_brute_force_mode_order():
+    # Transposing two modes of the solution must break agreement: the three
+    # coefficients differ, so the test is sensitive to the mode order.
+    prob = _tiny_problem(6, 0.5)
+    u = solve.solve_full(prob)
+    ub = brute.dense_solve(prob)
+    assert np.linalg.norm(u - ub) <= 1e-11 * np.linalg.norm(ub)
+    assert np.linalg.norm(u.transpose(1, 0, 2) - ub) > 1e-3 * np.linalg.norm(ub)
+
+
+@pytest.mark.parametrize("n", [12, 20])
+def test_alpha1_sparse_identity(n):
+    prob = _tiny_problem(n, 1.0, beta=1e-2, gamma=1.0)
+    u = solve.solve_full(prob)
+    us = brute.sparse_alpha1_solve(prob)
+    assert np.linalg.norm(u - us) <= 1e-9 * np.linalg.norm(us)
+
+
+def test_alpha0_is_scaled_identity():
+    prob = _tiny_problem(9, 0.0, beta=0.4, gamma=2.0)
+    u = solve.solve_full(prob)
+    y = tensor.cp_full(prob.w, prob.Y)
+    np.testing.assert_allclose(u, y / (0.4 + 2.0 / 0.4), rtol=1e-12, atol=1e-14)
+
+
+def test_eigenvector_triple_rhs():
+    base = wl.workload_sine(n=40, seed=3, rank=1)
+    sp = solve.Spectral(base)
+    p, q, r = 3, 17, 30
+    prob = wl.eigvec_rhs_problem(base, [sp.V[0][:, p], sp.V[1][:, q], sp.V[2][:, r]])
+    u = solve.solve_full(prob)
+    fval = solve.f_control(sp.lam[0][p] + sp.lam[1][q] + sp.lam[2][r], prob.alpha, prob.beta,
+                           prob.gamma)
+    y = tensor.cp_full(prob.w, prob.Y)
+    np.testing.assert_allclose(u, y / fval, rtol=1e-9, atol=1e-13 * np.abs(y).max() / fval)
+
+
+def test_symmetry_positivity_linearity():
+    p1 = _tiny_problem(10, 0.6, seed=1)
+    p2 = _tiny_problem(10, 0.6, seed=2)
+    u1, u2 = solve.solve_full(p1), solve.solve_full(p2)
+    y1, y2 = tensor.cp_full(p1.w, p1.Y), tensor.cp_full(p2.w, p2.Y)
+    s12, s21 = float(np.sum(y1 * u2)), float(np.sum(y2 * u1))
+    assert abs(s12 - s21) <= 1e-12 * max(abs(s12), 1e-300) + 1e-14
+    assert float(np.sum(y1 * u1)) > 0 and float(np.sum(y2 * u2)) > 0
+    p3 = wl.Problem("lin", 10, p1.a, 0.6, p1.beta, p1.gamma, 1e-6,
+                    np.concatenate([2.0 * p1.w, -3.0 * p2.w]),
+                    [np.hstack([p1.Y[l], p2.Y[l]]) for l in range(3)])
+    u3 = solve.solve_full(p3)
+    np.testing.assert_allclose(u3, 2.0 * u1 - 3.0 * u2, rtol=1e-10, atol=1e-12 * np.abs(u3).max())
+
+
+def test_canonical_definitions_against_full_grid():
+    rng = np.random.default_rng(5)
+    n = (6, 7, 8)
+    A = [rng.standard_normal((n[l], 3)) for l in range(3)]
+    B = [rng.standard_normal((n[l], 4)) for l in range(3)]
+    wa, wb = rng.standard_normal(3), rng.standard_normal(4)
+    TA, TB = tensor.cp_full(wa, A), tensor.cp_full(wb, B)
+    assert tensor.cp_inner(wa, A, wb, B) == pytest.approx(float(np.sum(TA * TB)), rel=1e-12)
+    wh, H = tensor.cp_hadamard(wa, A, wb, B)
+    np.testing.assert_allclose(tensor.cp_full(wh, H), TA * TB, rtol=1e-12, atol=1e-12)
+    assert len(wh) == 12 and wh[1 * 4 + 2] == pytest.approx(wa[1] * wb[2])
+
+
+def test_hosvd_orthonormal_closed_form():
+    # Orthonormal factors in every mode: the unfolding spectra are the |xi|,
+    # so truncation drops the smallest terms and nothing else.
+    rng = np.random.default_rng(3)
+    n, r = 12, 6
+    Q = [np.linalg.qr(rng.standard_normal((n, r)))[0] for _ in range(3)]
+    xi = np.array([1.0, 0.5, 0.1, 1e-3, 1e-5, 1e-8])
+    T = tensor.cp_full(xi, Q)
+    # per-mode budget tol^2 ||T||^2 / 3 = 1e-8: drops 1e-5 and 1e-8, keeps 1e-3
+    tol = 1e-4 * np.sqrt(3.0) / np.linalg.norm(xi)
+    Tt, ranks, _ = tensor.hosvd_truncate(T, tol)
+    assert ranks == (4, 4, 4)
+    np.testing.assert_allclose(Tt, tensor.cp_full(xi[:4], [q[:, :4] for q in Q]), atol=1e-12)
+
+
+def test_hosvd_recovers_tucker_rank():
+    rng = np.random.default_rng(4)
+    n, r = (14, 12, 10), (3, 4, 2)
+    Z = [np.linalg.qr(rng.standard_normal((n[l], r[l])))[0] for l in range(3)]
+    core = rng.standard_normal(r)
+    T = tensor.tucker_full(core, Z)
+    Tt, ranks, _ = tensor.hosvd_truncate(T, 1e-10)
+    assert ranks == r
+    assert np.linalg.norm(Tt - T) <= 1e-12 * np.linalg.norm(T)
+
+
+def test_error_evaluator_matches_full_grid():
+    prob = _tiny_problem(11, 0.5, rank=3)
+    sp = solve.Spectral(prob)
+    u = solve.solve_full(prob, sp)
+    rng = np.random.default_rng(9)
+    # a canonical candidate: perturbation of the exact solution is not low rank,
+    # so test with an arbitrary rank-4 tensor plus a consistency check.
+    F = [rng.standard_normal((11, 4)) for _ in range(3)]
+    w = rng.standard_normal(4)
+    Tc = tensor.cp_full(w, F)
+    rep = solve.rel_error(prob, w, F, sp)
+    want = np.linalg.norm(Tc - u) / np.linalg.norm(u)
+    assert rep["rel_l2"] == pytest.approx(want, rel=1e-10)
+    y = tensor.cp_full(prob.w, prob.Y)
+    Fu = brute.dense_operator_apply(prob, Tc)
+    assert rep["rel_residual"] == pytest.approx(np.linalg.norm(y - Fu) / np.linalg.norm(y), rel=1e-8)
+    # sampled slabs: numerator and denominator over the same slabs
+    rep_s = solve.rel_error(prob, w, F, sp, slabs=[0, 3, 4, 10])
+    idx = [0, 3, 4, 10]
+    want_s = np.linalg.norm(Tc[idx] - u[idx]) if False else None
+    Uh = solve.mode_products(Tc, [V.T for V in sp.V])
+    Ex = solve.mode_products(u, [V.T for V in sp.V])
+    want_s = np.linalg.norm(Uh[idx] - Ex[idx]) / np.linalg.norm(Ex[idx])
+    assert rep_s["rel_l2"] == pytest.approx(want_s, rel=1e-10)
+    assert rep_s["slabs"] == 4
+
+
+def test_state_recovery_dense():
+    prob = _tiny_problem(6, 0.5)
+    u = solve.solve_full(prob)
+    y = solve.state_full(prob, u)
+    A = brute.kron_sum_dense(prob)
+    mu, Q = np.linalg.eigh(A)
+    S = (Q * (prob.beta * mu ** (-prob.alpha))[None, :]) @ Q.T
+    np.testing.assert_allclose(y.reshape(-1), S @ u.reshape(-1), rtol=1e-10,
+                               atol=1e-12 * np.abs(y).max())
+
+
+def test_workload_shapes_and_determinism():
+    p = wl.workload_sine(n=64, seed=3)
+    q = wl.workload_sine(n=64, seed=3)
+    assert p.rank == 10 and all(Y.shape == (64, 10) for Y in p.Y)
+    assert all(np.array_equal(p.Y[l], q.Y[l]) for l in range(3))
+    assert all(len(a) == 65 and np.all(a > 0) for a in p.a)
+    b = wl.workload_batched(count=8)
+    assert len(b) == 8 and all(1 <= x.rank <= 10 and 0.2 <= x.alpha <= 0.8 for x in b)
+    s = wl.workload_small()
+    assert s.n == 32 and s.rank == 1
