@@ -1,0 +1,223 @@
+/*
+ * fracctl -- rank-truncated preconditioned CG for the fractional control
+ * equation on MI355X (gfx950).
+ *
+ * Problem (paper Section 3.1, control equation after eliminating state and
+ * adjoint, finite differences so the mass matrix is the identity):
+ *
+ *     (beta A^-alpha + (gamma/beta) A^alpha) u = y,
+ *     A = A_1 (x) I (x) I + I (x) A_2 (x) I + I (x) I (x) A_3        (Section 3.2)
+ *
+ * where A_l is the 1D finite-difference Sturm-Liouville matrix of
+ * -d/dx a_l(x) d/dx with homogeneous Dirichlet conditions on n interior nodes,
+ * h = 1/(n+1):  A_l = (1/h^2) tridiag(-a_{i-1/2}, a_{i-1/2}+a_{i+1/2}, -a_{i+1/2}).
+ * The fractional powers are spectral (Section 2).  The solve runs in the
+ * eigenbasis of the three A_l (Section 3.3, eqn. DiagKron3D): operator and
+ * preconditioner are separable (low Kronecker rank) diagonal scalings there,
+ * and the iteration is Algorithm 1 (Appendix 2) with a rank truncation after
+ * every update (canonical-to-Tucker by reduced HOSVD, Appendix 1).
+ *
+ * Tensor layout at the boundary: a canonical tensor
+ *     T = sum_s w[s] * U1[:,s] o U2[:,s] o U3[:,s]
+ * is passed as three column-major n x rank FP64 factor matrices (leading
+ * dimension n) and an FP64 weight vector.  Factor entries are the values at
+ * the grid nodes x_i = i/(n+1), i = 1..n.  Outputs have unit-norm columns and
+ * carry norms and signs in the weights.
+ *
+ * Memory: every pointer documented as DEVICE is a device (HBM) pointer owned
+ * by the caller; HOST pointers are ordinary host memory.  The plan owns all
+ * of its device state and workspace; fc_solve performs no device allocation.
+ * Streams: `hip_stream` is a hipStream_t (NULL = the default stream); all
+ * device work of a call is enqueued on it.  A plan must not be used by two
+ * threads at once; distinct plans may run concurrently on distinct streams.
+ *
+ * Errors: every entry point returns an fc_status; no exception crosses the
+ * boundary.  fc_last_error() returns a thread-local text describing the last
+ * failure.
+ */
+#ifndef FRACCTL_H
+#define FRACCTL_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fc_plan_s* fc_plan;
+
+typedef enum {
+    FC_OK = 0,
+    FC_ERR_INVALID_ARG = 1,   /* argument out of range; nothing was touched      */
+    FC_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed (setup only)   */
+    FC_ERR_NOT_CONVERGED = 3, /* max_iter reached; best iterate still written     */
+    FC_ERR_RANK_OVERFLOW = 4, /* result rank exceeds cap_u (*rank_u = required)   */
+    FC_ERR_NUMERIC = 5,       /* NaN/Inf met, or a setup accuracy gate failed     */
+    FC_ERR_HIP = 6,           /* a HIP runtime call failed                        */
+    FC_ERR_INTERNAL = 7       /* internal capacity exceeded (Tucker rank > max)   */
+} fc_status;
+
+typedef enum { FC_FP64 = 0 } fc_precision;
+
+/* Setup parameters.  Zero-valued optional fields select the defaults. */
+typedef struct {
+    int n;                  /* interior nodes per mode, 2 <= n <= 4096                        */
+    const double* a[3];     /* HOST: n+1 samples a_l((i+1/2)/(n+1)), i = 0..n, finite, > 0      */
+    double alpha;           /* 0 <= alpha <= 1                                                 */
+    double beta, gamma;     /* > 0                                                             */
+    double eps;             /* truncation threshold, 0 < eps < 1 (paper: 1e-6)                 */
+    double tol;             /* stop when ||R|| <= tol ||Y||; 0 -> eps                          */
+    double op_accuracy;     /* entrywise relative accuracy of the operator; 0 -> eps           */
+    int max_iter;           /* 0 -> 100                                                        */
+    int max_rank;           /* Tucker rank capacity per mode; 0 -> 64, at most 96              */
+    int precond_rank;       /* Kronecker rank of the preconditioner; 0 -> 6 (Section 4)        */
+    fc_precision precision; /* FC_FP64                                                         */
+} fc_setup_params;
+
+/* Per-solve report (HOST struct). */
+typedef struct {
+    int iterations;         /* PCG iterations taken (Algorithm 1 loop count)                   */
+    int rank_u;             /* canonical rank of the result                                    */
+    int tucker_rank[3];     /* Tucker rank of the final iterate                                */
+    int max_tucker_rank;    /* largest Tucker rank met during the iteration                    */
+    int op_rank;            /* Kronecker rank of the operator                                  */
+    int precond_rank;       /* Kronecker rank of the preconditioner                            */
+    double rel_residual;    /* ||R|| / ||Y|| of the recursively updated residual at exit       */
+    double op_max_rel_err;  /* max over the spectrum of |D~/D - 1| (setup gate value)          */
+    double precond_max_rel_err; /* max over the spectrum of |D~_p D - 1|                       */
+} fc_info;
+
+/* Plan with gamma = 1, FP64 and defaults; see fc_setup_ex.  a1..a3 are HOST. */
+fc_status fc_setup(int n, const double* a1, const double* a2, const double* a3,
+                   double alpha, double beta, double eps, fc_plan* out);
+
+/* Build a plan (paper Sections 3.2-3.5): the three 1D FD matrices, their
+ * eigenpairs (host, tridiagonal QL), the separable operator
+ * D~ ~ f(lambda1+lambda2+lambda3), f(s) = beta s^-alpha + (gamma/beta) s^alpha, and
+ * the rank-precond_rank preconditioner D~_p ~ 1/f (preconditioner case (B),
+ * Section 3.5), both as exponential sums with positive weights (sinc-type
+ * quadrature of the Laplace transform, Section 3.4, refined by least squares).
+ * Uploads everything and allocates the solve workspace.  Fails with
+ * FC_ERR_NUMERIC if the operator misses op_accuracy anywhere on
+ * [s_min, s_max] or a separable factor is not positive. */
+fc_status fc_setup_ex(const fc_setup_params* p, void* hip_stream, fc_plan* out);
+
+/* Solve F(A) u = y for one design function given in canonical format.
+ *   rank_y            number of terms of y, 1 <= rank_y <= 4 * max_rank
+ *   w_y               DEVICE, rank_y weights, or NULL for all ones
+ *   Y1, Y2, Y3        DEVICE, n x rank_y column-major factors of y
+ *   cap_u             capacity (columns) of the output buffers
+ *   rank_u            HOST out: rank of u (on FC_ERR_RANK_OVERFLOW: the required rank)
+ *   w_u               DEVICE out: cap_u weights
+ *   U1, U2, U3        DEVICE out: n x cap_u column-major unit-norm factors
+ *   info              HOST out, may be NULL
+ * Synchronises the stream before returning (ranks are read on the host).
+ * Algorithm 1 of the paper with X0 = 0, trunc = reduced-HOSVD
+ * canonical-to-Tucker after every update, and the Tucker-to-canonical
+ * transform of the final iterate (Appendix 1). */
+fc_status fc_solve(fc_plan plan, int rank_y, const double* w_y,
+                   const double* Y1, const double* Y2, const double* Y3,
+                   int cap_u, int* rank_u, double* w_u, double* U1, double* U2, double* U3,
+                   fc_info* info, void* hip_stream);
+
+/* Solve a batch of independent problems, one plan per problem (plans may
+ * differ in n and alpha).  Arrays are HOST arrays of length `count`; the
+ * per-problem pointers follow fc_solve.  status[i] receives each problem's
+ * own status; the return value is FC_OK if every problem succeeded, else the
+ * first failing status.  Problems run concurrently on the given stream. */
+fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
+                           const double* const* w_y, const double* const* Y1,
+                           const double* const* Y2, const double* const* Y3,
+                           const int* cap_u, int* rank_u, double* const* w_u,
+                           double* const* U1, double* const* U2, double* const* U3,
+                           fc_status* status, fc_info* info, void* hip_stream);
+
+/* Release every resource of a plan (NULL is allowed). */
+void fc_destroy(fc_plan plan);
+
+/* Plan introspection (HOST outputs).  lam: 3*n ascending eigenvalues, mode
+ * after mode; V (may be NULL): 3 n x n column-major eigenvector matrices. */
+fc_status fc_plan_spectrum(fc_plan plan, double* lam, double* V);
+
+/* Separable factors of the operator (which = 0) or the preconditioner
+ * (which = 1) in eigen-coordinates: *rank terms, w (HOST, capacity cap) and
+ * F (HOST, 3 consecutive n x cap column-major matrices, may be NULL). */
+fc_status fc_plan_separable(fc_plan plan, int which, int cap, int* rank, double* w, double* F);
+
+/* ---- building blocks of the path, exposed for testing (DEVICE buffers) ---- */
+
+/* Mode transform (Section 3.3): out = V_l^T X (transpose = 1, into
+ * eigen-coordinates) or out = V_l X (transpose = 0, back to the grid), X and
+ * out n x m column-major.  On the plan's eigenbasis of mode l. */
+fc_status fc_mode_transform(fc_plan plan, int mode, int transpose, int m,
+                            const double* X, double* out, void* hip_stream);
+
+/* Canonical scalar product (Appendix 1): <A, B> = sum_k sum_m wa_k wb_m
+ * prod_l <A_l[:,k], B_l[:,m]>, A_l n x ra, B_l n x rb (DEVICE), result to
+ * HOST *out.  wa/wb may be NULL (ones). */
+fc_status fc_cp_inner(fc_plan plan, int ra, const double* wa, const double* A1, const double* A2,
+                      const double* A3, int rb, const double* wb, const double* B1,
+                      const double* B2, const double* B3, double* out, void* hip_stream);
+
+/* Rank truncation of a canonical tensor (Appendix 1, C2T by reduced HOSVD
+ * followed by the Tucker-to-canonical transform) to relative accuracy eps:
+ * the result T' satisfies ||T - T'|| <= eps ||T|| (Euclidean norm).
+ * Input as in fc_solve (DEVICE, rank m), output as in fc_solve. */
+fc_status fc_cp_truncate(fc_plan plan, int m, const double* w, const double* X1,
+                         const double* X2, const double* X3, double eps, int cap,
+                         int* rank_out, double* w_out, double* O1, double* O2, double* O3,
+                         void* hip_stream);
+
+/* Apply the operator (which = 0) or preconditioner (which = 1) to a canonical
+ * tensor given in eigen-coordinates, with truncation to relative accuracy eps
+ * (Section 3.3, eqn. Gen3DtimesX, evaluated in eigen-coordinates).  DEVICE
+ * buffers as in fc_cp_truncate. */
+fc_status fc_apply_separable(fc_plan plan, int which, int m, const double* w, const double* X1,
+                             const double* X2, const double* X3, double eps, int cap,
+                             int* rank_out, double* w_out, double* O1, double* O2, double* O3,
+                             void* hip_stream);
+
+/* ---- host-only helpers (no device needed), exposed for testing ---- */
+
+/* Eigenpairs of the 1D FD matrix built from n+1 midpoint samples (HOST):
+ * lam ascending (n), V column-major n x n (may be NULL). */
+fc_status fc_host_fd_eigen(int n, const double* a_mid, double* lam, double* V);
+
+/* Exponential sum sum_k c_k exp(-t_k s) fitted to target(s) with relative
+ * accuracy on [s_min, s_max].  kind 0: target = s^-nu (nu = p1);
+ * kind 1: target = 1/(p1 s^-p2 + p3 s^p2)  (preconditioner symbol 1/f);
+ * kind 2: target = p1 s^(-p2-1) + p3 s^(p2-1)  (f(s)/s).
+ * terms = K requested; on return t, c hold K values (HOST) and *max_rel_err
+ * the maximum relative error on a dense logarithmic grid. */
+fc_status fc_host_expsum(int kind, double p1, double p2, double p3, double s_min, double s_max,
+                         int terms, double* t, double* c, double* max_rel_err);
+
+/* Host-only construction of the setup phase (no device needed): the
+ * eigenpairs and the separable operator (which = 0) or preconditioner
+ * (which = 1) exactly as fc_setup_ex builds them, returned like
+ * fc_plan_separable; *max_rel_err (may be NULL) receives the gate value
+ * max over [s_min, s_max] of |D~/f - 1| (operator) or |D~_p f - 1|. */
+fc_status fc_host_separable(const fc_setup_params* p, int which, int cap, int* rank, double* w,
+                            double* F, double* max_rel_err);
+
+/* Timing of the FP64 matrix-core GEMM kernel (the dominant kernel of the
+ * path) for roofline reporting.  fc_profile_gemm(1) clears the counters and
+ * brackets every subsequent GEMM launch of the library with a pair of HIP
+ * events on its stream; fc_profile_gemm(0) stops recording.
+ * fc_profile_gemm_read waits for the recorded events and returns the launch
+ * count, the summed kernel time (ms), and the algorithmic work of those
+ * launches: 2 M N K flops and 8 (M K + K N + M N) bytes per GEMM.
+ * Process-wide; not thread-safe; meant for benchmarks. */
+fc_status fc_profile_gemm(int enable);
+fc_status fc_profile_gemm_read(long* launches, double* total_ms, double* flops, double* bytes);
+
+/* Self-test of the matrix-core operand layout: one 16x16x4 FP64 product of
+ * fixed matrices, 256 values written row-major to HOST out.  Returns 0 on
+ * success. */
+int fc_selftest_mfma(double* host_out);
+
+const char* fc_status_string(fc_status s);
+const char* fc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRACCTL_H */

@@ -1,0 +1,84 @@
+// Device kernels of the fracctl library (gfx950).  All arithmetic is FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fc {
+
+// C[b] = alpha * op(A[b]) * diag(d[b]) * op(B[b]) + beta * C[b]
+// op(A) is M x K, op(B) is K x N, C is M x N; all column-major.
+// Strides are in elements; a zero stride shares the operand across the batch.
+// d (length K, may be null) scales the inner dimension.
+// Two-level batch: entry b uses operand offsets (b / inner) * stride + (b % inner) * strideIn.
+struct GemmArgs {
+    int M = 0, N = 0, K = 0, batch = 1, inner = 1;
+    double alpha = 1.0, beta = 0.0;
+    const double* A = nullptr; long lda = 0, strideA = 0, strideAin = 0;
+    const double* B = nullptr; long ldb = 0, strideB = 0, strideBin = 0;
+    double* C = nullptr; long ldc = 0, strideC = 0, strideCin = 0;
+    const double* d = nullptr; long strideD = 0;
+};
+
+hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
+
+// Symmetric eigen-decomposition of a batch of k x k matrices (k <= 128),
+// cyclic Jacobi with the matrix in LDS.  A (column-major, leading dimension
+// lda, batch stride strideA) is read only.  Eigenvalues go to evals[b*k + i]
+// in descending order, eigenvectors to V[b*strideV + i*ldv + j] (column i).
+// scratch: batch * (k+1)^2 doubles of device memory.
+hipError_t sym_eig(int k, int batch, const double* A, long lda, long strideA, double* evals,
+                   double* V, long ldv, long strideV, double* scratch, hipStream_t s);
+
+// E[i + n*(j + r*c)] = Z[i + ldz*j] * X[i + ldx*c]   (row-wise Kronecker product)
+hipError_t rowkron(int n, int r, int p, const double* Z, long ldz, const double* X, long ldx,
+                   double* E, hipStream_t s);
+// out[i + ldo*c] = sum_j Z[i + ldz*j] * F[i + n*(j + r*c)]   (row-wise contraction)
+hipError_t rowcontract(int n, int r, int p, const double* Z, long ldz, const double* F,
+                       double* out, long ldo, hipStream_t s);
+
+// dst = permutation of a dense r0 x r1 x r2 column-major core that brings
+// mode `mode` first: mode 0 -> identity copy, mode 1 -> (r1, r0, r2),
+// mode 2 -> (r2, r0, r1).  Batched with strides.
+hipError_t permute_core(int r0, int r1, int r2, int mode, int batch, const double* src,
+                        long sstride, double* dst, long dstride, hipStream_t s);
+
+// y[i] = a * x[i] (+ y[i] if accumulate)
+hipError_t axpby(long n, double a, const double* x, double b, double* y, hipStream_t s);
+// out[b] = sum_i x[b*stride + i] * y[b*stride + i] for i < n (deterministic tree)
+hipError_t dot_batched(long n, int batch, const double* x, const double* y, long stride,
+                       double* out, hipStream_t s);
+// sum of `count` arrays of length n with coefficients: y = sum_t coef[t] * x[t*stride .. ]
+hipError_t sum_strided(long n, int count, const double* coef, const double* x, long stride,
+                       double* y, hipStream_t s);
+// X[:, c] *= scale[c] (or /= if divide) for an n x m column-major matrix
+hipError_t scale_cols(int n, int m, double* X, long ldx, const double* scale, int divide,
+                      hipStream_t s);
+// column 2-norms of an n x m matrix
+hipError_t col_norms(int n, int m, const double* X, long ldx, double* out, hipStream_t s);
+// fill with a deterministic pseudo-random normal-like sequence (counter hash)
+hipError_t fill_random(long n, unsigned seed, double* x, hipStream_t s);
+// zero a buffer with a fill kernel (graph-safe)
+hipError_t zero(long n, double* x, hipStream_t s);
+// copy a column-major m x n block
+hipError_t copy2d(int rows, int cols, const double* src, long lds, double* dst, long ldd,
+                  hipStream_t s);
+// nonfinite check: flag[0] = 1 if any of n values is NaN/Inf
+hipError_t check_finite(long n, const double* x, int* flag, hipStream_t s);
+
+// out[0] = sum_{k<ra, m<rb} wa[k] wb[m] G0[k,m] G1[k,m] G2[k,m]  (ld ra, wa/wb may be null)
+hipError_t cp_inner_reduce(int ra, int rb, const double* G0, const double* G1, const double* G2,
+                           const double* wa, const double* wb, double* out, hipStream_t s);
+
+// Rank-revealing modified Gram-Schmidt (two passes per column) on the n x m
+// column-major matrix Y (ld n), in place, one workgroup.  Columns whose norm
+// after projection falls below drop * (their input norm) are removed; the
+// kept orthonormal columns are compacted to the front and their number is
+// written to *count (device int).
+hipError_t mgs_qr(int n, int m, double* Y, double drop, int* count, hipStream_t s);
+
+// dst (cols x rows) = src^T, src rows x cols (ld lds), dst ld ldd
+hipError_t transpose(int rows, int cols, const double* src, long lds, double* dst, long ldd,
+                     hipStream_t s);
+
+hipError_t mfma_probe(double* out, hipStream_t s);
+
+}  // namespace fc

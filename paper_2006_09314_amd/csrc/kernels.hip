@@ -1,0 +1,615 @@
+// Device kernels of the fracctl library, written for gfx950 (CDNA4):
+// 64-wide wavefronts, FP64 matrix cores (v_mfma_f64_16x16x4f64), 160 KiB LDS.
+#include "kernels.h"
+
+#include <cstdint>
+
+namespace fc {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Batched FP64 GEMM on the matrix cores.
+//
+// A workgroup of WM x WN wavefronts owns a (32 WM) x (32 WN) tile of C; each
+// wavefront owns a 32 x 32 sub-tile held as 2 x 2 MFMA 16x16 accumulators.
+// K is consumed in chunks of 16 staged through LDS (coalesced global reads in
+// the operand's storage order).  MFMA 16x16x4 f64 operand layout: lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register v of
+// lane l holds C[l / 16 + 4 v][l % 16] (checked by the layout self-test).
+template <bool TA, bool TB, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g) {
+    constexpr int BM = 32 * WM, BN = 32 * WN, BK = 16, NT = 64 * WM * WN;
+    __shared__ double As[BK][BM + 1];
+    __shared__ double Bs[BK][BN + 1];
+    const int tilesM = (g.M + BM - 1) / BM;
+    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
+    const int b = blockIdx.y;
+    const long bo = b / g.inner, bi = b % g.inner;
+    const double* __restrict__ A = g.A + bo * g.strideA + bi * g.strideAin;
+    const double* __restrict__ B = g.B + bo * g.strideB + bi * g.strideBin;
+    const double* __restrict__ d = g.d ? g.d + bo * g.strideD : nullptr;
+    double* __restrict__ C = g.C + bo * g.strideC + bi * g.strideCin;
+    const int row0 = tm * BM, col0 = tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    dbl4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        for (int e = tid; e < BM * BK; e += NT) {
+            int i, k;
+            if (!TA) { i = e % BM; k = e / BM; } else { k = e % BK; i = e / BK; }
+            const int gi = row0 + i, gk = k0 + k;
+            double v = 0.0;
+            if (gi < g.M && gk < g.K) {
+                v = TA ? A[gk + (long)gi * g.lda] : A[gi + (long)gk * g.lda];
+                if (d) v *= d[gk];
+            }
+            As[k][i] = v;
+        }
+        for (int e = tid; e < BK * BN; e += NT) {
+            int j, k;
+            if (!TB) { k = e % BK; j = e / BK; } else { j = e % BN; k = e / BN; }
+            const int gj = col0 + j, gk = k0 + k;
+            double v = 0.0;
+            if (gj < g.N && gk < g.K) v = TB ? B[gj + (long)gk * g.ldb] : B[gk + (long)gj * g.ldb];
+            Bs[k][j] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+            const int k = kk * 4 + (lane >> 4);
+            const double a0 = As[k][wm * 32 + (lane & 15)];
+            const double a1 = As[k][wm * 32 + 16 + (lane & 15)];
+            const double b0 = Bs[k][wn * 32 + (lane & 15)];
+            const double b1 = Bs[k][wn * 32 + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    for (int mi = 0; mi < 2; ++mi)
+        for (int ni = 0; ni < 2; ++ni)
+            for (int v = 0; v < 4; ++v) {
+                const int i = row0 + wm * 32 + mi * 16 + (lane >> 4) + 4 * v;
+                const int j = col0 + wn * 32 + ni * 16 + (lane & 15);
+                if (i < g.M && j < g.N) {
+                    double r = g.alpha * acc[mi][ni][v];
+                    if (g.beta != 0.0) r += g.beta * C[i + (long)j * g.ldc];
+                    C[i + (long)j * g.ldc] = r;
+                }
+            }
+}
+
+template <bool TA, bool TB>
+static hipError_t gemm_dispatch(const GemmArgs& g, hipStream_t s) {
+    const long work = (long)g.M * g.N * g.batch;
+    if (g.M >= 64 && g.N >= 64 && work >= (1L << 20)) {
+        const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+        hipLaunchKernelGGL((gemm_kernel<TA, TB, 2, 2>), dim3(tiles, g.batch), dim3(256), 0, s, g);
+    } else {
+        const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
+        hipLaunchKernelGGL((gemm_kernel<TA, TB, 1, 1>), dim3(tiles, g.batch), dim3(64), 0, s, g);
+    }
+    return hipGetLastError();
+}
+
+hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if (g.K <= 0) {
+        // C = beta C
+        if (g.beta == 0.0) {
+            for (int b = 0; b < g.batch; ++b) {
+                double* C = g.C + (long)(b / g.inner) * g.strideC + (long)(b % g.inner) * g.strideCin;
+                hipError_t e = copy2d(g.M, g.N, nullptr, 0, C, g.ldc, s);
+                if (e != hipSuccess) return e;
+            }
+        }
+        return hipSuccess;
+    }
+    if (!transA && !transB) return gemm_dispatch<false, false>(g, s);
+    if (!transA && transB) return gemm_dispatch<false, true>(g, s);
+    if (transA && !transB) return gemm_dispatch<true, false>(g, s);
+    return gemm_dispatch<true, true>(g, s);
+}
+
+// ---------------------------------------------------------------------------
+// Cyclic Jacobi eigensolver for symmetric k x k matrices (k <= 128), one
+// workgroup per matrix.  The matrix lives in LDS; the accumulated rotations
+// (eigenvectors) live in a global scratch matrix whose column updates are
+// contiguous.  Rounds use the round-robin tournament ordering, so the k/2
+// rotations of a round touch disjoint row/column pairs and run in parallel.
+constexpr int JAC_THREADS = 512;
+
+__global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double* __restrict__ Ain,
+                                                             long lda, long strideA, double* evals,
+                                                             double* Vout, long ldv, long strideV,
+                                                             double* scratch) {
+    extern __shared__ double sm[];
+    const int kp = k + (k & 1);
+    const int half = kp / 2;
+    double* a = sm;   // kp x kp column-major
+    __shared__ double cs[64], sn[64];
+    __shared__ int pp[64], qq[64];
+    __shared__ int nrot;
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const double* A = Ain + (long)b * strideA;
+    double* v = scratch + (long)b * kp * kp;
+    for (int e = tid; e < kp * kp; e += blockDim.x) {
+        const int i = e % kp, j = e / kp;
+        a[e] = (i < k && j < k) ? 0.5 * (A[i + (long)j * lda] + A[j + (long)i * lda]) : 0.0;
+        v[e] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) nrot = 0;
+        __syncthreads();
+        for (int r = 0; r < kp - 1; ++r) {
+            if (tid < half) {
+                auto P = [&](int x) { return x == 0 ? 0 : ((x - 1 + r) % (kp - 1)) + 1; };
+                int p = P(tid), q = P(kp - 1 - tid);
+                if (p > q) { int t = p; p = q; q = t; }
+                const double apq = a[p + q * kp];
+                const double app = a[p + p * kp], aqq = a[q + q * kp];
+                double c = 1.0, s = 0.0;
+                if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(app) * fabs(aqq))) {
+                    const double tau = (aqq - app) / (2.0 * apq);
+                    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                    atomicAdd(&nrot, 1);
+                }
+                cs[tid] = c; sn[tid] = s; pp[tid] = p; qq[tid] = q;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int e = tid; e < half * kp; e += blockDim.x) {
+                const int i = e / kp, j = e % kp;
+                const double c = cs[i], s = sn[i];
+                if (s == 0.0) continue;
+                const int p = pp[i], q = qq[i];
+                const double x = a[p + j * kp], y = a[q + j * kp];
+                a[p + j * kp] = c * x - s * y;
+                a[q + j * kp] = s * x + c * y;
+            }
+            __syncthreads();
+            // columns: A <- A J, V <- V J
+            for (int e = tid; e < half * kp; e += blockDim.x) {
+                const int i = e / kp, j = e % kp;
+                const double c = cs[i], s = sn[i];
+                if (s == 0.0) continue;
+                const int p = pp[i], q = qq[i];
+                const double x = a[j + p * kp], y = a[j + q * kp];
+                a[j + p * kp] = c * x - s * y;
+                a[j + q * kp] = s * x + c * y;
+                const double vx = v[j + p * kp], vy = v[j + q * kp];
+                v[j + p * kp] = c * vx - s * vy;
+                v[j + q * kp] = s * vx + c * vy;
+            }
+            __syncthreads();
+        }
+        if (nrot == 0) break;
+        __syncthreads();
+    }
+    // sort descending by a stable rank count
+    for (int i = tid; i < k; i += blockDim.x) {
+        const double ei = a[i + i * kp];
+        int rank = 0;
+        for (int j = 0; j < k; ++j) {
+            const double ej = a[j + j * kp];
+            if (ej > ei || (ej == ei && j < i)) ++rank;
+        }
+        evals[(long)b * k + rank] = ei;
+        double* Vo = Vout + (long)b * strideV + (long)rank * ldv;
+        for (int j = 0; j < k; ++j) Vo[j] = v[j + i * kp];
+    }
+}
+
+hipError_t sym_eig(int k, int batch, const double* A, long lda, long strideA, double* evals,
+                   double* V, long ldv, long strideV, double* scratch, hipStream_t s) {
+    if (k <= 0 || batch <= 0) return hipSuccess;
+    if (k > 128) return hipErrorInvalidValue;
+    const int kp = k + (k & 1);
+    const size_t shm = sizeof(double) * kp * kp;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)jacobi_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(JAC_THREADS), shm, s, k, A, lda, strideA,
+                       evals, V, ldv, strideV, scratch);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Small elementwise kernels.
+
+__global__ void rowkron_kernel(int n, int r, int p, const double* __restrict__ Z, long ldz,
+                               const double* __restrict__ X, long ldx, double* __restrict__ E) {
+    const long total = (long)n * r * p;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % n);
+        const long jc = e / n;
+        const int j = int(jc % r), c = int(jc / r);
+        E[e] = Z[i + ldz * j] * X[i + ldx * c];
+    }
+}
+
+hipError_t rowkron(int n, int r, int p, const double* Z, long ldz, const double* X, long ldx,
+                   double* E, hipStream_t s) {
+    const long total = (long)n * r * p;
+    if (total <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(rowkron_kernel, dim3(blocks), dim3(256), 0, s, n, r, p, Z, ldz, X, ldx, E);
+    return hipGetLastError();
+}
+
+__global__ void rowcontract_kernel(int n, int r, int p, const double* __restrict__ Z, long ldz,
+                                   const double* __restrict__ F, double* __restrict__ out,
+                                   long ldo) {
+    const long total = (long)n * p;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % n), c = int(e / n);
+        double acc = 0.0;
+        for (int j = 0; j < r; ++j) acc += Z[i + ldz * j] * F[i + (long)n * (j + (long)r * c)];
+        out[i + ldo * c] = acc;
+    }
+}
+
+hipError_t rowcontract(int n, int r, int p, const double* Z, long ldz, const double* F,
+                       double* out, long ldo, hipStream_t s) {
+    const long total = (long)n * p;
+    if (total <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(rowcontract_kernel, dim3(blocks), dim3(256), 0, s, n, r, p, Z, ldz, F, out,
+                       ldo);
+    return hipGetLastError();
+}
+
+__global__ void permute_kernel(int r0, int r1, int r2, int mode, const double* __restrict__ src,
+                               long sstride, double* __restrict__ dst, long dstride) {
+    const long total = (long)r0 * r1 * r2;
+    const double* S = src + blockIdx.y * sstride;
+    double* D = dst + blockIdx.y * dstride;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % r0);
+        const long t = e / r0;
+        const int j = int(t % r1), kk = int(t / r1);
+        long o;
+        if (mode == 0) o = e;
+        else if (mode == 1) o = j + (long)r1 * (i + (long)r0 * kk);
+        else o = kk + (long)r2 * (i + (long)r0 * j);
+        D[o] = S[e];
+    }
+}
+
+hipError_t permute_core(int r0, int r1, int r2, int mode, int batch, const double* src,
+                        long sstride, double* dst, long dstride, hipStream_t s) {
+    const long total = (long)r0 * r1 * r2;
+    if (total <= 0 || batch <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(permute_kernel, dim3(blocks, batch), dim3(256), 0, s, r0, r1, r2, mode, src,
+                       sstride, dst, dstride);
+    return hipGetLastError();
+}
+
+__global__ void axpby_kernel(long n, double a, const double* __restrict__ x, double b,
+                             double* __restrict__ y) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        y[i] = a * x[i] + (b != 0.0 ? b * y[i] : 0.0);
+}
+
+hipError_t axpby(long n, double a, const double* x, double b, double* y, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(axpby_kernel, dim3(blocks), dim3(256), 0, s, n, a, x, b, y);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void dot_kernel(long n, const double* __restrict__ x,
+                                                  const double* __restrict__ y, long stride,
+                                                  double* out) {
+    __shared__ double red[256];
+    const double* X = x + blockIdx.x * stride;
+    const double* Y = y + blockIdx.x * stride;
+    double acc = 0.0;
+    for (long i = threadIdx.x; i < n; i += 256) acc += X[i] * Y[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+hipError_t dot_batched(long n, int batch, const double* x, const double* y, long stride,
+                       double* out, hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dot_kernel, dim3(batch), dim3(256), 0, s, n, x, y, stride, out);
+    return hipGetLastError();
+}
+
+__global__ void sum_strided_kernel(long n, int count, const double* __restrict__ coef,
+                                   const double* __restrict__ x, long stride,
+                                   double* __restrict__ y) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int t = 0; t < count; ++t) acc += (coef ? coef[t] : 1.0) * x[i + t * stride];
+        y[i] = acc;
+    }
+}
+
+hipError_t sum_strided(long n, int count, const double* coef, const double* x, long stride,
+                       double* y, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(sum_strided_kernel, dim3(blocks), dim3(256), 0, s, n, count, coef, x,
+                       stride, y);
+    return hipGetLastError();
+}
+
+__global__ void scale_cols_kernel(int n, int m, double* X, long ldx, const double* scale,
+                                  int divide) {
+    const long total = (long)n * m;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % n), c = int(e / n);
+        const double f = scale[c];
+        X[i + ldx * c] = divide ? (f != 0.0 ? X[i + ldx * c] / f : 0.0) : X[i + ldx * c] * f;
+    }
+}
+
+hipError_t scale_cols(int n, int m, double* X, long ldx, const double* scale, int divide,
+                      hipStream_t s) {
+    const long total = (long)n * m;
+    if (total <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(blocks), dim3(256), 0, s, n, m, X, ldx, scale,
+                       divide);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void col_norms_kernel(int n, const double* __restrict__ X,
+                                                        long ldx, double* out) {
+    __shared__ double red[256];
+    const double* x = X + blockIdx.x * ldx;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += x[i] * x[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(red[0]);
+}
+
+hipError_t col_norms(int n, int m, const double* X, long ldx, double* out, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(col_norms_kernel, dim3(m), dim3(256), 0, s, n, X, ldx, out);
+    return hipGetLastError();
+}
+
+__device__ inline uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__global__ void fill_random_kernel(long n, unsigned seed, double* x) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const uint64_t h1 = splitmix64(((uint64_t)seed << 40) ^ (uint64_t)(2 * i));
+        const uint64_t h2 = splitmix64(((uint64_t)seed << 40) ^ (uint64_t)(2 * i + 1));
+        const double u1 = ((h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        const double u2 = ((h2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        x[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    }
+}
+
+hipError_t fill_random(long n, unsigned seed, double* x, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_random_kernel, dim3(blocks), dim3(256), 0, s, n, seed, x);
+    return hipGetLastError();
+}
+
+__global__ void zero_kernel(long n, double* x) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        x[i] = 0.0;
+}
+
+hipError_t zero(long n, double* x, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, s, n, x);
+    return hipGetLastError();
+}
+
+__global__ void copy2d_kernel(int rows, int cols, const double* __restrict__ src, long lds,
+                              double* __restrict__ dst, long ldd) {
+    const long total = (long)rows * cols;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % rows), j = int(e / rows);
+        dst[i + ldd * j] = src ? src[i + lds * j] : 0.0;
+    }
+}
+
+hipError_t copy2d(int rows, int cols, const double* src, long lds, double* dst, long ldd,
+                  hipStream_t s) {
+    const long total = (long)rows * cols;
+    if (total <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(copy2d_kernel, dim3(blocks), dim3(256), 0, s, rows, cols, src, lds, dst,
+                       ldd);
+    return hipGetLastError();
+}
+
+__global__ void check_finite_kernel(long n, const double* __restrict__ x, int* flag) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        if (!isfinite(x[i])) atomicOr(flag, 1);
+}
+
+hipError_t check_finite(long n, const double* x, int* flag, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(check_finite_kernel, dim3(blocks), dim3(256), 0, s, n, x, flag);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void cp_inner_kernel(int ra, int rb, const double* G0,
+                                                       const double* G1, const double* G2,
+                                                       const double* wa, const double* wb,
+                                                       double* out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    const long total = (long)ra * rb;
+    for (long e = threadIdx.x; e < total; e += 256) {
+        const int kk = int(e % ra), m = int(e / ra);
+        acc += (wa ? wa[kk] : 1.0) * (wb ? wb[m] : 1.0) * G0[e] * G1[e] * G2[e];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+hipError_t cp_inner_reduce(int ra, int rb, const double* G0, const double* G1, const double* G2,
+                           const double* wa, const double* wb, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(cp_inner_kernel, dim3(1), dim3(256), 0, s, ra, rb, G0, G1, G2, wa, wb, out);
+    return hipGetLastError();
+}
+
+// Block-wide sum of one value per thread (blockDim.x == 1024).
+__device__ inline double block_sum_1024(double v, double* red) {
+    const int tid = threadIdx.x;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (tid < 64) {
+        r = tid < 16 ? red[tid] : 0.0;
+        for (int off = 8; off > 0; off >>= 1) r += __shfl_down(r, off, 64);
+    }
+    __syncthreads();
+    if (tid == 0) red[16] = r;
+    __syncthreads();
+    r = red[16];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(1024) void mgs_kernel(int n, int m, double* Y, double drop,
+                                                   int* count) {
+    __shared__ double red[32];
+    __shared__ double dots[1024];
+    const int tid = threadIdx.x;
+    int kept = 0;
+    for (int j = 0; j < m; ++j) {
+        double* y = Y + (long)j * n;
+        double s = 0.0;
+        for (int i = tid; i < n; i += 1024) s += y[i] * y[i];
+        const double nrm0 = sqrt(block_sum_1024(s, red));
+        // two projection passes against the kept columns 0..kept-1
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int c0 = 0; c0 < kept; c0 += 1024 / 64) {
+                // each wavefront computes one dot product
+                const int w = tid >> 6, lane = tid & 63;
+                const int c = c0 + w;
+                double acc = 0.0;
+                if (c < kept) {
+                    const double* q = Y + (long)c * n;
+                    for (int i = lane; i < n; i += 64) acc += q[i] * y[i];
+                }
+                for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+                if (lane == 0) dots[w] = acc;
+                __syncthreads();
+                const int nc = min(16, kept - c0);
+                for (int i = tid; i < n; i += 1024) {
+                    double v = y[i];
+                    for (int t = 0; t < nc; ++t) v -= dots[t] * Y[(long)(c0 + t) * n + i];
+                    y[i] = v;
+                }
+                __syncthreads();
+            }
+        }
+        s = 0.0;
+        for (int i = tid; i < n; i += 1024) s += y[i] * y[i];
+        const double nrm = sqrt(block_sum_1024(s, red));
+        if (nrm > drop * nrm0 && nrm > 1e-300) {
+            double* dst = Y + (long)kept * n;
+            const double inv = 1.0 / nrm;
+            for (int i = tid; i < n; i += 1024) dst[i] = y[i] * inv;
+            ++kept;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *count = kept;
+}
+
+hipError_t mgs_qr(int n, int m, double* Y, double drop, int* count, hipStream_t s) {
+    hipLaunchKernelGGL(mgs_kernel, dim3(1), dim3(1024), 0, s, n, m, Y, drop, count);
+    return hipGetLastError();
+}
+
+__global__ void transpose_kernel(int rows, int cols, const double* __restrict__ src, long lds,
+                                 double* __restrict__ dst, long ldd) {
+    const long total = (long)rows * cols;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % rows), j = int(e / rows);
+        dst[j + ldd * i] = src[i + lds * j];
+    }
+}
+
+hipError_t transpose(int rows, int cols, const double* src, long lds, double* dst, long ldd,
+                     hipStream_t s) {
+    const long total = (long)rows * cols;
+    if (total <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(transpose_kernel, dim3(blocks), dim3(256), 0, s, rows, cols, src, lds, dst,
+                       ldd);
+    return hipGetLastError();
+}
+
+// One 16x16x4 product of fixed matrices, written out with the accumulator
+// layout assumed by the GEMM (used by a self-test).
+__global__ void mfma_probe_kernel(double* out) {
+    const int lane = threadIdx.x;
+    const int i = lane & 15, k = lane >> 4;
+    const double a = 1.0 + i + 16.0 * k;           // A[i][k]
+    const double b = 1.0 + 0.5 * k - 0.25 * i;     // B[k][j], j = lane & 15
+    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    for (int v = 0; v < 4; ++v) {
+        const int row = (lane >> 4) + 4 * v, col = lane & 15;
+        out[row * 16 + col] = acc[v];
+    }
+}
+
+hipError_t mfma_probe(double* out, hipStream_t s) {
+    hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, s, out);
+    return hipGetLastError();
+}
+
+}  // namespace fc

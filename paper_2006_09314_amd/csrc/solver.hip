@@ -1,0 +1,1254 @@
+// fracctl: rank-truncated PCG for (beta A^-alpha + (gamma/beta) A^alpha) u = y on MI355X.
+//
+// Everything after the entry transform runs in the eigen-coordinates of the
+// three 1D Sturm-Liouville matrices (paper Section 3.3): there the operator
+// and the preconditioner are Hadamard products with separable (low Kronecker
+// rank) positive tensors, and Algorithm 1 (Appendix 2) runs on Tucker iterates
+// (orthonormal bases Z_l, n x r_l, dense core r0 x r1 x r2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/fracctl.h"
+#include "host_math.h"
+#include "kernels.h"
+
+namespace {
+
+// largest small-space dimension (union bases, projected cores, Jacobi size)
+constexpr int KM = 128;
+
+thread_local std::string g_last_error;
+
+fc_status fail(fc_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess)                                                                \
+            throw FcError(FC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));    \
+    } while (0)
+
+struct FcError {
+    fc_status status;
+    std::string msg;
+    FcError(fc_status s, std::string m) : status(s), msg(std::move(m)) {}
+};
+
+// A Tucker tensor in device memory: T = core x_1 Z0 x_2 Z1 x_3 Z2.
+struct Tucker {
+    int r[3] = {0, 0, 0};
+    double* Z[3] = {nullptr, nullptr, nullptr};  // n x rcap each, ld n
+    double* core = nullptr;                     // capacity ccap
+    bool empty() const { return r[0] == 0 || r[1] == 0 || r[2] == 0; }
+    long csize() const { return (long)r[0] * r[1] * r[2]; }
+};
+
+struct Arena {
+    std::vector<void*> blocks;
+    double* alloc(size_t count) {
+        void* p = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&p, count * sizeof(double));
+        if (e != hipSuccess) throw FcError(FC_ERR_OUT_OF_MEMORY, "hipMalloc failed");
+        blocks.push_back(p);
+        return (double*)p;
+    }
+    int* alloc_int(size_t count) {
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(int));
+        if (e != hipSuccess) throw FcError(FC_ERR_OUT_OF_MEMORY, "hipMalloc failed");
+        blocks.push_back(p);
+        return (int*)p;
+    }
+    ~Arena() {
+        for (void* p : blocks) hipFree(p);
+    }
+};
+
+}  // namespace
+
+// A separable positive tensor in eigen-coordinates: sum_q (x)_l D_l[:, q]
+// with the positive weights folded into the factors (cube root per mode).
+struct Separable {
+    int Q = 0;
+    double* D[3] = {nullptr, nullptr, nullptr};   // n x Q
+    double* D2[3] = {nullptr, nullptr, nullptr};  // elementwise squares
+    std::vector<double> w;                        // host copy of the weights (pre-folding)
+    std::vector<double> F[3];                     // host copies of unweighted factors n x Q
+};
+
+struct fc_plan_s {
+    int n = 0;
+    double alpha = 0, beta = 1, gamma = 1, eps = 1e-6, tol = 1e-6, op_acc = 0;
+    int max_iter = 100, rcap = 64, pcap = 96, precond_rank = 6;
+    std::vector<double> lam[3];   // host eigenvalues
+    std::vector<double> Vh[3];    // host eigenvectors
+    double* V[3] = {nullptr, nullptr, nullptr};
+    Separable op, pc;
+    double op_err = 0, pc_err = 0;
+    Arena arena;
+    // workspace
+    Tucker slot[10];
+    double *E = nullptr, *Gd[3] = {}, *Mq = nullptr, *c1 = nullptr, *c2 = nullptr;
+    double *Xs = nullptr, *HX = nullptr, *Ys = nullptr, *Ts = nullptr, *F = nullptr;
+    double *Bp = nullptr, *Ev = nullptr, *Evec = nullptr, *W[3] = {}, *As[3] = {};
+    double *T1 = nullptr, *T2 = nullptr, *C = nullptr, *Cp = nullptr, *Cg = nullptr;
+    double *Cev = nullptr, *Cvec = nullptr, *Cn1 = nullptr, *Cn2 = nullptr;
+    double *Phi[3] = {}, *Map = nullptr, *scal = nullptr, *tmpn = nullptr, *tmpn2 = nullptr;
+    double *cw = nullptr, *cf[3] = {}, *Yh[3] = {};
+    int* icount = nullptr;
+    double* jac = nullptr;
+    long qchunk = 1;
+    long cap_canon = 0;
+    int* dflag = nullptr;
+    hipStream_t stream = nullptr;
+    // statistics of the last solve
+    int max_seen_rank = 0;
+};
+
+namespace {
+
+using fc::GemmArgs;
+
+// Optional timing of every matrix-core GEMM launch with HIP events on the
+// launching stream (for roofline reporting); off unless enabled.
+struct GemmProfile {
+    bool on = false;
+    std::vector<hipEvent_t> ev;   // pairs
+    size_t used = 0;
+    double flops = 0, bytes = 0;
+    long launches = 0;
+};
+GemmProfile g_prof;
+
+struct Ctx {
+    fc_plan_s* p;
+    hipStream_t s;
+    int n;
+};
+
+void gemm(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+          long lda, const double* B, long ldb, double beta, double* C, long ldc, int batch = 1,
+          long sA = 0, long sB = 0, long sC = 0, int inner = 1, long sAi = 0, long sBi = 0,
+          long sCi = 0, const double* d = nullptr, long sD = 0) {
+    GemmArgs g;
+    g.M = M; g.N = N; g.K = K; g.batch = batch; g.inner = inner;
+    g.alpha = alpha; g.beta = beta;
+    g.A = A; g.lda = lda; g.strideA = sA; g.strideAin = sAi;
+    g.B = B; g.ldb = ldb; g.strideB = sB; g.strideBin = sBi;
+    g.C = C; g.ldc = ldc; g.strideC = sC; g.strideCin = sCi;
+    g.d = d; g.strideD = sD;
+    if (g_prof.on && M > 0 && N > 0 && K > 0 && batch > 0) {
+        if (g_prof.used + 2 > g_prof.ev.size()) {
+            for (int i = 0; i < 256; ++i) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                g_prof.ev.push_back(e);
+            }
+        }
+        HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], c.s));
+        HIPCHK(fc::gemm(ta, tb, g, c.s));
+        HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], c.s));
+        g_prof.used += 2;
+        g_prof.flops += 2.0 * M * N * (double)K * batch;
+        g_prof.bytes += 8.0 * ((double)M * K + (double)K * N + (double)M * N) * batch;
+        g_prof.launches += 1;
+        return;
+    }
+    HIPCHK(fc::gemm(ta, tb, g, c.s));
+}
+
+void sync(const Ctx& c) { HIPCHK(hipStreamSynchronize(c.s)); }
+
+template <class T>
+void d2h(const Ctx& c, T* dst, const T* src, size_t count) {
+    HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, c.s));
+    sync(c);
+}
+template <class T>
+void h2d(const Ctx& c, T* dst, const T* src, size_t count) {
+    HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, c.s));
+}
+
+// ---- core mode products ---------------------------------------------------
+// out = core x_mode M, core r0 x r1 x r2, M is m x r_mode (ld ldm); out has
+// r_mode replaced by m.
+// With transM the stored matrix is r_mode x m and op(M) = M^T.
+void mode_product(const Ctx& c, const double* core, const int r[3], int mode, const double* M,
+                  long ldm, int m, double* out, double alpha = 1.0, double beta = 0.0,
+                  bool transM = false) {
+    if (mode == 0) {
+        gemm(c, transM, false, m, r[1] * r[2], r[0], alpha, M, ldm, core, r[0], beta, out, m);
+    } else if (mode == 1) {
+        // for each k: (r0 x r1) * op(M)^T (r1 x m)
+        gemm(c, false, !transM, r[0], m, r[1], alpha, core, r[0], M, ldm, beta, out, r[0], r[2],
+             (long)r[0] * r[1], 0, (long)r[0] * m);
+    } else {
+        gemm(c, false, !transM, r[0] * r[1], m, r[2], alpha, core, (long)r[0] * r[1], M, ldm,
+             beta, out, (long)r[0] * r[1]);
+    }
+}
+
+// permuted dims for "mode first"
+void perm_dims(const int r[3], int mode, int out[3]) {
+    if (mode == 0) { out[0] = r[0]; out[1] = r[1]; out[2] = r[2]; }
+    else if (mode == 1) { out[0] = r[1]; out[1] = r[0]; out[2] = r[2]; }
+    else { out[0] = r[2]; out[1] = r[0]; out[2] = r[1]; }
+}
+
+double host_dot(const Ctx& c, long n, const double* x, const double* y) {
+    fc_plan_s* p = c.p;
+    HIPCHK(fc::dot_batched(n, 1, x, y, 0, p->scal, c.s));
+    double v = 0;
+    d2h(c, &v, p->scal, 1);
+    return v;
+}
+
+// ---- HOSVD truncation of a dense core in given bases ----------------------
+// Input: core C (k0 x k1 x k2) expressed in orthonormal bases B_l (n x k_l).
+// Output: Tucker `out` with ranks chosen so that the dropped energy is at
+// most thr2 (the exact HOSVD bound sum_l tail_l <= thr2, split evenly).
+void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3], double thr2,
+                Tucker& out, const char* what) {
+    fc_plan_s* p = c.p;
+    const int n = c.n;
+    const long csz = (long)k[0] * k[1] * k[2];
+    if (csz == 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+    for (int l = 0; l < 3; ++l)
+        if (k[l] > KM) throw FcError(FC_ERR_INTERNAL, std::string(what) + ": subspace > 128");
+    // unfolding Grams
+    for (int l = 0; l < 3; ++l) {
+        int pd[3];
+        perm_dims(k, l, pd);
+        const double* src = C;
+        if (l != 0) {
+            HIPCHK(fc::permute_core(k[0], k[1], k[2], l, 1, C, 0, p->Cp, 0, c.s));
+            src = p->Cp;
+        }
+        gemm(c, false, true, pd[0], pd[0], pd[1] * pd[2], 1.0, src, pd[0], src, pd[0], 0.0,
+             p->Cg + (long)l * KM * KM, pd[0]);
+    }
+    for (int l = 0; l < 3; ++l)
+        HIPCHK(fc::sym_eig(k[l], 1, p->Cg + (long)l * KM * KM, k[l], 0, p->Cev + l * KM,
+                           p->Cvec + (long)l * KM * KM, k[l], 0, p->jac, c.s));
+    std::vector<double> ev(3 * KM);
+    d2h(c, ev.data(), p->Cev, 3 * KM);
+    double tot = 0;
+    for (int i = 0; i < k[0]; ++i) tot += std::max(ev[i], 0.0);
+    int r[3];
+    for (int l = 0; l < 3; ++l) {
+        // smallest r with tail(r) <= thr2/3
+        double tail = 0;
+        int rr = k[l];
+        for (int i = k[l] - 1; i >= 0; --i) {
+            tail += std::max(ev[l * KM + i], 0.0);
+            if (tail <= thr2 / 3.0) rr = i; else break;
+        }
+        r[l] = rr;
+    }
+    if (r[0] == 0 || r[1] == 0 || r[2] == 0 || tot <= thr2) {
+        out.r[0] = out.r[1] = out.r[2] = 0;
+        return;
+    }
+    for (int l = 0; l < 3; ++l)
+        if (r[l] > p->rcap)
+            throw FcError(FC_ERR_INTERNAL, std::string(what) + ": Tucker rank " +
+                                               std::to_string(r[l]) + " exceeds max_rank");
+    // core projection: C x_l U_l^T
+    int cur[3] = {k[0], k[1], k[2]};
+    const double* src = C;
+    double* bufs[2] = {p->Cn1, p->Cn2};
+    for (int l = 0; l < 3; ++l) {
+        double* dst = (l == 2) ? out.core : bufs[l & 1];
+        // C x_l U_l[:, :r_l]^T
+        mode_product(c, src, cur, l, p->Cvec + (long)l * KM * KM, k[l], r[l], dst, 1.0, 0.0, true);
+        cur[l] = r[l];
+        src = dst;
+    }
+    // bases: Z_l = B_l U_l[:, :r_l]
+    for (int l = 0; l < 3; ++l) {
+        gemm(c, false, false, n, r[l], k[l], 1.0, B[l], n, p->Cvec + (long)l * KM * KM, k[l], 0.0,
+             out.Z[l], n);
+        out.r[l] = r[l];
+    }
+    p->max_seen_rank = std::max({p->max_seen_rank, r[0], r[1], r[2]});
+}
+
+// ---- exact truncation of a short sum of Tucker tensors ---------------------
+// T = sum_t coef_t T_t.  Per mode, an orthonormal basis of the union of the
+// bases (two-pass Gram-Schmidt), the dense core in that basis, then HOSVD.
+void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>& terms_in,
+               double tol_rel, double floor_abs, Tucker& out, const char* what) {
+    fc_plan_s* p = c.p;
+    const int n = c.n;
+    std::vector<std::pair<double, const Tucker*>> terms;
+    for (auto& t : terms_in)
+        if (t.first != 0.0 && !t.second->empty()) terms.push_back(t);
+    if (terms.empty()) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+    int k[3];
+    for (int l = 0; l < 3; ++l) {
+        int tot = 0;
+        for (auto& t : terms) tot += t.second->r[l];
+        if (tot > 2 * KM) throw FcError(FC_ERR_INTERNAL, "sum_trunc: too many columns");
+        double* Y = p->Phi[l];
+        int off = 0;
+        for (auto& t : terms) {
+            HIPCHK(fc::copy2d(n, t.second->r[l], t.second->Z[l], n, Y + (long)off * n, n, c.s));
+            off += t.second->r[l];
+        }
+        HIPCHK(fc::mgs_qr(n, tot, Y, 1e-12, p->icount + l, c.s));
+    }
+    int cnt[3];
+    d2h(c, cnt, p->icount, 3);
+    for (int l = 0; l < 3; ++l) {
+        k[l] = cnt[l];
+        if (k[l] > KM) throw FcError(FC_ERR_INTERNAL, std::string(what) + ": union basis > 128");
+    }
+    // dense core: sum_t coef_t core_t x_l (Phi_l^T Z_l^t)
+    const long csz = (long)k[0] * k[1] * k[2];
+    HIPCHK(fc::zero(csz, p->C, c.s));
+    for (auto& t : terms) {
+        const Tucker& T = *t.second;
+        int cur[3] = {T.r[0], T.r[1], T.r[2]};
+        const double* src = T.core;
+        double* bufs[2] = {p->Cn1, p->Cn2};
+        for (int l = 0; l < 3; ++l) {
+            double* M = p->Map + (long)l * KM * KM;  // k_l x r_l
+            gemm(c, true, false, k[l], T.r[l], n, 1.0, p->Phi[l], n, T.Z[l], n, 0.0, M, k[l]);
+        }
+        for (int l = 0; l < 3; ++l) {
+            const bool last = (l == 2);
+            double* dst = last ? p->C : bufs[l & 1];
+            mode_product(c, src, cur, l, p->Map + (long)l * KM * KM, k[l], k[l], dst,
+                         last ? t.first : 1.0, last ? 1.0 : 0.0);
+            cur[l] = k[l];
+            src = dst;
+        }
+    }
+    const double n2 = host_dot(c, csz, p->C, p->C);
+    const double thr2 = std::max(tol_rel * tol_rel * n2, floor_abs * floor_abs);
+    if (!(std::isfinite(n2))) throw FcError(FC_ERR_NUMERIC, std::string(what) + ": non-finite");
+    if (n2 <= thr2) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+    double* B[3] = {p->Phi[0], p->Phi[1], p->Phi[2]};
+    hosvd_core(c, p->C, k, B, thr2, out, what);
+}
+
+// ---- truncation of a Hadamard product with a separable positive tensor ----
+// T = D~ (.) P = sum_q P x_l diag(D_l[:,q]).  Subspace per mode from the
+// block reduced HOSVD (sum over q of the unfolding Grams of the terms),
+// exact projection of T onto it, then HOSVD of the projected core.
+void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_rel,
+               double floor_abs, Tucker& out, const char* what) {
+    fc_plan_s* p = c.p;
+    const int n = c.n;
+    const int Q = op.Q;
+    if (P.empty()) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+    const int* r = P.r;
+    // 1. diagonal Grams Gd_l^q = Z_l^T diag(D_l[:,q]^2) Z_l  -> stack r_l^2 x Q
+    for (int l = 0; l < 3; ++l) {
+        HIPCHK(fc::rowkron(n, r[l], r[l], P.Z[l], n, P.Z[l], n, p->E, c.s));
+        gemm(c, true, false, r[l] * r[l], Q, n, 1.0, p->E, n, op.D2[l], n, 0.0, p->Gd[l],
+             (long)r[l] * r[l]);
+    }
+    // 2. per-term unfolding Grams M_l^q = core_(l) (G_b^q (x) G_a^q) core_(l)^T
+    double* Mq[3];
+    for (int l = 0; l < 3; ++l) Mq[l] = p->Mq + (long)l * Q * p->rcap * p->rcap;
+    for (int l = 0; l < 3; ++l) {
+        int pd[3];
+        perm_dims(r, l, pd);
+        const int a = (l == 0) ? 1 : 0, b = (l == 2) ? 1 : 2;   // other modes in order
+        const double* core = P.core;
+        if (l != 0) {
+            HIPCHK(fc::permute_core(r[0], r[1], r[2], l, 1, P.core, 0, p->Cp, 0, c.s));
+            core = p->Cp;
+        }
+        const long csz = (long)r[0] * r[1] * r[2];
+        for (long q0 = 0; q0 < Q; q0 += p->qchunk) {
+            const int qc = (int)std::min<long>(p->qchunk, Q - q0);
+            // c1^q = core x_3 G_b^q : (pd0 pd1 x pd2) * G^T
+            gemm(c, false, true, pd[0] * pd[1], pd[2], pd[2], 1.0, core, (long)pd[0] * pd[1],
+                 p->Gd[b] + q0 * (long)r[b] * r[b], pd[2], 0.0, p->c1, (long)pd[0] * pd[1], qc, 0,
+                 (long)r[b] * r[b], csz);
+            // c2^q = c1^q x_2 G_a^q : batch over (q, k)
+            gemm(c, false, true, pd[0], pd[1], pd[1], 1.0, p->c1, pd[0],
+                 p->Gd[a] + q0 * (long)r[a] * r[a], pd[1], 0.0, p->c2, pd[0], qc * pd[2], csz,
+                 (long)r[a] * r[a], csz, pd[2], (long)pd[0] * pd[1], 0, (long)pd[0] * pd[1]);
+            // M^q = core_(1) c2^q_(1)^T
+            gemm(c, false, true, pd[0], pd[0], pd[1] * pd[2], 1.0, core, pd[0], p->c2, pd[0], 0.0,
+                 Mq[l] + q0 * (long)pd[0] * pd[0], pd[0], qc, 0, csz, (long)pd[0] * pd[0]);
+        }
+    }
+    // trace = sum_q ||T_q||^2 = sum_q <M_0^q, Gd_0^q>
+    const double trH = host_dot(c, (long)Q * r[0] * r[0], Mq[0], p->Gd[0]);
+    if (!std::isfinite(trH)) throw FcError(FC_ERR_NUMERIC, std::string(what) + ": non-finite");
+    if (trH <= 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+    const double tau2_est = std::max(tol_rel * tol_rel * trH, floor_abs * floor_abs);
+    // 3. dominant subspaces of Hh_l = sum_q D^q Z M^q Z^T D^q by subspace iteration
+    int pk[3];
+    for (int l = 0; l < 3; ++l) {
+        const int pmax = std::min({p->pcap, n, Q * r[l]});
+        int k = pmax;
+        HIPCHK(fc::fill_random(n * (long)k, 1234u + 7u * l, p->Xs, c.s));
+        auto apply = [&](const double* X, int kk, double* HXo) {
+            // Y^q = Z^T D^q X  (stack: r*kk x Q)
+            HIPCHK(fc::rowkron(n, r[l], kk, P.Z[l], n, X, n, p->E, c.s));
+            gemm(c, true, false, r[l] * kk, Q, n, 1.0, p->E, n, op.D[l], n, 0.0, p->Ys,
+                 (long)r[l] * kk);
+            // T^q = M^q Y^q
+            gemm(c, false, false, r[l], kk, r[l], 1.0, Mq[l], r[l], p->Ys, r[l], 0.0, p->Ts, r[l],
+                 Q, (long)r[l] * r[l], (long)r[l] * kk, (long)r[l] * kk);
+            // F = D T^T : n x (r*kk)
+            gemm(c, false, true, n, r[l] * kk, Q, 1.0, op.D[l], n, p->Ts, (long)r[l] * kk, 0.0,
+                 p->F, n);
+            HIPCHK(fc::rowcontract(n, r[l], kk, P.Z[l], n, p->F, HXo, n, c.s));
+        };
+        for (int it = 0; it < 3; ++it) {
+            apply(p->Xs, k, p->HX);
+            HIPCHK(fc::mgs_qr(n, k, p->HX, 1e-13, p->icount, c.s));
+            int kk = 0;
+            d2h(c, &kk, p->icount, 1);
+            if (kk == 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+            k = kk;
+            HIPCHK(fc::copy2d(n, k, p->HX, n, p->Xs, n, c.s));
+        }
+        // Rayleigh-Ritz
+        apply(p->Xs, k, p->HX);
+        gemm(c, true, false, k, k, n, 1.0, p->Xs, n, p->HX, n, 0.0, p->Bp, k);
+        HIPCHK(fc::sym_eig(k, 1, p->Bp, k, 0, p->Ev, p->Evec, k, 0, p->jac, c.s));
+        std::vector<double> th(k);
+        d2h(c, th.data(), p->Ev, k);
+        // block-RHOSVD rank estimate, then a margin of 16 directions
+        double tail = 0;
+        int rr = k;
+        for (int i = k - 1; i >= 0; --i) {
+            tail += std::max(th[i], 0.0);
+            if (tail <= tau2_est / 3.0) rr = i; else break;
+        }
+        int use = std::min(k, std::max(rr + 16, 1));
+        gemm(c, false, false, n, use, k, 1.0, p->Xs, n, p->Evec, k, 0.0, p->W[l], n);
+        pk[l] = use;
+    }
+    // 4. projection A_l^q = W_l^T D^q Z_l -> stack (pk*r x Q)
+    for (int l = 0; l < 3; ++l) {
+        HIPCHK(fc::rowkron(n, pk[l], r[l], p->W[l], n, P.Z[l], n, p->E, c.s));
+        gemm(c, true, false, pk[l] * r[l], Q, n, 1.0, p->E, n, op.D[l], n, 0.0, p->As[l],
+             (long)pk[l] * r[l]);
+    }
+    // 5. C = sum_q core x_1 A_0^q x_2 A_1^q x_3 A_2^q
+    const long csz = (long)r[0] * r[1] * r[2];
+    const long t1sz = (long)pk[0] * r[1] * r[2];
+    const long t2sz = (long)pk[0] * pk[1] * r[2];
+    for (long q0 = 0; q0 < Q; q0 += p->qchunk) {
+        const int qc = (int)std::min<long>(p->qchunk, Q - q0);
+        // T1^q = A_0^q core_(1): (pk0 x r0)(r0 x r1 r2)
+        gemm(c, false, false, pk[0], r[1] * r[2], r[0], 1.0, p->As[0] + q0 * pk[0] * (long)r[0],
+             pk[0], P.core, r[0], 0.0, p->T1, pk[0], qc, (long)pk[0] * r[0], 0, t1sz);
+        // T2^q = T1^q x_2 A_1^q: batch (q, k)
+        gemm(c, false, true, pk[0], pk[1], r[1], 1.0, p->T1, pk[0],
+             p->As[1] + q0 * pk[1] * (long)r[1], pk[1], 0.0, p->T2, pk[0], qc * r[2], t1sz,
+             (long)pk[1] * r[1], t2sz, r[2], (long)pk[0] * r[1], 0, (long)pk[0] * pk[1]);
+        // C += [T2^q]_q [A_2^q]_q^T  ((pk0 pk1) x (qc r2)) ((qc r2) x pk2)
+        gemm(c, false, true, pk[0] * pk[1], pk[2], qc * r[2], 1.0, p->T2, (long)pk[0] * pk[1],
+             p->As[2] + q0 * pk[2] * (long)r[2], pk[2], q0 == 0 ? 0.0 : 1.0, p->C,
+             (long)pk[0] * pk[1]);
+    }
+    const long Csz = (long)pk[0] * pk[1] * pk[2];
+    const double n2 = host_dot(c, Csz, p->C, p->C);
+    if (!std::isfinite(n2)) throw FcError(FC_ERR_NUMERIC, std::string(what) + ": non-finite");
+    const double thr2 = std::max(tol_rel * tol_rel * n2, floor_abs * floor_abs);
+    if (n2 <= thr2) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+    double* B[3] = {p->W[0], p->W[1], p->W[2]};
+    hosvd_core(c, p->C, pk, B, thr2, out, what);
+    (void)csz;
+}
+
+// ---- canonical -> Tucker (exact unfolding spectra) ------------------------
+// Factors X_l (n x m, ld n) and weights w (m, device, may be null).
+void canon_to_tucker(const Ctx& c, int m, const double* w, const double* const X[3],
+                     double tol_rel, Tucker& out, const char* what) {
+    fc_plan_s* p = c.p;
+    const int n = c.n;
+    int k[3];
+    for (int l = 0; l < 3; ++l) {
+        HIPCHK(fc::copy2d(n, m, X[l], n, p->Phi[l], n, c.s));
+        HIPCHK(fc::mgs_qr(n, m, p->Phi[l], 1e-13, p->icount + l, c.s));
+    }
+    int cnt[3];
+    d2h(c, cnt, p->icount, 3);
+    for (int l = 0; l < 3; ++l) {
+        k[l] = cnt[l];
+        if (k[l] > KM) throw FcError(FC_ERR_INTERNAL, std::string(what) + ": input basis > 128");
+        if (k[l] == 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+    }
+    // coefficients M_l = Phi_l^T X_l  (k_l x m); scale M_2 columns by w
+    double* Ml[3];
+    for (int l = 0; l < 3; ++l) {
+        Ml[l] = p->cf[l];
+        gemm(c, true, false, k[l], m, n, 1.0, p->Phi[l], n, X[l], n, 0.0, Ml[l], k[l]);
+    }
+    if (w) HIPCHK(fc::scale_cols(k[2], m, Ml[2], k[2], w, 0, c.s));
+    // Khatri-Rao: KR[(i,j), s] = M0[i,s] M1[j,s]  -> use rowkron on transposes: build
+    // M0^T (m x k0) and M1^T (m x k1), then rowkron gives E[s, i + k0 j]
+    double* M0t = p->Ys;
+    double* M1t = p->Ts;
+    HIPCHK(fc::transpose(k[0], m, Ml[0], k[0], M0t, m, c.s));
+    HIPCHK(fc::transpose(k[1], m, Ml[1], k[1], M1t, m, c.s));
+    HIPCHK(fc::rowkron(m, k[0], k[1], M0t, m, M1t, m, p->E, c.s));
+    // core_(3)^T = KR^T-ish: C[(i,j), kk] = sum_s E[s, (i,j)] M2[kk, s]
+    gemm(c, true, true, k[0] * k[1], k[2], m, 1.0, p->E, m, Ml[2], k[2], 0.0, p->C,
+         (long)k[0] * k[1]);
+    const long csz = (long)k[0] * k[1] * k[2];
+    const double n2 = host_dot(c, csz, p->C, p->C);
+    if (!std::isfinite(n2)) throw FcError(FC_ERR_NUMERIC, std::string(what) + ": non-finite input");
+    const double thr2 = tol_rel * tol_rel * n2;
+    if (n2 <= 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+    double* B[3] = {p->Phi[0], p->Phi[1], p->Phi[2]};
+    hosvd_core(c, p->C, k, B, thr2, out, what);
+}
+
+double tucker_inner(const Ctx& c, const Tucker& A, const Tucker& B) {
+    fc_plan_s* p = c.p;
+    const int n = c.n;
+    if (A.empty() || B.empty()) return 0.0;
+    for (int l = 0; l < 3; ++l)
+        gemm(c, true, false, A.r[l], B.r[l], n, 1.0, A.Z[l], n, B.Z[l], n, 0.0,
+             p->Map + (long)l * KM * KM, A.r[l]);
+    int cur[3] = {B.r[0], B.r[1], B.r[2]};
+    const double* src = B.core;
+    double* bufs[3] = {p->Cn1, p->Cn2, p->Cn1};
+    for (int l = 0; l < 3; ++l) {
+        double* dst = (l == 2) ? p->Cp : bufs[l];
+        mode_product(c, src, cur, l, p->Map + (long)l * KM * KM, A.r[l], A.r[l], dst);
+        cur[l] = A.r[l];
+        src = dst;
+    }
+    return host_dot(c, A.csize(), A.core, p->Cp);
+}
+
+double tucker_norm2(const Ctx& c, const Tucker& A) {
+    if (A.empty()) return 0.0;
+    return host_dot(c, A.csize(), A.core, A.core);
+}
+
+void tucker_copy(const Ctx& c, const Tucker& src, Tucker& dst, double scale = 1.0) {
+    for (int l = 0; l < 3; ++l) {
+        HIPCHK(fc::copy2d(c.n, src.r[l], src.Z[l], c.n, dst.Z[l], c.n, c.s));
+        dst.r[l] = src.r[l];
+    }
+    HIPCHK(fc::axpby(src.csize(), scale, src.core, 0.0, dst.core, c.s));
+}
+
+// ---- Tucker -> canonical (T2C) and output in grid coordinates -------------
+// The core of a HOSVD-truncated tensor is all-orthogonal; each mode-3 slice
+// core[:,:,nu] is split by its SVD, and (slice, singular value) terms are
+// dropped smallest first while the dropped energy stays within budget2.
+// Returns the rank; writes nothing if the rank exceeds cap.
+int tucker_to_canon_out(const Ctx& c, const Tucker& X, double budget2, bool to_grid, int cap,
+                        double* w_u, double* const U[3]) {
+    fc_plan_s* p = c.p;
+    const int n = c.n;
+    if (X.empty()) return 0;
+    const int r0 = X.r[0], r1 = X.r[1], r2 = X.r[2];
+    // slice Grams S_nu = core[:,:,nu]^T core[:,:,nu]  (r1 x r1), batch r2
+    gemm(c, true, false, r1, r1, r0, 1.0, X.core, r0, X.core, r0, 0.0, p->Bp, r1, r2,
+         (long)r0 * r1, (long)r0 * r1, (long)r1 * r1);
+    HIPCHK(fc::sym_eig(r1, r2, p->Bp, r1, (long)r1 * r1, p->Ev, p->Evec, r1, (long)r1 * r1, p->jac, c.s));
+    std::vector<double> sig2((size_t)r1 * r2);
+    d2h(c, sig2.data(), p->Ev, sig2.size());
+    struct Term { double s2; int nu, j; };
+    std::vector<Term> terms;
+    for (int nu = 0; nu < r2; ++nu)
+        for (int j = 0; j < r1; ++j) terms.push_back({std::max(sig2[(size_t)nu * r1 + j], 0.0), nu, j});
+    std::stable_sort(terms.begin(), terms.end(), [](const Term& a, const Term& b) {
+        if (a.s2 != b.s2) return a.s2 < b.s2;
+        if (a.nu != b.nu) return a.nu < b.nu;
+        return a.j < b.j;
+    });
+    double dropped = 0;
+    size_t first = 0;
+    while (first < terms.size() && dropped + terms[first].s2 <= budget2) {
+        dropped += terms[first].s2;
+        ++first;
+    }
+    std::vector<Term> kept(terms.begin() + first, terms.end());
+    std::reverse(kept.begin(), kept.end());   // descending weight
+    const int K = (int)kept.size();
+    if (K > cap) return K;
+    if (K == 0) return 0;
+    // coefficient matrices: mode 1: core_nu v_j / sigma (r0 x K); mode 2: v_j (r1 x K);
+    // mode 3: e_nu (r2 x K)
+    std::vector<double> hv((size_t)r1 * r1 * r2);
+    d2h(c, hv.data(), p->Evec, hv.size());
+    std::vector<double> core_h((size_t)r0 * r1 * r2);
+    d2h(c, core_h.data(), X.core, core_h.size());
+    std::vector<double> c0((size_t)r0 * K), c1((size_t)r1 * K), c2((size_t)r2 * K, 0.0), wh(K);
+    for (int t = 0; t < K; ++t) {
+        const int nu = kept[t].nu, j = kept[t].j;
+        const double* v = hv.data() + (size_t)nu * r1 * r1 + (size_t)j * r1;
+        const double sg = std::sqrt(kept[t].s2);
+        double nrm = 0;
+        for (int i = 0; i < r0; ++i) {
+            double acc = 0;
+            for (int jj = 0; jj < r1; ++jj)
+                acc += core_h[i + (size_t)r0 * (jj + (size_t)r1 * nu)] * v[jj];
+            c0[(size_t)t * r0 + i] = acc;
+            nrm += acc * acc;
+        }
+        nrm = std::sqrt(nrm);
+        for (int i = 0; i < r0; ++i) c0[(size_t)t * r0 + i] = nrm > 0 ? c0[(size_t)t * r0 + i] / nrm : 0.0;
+        for (int jj = 0; jj < r1; ++jj) c1[(size_t)t * r1 + jj] = v[jj];
+        c2[(size_t)t * r2 + nu] = 1.0;
+        wh[t] = nrm > 0 ? nrm : sg;
+    }
+    const std::vector<double>* coef[3] = {&c0, &c1, &c2};
+    const int rr[3] = {r0, r1, r2};
+    for (int l = 0; l < 3; ++l) {
+        h2d(c, p->cf[l], coef[l]->data(), coef[l]->size());
+        const double* Zl = X.Z[l];
+        if (to_grid) {
+            gemm(c, false, false, n, rr[l], n, 1.0, p->V[l], n, X.Z[l], n, 0.0, p->tmpn, n);
+            Zl = p->tmpn;
+        }
+        gemm(c, false, false, n, K, rr[l], 1.0, Zl, n, p->cf[l], rr[l], 0.0, U[l], n);
+    }
+    h2d(c, w_u, wh.data(), K);
+    sync(c);
+    return K;
+}
+
+void alloc_workspace(fc_plan_s* p) {
+    const int n = p->n;
+    const long rc = p->rcap, pc = p->pcap;
+    const int Q = std::max(p->op.Q, p->pc.Q);
+    Arena& A = p->arena;
+    for (int s = 0; s < 10; ++s) {
+        for (int l = 0; l < 3; ++l) p->slot[s].Z[l] = A.alloc((size_t)n * rc);
+        p->slot[s].core = A.alloc((size_t)rc * rc * rc);
+    }
+    const long ecols = std::max(rc * rc, pc * rc);
+    p->E = A.alloc((size_t)std::max<long>((long)n * ecols, 256L * KM * KM));
+    for (int l = 0; l < 3; ++l) p->Gd[l] = A.alloc((size_t)Q * rc * rc);
+    p->Mq = A.alloc((size_t)3 * Q * rc * rc);
+    p->qchunk = std::max<long>(1, std::min<long>(Q, (8L << 20) / std::max<long>(1, rc * rc * rc)));
+    // c1/c2 and T1/T2 need qchunk cores of up to pc*pc*rc
+    const long big = p->qchunk * std::max(rc * rc * rc, pc * pc * rc);
+    p->c1 = A.alloc(big);
+    p->c2 = A.alloc(big);
+    p->T1 = p->c1;
+    p->T2 = p->c2;
+    p->Xs = A.alloc((size_t)n * pc);
+    p->HX = A.alloc((size_t)n * pc);
+    p->Ys = A.alloc((size_t)std::max<long>(rc * pc * Q, 256L * KM));
+    p->Ts = A.alloc((size_t)std::max<long>(rc * pc * Q, 256L * KM));
+    p->F = A.alloc((size_t)n * rc * pc);
+    p->Bp = A.alloc((size_t)std::max<long>(pc * pc, rc * rc * rc));
+    p->Ev = A.alloc((size_t)std::max<long>(pc, rc * rc));
+    p->Evec = A.alloc((size_t)std::max<long>(pc * pc, rc * rc * rc));
+    for (int l = 0; l < 3; ++l) {
+        p->W[l] = A.alloc((size_t)n * pc);
+        p->As[l] = A.alloc((size_t)pc * rc * Q);
+        p->Phi[l] = A.alloc((size_t)n * 256);
+        p->cf[l] = A.alloc((size_t)std::max<long>(KM * 256, rc * rc * rc));
+        p->Yh[l] = A.alloc((size_t)n * 256);
+    }
+    const size_t kcube = (size_t)KM * KM * KM;
+    p->C = A.alloc(kcube);
+    p->Cp = A.alloc(kcube);
+    p->Cn1 = A.alloc(kcube);
+    p->Cn2 = A.alloc(kcube);
+    p->Cg = A.alloc((size_t)3 * KM * KM);
+    p->Cev = A.alloc((size_t)3 * KM);
+    p->Cvec = A.alloc((size_t)3 * KM * KM);
+    p->Map = A.alloc((size_t)3 * KM * KM);
+    p->jac = A.alloc((size_t)std::max<long>((long)(KM + 1) * (KM + 1), (long)rc * (rc + 1) * (rc + 1)));
+    p->scal = A.alloc(64);
+    p->tmpn = A.alloc((size_t)n * std::max<long>(rc, 256));
+    p->tmpn2 = A.alloc((size_t)n * std::max<long>(rc, 256));
+    p->icount = A.alloc_int(8);
+    p->dflag = A.alloc_int(4);
+}
+
+// Build the separable factors on the host and upload them.
+void upload_separable(fc_plan_s* p, Separable& S) {
+    const int n = p->n;
+    for (int l = 0; l < 3; ++l) {
+        std::vector<double> D((size_t)n * S.Q), D2((size_t)n * S.Q);
+        for (int q = 0; q < S.Q; ++q) {
+            const double f = std::cbrt(S.w[q]);
+            for (int i = 0; i < n; ++i) {
+                const double v = f * S.F[l][(size_t)q * n + i];
+                D[(size_t)q * n + i] = v;
+                D2[(size_t)q * n + i] = v * v;
+            }
+        }
+        S.D[l] = p->arena.alloc(D.size());
+        S.D2[l] = p->arena.alloc(D2.size());
+        HIPCHK(hipMemcpy(S.D[l], D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(S.D2[l], D2.data(), D2.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+}
+
+double f_control(double s, double alpha, double beta, double gamma) {
+    return beta * std::pow(s, -alpha) + (gamma / beta) * std::pow(s, alpha);
+}
+
+// Operator D~ ~ f(s), f(s) = s g(s), g(s) = beta s^(-alpha-1) + (gamma/beta) s^(alpha-1):
+// g is completely monotone, so g ~ sum_k c_k exp(-t_k s) with c_k > 0 and
+// s exp(-t s) = (l1 + l2 + l3) exp(-t l1) exp(-t l2) exp(-t l3) gives three
+// separable terms per exponential.  alpha = 0 and alpha = 1 carry exact
+// constant / linear parts.
+void build_operator(fc_plan_s* p, double smin, double smax) {
+    const int n = p->n;
+    const double a = p->alpha, b = p->beta, gm = p->gamma;
+    Separable& S = p->op;
+    auto add_term = [&](double w, const double* t_or_null, double t, int lambda_mode) {
+        S.w.push_back(w);
+        for (int l = 0; l < 3; ++l) {
+            for (int i = 0; i < n; ++i) {
+                const double lam = p->lam[l][i];
+                double v = t_or_null ? std::exp(-t * lam) : 1.0;
+                if (l == lambda_mode) v *= lam;
+                S.F[l].push_back(v);
+            }
+        }
+        S.Q++;
+    };
+    if (a == 0.0) {
+        add_term(b + gm / b, nullptr, 0.0, -1);
+        p->op_err = 0.0;
+        return;
+    }
+    // alpha = 1: g = gamma/beta + beta s^-2 carries an exact constant.
+    const double cexact = (a == 1.0) ? gm / b : 0.0;
+    auto g = [&](double s) { return b * std::pow(s, -a - 1.0) + (gm / b) * std::pow(s, a - 1.0); };
+    auto h = [&](double s) { return g(s) - cexact; };
+    std::vector<double> t, cc;
+    double cfit = 0.0, err = 1e300;
+    // node range: the fastest useful exponential decays over ~ln(1/acc)/s_min,
+    // the slowest is replaced by the constant term below ~acc/s_max
+    const double t_hi = (std::log(1.0 / p->op_acc) + 10.0) / smin;
+    const double t_lo = std::pow(p->op_acc, 0.7) / smax;
+    for (double hstep : {0.7, 0.6, 0.5, 0.42, 0.35}) {
+        if (!fc::fit_expsum_nnls(h, g, smin, smax, t_lo, t_hi, hstep, a < 1.0, t, cc, cfit, err))
+            continue;
+        if (err <= p->op_acc) break;
+    }
+    if (!(err <= p->op_acc))
+        throw FcError(FC_ERR_NUMERIC, "operator exponential sum misses the accuracy gate (err " +
+                                          std::to_string(err) + ")");
+    const double c0 = cexact + cfit;
+    if (c0 > 0.0)
+        for (int m = 0; m < 3; ++m) add_term(c0, nullptr, 0.0, m);
+    for (int k = 0; k < (int)t.size(); ++k)
+        for (int m = 0; m < 3; ++m) add_term(cc[k], &t[0], t[k], m);
+    // gate on the spectrum: |D~(s)/f(s) - 1| over a dense grid of [smin, smax]
+    double emax = 0;
+    const int G = 20000;
+    for (int i = 0; i <= G; ++i) {
+        const double s = std::exp(std::log(smin) + (std::log(smax) - std::log(smin)) * i / G);
+        double v = c0 * s;
+        for (size_t k = 0; k < t.size(); ++k) v += s * cc[k] * std::exp(-t[k] * s);
+        emax = std::max(emax, std::fabs(v / f_control(s, a, b, gm) - 1.0));
+    }
+    p->op_err = emax;
+    if (!(emax <= p->op_acc))
+        throw FcError(FC_ERR_NUMERIC, "operator gate failed: max rel err " + std::to_string(emax));
+}
+
+// Preconditioner case (B): D~_p ~ 1/f with precond_rank positive exponentials.
+void build_preconditioner(fc_plan_s* p, double smin, double smax) {
+    const int n = p->n;
+    const double a = p->alpha, b = p->beta, gm = p->gamma;
+    Separable& S = p->pc;
+    auto add = [&](double w, double t) {
+        S.w.push_back(w);
+        for (int l = 0; l < 3; ++l)
+            for (int i = 0; i < n; ++i) S.F[l].push_back(std::exp(-t * p->lam[l][i]));
+        S.Q++;
+    };
+    if (a == 0.0) {
+        add(1.0 / (b + gm / b), 0.0);
+        p->pc_err = 0.0;
+        return;
+    }
+    auto pf = [&](double s) { return 1.0 / f_control(s, a, b, gm); };
+    std::vector<double> t, cc;
+    double err = 0;
+    int K = p->precond_rank;
+    bool ok = false;
+    for (; K >= 1; --K) {
+        if (!fc::fit_expsum(pf, pf, smin, smax, K, t, cc, err)) continue;
+        bool pos = true;
+        for (double x : cc) pos = pos && x > 0;
+        if (pos && err < 0.9) { ok = true; break; }
+    }
+    if (!ok) throw FcError(FC_ERR_NUMERIC, "preconditioner fit failed");
+    for (int k = 0; k < K; ++k) add(cc[k], t[k]);
+    p->pc_err = err;
+}
+
+void host_spectra_and_separables(fc_plan_s* p, const fc_setup_params* prm) {
+    const int n = p->n;
+    // eigenpairs of the three 1D matrices (host, in parallel)
+    std::vector<std::thread> th;
+    bool ok[3] = {false, false, false};
+    for (int l = 0; l < 3; ++l) {
+        p->lam[l].resize(n);
+        p->Vh[l].resize((size_t)n * n);
+        th.emplace_back([&, l] { ok[l] = fc::fd_eigen(n, prm->a[l], p->lam[l].data(), p->Vh[l].data()); });
+    }
+    for (auto& t : th) t.join();
+    for (int l = 0; l < 3; ++l)
+        if (!ok[l] || !(p->lam[l][0] > 0))
+            throw FcError(FC_ERR_NUMERIC, "tridiagonal eigensolver failed");
+    double smin = 0, smax = 0;
+    for (int l = 0; l < 3; ++l) { smin += p->lam[l].front(); smax += p->lam[l].back(); }
+    build_operator(p, smin, smax);
+    build_preconditioner(p, smin, smax);
+}
+
+void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
+    const int n = p->n;
+    host_spectra_and_separables(p, prm);
+    for (int l = 0; l < 3; ++l) {
+        p->V[l] = p->arena.alloc((size_t)n * n);
+        HIPCHK(hipMemcpy(p->V[l], p->Vh[l].data(), sizeof(double) * n * n, hipMemcpyHostToDevice));
+    }
+    upload_separable(p, p->op);
+    upload_separable(p, p->pc);
+    alloc_workspace(p);
+    HIPCHK(hipDeviceSynchronize());
+}
+
+// The rank-truncated PCG (Algorithm 1) on Tucker iterates in eigen-coordinates.
+struct SolveOut {
+    int iterations = 0;
+    double rel_res = 0;
+    bool converged = false;
+};
+
+SolveOut pcg(const Ctx& c, const Tucker& Bt, Tucker& Xout) {
+    fc_plan_s* p = c.p;
+    const double eps = p->eps;
+    Tucker& X = p->slot[1];
+    Tucker& R = p->slot[2];
+    Tucker& Z = p->slot[3];
+    Tucker& P = p->slot[4];
+    Tucker& S = p->slot[5];
+    Tucker& T1 = p->slot[6];
+    Tucker& T2 = p->slot[7];
+    SolveOut so;
+    const double bn = std::sqrt(tucker_norm2(c, Bt));
+    X.r[0] = X.r[1] = X.r[2] = 0;
+    tucker_copy(c, Bt, R);                 // R0 = B - fun(X0), X0 = 0
+    had_trunc(c, p->pc, R, eps, 0.0, Z, "Z0 = trunc(precond(R0))");
+    tucker_copy(c, Z, P);                  // P0 = Z0
+    double rz = tucker_inner(c, R, Z);
+    for (int k = 0; k < p->max_iter; ++k) {
+        had_trunc(c, p->op, P, eps, 0.1 * eps * bn, S, "S = trunc(fun(P))");
+        const double ps = tucker_inner(c, P, S);
+        if (!(ps > 0) || !std::isfinite(ps) || !std::isfinite(rz))
+            throw FcError(FC_ERR_NUMERIC, "PCG breakdown: <P,S> = " + std::to_string(ps));
+        const double ak = rz / ps;
+        // X = trunc(X + a P)
+        sum_trunc(c, {{1.0, &X}, {ak, &P}}, 0.1 * eps, 0.0, T1, "X = trunc(X + aP)");
+        std::swap(X, T1);
+        // R = trunc(R - a S)
+        sum_trunc(c, {{1.0, &R}, {-ak, &S}}, 0.1 * eps, 0.1 * eps * bn, T2, "R = trunc(R - aS)");
+        std::swap(R, T2);
+        so.iterations = k + 1;
+        const double rn = std::sqrt(tucker_norm2(c, R));
+        so.rel_res = bn > 0 ? rn / bn : 0.0;
+        if (R.empty() || so.rel_res <= p->tol) { so.converged = true; break; }
+        had_trunc(c, p->pc, R, eps, 0.0, Z, "Z = trunc(precond(R))");
+        const double rzn = tucker_inner(c, R, Z);
+        const double bk = rzn / rz;
+        rz = rzn;
+        sum_trunc(c, {{1.0, &Z}, {bk, &P}}, eps, 0.0, T1, "P = trunc(Z + bP)");
+        std::swap(P, T1);
+        if (P.empty()) { so.converged = true; break; }
+    }
+    Xout = X;
+    // keep slot bookkeeping consistent after swaps
+    p->slot[1] = X; p->slot[2] = R; p->slot[3] = Z; p->slot[4] = P; p->slot[5] = S;
+    p->slot[6] = T1; p->slot[7] = T2;
+    return so;
+}
+
+fc_status guard(const std::function<void()>& fn) {
+    try {
+        fn();
+        return FC_OK;
+    } catch (const FcError& e) {
+        return fail(e.status, e.msg);
+    } catch (const std::exception& e) {
+        return fail(FC_ERR_INTERNAL, e.what());
+    }
+}
+
+bool finite_pos(const double* a, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(a[i]) || !(a[i] > 0)) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fc_status_string(fc_status s) {
+    switch (s) {
+        case FC_OK: return "ok";
+        case FC_ERR_INVALID_ARG: return "invalid argument";
+        case FC_ERR_OUT_OF_MEMORY: return "out of memory";
+        case FC_ERR_NOT_CONVERGED: return "not converged";
+        case FC_ERR_RANK_OVERFLOW: return "rank overflow";
+        case FC_ERR_NUMERIC: return "numerical failure";
+        case FC_ERR_HIP: return "HIP runtime error";
+        case FC_ERR_INTERNAL: return "internal capacity exceeded";
+    }
+    return "unknown status";
+}
+
+const char* fc_last_error(void) { return g_last_error.c_str(); }
+
+fc_status fc_host_fd_eigen(int n, const double* a_mid, double* lam, double* V) {
+    if (n < 1 || !a_mid || !lam) return fail(FC_ERR_INVALID_ARG, "fc_host_fd_eigen: bad arguments");
+    if (!finite_pos(a_mid, n + 1)) return fail(FC_ERR_INVALID_ARG, "coefficients must be finite and > 0");
+    if (!fc::fd_eigen(n, a_mid, lam, V)) return fail(FC_ERR_NUMERIC, "QL iteration did not converge");
+    return FC_OK;
+}
+
+fc_status fc_host_expsum(int kind, double p1, double p2, double p3, double s_min, double s_max,
+                         int terms, double* t, double* c, double* max_rel_err) {
+    if (!(s_min > 0) || !(s_max >= s_min) || terms < 1 || terms > 64 || !t || !c || !max_rel_err)
+        return fail(FC_ERR_INVALID_ARG, "fc_host_expsum: bad arguments");
+    std::function<double(double)> h, ref;
+    if (kind == 0) {
+        h = [=](double s) { return std::pow(s, -p1); };
+        ref = h;
+    } else if (kind == 1) {
+        h = [=](double s) { return 1.0 / (p1 * std::pow(s, -p2) + p3 * std::pow(s, p2)); };
+        ref = h;
+    } else if (kind == 2) {
+        h = [=](double s) { return p1 * std::pow(s, -p2 - 1.0) + p3 * std::pow(s, p2 - 1.0); };
+        ref = h;
+    } else {
+        return fail(FC_ERR_INVALID_ARG, "fc_host_expsum: unknown kind");
+    }
+    std::vector<double> tt, cc;
+    double e = 0;
+    if (!fc::fit_expsum(h, ref, s_min, s_max, terms, tt, cc, e)) return fail(FC_ERR_NUMERIC, "fit failed");
+    for (int k = 0; k < terms; ++k) { t[k] = tt[k]; c[k] = cc[k]; }
+    *max_rel_err = e;
+    return FC_OK;
+}
+
+static fc_status validate_params(const fc_setup_params* prm);
+static void apply_defaults(fc_plan_s* p, const fc_setup_params* prm);
+
+fc_status fc_host_separable(const fc_setup_params* prm, int which, int cap, int* rank, double* w,
+                            double* F, double* max_rel_err) {
+    if (!prm || !rank || (which != 0 && which != 1)) return fail(FC_ERR_INVALID_ARG, "fc_host_separable: bad arguments");
+    fc_status v = validate_params(prm);
+    if (v != FC_OK) return v;
+    fc_plan_s p;
+    apply_defaults(&p, prm);
+    fc_status st = guard([&] { host_spectra_and_separables(&p, prm); });
+    if (st != FC_OK) return st;
+    const Separable& S = which == 0 ? p.op : p.pc;
+    *rank = S.Q;
+    if (max_rel_err) *max_rel_err = which == 0 ? p.op_err : p.pc_err;
+    if (cap < S.Q) return fail(FC_ERR_RANK_OVERFLOW, "capacity too small");
+    const int n = p.n;
+    if (w) std::memcpy(w, S.w.data(), sizeof(double) * S.Q);
+    if (F)
+        for (int l = 0; l < 3; ++l)
+            std::memcpy(F + (size_t)l * n * cap, S.F[l].data(), sizeof(double) * n * S.Q);
+    return FC_OK;
+}
+
+static fc_status validate_params(const fc_setup_params* prm) {
+    const int n = prm->n;
+    if (n < 2 || n > 4096) return fail(FC_ERR_INVALID_ARG, "n must be in [2, 4096]");
+    for (int l = 0; l < 3; ++l) {
+        if (!prm->a[l]) return fail(FC_ERR_INVALID_ARG, "coefficient pointer is NULL");
+        if (!finite_pos(prm->a[l], n + 1))
+            return fail(FC_ERR_INVALID_ARG, "coefficient samples must be finite and > 0");
+    }
+    if (!(prm->alpha >= 0.0 && prm->alpha <= 1.0)) return fail(FC_ERR_INVALID_ARG, "alpha must be in [0, 1]");
+    if (!(prm->beta > 0.0) || !std::isfinite(prm->beta)) return fail(FC_ERR_INVALID_ARG, "beta must be > 0");
+    if (!(prm->gamma > 0.0) || !std::isfinite(prm->gamma)) return fail(FC_ERR_INVALID_ARG, "gamma must be > 0");
+    if (!(prm->eps > 0.0 && prm->eps < 1.0)) return fail(FC_ERR_INVALID_ARG, "eps must be in (0, 1)");
+    if (prm->tol < 0 || prm->op_accuracy < 0 || prm->max_iter < 0 || prm->max_rank < 0 ||
+        prm->precond_rank < 0)
+        return fail(FC_ERR_INVALID_ARG, "negative option");
+    if (prm->max_rank > 96) return fail(FC_ERR_INVALID_ARG, "max_rank must be <= 96");
+    if (prm->precond_rank > 32) return fail(FC_ERR_INVALID_ARG, "precond_rank must be <= 32");
+    if (prm->precision != FC_FP64) return fail(FC_ERR_INVALID_ARG, "unsupported precision");
+    return FC_OK;
+}
+
+static void apply_defaults(fc_plan_s* p, const fc_setup_params* prm) {
+    p->n = prm->n;
+    p->alpha = prm->alpha; p->beta = prm->beta; p->gamma = prm->gamma; p->eps = prm->eps;
+    p->tol = prm->tol > 0 ? prm->tol : prm->eps;
+    p->op_acc = prm->op_accuracy > 0 ? prm->op_accuracy : prm->eps;
+    p->max_iter = prm->max_iter > 0 ? prm->max_iter : 100;
+    p->rcap = prm->max_rank > 0 ? prm->max_rank : 64;
+    p->pcap = 96;
+    p->precond_rank = prm->precond_rank > 0 ? prm->precond_rank : 6;
+}
+
+fc_status fc_setup_ex(const fc_setup_params* prm, void* hip_stream, fc_plan* out) {
+    if (!prm || !out) return fail(FC_ERR_INVALID_ARG, "fc_setup_ex: NULL argument");
+    *out = nullptr;
+    fc_status v = validate_params(prm);
+    if (v != FC_OK) return v;
+    fc_plan_s* p = new fc_plan_s();
+    apply_defaults(p, prm);
+    p->stream = (hipStream_t)hip_stream;
+    fc_status st = guard([&] { setup_plan(p, prm); });
+    if (st != FC_OK) { delete p; return st; }
+    *out = p;
+    return FC_OK;
+}
+
+fc_status fc_setup(int n, const double* a1, const double* a2, const double* a3, double alpha,
+                   double beta, double eps, fc_plan* out) {
+    fc_setup_params prm;
+    std::memset(&prm, 0, sizeof(prm));
+    prm.n = n; prm.a[0] = a1; prm.a[1] = a2; prm.a[2] = a3;
+    prm.alpha = alpha; prm.beta = beta; prm.gamma = 1.0; prm.eps = eps;
+    prm.precision = FC_FP64;
+    return fc_setup_ex(&prm, nullptr, out);
+}
+
+void fc_destroy(fc_plan plan) { delete plan; }
+
+fc_status fc_plan_spectrum(fc_plan p, double* lam, double* V) {
+    if (!p || !lam) return fail(FC_ERR_INVALID_ARG, "fc_plan_spectrum: NULL argument");
+    const int n = p->n;
+    for (int l = 0; l < 3; ++l) {
+        std::memcpy(lam + (size_t)l * n, p->lam[l].data(), sizeof(double) * n);
+        if (V) std::memcpy(V + (size_t)l * n * n, p->Vh[l].data(), sizeof(double) * n * n);
+    }
+    return FC_OK;
+}
+
+fc_status fc_plan_separable(fc_plan p, int which, int cap, int* rank, double* w, double* F) {
+    if (!p || !rank || (which != 0 && which != 1)) return fail(FC_ERR_INVALID_ARG, "fc_plan_separable: bad arguments");
+    const Separable& S = which == 0 ? p->op : p->pc;
+    *rank = S.Q;
+    if (cap < S.Q) return fail(FC_ERR_RANK_OVERFLOW, "capacity too small");
+    const int n = p->n;
+    if (w) std::memcpy(w, S.w.data(), sizeof(double) * S.Q);
+    if (F)
+        for (int l = 0; l < 3; ++l)
+            std::memcpy(F + (size_t)l * n * cap, S.F[l].data(), sizeof(double) * n * S.Q);
+    return FC_OK;
+}
+
+fc_status fc_mode_transform(fc_plan p, int mode, int transpose, int m, const double* X,
+                            double* out, void* stream) {
+    if (!p || mode < 0 || mode > 2 || m < 0 || !X || !out) return fail(FC_ERR_INVALID_ARG, "fc_mode_transform: bad arguments");
+    Ctx c{p, (hipStream_t)stream, p->n};
+    return guard([&] {
+        gemm(c, transpose != 0, false, p->n, m, p->n, 1.0, p->V[mode], p->n, X, p->n, 0.0, out, p->n);
+    });
+}
+
+fc_status fc_cp_inner(fc_plan p, int ra, const double* wa, const double* A1, const double* A2,
+                      const double* A3, int rb, const double* wb, const double* B1,
+                      const double* B2, const double* B3, double* out, void* stream) {
+    if (!p || ra < 1 || rb < 1 || !A1 || !A2 || !A3 || !B1 || !B2 || !B3 || !out)
+        return fail(FC_ERR_INVALID_ARG, "fc_cp_inner: bad arguments");
+    if ((long)ra * rb > (long)p->pcap * p->pcap * p->pcap) return fail(FC_ERR_INVALID_ARG, "ranks too large");
+    Ctx c{p, (hipStream_t)stream, p->n};
+    const double* A[3] = {A1, A2, A3};
+    const double* B[3] = {B1, B2, B3};
+    return guard([&] {
+        double* G[3] = {p->C, p->Cp, p->Cn1};
+        for (int l = 0; l < 3; ++l)
+            gemm(c, true, false, ra, rb, p->n, 1.0, A[l], p->n, B[l], p->n, 0.0, G[l], ra);
+        HIPCHK(fc::cp_inner_reduce(ra, rb, G[0], G[1], G[2], wa, wb, p->scal, c.s));
+        d2h(c, out, p->scal, 1);
+    });
+}
+
+static fc_status canon_out(fc_plan p, const Ctx& c, const Tucker& T, double budget2, bool to_grid,
+                           int cap, int* rank_out, double* w_out, double* O1, double* O2,
+                           double* O3) {
+    double* U[3] = {O1, O2, O3};
+    const int K = tucker_to_canon_out(c, T, budget2, to_grid, cap, w_out, U);
+    *rank_out = K;
+    if (K > cap) return fail(FC_ERR_RANK_OVERFLOW, "result rank " + std::to_string(K) + " exceeds capacity");
+    return FC_OK;
+}
+
+fc_status fc_cp_truncate(fc_plan p, int m, const double* w, const double* X1, const double* X2,
+                         const double* X3, double eps, int cap, int* rank_out, double* w_out,
+                         double* O1, double* O2, double* O3, void* stream) {
+    if (!p || m < 1 || m > 256 || !X1 || !X2 || !X3 || !(eps > 0 && eps < 1) || cap < 0 ||
+        !rank_out || !w_out || !O1 || !O2 || !O3)
+        return fail(FC_ERR_INVALID_ARG, "fc_cp_truncate: bad arguments");
+    Ctx c{p, (hipStream_t)stream, p->n};
+    fc_status inner = FC_OK;
+    fc_status st = guard([&] {
+        const double* X[3] = {X1, X2, X3};
+        Tucker& T = p->slot[8];
+        // split the budget: half to C2T, half to T2C
+        canon_to_tucker(c, m, w, X, eps / std::sqrt(2.0), T, "trunc");
+        const double n2 = tucker_norm2(c, T);
+        inner = canon_out(p, c, T, 0.5 * eps * eps * n2, false, cap, rank_out, w_out, O1, O2, O3);
+    });
+    return st != FC_OK ? st : inner;
+}
+
+fc_status fc_apply_separable(fc_plan p, int which, int m, const double* w, const double* X1,
+                             const double* X2, const double* X3, double eps, int cap,
+                             int* rank_out, double* w_out, double* O1, double* O2, double* O3,
+                             void* stream) {
+    if (!p || (which != 0 && which != 1) || m < 1 || m > 256 || !X1 || !X2 || !X3 ||
+        !(eps > 0 && eps < 1) || cap < 0 || !rank_out || !w_out || !O1 || !O2 || !O3)
+        return fail(FC_ERR_INVALID_ARG, "fc_apply_separable: bad arguments");
+    Ctx c{p, (hipStream_t)stream, p->n};
+    fc_status inner = FC_OK;
+    fc_status st = guard([&] {
+        const double* X[3] = {X1, X2, X3};
+        Tucker& T = p->slot[8];
+        Tucker& O = p->slot[9];
+        canon_to_tucker(c, m, w, X, 1e-3 * eps, T, "input");
+        had_trunc(c, which == 0 ? p->op : p->pc, T, eps / std::sqrt(2.0), 0.0, O, "apply");
+        const double n2 = tucker_norm2(c, O);
+        inner = canon_out(p, c, O, 0.5 * eps * eps * n2, false, cap, rank_out, w_out, O1, O2, O3);
+    });
+    return st != FC_OK ? st : inner;
+}
+
+fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, const double* Y2,
+                   const double* Y3, int cap_u, int* rank_u, double* w_u, double* U1,
+                   double* U2, double* U3, fc_info* info, void* stream) {
+    if (!p || rank_y < 1 || rank_y > 256 || !Y1 || !Y2 || !Y3 || cap_u < 0 || !rank_u ||
+        !w_u || !U1 || !U2 || !U3)
+        return fail(FC_ERR_INVALID_ARG, "fc_solve: bad arguments");
+    Ctx c{p, (hipStream_t)stream, p->n};
+    const int n = p->n;
+    fc_status result = FC_OK;
+    p->max_seen_rank = 0;
+    fc_status st = guard([&] {
+        // NaN guard on the input
+        static const int zero_flag = 0;
+        h2d(c, p->dflag, &zero_flag, 1);
+        const double* Y[3] = {Y1, Y2, Y3};
+        for (int l = 0; l < 3; ++l) HIPCHK(fc::check_finite((long)n * rank_y, Y[l], p->dflag, c.s));
+        if (w_y) HIPCHK(fc::check_finite(rank_y, w_y, p->dflag, c.s));
+        int flag = 0;
+        d2h(c, &flag, p->dflag, 1);
+        if (flag) throw FcError(FC_ERR_NUMERIC, "non-finite value in the design function");
+        // entry transform Y_hat_l = V_l^T Y_l (into workspace tmp buffers)
+        double* Yh[3] = {p->Yh[0], p->Yh[1], p->Yh[2]};
+        for (int l = 0; l < 3; ++l)
+            gemm(c, true, false, n, rank_y, n, 1.0, p->V[l], n, Y[l], n, 0.0, Yh[l], n);
+        Tucker& B = p->slot[0];
+        const double* Yc[3] = {Yh[0], Yh[1], Yh[2]};
+        canon_to_tucker(c, rank_y, w_y, Yc, 1e-2 * p->eps, B, "B = C2T(Y_hat)");
+        Tucker X;
+        SolveOut so;
+        if (B.empty()) {
+            so.converged = true;
+        } else {
+            so = pcg(c, B, X);
+        }
+        // T2C of the result and exit transform U_l = V_l (Z_l coef)
+        const double xn2 = X.empty() ? 0.0 : tucker_norm2(c, X);
+        double* U[3] = {U1, U2, U3};
+        const int K = X.empty() ? 0 : tucker_to_canon_out(c, X, 0.01 * p->eps * p->eps * xn2, true,
+                                                          cap_u, w_u, U);
+        *rank_u = K;
+        if (info) {
+            info->iterations = so.iterations;
+            info->rank_u = K;
+            for (int l = 0; l < 3; ++l) info->tucker_rank[l] = X.r[l];
+            info->max_tucker_rank = p->max_seen_rank;
+            info->op_rank = p->op.Q;
+            info->precond_rank = p->pc.Q;
+            info->rel_residual = so.rel_res;
+            info->op_max_rel_err = p->op_err;
+            info->precond_max_rel_err = p->pc_err;
+        }
+        if (K > cap_u) result = fail(FC_ERR_RANK_OVERFLOW, "result rank exceeds cap_u");
+        else if (!so.converged) result = fail(FC_ERR_NOT_CONVERGED, "max_iter reached");
+    });
+    return st != FC_OK ? st : result;
+}
+
+fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
+                           const double* const* w_y, const double* const* Y1,
+                           const double* const* Y2, const double* const* Y3, const int* cap_u,
+                           int* rank_u, double* const* w_u, double* const* U1,
+                           double* const* U2, double* const* U3, fc_status* status,
+                           fc_info* info, void* stream) {
+    if (count < 0 || (count > 0 && (!plans || !rank_y || !Y1 || !Y2 || !Y3 || !cap_u || !rank_u ||
+                                    !w_u || !U1 || !U2 || !U3 || !status)))
+        return fail(FC_ERR_INVALID_ARG, "fc_solve_batched: bad arguments");
+    fc_status first = FC_OK;
+    for (int i = 0; i < count; ++i) {
+        status[i] = fc_solve(plans[i], rank_y[i], w_y ? w_y[i] : nullptr, Y1[i], Y2[i], Y3[i],
+                             cap_u[i], &rank_u[i], w_u[i], U1[i], U2[i], U3[i],
+                             info ? &info[i] : nullptr, stream);
+        if (status[i] != FC_OK && first == FC_OK) first = status[i];
+    }
+    return first;
+}
+
+fc_status fc_profile_gemm(int enable) {
+    if (enable) {
+        g_prof.on = true;
+        g_prof.used = 0;
+        g_prof.flops = g_prof.bytes = 0;
+        g_prof.launches = 0;
+    } else {
+        g_prof.on = false;
+    }
+    return FC_OK;
+}
+
+fc_status fc_profile_gemm_read(long* launches, double* total_ms, double* flops, double* bytes) {
+    if (!launches || !total_ms || !flops || !bytes) return fail(FC_ERR_INVALID_ARG, "NULL argument");
+    double ms = 0;
+    for (size_t i = 0; i + 1 < g_prof.used; i += 2) {
+        if (hipEventSynchronize(g_prof.ev[i + 1]) != hipSuccess)
+            return fail(FC_ERR_HIP, "hipEventSynchronize failed");
+        float t = 0;
+        if (hipEventElapsedTime(&t, g_prof.ev[i], g_prof.ev[i + 1]) != hipSuccess)
+            return fail(FC_ERR_HIP, "hipEventElapsedTime failed");
+        ms += t;
+    }
+    *launches = g_prof.launches;
+    *total_ms = ms;
+    *flops = g_prof.flops;
+    *bytes = g_prof.bytes;
+    return FC_OK;
+}
+
+int fc_selftest_mfma(double* host_out) {
+    double* d = nullptr;
+    if (hipMalloc(&d, 256 * sizeof(double)) != hipSuccess) return 1;
+    fc::mfma_probe(d, nullptr);
+    hipMemcpy(host_out, d, 256 * sizeof(double), hipMemcpyDeviceToHost);
+    hipFree(d);
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+"""GPU parity of the building blocks, through the C ABI, against the oracle's
+definitions (Appendix 1 formats; Section 3.3 transforms)."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import solve as osolve
+from oracle import tensor as ot
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    from tests.gpu_util import require_gpu
+    require_gpu()
+
+
+def test_mfma_operand_layout():
+    import ctypes as C
+    from paper_2006_09314_amd._lib import lib
+    out = np.zeros(256)
+    assert lib().fc_selftest_mfma(out.ctypes.data_as(C.POINTER(C.c_double))) == 0
+    i = np.arange(16)[:, None]
+    k = np.arange(4)[None, :]
+    A = 1.0 + i + 16.0 * k
+    B = 1.0 + 0.5 * np.arange(4)[:, None] - 0.25 * np.arange(16)[None, :]
+    np.testing.assert_allclose(out.reshape(16, 16), A @ B, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,m", [(32, 1), (100, 10), (257, 37)])
+def test_mode_transform_matches_oracle_basis(n, m):
+    from tests.gpu_util import dev, host, plan_for
+    prob = wl.workload_quadratic(n=n, seed=4)
+    plan = plan_for(prob)
+    lam, V = plan.spectrum(with_vectors=True)
+    sp = osolve.Spectral(prob)
+    np.testing.assert_allclose(lam[0], sp.lam[0], rtol=1e-10, atol=1e-12 * sp.lam[0].max())
+    rng = np.random.default_rng(n + m)
+    X = rng.standard_normal((n, m))
+    for mode in range(3):
+        Yt = host(plan.mode_transform(mode, True, dev(X)))
+        np.testing.assert_allclose(Yt, V[mode].T @ X, rtol=0, atol=1e-12 * np.abs(X).sum(0).max())
+        Xb = host(plan.mode_transform(mode, False, dev(Yt)))
+        np.testing.assert_allclose(Xb, X, rtol=0, atol=1e-12 * np.abs(X).max() * n)
+        # the library's basis spans the oracle's invariant subspaces
+        P = V[mode][:, :10] @ V[mode][:, :10].T
+        Po = sp.V[mode][:, :10] @ sp.V[mode][:, :10].T
+        assert np.abs(P - Po).max() < 1e-9
+
+
+def test_cp_inner_matches_definition():
+    import torch
+    from tests.gpu_util import dev, plan_for
+    prob = wl.workload_small(n=24)
+    plan = plan_for(prob)
+    rng = np.random.default_rng(7)
+    A = [rng.standard_normal((24, 5)) for _ in range(3)]
+    B = [rng.standard_normal((24, 70)) for _ in range(3)]
+    wa, wb = rng.standard_normal(5), rng.standard_normal(70)
+    got = plan.cp_inner(torch.from_numpy(wa).cuda(), [dev(x) for x in A],
+                        torch.from_numpy(wb).cuda(), [dev(x) for x in B])
+    want = ot.cp_inner(wa, A, wb, B)
+    full = float(np.sum(ot.cp_full(wa, A) * ot.cp_full(wb, B)))
+    assert got == pytest.approx(want, rel=1e-12, abs=1e-12 * abs(full) + 1e-14)
+    assert got == pytest.approx(full, rel=1e-10)
+
+
+def _tucker_as_canonical(rng, n, r, decay=0.5):
+    Z = [np.linalg.qr(rng.standard_normal((n, r[l])))[0] for l in range(3)]
+    core = rng.standard_normal(r) * np.exp(-decay * np.add.outer(np.add.outer(
+        np.arange(r[0]), np.arange(r[1])), np.arange(r[2])))
+    I, J, K = np.meshgrid(range(r[0]), range(r[1]), range(r[2]), indexing="ij")
+    w = core.ravel()
+    F = [Z[0][:, I.ravel()], Z[1][:, J.ravel()], Z[2][:, K.ravel()]]
+    return w, F
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6, 1e-10])
+def test_cp_truncate_error_bound_and_rank(eps):
+    import torch
+    from tests.gpu_util import dev, host, plan_for
+    rng = np.random.default_rng(11)
+    n = 30
+    w, F = _tucker_as_canonical(rng, n, (4, 5, 6), decay=1.5)
+    T = ot.cp_full(w, F)
+    plan = plan_for(wl.workload_small(n=n))
+    wo, O = plan.cp_truncate(torch.from_numpy(w).cuda(), [dev(f) for f in F], eps)
+    To = ot.cp_full(host(wo), [host(o) for o in O])
+    err = np.linalg.norm(To - T) / np.linalg.norm(T)
+    assert err <= eps * (1 + 1e-6) + 1e-14, err
+    # unit-norm output columns
+    for o in O:
+        np.testing.assert_allclose(np.linalg.norm(host(o), axis=0), 1.0, rtol=1e-12)
+    # Tucker ranks of the result never exceed the input's, and the HOSVD of the
+    # oracle gives the same ranks at the C2T share of the budget
+    Tt, ranks, _ = ot.hosvd_truncate(T, eps / np.sqrt(2))
+    sv = ot.mode_spectra(To)
+    for l in range(3):
+        rr = int(np.sum(sv[l] > 1e-13 * sv[l][0]))
+        assert rr <= (4, 5, 6)[l]
+        assert rr == ranks[l]
+
+
+def test_cp_truncate_orthonormal_closed_form():
+    import torch
+    from tests.gpu_util import dev, host, plan_for
+    rng = np.random.default_rng(3)
+    n, r = 40, 6
+    Q = [np.linalg.qr(rng.standard_normal((n, r)))[0] for _ in range(3)]
+    xi = np.array([1.0, -0.5, 0.1, 1e-3, 1e-5, 1e-8])
+    plan = plan_for(wl.workload_small(n=n))
+    eps = 2e-4 / np.linalg.norm(xi)      # keeps 1e-3, drops 1e-5 and 1e-8
+    wo, O = plan.cp_truncate(torch.from_numpy(xi).cuda(), [dev(q) for q in Q], eps)
+    assert len(host(wo)) == 4
+    np.testing.assert_allclose(np.sort(np.abs(host(wo))), np.sort(np.abs(xi[:4])), rtol=1e-10)
+    T4 = ot.cp_full(xi[:4], [q[:, :4] for q in Q])
+    To = ot.cp_full(host(wo), [host(o) for o in O])
+    assert np.linalg.norm(To - T4) <= 1e-12 * np.linalg.norm(T4)
+
+
+def test_cp_truncate_cancellation():
+    import torch
+    from tests.gpu_util import dev, host, plan_for
+    rng = np.random.default_rng(5)
+    n = 28
+    wa, A = _tucker_as_canonical(rng, n, (3, 3, 3), decay=0.3)
+    wb, B = _tucker_as_canonical(rng, n, (4, 4, 4), decay=0.1)
+    wb = wb * 1e3 * np.linalg.norm(wa) / np.linalg.norm(wb)
+    w = np.concatenate([wa, wb, -wb])
+    F = [np.hstack([A[l], B[l], B[l]]) for l in range(3)]
+    plan = plan_for(wl.workload_small(n=n))
+    wo, O = plan.cp_truncate(torch.from_numpy(w).cuda(), [dev(f) for f in F], 1e-6)
+    TA = ot.cp_full(wa, A)
+    To = ot.cp_full(host(wo), [host(o) for o in O])
+    assert np.linalg.norm(To - TA) <= 1e-6 * np.linalg.norm(TA) + 1e-10 * np.linalg.norm(wb)
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_apply_separable_matches_full_grid(which):
+    import torch
+    from tests.gpu_util import dev, host, plan_for
+    prob = wl.workload_quadratic(n=24, seed=9)
+    plan = plan_for(prob)
+    sp = osolve.Spectral(prob)
+    rng = np.random.default_rng(12)
+    F = [np.exp(-np.arange(24)[:, None] / 4.0) * rng.standard_normal((24, 3)) for _ in range(3)]
+    w = np.array([1.0, 0.3, -0.2])
+    eps = 1e-6
+    wo, O = plan.apply_separable(which, torch.from_numpy(w).cuda(), [dev(f) for f in F], eps)
+    T = ot.cp_full(w, F)
+    s = sp.lam[0][:, None, None] + sp.lam[1][None, :, None] + sp.lam[2][None, None, :]
+    D = osolve.f_control(s, prob.alpha, prob.beta, prob.gamma)
+    ws, Fs = plan.separable(which)
+    Dt = ot.cp_full(ws, Fs)
+    if which == 0:
+        # operator: the separable tensor is the exact symbol to its gate accuracy
+        assert np.abs(Dt / D - 1).max() <= 1.01 * prob.eps
+    got = ot.cp_full(host(wo), [host(o) for o in O])
+    want = Dt * T
+    assert np.linalg.norm(got - want) <= 1.01 * eps * np.linalg.norm(want)

@@ -1,0 +1,121 @@
+"""End-to-end GPU parity: rank-truncated PCG (Algorithm 1) through fc_solve
+against the oracle's exact solution, relative L2 error <= 10 eps."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import solve as osolve
+
+pytestmark = pytest.mark.gpu
+
+GATE = 10.0  # error gate in units of eps
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    from tests.gpu_util import require_gpu
+    require_gpu()
+
+
+def _check(prob, slabs=None, **kw):
+    from tests.gpu_util import plan_for, solve
+    print(f"[case] {prob.name} n={prob.n} rank={prob.rank} alpha={prob.alpha}", flush=True)
+    plan = plan_for(prob, **kw)
+    w_u, U, info = solve(plan, prob)
+    rep = osolve.rel_error(prob, w_u, U, slabs=slabs)
+    print(f"[result] {prob.name}: rel_l2={rep['rel_l2']:.3e} res={rep['rel_residual']:.3e} "
+          f"info={info}", flush=True)
+    assert rep["rel_l2"] <= GATE * prob.eps, rep
+    return rep, info, w_u, U
+
+
+def test_small_workload():
+    rep, info, w, U = _check(wl.workload_small())
+    assert info["iterations"] <= 20
+    for u in U:
+        np.testing.assert_allclose(np.linalg.norm(u, axis=0), 1.0, rtol=1e-10)
+
+
+@pytest.mark.parametrize("alpha", [0.25, 0.5, 0.75])
+def test_quadratic_coefficients(alpha):
+    _check(wl.workload_quadratic(n=64, alpha=alpha))
+
+
+def test_sine_coefficients_n128():
+    _check(wl.workload_sine(n=128, seed=3))
+
+
+def test_paper_shaped_alpha1():
+    _check(wl.workload_paper_shaped(40, 1.0))
+
+
+def test_alpha0_closed_form():
+    from tests.gpu_util import plan_for, solve
+    from oracle import tensor as ot
+    prob = wl.workload_quadratic(n=24, alpha=0.0, rank=2)
+    plan = plan_for(prob)
+    w_u, U, info = solve(plan, prob)
+    y = ot.cp_full(prob.w, prob.Y)
+    u = ot.cp_full(w_u, U)
+    np.testing.assert_allclose(u, y / (prob.beta + prob.gamma / prob.beta), rtol=0,
+                               atol=1e-9 * np.abs(y).max() / (prob.beta + prob.gamma / prob.beta))
+
+
+def test_eigenvector_design():
+    from tests.gpu_util import plan_for, solve
+    base = wl.workload_sine(n=48, seed=3, rank=1)
+    sp = osolve.Spectral(base)
+    p, q, r = 2, 9, 30
+    prob = wl.eigvec_rhs_problem(base, [sp.V[0][:, p], sp.V[1][:, q], sp.V[2][:, r]])
+    plan = plan_for(prob)
+    w_u, U, info = solve(plan, prob)
+    rep = osolve.rel_error(prob, w_u, U)
+    assert rep["rel_l2"] <= GATE * prob.eps
+    assert len(w_u) == 1
+
+
+def test_rank_overflow_reports_required_rank():
+    import ctypes as C
+    import torch
+    from paper_2006_09314_amd._lib import lib
+    from tests.gpu_util import dev, plan_for
+    prob = wl.workload_quadratic(n=32)
+    plan = plan_for(prob)
+    Y = [dev(y) for y in prob.Y]
+    w = torch.from_numpy(prob.w).cuda()
+    out_w = torch.empty(1, dtype=torch.float64, device="cuda")
+    out_U = [torch.empty((1, 32), dtype=torch.float64, device="cuda").t() for _ in range(3)]
+    rank = C.c_int()
+    st = lib().fc_solve(plan.handle, prob.rank, w.data_ptr(), Y[0].data_ptr(), Y[1].data_ptr(),
+                        Y[2].data_ptr(), 1, C.byref(rank), out_w.data_ptr(), out_U[0].data_ptr(),
+                        out_U[1].data_ptr(), out_U[2].data_ptr(), None, None)
+    assert st == 4 and rank.value > 1
+
+
+def test_nan_input_is_rejected():
+    import ctypes as C
+    import torch
+    from paper_2006_09314_amd._lib import lib
+    from tests.gpu_util import dev, plan_for
+    prob = wl.workload_small(n=16)
+    plan = plan_for(prob)
+    Y = [y.copy() for y in prob.Y]
+    Y[1][3, 0] = np.nan
+    Yd = [dev(y) for y in Y]
+    out_w = torch.empty(64, dtype=torch.float64, device="cuda")
+    out_U = [torch.empty((64, 16), dtype=torch.float64, device="cuda").t() for _ in range(3)]
+    rank = C.c_int()
+    st = lib().fc_solve(plan.handle, 1, None, Yd[0].data_ptr(), Yd[1].data_ptr(),
+                        Yd[2].data_ptr(), 64, C.byref(rank), out_w.data_ptr(), out_U[0].data_ptr(),
+                        out_U[1].data_ptr(), out_U[2].data_ptr(), None, None)
+    assert st == 5
+
+
+def test_max_iter_reports_not_converged():
+    from paper_2006_09314_amd._lib import FcError
+    from tests.gpu_util import plan_for, solve
+    prob = wl.workload_sine(n=48, seed=3)
+    plan = plan_for(prob, max_iter=1)
+    with pytest.raises(FcError) as ei:
+        solve(plan, prob)
+    assert ei.value.status == 3

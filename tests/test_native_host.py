@@ -1,0 +1,180 @@
+"""CPU-side checks of the native library: it loads, exports every symbol the
+header declares, validates arguments before touching a device, and its
+host-side setup numerics (1D eigenpairs, separable operator and
+preconditioner) agree with the oracle."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import fd, solve as osolve
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fracctl.h")
+
+lib_mod = pytest.importorskip("paper_2006_09314_amd._lib")
+
+
+def _lib():
+    try:
+        return lib_mod.lib()
+    except lib_mod.LibraryMissing:
+        pytest.skip("libfracctl.so not built")
+
+
+def test_exports_every_declared_symbol():
+    h = _lib()
+    text = open(HEADER).read()
+    names = set(re.findall(r"\b(fc_[a-z_0-9]+)\s*\(", text))
+    names -= {"fc_plan", "fc_status", "fc_info"}
+    assert len(names) >= 15
+    for name in sorted(names):
+        assert hasattr(h, name), name
+    # and the binding declares a prototype for each of them
+    assert names <= set(lib_mod.PROTOTYPES), names - set(lib_mod.PROTOTYPES)
+
+
+def _params(prob, **kw):
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in prob.a]
+    p = lib_mod.SetupParams()
+    p.n = prob.n
+    for l in range(3):
+        p.a[l] = a[l].ctypes.data_as(C.POINTER(C.c_double))
+    p.alpha, p.beta, p.gamma, p.eps = prob.alpha, prob.beta, prob.gamma, prob.eps
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p, a
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n", 1), ("alpha", -0.1), ("alpha", 1.5), ("beta", 0.0), ("gamma", -1.0),
+    ("eps", 0.0), ("eps", 1.0), ("max_rank", 200), ("precision", 3),
+])
+def test_setup_rejects_invalid_arguments(field, value):
+    h = _lib()
+    prob = wl.workload_small(n=16)
+    p, keep = _params(prob)
+    setattr(p, field, value)
+    out = C.c_void_p()
+    st = h.fc_setup_ex(C.byref(p), None, C.byref(out))
+    assert st == 1, (field, value, st)
+    assert not out.value
+    assert h.fc_last_error()
+
+
+def test_setup_rejects_bad_coefficients():
+    h = _lib()
+    prob = wl.workload_small(n=16)
+    prob.a[1] = prob.a[1].copy()
+    prob.a[1][3] = -1.0
+    p, keep = _params(prob)
+    out = C.c_void_p()
+    assert h.fc_setup_ex(C.byref(p), None, C.byref(out)) == 1
+    prob.a[1][3] = np.nan
+    p, keep = _params(prob)
+    assert h.fc_setup_ex(C.byref(p), None, C.byref(out)) == 1
+
+
+def test_status_strings():
+    h = _lib()
+    for s in range(8):
+        assert h.fc_status_string(s)
+
+
+@pytest.mark.parametrize("n,c", [(7, 1.0), (64, 0.6), (255, 1.9)])
+def test_native_eigen_closed_form(n, c):
+    from paper_2006_09314_amd import api
+    lam, V = api.host_fd_eigen(np.full(n + 1, c))
+    lam_cf, V_cf = fd.laplacian_closed_form(n, c)
+    np.testing.assert_allclose(lam, lam_cf, rtol=1e-12, atol=64 * 2.2e-16 * lam_cf.max())
+    np.testing.assert_allclose(np.abs(V.T @ V_cf), np.eye(n), atol=1e-9)
+
+
+@pytest.mark.parametrize("maker", [lambda: wl.workload_sine(n=300, seed=3),
+                                   lambda: wl.workload_quadratic(n=200)])
+def test_native_eigen_matches_oracle(maker):
+    from paper_2006_09314_amd import api
+    prob = maker()
+    for l in range(3):
+        lam, V = api.host_fd_eigen(prob.a[l])
+        lo, Vo = fd.eig1d(prob.a[l])
+        n = prob.n
+        np.testing.assert_allclose(lam, lo, rtol=1e-10, atol=64 * 2.2e-16 * lo.max())
+        assert np.abs(V.T @ V - np.eye(n)).max() < 1e-12
+        A = fd.stiffness_dense(prob.a[l])
+        assert np.linalg.norm(A @ V - V * lam[None, :]) <= 1e-12 * np.linalg.norm(A)
+        # same invariant subspaces: projector onto the lowest 40 modes agrees
+        P1 = V[:, :40] @ V[:, :40].T
+        P2 = Vo[:, :40] @ Vo[:, :40].T
+        assert np.abs(P1 - P2).max() < 1e-9
+
+
+def _host_separable(prob, which, **kw):
+    h = _lib()
+    p, keep = _params(prob, **kw)
+    cap = 512
+    n = prob.n
+    w = np.zeros(cap)
+    F = np.zeros(3 * n * cap)
+    rank = C.c_int()
+    err = C.c_double()
+    st = h.fc_host_separable(C.byref(p), which, cap, C.byref(rank),
+                             w.ctypes.data_as(C.POINTER(C.c_double)),
+                             F.ctypes.data_as(C.POINTER(C.c_double)), C.byref(err))
+    assert st == 0, h.fc_last_error()
+    Q = rank.value
+    return w[:Q], [F[l * n * cap:(l + 1) * n * cap].reshape(n, cap, order="F")[:, :Q]
+                   for l in range(3)], err.value
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: wl.workload_small(),
+    lambda: wl.workload_quadratic(n=128, alpha=0.25),
+    lambda: wl.workload_quadratic(n=128, alpha=0.75),
+    lambda: wl.workload_sine(n=160, seed=3),
+    lambda: wl.workload_paper_shaped(48, 1.0),
+    lambda: wl.workload_paper_shaped(48, 0.1),
+])
+def test_operator_matches_exact_symbol(maker):
+    """Separable operator vs the oracle's f(lam1_i + lam2_j + lam3_k), entrywise
+    relative, on sampled entries (including the low corner where the solution
+    lives) -- within the accuracy the setup gate reports, which is <= eps."""
+    prob = maker()
+    w, F, gate = _host_separable(prob, 0)
+    assert np.all(w > 0) and all(np.all(f >= 0) for f in F)
+    assert gate <= prob.eps
+    sp = osolve.Spectral(prob)
+    rng = np.random.default_rng(1)
+    idx = rng.integers(0, prob.n, size=(3, 40000))
+    idx[:, :4000] = rng.integers(0, min(prob.n, 12), size=(3, 4000))
+    s = sp.lam[0][idx[0]] + sp.lam[1][idx[1]] + sp.lam[2][idx[2]]
+    D = osolve.f_control(s, prob.alpha, prob.beta, prob.gamma)
+    Dt = np.prod([F[l][idx[l]] for l in range(3)], axis=0) @ w
+    err = np.abs(Dt / D - 1).max()
+    assert err <= max(gate, 1e-14) * 1.05 + 1e-13, (err, gate)
+
+
+def test_alpha0_operator_is_exact_constant():
+    prob = wl.workload_small(n=20)
+    prob.alpha = 0.0
+    w, F, gate = _host_separable(prob, 0)
+    assert len(w) == 1 and gate == 0.0
+    assert w[0] == pytest.approx(prob.beta + prob.gamma / prob.beta)
+
+
+def test_preconditioner_positive_and_spectrally_close():
+    prob = wl.workload_sine(n=128, seed=3)
+    w, F, gate = _host_separable(prob, 1)
+    assert len(w) == 6 and np.all(w > 0)
+    assert gate < 0.5
+    sp = osolve.Spectral(prob)
+    rng = np.random.default_rng(2)
+    idx = rng.integers(0, prob.n, size=(3, 20000))
+    s = sp.lam[0][idx[0]] + sp.lam[1][idx[1]] + sp.lam[2][idx[2]]
+    D = osolve.f_control(s, prob.alpha, prob.beta, prob.gamma)
+    Dp = np.prod([F[l][idx[l]] for l in range(3)], axis=0) @ w
+    ratio = Dp * D
+    assert ratio.min() > 1 - gate - 1e-9 and ratio.max() < 1 + gate + 1e-9
