@@ -16,6 +16,10 @@ struct GemmArgs {
     const double* B = nullptr; long ldb = 0, strideB = 0, strideBin = 0;
     double* C = nullptr; long ldc = 0, strideC = 0, strideCin = 0;
     const double* d = nullptr; long strideD = 0;
+    // split-K workspace: when few output tiles face a long reduction, K is
+    // split over extra workgroups whose partial products land here and are
+    // summed in a fixed order by a second kernel (deterministic).
+    double* part = nullptr; long part_cap = 0;
 };
 
 hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
@@ -27,6 +31,18 @@ hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
 // scratch: batch * (k+1)^2 doubles of device memory.
 hipError_t sym_eig(int k, int batch, const double* A, long lda, long strideA, double* evals,
                    double* V, long ldv, long strideV, double* scratch, hipStream_t s);
+
+// Up to four independent eigenproblems of different sizes in one launch.
+struct EigJob {
+    const double* A = nullptr; long lda = 0; int k = 0;
+    double* evals = nullptr; double* V = nullptr; long ldv = 0; double* scratch = nullptr;
+};
+struct EigJobs {
+    EigJob job[4];
+    int count = 0;
+    int kpmax = 0;
+};
+hipError_t sym_eig_multi(const EigJobs& jobs, hipStream_t s);
 
 // E[i + n*(j + r*c)] = Z[i + ldz*j] * X[i + ldx*c]   (row-wise Kronecker product)
 hipError_t rowkron(int n, int r, int p, const double* Z, long ldz, const double* X, long ldx,
@@ -74,6 +90,16 @@ hipError_t cp_inner_reduce(int ra, int rb, const double* G0, const double* G1, c
 // kept orthonormal columns are compacted to the front and their number is
 // written to *count (device int).
 hipError_t mgs_qr(int n, int m, double* Y, double drop, int* count, hipStream_t s);
+
+// Panel step of a blocked Gram-Schmidt: orthonormalise the n x b panel Y
+// (ld n, b <= 32) in place with two-pass MGS; a column whose norm after
+// projection is <= drop * norm0[j] is set to zero and flagged 0 in keep[j].
+hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, int* keep,
+                     hipStream_t s);
+// Move the kept columns (keep[j] != 0) of the n x m matrix Y to the front, in
+// order, and write their number to *count.  tmp: n x m scratch.
+hipError_t compact_cols(int n, int m, double* Y, const int* keep, double* tmp, int* count,
+                        hipStream_t s);
 
 // dst (cols x rows) = src^T, src rows x cols (ld lds), dst ld ldd
 hipError_t transpose(int rows, int cols, const double* src, long lds, double* dst, long ldd,

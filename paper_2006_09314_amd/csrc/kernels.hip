@@ -18,7 +18,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register v of
 // lane l holds C[l / 16 + 4 v][l % 16] (checked by the layout self-test).
 template <bool TA, bool TB, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g) {
+__global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g, int kchunk) {
     constexpr int BM = 32 * WM, BN = 32 * WN, BK = 16, NT = 64 * WM * WN;
     __shared__ double As[BK][BM + 1];
     __shared__ double Bs[BK][BN + 1];
@@ -30,6 +30,17 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g) {
     const double* __restrict__ B = g.B + bo * g.strideB + bi * g.strideBin;
     const double* __restrict__ d = g.d ? g.d + bo * g.strideD : nullptr;
     double* __restrict__ C = g.C + bo * g.strideC + bi * g.strideCin;
+    long ldc = g.ldc;
+    double alpha = g.alpha, beta = g.beta;
+    const int kz = blockIdx.z;
+    const int kbeg = kz * kchunk, kend = min(g.K, kbeg + kchunk);
+    if (gridDim.z > 1) {
+        // partial product of this K slice -> part[kz][b] (M x N, ld M)
+        C = g.part + ((long)kz * g.batch + b) * (long)g.M * g.N;
+        ldc = g.M;
+        alpha = 1.0;
+        beta = 0.0;
+    }
     const int row0 = tm * BM, col0 = tn * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
@@ -37,13 +48,13 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
         for (int e = tid; e < BM * BK; e += NT) {
             int i, k;
             if (!TA) { i = e % BM; k = e / BM; } else { k = e % BK; i = e / BK; }
             const int gi = row0 + i, gk = k0 + k;
             double v = 0.0;
-            if (gi < g.M && gk < g.K) {
+            if (gi < g.M && gk < kend) {
                 v = TA ? A[gk + (long)gi * g.lda] : A[gi + (long)gk * g.lda];
                 if (d) v *= d[gk];
             }
@@ -54,7 +65,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g) {
             if (!TB) { k = e % BK; j = e / BK; } else { j = e % BN; k = e / BN; }
             const int gj = col0 + j, gk = k0 + k;
             double v = 0.0;
-            if (gj < g.N && gk < g.K) v = TB ? B[gj + (long)gk * g.ldb] : B[gk + (long)gj * g.ldb];
+            if (gj < g.N && gk < kend) v = TB ? B[gj + (long)gk * g.ldb] : B[gk + (long)gj * g.ldb];
             Bs[k][j] = v;
         }
         __syncthreads();
@@ -78,22 +89,56 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g) {
                 const int i = row0 + wm * 32 + mi * 16 + (lane >> 4) + 4 * v;
                 const int j = col0 + wn * 32 + ni * 16 + (lane & 15);
                 if (i < g.M && j < g.N) {
-                    double r = g.alpha * acc[mi][ni][v];
-                    if (g.beta != 0.0) r += g.beta * C[i + (long)j * g.ldc];
-                    C[i + (long)j * g.ldc] = r;
+                    double r = alpha * acc[mi][ni][v];
+                    if (beta != 0.0) r += beta * C[i + (long)j * ldc];
+                    C[i + (long)j * ldc] = r;
                 }
             }
+}
+
+// sum of the split-K partial products: C = alpha sum_z part[z] + beta C
+__global__ void splitk_reduce_kernel(GemmArgs g, int ksplit) {
+    const long mn = (long)g.M * g.N;
+    const long total = mn * g.batch;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const long b = e / mn, ij = e % mn;
+        const int i = int(ij % g.M), j = int(ij / g.M);
+        double s = 0.0;
+        for (int z = 0; z < ksplit; ++z) s += g.part[((long)z * g.batch + b) * mn + ij];
+        const long bo = b / g.inner, bi = b % g.inner;
+        double* C = g.C + bo * g.strideC + bi * g.strideCin;
+        double r = g.alpha * s;
+        if (g.beta != 0.0) r += g.beta * C[i + (long)j * g.ldc];
+        C[i + (long)j * g.ldc] = r;
+    }
 }
 
 template <bool TA, bool TB>
 static hipError_t gemm_dispatch(const GemmArgs& g, hipStream_t s) {
     const long work = (long)g.M * g.N * g.batch;
-    if (g.M >= 64 && g.N >= 64 && work >= (1L << 20)) {
-        const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
-        hipLaunchKernelGGL((gemm_kernel<TA, TB, 2, 2>), dim3(tiles, g.batch), dim3(256), 0, s, g);
-    } else {
-        const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
-        hipLaunchKernelGGL((gemm_kernel<TA, TB, 1, 1>), dim3(tiles, g.batch), dim3(64), 0, s, g);
+    const bool big = g.M >= 64 && g.N >= 64 && work >= (1L << 20);
+    const int BMN = big ? 64 : 32;
+    const long tiles = (long)((g.M + BMN - 1) / BMN) * ((g.N + BMN - 1) / BMN);
+    const long wgs = tiles * g.batch;
+    int ksplit = 1;
+    if (g.part && wgs < 256 && g.K >= 256) {
+        ksplit = (int)std::min<long>(std::max<long>(1, 512 / wgs), g.K / 128);
+        while (ksplit > 1 && (long)ksplit * g.batch * g.M * g.N > g.part_cap) --ksplit;
+    }
+    int kchunk = (g.K + ksplit - 1) / ksplit;
+    kchunk = (kchunk + 15) / 16 * 16;
+    ksplit = (g.K + kchunk - 1) / kchunk;
+    if (big)
+        hipLaunchKernelGGL((gemm_kernel<TA, TB, 2, 2>), dim3(tiles, g.batch, ksplit), dim3(256), 0, s,
+                           g, kchunk);
+    else
+        hipLaunchKernelGGL((gemm_kernel<TA, TB, 1, 1>), dim3(tiles, g.batch, ksplit), dim3(64), 0, s,
+                           g, kchunk);
+    if (ksplit > 1) {
+        const long total = (long)g.M * g.N * g.batch;
+        const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, s, g, ksplit);
     }
     return hipGetLastError();
 }
@@ -125,21 +170,14 @@ hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s) {
 // rotations of a round touch disjoint row/column pairs and run in parallel.
 constexpr int JAC_THREADS = 512;
 
-__global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double* __restrict__ Ain,
-                                                             long lda, long strideA, double* evals,
-                                                             double* Vout, long ldv, long strideV,
-                                                             double* scratch) {
-    extern __shared__ double sm[];
+__device__ void jacobi_body(int k, const double* __restrict__ A, long lda, double* evals,
+                            double* Vo_base, long ldv, double* v, double* a) {
     const int kp = k + (k & 1);
     const int half = kp / 2;
-    double* a = sm;   // kp x kp column-major
     __shared__ double cs[64], sn[64];
     __shared__ int pp[64], qq[64];
     __shared__ int nrot;
     const int tid = threadIdx.x;
-    const int b = blockIdx.x;
-    const double* A = Ain + (long)b * strideA;
-    double* v = scratch + (long)b * kp * kp;
     for (int e = tid; e < kp * kp; e += blockDim.x) {
         const int i = e % kp, j = e / kp;
         a[e] = (i < k && j < k) ? 0.5 * (A[i + (long)j * lda] + A[j + (long)i * lda]) : 0.0;
@@ -167,7 +205,6 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double
                 cs[tid] = c; sn[tid] = s; pp[tid] = p; qq[tid] = q;
             }
             __syncthreads();
-            // rows: A <- J^T A
             for (int e = tid; e < half * kp; e += blockDim.x) {
                 const int i = e / kp, j = e % kp;
                 const double c = cs[i], s = sn[i];
@@ -178,7 +215,6 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double
                 a[q + j * kp] = s * x + c * y;
             }
             __syncthreads();
-            // columns: A <- A J, V <- V J
             for (int e = tid; e < half * kp; e += blockDim.x) {
                 const int i = e / kp, j = e % kp;
                 const double c = cs[i], s = sn[i];
@@ -196,7 +232,6 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double
         if (nrot == 0) break;
         __syncthreads();
     }
-    // sort descending by a stable rank count
     for (int i = tid; i < k; i += blockDim.x) {
         const double ei = a[i + i * kp];
         int rank = 0;
@@ -204,10 +239,54 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double
             const double ej = a[j + j * kp];
             if (ej > ei || (ej == ei && j < i)) ++rank;
         }
-        evals[(long)b * k + rank] = ei;
-        double* Vo = Vout + (long)b * strideV + (long)rank * ldv;
+        evals[rank] = ei;
+        double* Vo = Vo_base + (long)rank * ldv;
         for (int j = 0; j < k; ++j) Vo[j] = v[j + i * kp];
     }
+}
+
+__global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double* __restrict__ Ain,
+                                                             long lda, long strideA, double* evals,
+                                                             double* Vout, long ldv, long strideV,
+                                                             double* scratch) {
+    extern __shared__ double sm[];
+    const int kp = k + (k & 1);
+    const int b = blockIdx.x;
+    jacobi_body(k, Ain + (long)b * strideA, lda, evals + (long)b * k, Vout + (long)b * strideV, ldv,
+                scratch + (long)b * kp * kp, sm);
+}
+
+__global__ __launch_bounds__(JAC_THREADS) void jacobi_multi_kernel(EigJobs jobs, int vlds) {
+    extern __shared__ double sm[];
+    const EigJob& J = jobs.job[blockIdx.x];
+    const int kp = J.k + (J.k & 1);
+    // rotations accumulate in LDS when both matrices fit, else in global scratch
+    double* v = vlds ? sm + jobs.kpmax * jobs.kpmax : J.scratch;
+    jacobi_body(J.k, J.A, J.lda, J.evals, J.V, J.ldv, v, sm);
+    (void)kp;
+}
+
+hipError_t sym_eig_multi(const EigJobs& jobs, hipStream_t s) {
+    int kmax = 0;
+    for (int i = 0; i < jobs.count; ++i) {
+        if (jobs.job[i].k > 128) return hipErrorInvalidValue;
+        kmax = std::max(kmax, jobs.job[i].k);
+    }
+    if (jobs.count <= 0 || kmax <= 0) return hipSuccess;
+    const int kp = kmax + (kmax & 1);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)jacobi_multi_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    EigJobs j2 = jobs;
+    j2.kpmax = kp;
+    const int vlds = (2L * kp * kp * sizeof(double) <= 150L * 1024) ? 1 : 0;
+    hipLaunchKernelGGL(jacobi_multi_kernel, dim3(jobs.count), dim3(JAC_THREADS),
+                       sizeof(double) * kp * kp * (vlds ? 2 : 1), s, j2, vlds);
+    return hipGetLastError();
 }
 
 hipError_t sym_eig(int k, int batch, const double* A, long lda, long strideA, double* evals,
@@ -589,6 +668,87 @@ hipError_t transpose(int rows, int cols, const double* src, long lds, double* ds
     const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(transpose_kernel, dim3(blocks), dim3(256), 0, s, rows, cols, src, lds, dst,
                        ldd);
+    return hipGetLastError();
+}
+
+// Two-pass classical Gram-Schmidt inside a panel: for column j, all dot
+// products against the kept panel columns are formed in one sweep (one
+// wavefront per column, 16 wavefronts), then subtracted in one sweep.
+__global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, int b, double* Y,
+                                                         const double* norm0, double drop,
+                                                         int* keep) {
+    __shared__ double red[32];
+    __shared__ double dots[32];
+    __shared__ int kp[32];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int j = 0; j < b; ++j) {
+        double* y = Y + (long)j * n;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (j > 0) {
+                for (int c = w; c < j; c += 16) {
+                    double acc = 0.0;
+                    if (kp[c]) {
+                        const double* q = Y + (long)c * n;
+                        for (int i = lane; i < n; i += 64) acc += q[i] * y[i];
+                    }
+                    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+                    if (lane == 0) dots[c] = acc;
+                }
+                __syncthreads();
+                for (int i = tid; i < n; i += 1024) {
+                    double v = y[i];
+                    for (int c = 0; c < j; ++c) v -= dots[c] * Y[(long)c * n + i];
+                    y[i] = v;
+                }
+                __syncthreads();
+            }
+        }
+        double s = 0.0;
+        for (int i = tid; i < n; i += 1024) s += y[i] * y[i];
+        const double nrm = sqrt(block_sum_1024(s, red));
+        const bool ok = nrm > drop * norm0[j] && nrm > 1e-300;
+        const double f = ok ? 1.0 / nrm : 0.0;
+        for (int i = tid; i < n; i += 1024) y[i] *= f;
+        if (tid == 0) { kp[j] = ok ? 1 : 0; keep[j] = ok ? 1 : 0; }
+        __syncthreads();
+    }
+}
+
+hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, int* keep,
+                     hipStream_t s) {
+    if (b <= 0) return hipSuccess;
+    hipLaunchKernelGGL(panel_mgs_kernel, dim3(1), dim3(1024), 0, s, n, b, Y, norm0, drop, keep);
+    return hipGetLastError();
+}
+
+__global__ void compact_pos_kernel(int m, const int* keep, int* pos, int* count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int c = 0;
+        for (int j = 0; j < m; ++j) { pos[j] = keep[j] ? c : -1; c += keep[j] ? 1 : 0; }
+        *count = c;
+    }
+}
+
+__global__ void compact_copy_kernel(int n, int m, const double* __restrict__ src,
+                                    const int* __restrict__ pos, double* __restrict__ dst) {
+    const long total = (long)n * m;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % n), j = int(e / n);
+        const int p = pos[j];
+        if (p >= 0) dst[i + (long)p * n] = src[e];
+    }
+}
+
+hipError_t compact_cols(int n, int m, double* Y, const int* keep, double* tmp, int* count,
+                        hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    int* pos = (int*)(tmp + (long)n * m);
+    hipLaunchKernelGGL(compact_pos_kernel, dim3(1), dim3(64), 0, s, m, keep, pos, count);
+    const long total = (long)n * m;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(copy2d_kernel, dim3(blocks), dim3(256), 0, s, n, m, Y, (long)n, tmp, (long)n);
+    hipLaunchKernelGGL(compact_copy_kernel, dim3(blocks), dim3(256), 0, s, n, m, tmp, pos, Y);
     return hipGetLastError();
 }
 

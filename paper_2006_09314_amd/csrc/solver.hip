@@ -108,6 +108,12 @@ struct fc_plan_s {
     double *cw = nullptr, *cf[3] = {}, *Yh[3] = {};
     int* icount = nullptr;
     double* jac = nullptr;
+    double *qrN = nullptr, *qrC = nullptr, *qrTmp = nullptr;
+    double *Xs3[3] = {}, *HX3[3] = {}, *Bp3 = nullptr, *Ev3 = nullptr, *Evec3 = nullptr;
+    int* qrKeep = nullptr;
+    double* splitws = nullptr;
+    long splitws_cap = 0;
+    double *SG[3] = {}, *SM[3] = {};
     long qchunk = 1;
     long cap_canon = 0;
     int* dflag = nullptr;
@@ -148,6 +154,7 @@ void gemm(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, con
     g.B = B; g.ldb = ldb; g.strideB = sB; g.strideBin = sBi;
     g.C = C; g.ldc = ldc; g.strideC = sC; g.strideCin = sCi;
     g.d = d; g.strideD = sD;
+    g.part = c.p->splitws; g.part_cap = c.p->splitws_cap;
     if (g_prof.on && M > 0 && N > 0 && K > 0 && batch > 0) {
         if (g_prof.used + 2 > g_prof.ev.size()) {
             for (int i = 0; i < 256; ++i) {
@@ -214,6 +221,37 @@ double host_dot(const Ctx& c, long n, const double* x, const double* y) {
     return v;
 }
 
+// ---- rank-revealing orthonormalisation of n x m columns (in place) --------
+// Blocked classical Gram-Schmidt with reorthogonalisation (BCGS2): panels of
+// 16 columns are projected against all earlier columns by two GEMM passes and
+// then orthonormalised by a two-pass MGS panel kernel.  Columns whose norm
+// after projection drops below `drop` times their input norm are removed.
+// Returns the number of kept columns (compacted to the front).
+int orthonormalize(const Ctx& c, int m, double* Y, double drop, int slot = 0) {
+    fc_plan_s* p = c.p;
+    const int n = c.n;
+    if (m <= 0) return 0;
+    double* norms = p->qrN;
+    int* keep = p->qrKeep;
+    HIPCHK(fc::col_norms(n, m, Y, n, norms, c.s));
+    const int b = 16;
+    for (int j0 = 0; j0 < m; j0 += b) {
+        const int bw = std::min(b, m - j0);
+        double* P = Y + (long)j0 * n;
+        if (j0 > 0) {
+            for (int pass = 0; pass < 2; ++pass) {
+                gemm(c, true, false, j0, bw, n, 1.0, Y, n, P, n, 0.0, p->qrC, j0);
+                gemm(c, false, false, n, bw, j0, -1.0, Y, n, p->qrC, j0, 1.0, P, n);
+            }
+        }
+        HIPCHK(fc::panel_mgs(n, bw, P, norms + j0, drop, keep + j0, c.s));
+    }
+    HIPCHK(fc::compact_cols(n, m, Y, keep, p->qrTmp, p->icount + 4 + slot, c.s));
+    int cnt = 0;
+    d2h(c, &cnt, p->icount + 4 + slot, 1);
+    return cnt;
+}
+
 // ---- HOSVD truncation of a dense core in given bases ----------------------
 // Input: core C (k0 x k1 x k2) expressed in orthonormal bases B_l (n x k_l).
 // Output: Tucker `out` with ranks chosen so that the dropped energy is at
@@ -238,9 +276,17 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
         gemm(c, false, true, pd[0], pd[0], pd[1] * pd[2], 1.0, src, pd[0], src, pd[0], 0.0,
              p->Cg + (long)l * KM * KM, pd[0]);
     }
-    for (int l = 0; l < 3; ++l)
-        HIPCHK(fc::sym_eig(k[l], 1, p->Cg + (long)l * KM * KM, k[l], 0, p->Cev + l * KM,
-                           p->Cvec + (long)l * KM * KM, k[l], 0, p->jac, c.s));
+    {
+        fc::EigJobs jobs;
+        jobs.count = 3;
+        for (int l = 0; l < 3; ++l) {
+            fc::EigJob& J = jobs.job[l];
+            J.A = p->Cg + (long)l * KM * KM; J.lda = k[l]; J.k = k[l];
+            J.evals = p->Cev + l * KM; J.V = p->Cvec + (long)l * KM * KM; J.ldv = k[l];
+            J.scratch = p->jac + (long)l * KM * KM;
+        }
+        HIPCHK(fc::sym_eig_multi(jobs, c.s));
+    }
     std::vector<double> ev(3 * KM);
     d2h(c, ev.data(), p->Cev, 3 * KM);
     double tot = 0;
@@ -284,9 +330,50 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
     p->max_seen_rank = std::max({p->max_seen_rank, r[0], r[1], r[2]});
 }
 
+// Rayleigh-Ritz on the three orthonormal subspaces X_l (n x kk_l, in Xs3):
+// eigenpairs of X_l^T H_l X_l in one batched launch, then W_l = X_l V_l[:, :pk_l]
+// with pk_l = (smallest rank whose Ritz tail is <= tail_budget) + margin.
+template <class Apply>
+void ritz(const Ctx& c, const int kk[3], double tail_budget, int margin, Apply& apply, int pk[3]) {
+    fc_plan_s* p = c.p;
+    const int n = c.n;
+    fc::EigJobs jobs;
+    jobs.count = 3;
+    for (int l = 0; l < 3; ++l) {
+        apply(l, p->Xs3[l], kk[l], p->HX3[l]);
+        double* Bl = p->Bp3 + (long)l * KM * KM;
+        gemm(c, true, false, kk[l], kk[l], n, 1.0, p->Xs3[l], n, p->HX3[l], n, 0.0, Bl, kk[l]);
+        fc::EigJob& J = jobs.job[l];
+        J.A = Bl; J.lda = kk[l]; J.k = kk[l];
+        J.evals = p->Ev3 + l * KM; J.V = p->Evec3 + (long)l * KM * KM; J.ldv = kk[l];
+        J.scratch = p->jac + (long)l * KM * KM;
+    }
+    HIPCHK(fc::sym_eig_multi(jobs, c.s));
+    std::vector<double> th(3 * KM);
+    d2h(c, th.data(), p->Ev3, 3 * KM);
+    for (int l = 0; l < 3; ++l) {
+        double tail = 0;
+        int rr = kk[l];
+        for (int i = kk[l] - 1; i >= 0; --i) {
+            tail += std::max(th[l * KM + i], 0.0);
+            if (tail <= tail_budget) rr = i; else break;
+        }
+        const int use = std::min(kk[l], std::max(rr + margin, 1));
+        gemm(c, false, false, n, use, kk[l], 1.0, p->Xs3[l], n, p->Evec3 + (long)l * KM * KM, kk[l],
+             0.0, p->W[l], n);
+        pk[l] = use;
+    }
+}
+
 // ---- exact truncation of a short sum of Tucker tensors ---------------------
-// T = sum_t coef_t T_t.  Per mode, an orthonormal basis of the union of the
-// bases (two-pass Gram-Schmidt), the dense core in that basis, then HOSVD.
+// T = sum_t c_t T_t (t < 4).  With the concatenated bases B_l = [Z_l^0 ...]
+// (not orthonormal) and the block-diagonal core, the mode-l unfolding Gram
+// is H_l = B_l M_l B_l^T, M_l[t,t'] = c_t c_t' core_t,(l) (G_b^{tt'} (x) G_a^{tt'})
+// core_t',(l)^T with the cross Grams G^{tt'} = Z^t^T Z^t'.  Its dominant
+// subspace comes from subspace iteration in R^n; T is projected onto it
+// exactly, and the HOSVD of the projected core finishes the truncation.
+// ||T||^2 = trace(M_l G_l) is exact, so the energy the subspace misses is
+// known and charged to the tolerance.
 void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>& terms_in,
                double tol_rel, double floor_abs, Tucker& out, const char* what) {
     fc_plan_s* p = c.p;
@@ -295,52 +382,102 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
     for (auto& t : terms_in)
         if (t.first != 0.0 && !t.second->empty()) terms.push_back(t);
     if (terms.empty()) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
-    int k[3];
+    const int m = (int)terms.size();
+    int k[3], off[4][3];
     for (int l = 0; l < 3; ++l) {
         int tot = 0;
-        for (auto& t : terms) tot += t.second->r[l];
-        if (tot > 2 * KM) throw FcError(FC_ERR_INTERNAL, "sum_trunc: too many columns");
-        double* Y = p->Phi[l];
-        int off = 0;
-        for (auto& t : terms) {
-            HIPCHK(fc::copy2d(n, t.second->r[l], t.second->Z[l], n, Y + (long)off * n, n, c.s));
-            off += t.second->r[l];
-        }
-        HIPCHK(fc::mgs_qr(n, tot, Y, 1e-12, p->icount + l, c.s));
+        for (int t = 0; t < m; ++t) { off[t][l] = tot; tot += terms[t].second->r[l]; }
+        k[l] = tot;
+        if (tot > 256) throw FcError(FC_ERR_INTERNAL, std::string(what) + ": too many columns");
+        for (int t = 0; t < m; ++t)
+            HIPCHK(fc::copy2d(n, terms[t].second->r[l], terms[t].second->Z[l], n,
+                              p->Phi[l] + (long)off[t][l] * n, n, c.s));
+        // full Gram of the concatenated bases (k_l x k_l)
+        gemm(c, true, false, k[l], k[l], n, 1.0, p->Phi[l], n, p->Phi[l], n, 0.0, p->SG[l], k[l]);
     }
-    int cnt[3];
-    d2h(c, cnt, p->icount, 3);
+    // block unfolding Grams M_l (k_l x k_l)
     for (int l = 0; l < 3; ++l) {
-        k[l] = cnt[l];
-        if (k[l] > KM) throw FcError(FC_ERR_INTERNAL, std::string(what) + ": union basis > 128");
+        const int a = (l == 0) ? 1 : 0, b = (l == 2) ? 1 : 2;
+        for (int t = 0; t < m; ++t) {
+            const Tucker& Tt = *terms[t].second;
+            int pt[3];
+            perm_dims(Tt.r, l, pt);
+            const double* coret = Tt.core;
+            if (l != 0) {
+                HIPCHK(fc::permute_core(Tt.r[0], Tt.r[1], Tt.r[2], l, 1, Tt.core, 0, p->Cn2, 0, c.s));
+                coret = p->Cn2;
+            }
+            for (int u = 0; u < m; ++u) {
+                const Tucker& Tu = *terms[u].second;
+                int pu[3];
+                perm_dims(Tu.r, l, pu);
+                const double* coreu = Tu.core;
+                if (l != 0) {
+                    HIPCHK(fc::permute_core(Tu.r[0], Tu.r[1], Tu.r[2], l, 1, Tu.core, 0, p->Cp, 0, c.s));
+                    coreu = p->Cp;
+                }
+                // c1 = core_u x_3 G_b^{tu}   (G_b^{tu}: r_t,b x r_u,b block of SG[b])
+                const int cur1[3] = {pu[0], pu[1], pu[2]};
+                mode_product(c, coreu, cur1, 2, p->SG[b] + off[t][b] + (long)off[u][b] * k[b], k[b],
+                             pt[2], p->c1);
+                const int cur2[3] = {pu[0], pu[1], pt[2]};
+                mode_product(c, p->c1, cur2, 1, p->SG[a] + off[t][a] + (long)off[u][a] * k[a], k[a],
+                             pt[1], p->c2);
+                // M[t,u] = c_t c_u core_t,(1) c2_(1)^T : (pt0 x pt1 pt2)(pt1 pt2 x pu0)
+                gemm(c, false, true, pt[0], pu[0], pt[1] * pt[2], terms[t].first * terms[u].first,
+                     coret, pt[0], p->c2, pu[0], 0.0, p->SM[l] + off[t][l] + (long)off[u][l] * k[l],
+                     k[l]);
+            }
+        }
     }
-    // dense core: sum_t coef_t core_t x_l (Phi_l^T Z_l^t)
-    const long csz = (long)k[0] * k[1] * k[2];
-    HIPCHK(fc::zero(csz, p->C, c.s));
-    for (auto& t : terms) {
-        const Tucker& T = *t.second;
+    const double n2 = host_dot(c, (long)k[0] * k[0], p->SM[0], p->SG[0]);
+    if (!std::isfinite(n2)) throw FcError(FC_ERR_NUMERIC, std::string(what) + ": non-finite");
+    const double thr2 = std::max(tol_rel * tol_rel * n2, floor_abs * floor_abs);
+    if (n2 <= thr2) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+    // dominant subspaces of H_l = B M B^T (the three modes in lockstep)
+    int pk[3], kk[3];
+    auto apply = [&](int l, const double* X, int q, double* HXo) {
+        gemm(c, true, false, k[l], q, n, 1.0, p->Phi[l], n, X, n, 0.0, p->Ys, k[l]);
+        gemm(c, false, false, k[l], q, k[l], 1.0, p->SM[l], k[l], p->Ys, k[l], 0.0, p->Ts, k[l]);
+        gemm(c, false, false, n, q, k[l], 1.0, p->Phi[l], n, p->Ts, k[l], 0.0, HXo, n);
+    };
+    for (int l = 0; l < 3; ++l) {
+        kk[l] = std::min({p->pcap, n, k[l]});
+        HIPCHK(fc::fill_random(n * (long)kk[l], 4321u + 13u * l, p->Xs3[l], c.s));
+    }
+    for (int it = 0; it < 3; ++it) {
+        for (int l = 0; l < 3; ++l) {
+            apply(l, p->Xs3[l], kk[l], p->HX3[l]);
+            kk[l] = orthonormalize(c, kk[l], p->HX3[l], 1e-13);
+            if (kk[l] == 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+            std::swap(p->Xs3[l], p->HX3[l]);
+        }
+    }
+    ritz(c, kk, thr2 / 6.0, 8, apply, pk);
+    // exact projection C = sum_t c_t core_t x_l (W_l^T Z_l^t)
+    for (int l = 0; l < 3; ++l)
+        gemm(c, true, false, pk[l], k[l], n, 1.0, p->W[l], n, p->Phi[l], n, 0.0, p->Map + (long)l * KM * 256,
+             pk[l]);
+    const long Csz = (long)pk[0] * pk[1] * pk[2];
+    for (int t = 0; t < m; ++t) {
+        const Tucker& T = *terms[t].second;
         int cur[3] = {T.r[0], T.r[1], T.r[2]};
         const double* src = T.core;
         double* bufs[2] = {p->Cn1, p->Cn2};
         for (int l = 0; l < 3; ++l) {
-            double* M = p->Map + (long)l * KM * KM;  // k_l x r_l
-            gemm(c, true, false, k[l], T.r[l], n, 1.0, p->Phi[l], n, T.Z[l], n, 0.0, M, k[l]);
-        }
-        for (int l = 0; l < 3; ++l) {
             const bool last = (l == 2);
             double* dst = last ? p->C : bufs[l & 1];
-            mode_product(c, src, cur, l, p->Map + (long)l * KM * KM, k[l], k[l], dst,
-                         last ? t.first : 1.0, last ? 1.0 : 0.0);
-            cur[l] = k[l];
+            mode_product(c, src, cur, l, p->Map + (long)l * KM * 256 + (long)off[t][l] * pk[l], pk[l],
+                         pk[l], dst, last ? terms[t].first : 1.0, (last && t > 0) ? 1.0 : 0.0);
+            cur[l] = pk[l];
             src = dst;
         }
     }
-    const double n2 = host_dot(c, csz, p->C, p->C);
-    const double thr2 = std::max(tol_rel * tol_rel * n2, floor_abs * floor_abs);
-    if (!(std::isfinite(n2))) throw FcError(FC_ERR_NUMERIC, std::string(what) + ": non-finite");
-    if (n2 <= thr2) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
-    double* B[3] = {p->Phi[0], p->Phi[1], p->Phi[2]};
-    hosvd_core(c, p->C, k, B, thr2, out, what);
+    const double c2 = host_dot(c, Csz, p->C, p->C);
+    const double missed = std::max(n2 - c2, 0.0);
+    const double thr_core = std::max(thr2 - missed, 0.0);
+    double* B[3] = {p->W[0], p->W[1], p->W[2]};
+    hosvd_core(c, p->C, pk, B, thr_core, out, what);
 }
 
 // ---- truncation of a Hadamard product with a separable positive tensor ----
@@ -394,50 +531,32 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     if (trH <= 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
     const double tau2_est = std::max(tol_rel * tol_rel * trH, floor_abs * floor_abs);
     // 3. dominant subspaces of Hh_l = sum_q D^q Z M^q Z^T D^q by subspace iteration
-    int pk[3];
+    //    (the three modes in lockstep)
+    int pk[3], kk[3];
+    auto apply = [&](int l, const double* X, int q, double* HXo) {
+        // Y^q = Z^T D^q X  (stack: r*q x Q)
+        HIPCHK(fc::rowkron(n, r[l], q, P.Z[l], n, X, n, p->E, c.s));
+        gemm(c, true, false, r[l] * q, Q, n, 1.0, p->E, n, op.D[l], n, 0.0, p->Ys, (long)r[l] * q);
+        // T^q = M^q Y^q
+        gemm(c, false, false, r[l], q, r[l], 1.0, Mq[l], r[l], p->Ys, r[l], 0.0, p->Ts, r[l], Q,
+             (long)r[l] * r[l], (long)r[l] * q, (long)r[l] * q);
+        // F = D T^T : n x (r*q)
+        gemm(c, false, true, n, r[l] * q, Q, 1.0, op.D[l], n, p->Ts, (long)r[l] * q, 0.0, p->F, n);
+        HIPCHK(fc::rowcontract(n, r[l], q, P.Z[l], n, p->F, HXo, n, c.s));
+    };
     for (int l = 0; l < 3; ++l) {
-        const int pmax = std::min({p->pcap, n, Q * r[l]});
-        int k = pmax;
-        HIPCHK(fc::fill_random(n * (long)k, 1234u + 7u * l, p->Xs, c.s));
-        auto apply = [&](const double* X, int kk, double* HXo) {
-            // Y^q = Z^T D^q X  (stack: r*kk x Q)
-            HIPCHK(fc::rowkron(n, r[l], kk, P.Z[l], n, X, n, p->E, c.s));
-            gemm(c, true, false, r[l] * kk, Q, n, 1.0, p->E, n, op.D[l], n, 0.0, p->Ys,
-                 (long)r[l] * kk);
-            // T^q = M^q Y^q
-            gemm(c, false, false, r[l], kk, r[l], 1.0, Mq[l], r[l], p->Ys, r[l], 0.0, p->Ts, r[l],
-                 Q, (long)r[l] * r[l], (long)r[l] * kk, (long)r[l] * kk);
-            // F = D T^T : n x (r*kk)
-            gemm(c, false, true, n, r[l] * kk, Q, 1.0, op.D[l], n, p->Ts, (long)r[l] * kk, 0.0,
-                 p->F, n);
-            HIPCHK(fc::rowcontract(n, r[l], kk, P.Z[l], n, p->F, HXo, n, c.s));
-        };
-        for (int it = 0; it < 3; ++it) {
-            apply(p->Xs, k, p->HX);
-            HIPCHK(fc::mgs_qr(n, k, p->HX, 1e-13, p->icount, c.s));
-            int kk = 0;
-            d2h(c, &kk, p->icount, 1);
-            if (kk == 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
-            k = kk;
-            HIPCHK(fc::copy2d(n, k, p->HX, n, p->Xs, n, c.s));
-        }
-        // Rayleigh-Ritz
-        apply(p->Xs, k, p->HX);
-        gemm(c, true, false, k, k, n, 1.0, p->Xs, n, p->HX, n, 0.0, p->Bp, k);
-        HIPCHK(fc::sym_eig(k, 1, p->Bp, k, 0, p->Ev, p->Evec, k, 0, p->jac, c.s));
-        std::vector<double> th(k);
-        d2h(c, th.data(), p->Ev, k);
-        // block-RHOSVD rank estimate, then a margin of 16 directions
-        double tail = 0;
-        int rr = k;
-        for (int i = k - 1; i >= 0; --i) {
-            tail += std::max(th[i], 0.0);
-            if (tail <= tau2_est / 3.0) rr = i; else break;
-        }
-        int use = std::min(k, std::max(rr + 16, 1));
-        gemm(c, false, false, n, use, k, 1.0, p->Xs, n, p->Evec, k, 0.0, p->W[l], n);
-        pk[l] = use;
+        kk[l] = std::min({p->pcap, n, Q * r[l]});
+        HIPCHK(fc::fill_random(n * (long)kk[l], 1234u + 7u * l, p->Xs3[l], c.s));
     }
+    for (int it = 0; it < 3; ++it) {
+        for (int l = 0; l < 3; ++l) {
+            apply(l, p->Xs3[l], kk[l], p->HX3[l]);
+            kk[l] = orthonormalize(c, kk[l], p->HX3[l], 1e-13);
+            if (kk[l] == 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+            std::swap(p->Xs3[l], p->HX3[l]);
+        }
+    }
+    ritz(c, kk, tau2_est / 3.0, 16, apply, pk);
     // 4. projection A_l^q = W_l^T D^q Z_l -> stack (pk*r x Q)
     for (int l = 0; l < 3; ++l) {
         HIPCHK(fc::rowkron(n, pk[l], r[l], p->W[l], n, P.Z[l], n, p->E, c.s));
@@ -481,10 +600,9 @@ void canon_to_tucker(const Ctx& c, int m, const double* w, const double* const X
     int k[3];
     for (int l = 0; l < 3; ++l) {
         HIPCHK(fc::copy2d(n, m, X[l], n, p->Phi[l], n, c.s));
-        HIPCHK(fc::mgs_qr(n, m, p->Phi[l], 1e-13, p->icount + l, c.s));
     }
     int cnt[3];
-    d2h(c, cnt, p->icount, 3);
+    for (int l = 0; l < 3; ++l) cnt[l] = orthonormalize(c, m, p->Phi[l], 1e-13);
     for (int l = 0; l < 3; ++l) {
         k[l] = cnt[l];
         if (k[l] > KM) throw FcError(FC_ERR_INTERNAL, std::string(what) + ": input basis > 128");
@@ -669,12 +787,29 @@ void alloc_workspace(fc_plan_s* p) {
     p->Cg = A.alloc((size_t)3 * KM * KM);
     p->Cev = A.alloc((size_t)3 * KM);
     p->Cvec = A.alloc((size_t)3 * KM * KM);
-    p->Map = A.alloc((size_t)3 * KM * KM);
+    p->Map = A.alloc((size_t)3 * KM * 256);
+    for (int l = 0; l < 3; ++l) {
+        p->SG[l] = A.alloc((size_t)256 * 256);
+        p->SM[l] = A.alloc((size_t)256 * 256);
+    }
     p->jac = A.alloc((size_t)std::max<long>((long)(KM + 1) * (KM + 1), (long)rc * (rc + 1) * (rc + 1)));
     p->scal = A.alloc(64);
     p->tmpn = A.alloc((size_t)n * std::max<long>(rc, 256));
     p->tmpn2 = A.alloc((size_t)n * std::max<long>(rc, 256));
-    p->icount = A.alloc_int(8);
+    p->icount = A.alloc_int(16);
+    p->qrN = A.alloc(512);
+    p->qrC = A.alloc(256 * 32);
+    p->qrTmp = A.alloc((size_t)n * 256 + 256);
+    p->qrKeep = A.alloc_int(512);
+    for (int l = 0; l < 3; ++l) {
+        p->Xs3[l] = A.alloc((size_t)n * pc);
+        p->HX3[l] = A.alloc((size_t)n * pc);
+    }
+    p->Bp3 = A.alloc((size_t)3 * KM * KM);
+    p->Ev3 = A.alloc((size_t)3 * KM);
+    p->Evec3 = A.alloc((size_t)3 * KM * KM);
+    p->splitws_cap = 8L << 20;
+    p->splitws = A.alloc((size_t)p->splitws_cap);
     p->dflag = A.alloc_int(4);
 }
 
@@ -1005,8 +1140,8 @@ static void apply_defaults(fc_plan_s* p, const fc_setup_params* prm) {
     p->tol = prm->tol > 0 ? prm->tol : prm->eps;
     p->op_acc = prm->op_accuracy > 0 ? prm->op_accuracy : prm->eps;
     p->max_iter = prm->max_iter > 0 ? prm->max_iter : 100;
-    p->rcap = prm->max_rank > 0 ? prm->max_rank : 64;
-    p->pcap = 96;
+    p->rcap = prm->max_rank > 0 ? prm->max_rank : 96;
+    p->pcap = 128;
     p->precond_rank = prm->precond_rank > 0 ? prm->precond_rank : 6;
 }
 
