@@ -214,6 +214,12 @@ fc_status fc_profile_gemm_read(long* launches, double* total_ms, double* flops, 
  * success. */
 int fc_selftest_mfma(double* host_out);
 
+/* Self-test of the device symmetric eigensolver used by the truncations:
+ * A_host is a k x k column-major symmetric matrix (k <= 128); eigenvalues
+ * (descending) and eigenvectors (columns) are returned to host memory.
+ * Returns 0 on success. */
+int fc_selftest_eig(int k, const double* A_host, double* evals_host, double* V_host);
+
 const char* fc_status_string(fc_status s);
 const char* fc_last_error(void);
 

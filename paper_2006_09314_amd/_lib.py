@@ -91,6 +91,7 @@ PROTOTYPES = {
     "fc_host_expsum": (_I, [_I, _D, _D, _D, _D, _D, _I, _PD, _PD, _PD]),
     "fc_host_separable": (_I, [C.POINTER(SetupParams), _I, _I, _PI, _PD, _PD, _PD]),
     "fc_selftest_mfma": (_I, [_PD]),
+    "fc_selftest_eig": (_I, [_I, _PD, _PD, _PD]),
     "fc_profile_gemm": (_I, [_I]),
     "fc_profile_gemm_read": (_I, [C.POINTER(C.c_long), _PD, _PD, _PD]),
     "fc_status_string": (C.c_char_p, [_I]),

@@ -32,7 +32,9 @@ hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
 hipError_t sym_eig(int k, int batch, const double* A, long lda, long strideA, double* evals,
                    double* V, long ldv, long strideV, double* scratch, hipStream_t s);
 
-// Up to four independent eigenproblems of different sizes in one launch.
+// Up to four independent eigenproblems of different sizes in one launch
+// (Householder tridiagonalisation + bisection + inverse iteration).  Each job
+// needs 6 k^2 doubles of device scratch.
 struct EigJob {
     const double* A = nullptr; long lda = 0; int k = 0;
     double* evals = nullptr; double* V = nullptr; long ldv = 0; double* scratch = nullptr;

@@ -266,6 +266,307 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_multi_kernel(EigJobs jobs,
     (void)kp;
 }
 
+// ---------------------------------------------------------------------------
+// Dense symmetric eigensolver for k <= 128, one workgroup per matrix:
+//  1. Householder reduction to tridiagonal form in LDS (reflectors kept in
+//     the lower triangle);
+//  2. eigenvalues by bisection on Sturm counts, one eigenvalue per thread;
+//  3. eigenvectors of the tridiagonal matrix by inverse iteration with a
+//     partially pivoted tridiagonal LU, one vector per thread (factors in a
+//     coalesced global scratch), re-orthogonalised within clusters of close
+//     eigenvalues;
+//  4. back-transformation by the reflectors.
+// Eigenvalues are returned in descending order.  Eigenvectors belonging to
+// eigenvalues below 1e-17 of the largest in magnitude are not computed
+// accurately (callers do not use them).
+constexpr int TD_THREADS = 512;
+
+__device__ inline double td_block_sum(double v, double* red) {
+    const int tid = threadIdx.x;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < TD_THREADS / 64; ++w) s += red[w];
+        red[15] = s;
+    }
+    __syncthreads();
+    const double r = red[15];
+    __syncthreads();
+    return r;
+}
+
+__device__ int sturm_count(int k, const double* d, const double* e, double x, double pivmin) {
+    // number of eigenvalues < x
+    int cnt = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < k; ++i) {
+        q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0) ++cnt;
+    }
+    return cnt;
+}
+
+__global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
+    extern __shared__ double sm[];
+    __shared__ double red[16];
+    const EigJob& J = jobs.job[blockIdx.x];
+    const int k = J.k;
+    const int tid = threadIdx.x;
+    double* a = sm;              // k x k, ld k
+    double* d = a + k * k;       // diagonal
+    double* e = d + k;           // off-diagonal
+    double* tau = e + k;         // reflector scalars
+    double* vv = tau + k;        // current reflector
+    double* pw = vv + k;         // p / w
+    double* lam = pw + k;        // eigenvalues, descending
+    for (int x = tid; x < k * k; x += blockDim.x) {
+        const int i = x % k, j = x / k;
+        a[x] = 0.5 * (J.A[i + (long)j * J.lda] + J.A[j + (long)i * J.lda]);
+    }
+    __syncthreads();
+    if (k == 1) {
+        if (tid == 0) { J.evals[0] = a[0]; J.V[0] = 1.0; }
+        return;
+    }
+    // 1. tridiagonalisation
+    for (int j = 0; j + 2 < k; ++j) {
+        const int m = k - j - 1;
+        double s = 0.0;
+        for (int r = tid; r < m; r += blockDim.x) { const double x = a[(j + 1 + r) + j * k]; s += x * x; }
+        const double nrm2 = td_block_sum(s, red);
+        const double x0 = a[(j + 1) + j * k];
+        const double sub = sqrt(nrm2 - x0 * x0 > 0 ? nrm2 - x0 * x0 : 0.0);
+        if (sub == 0.0) {
+            if (tid == 0) { d[j] = a[j + j * k]; e[j] = x0; tau[j] = 0.0; }
+            __syncthreads();
+            continue;
+        }
+        const double alpha = x0 > 0 ? -sqrt(nrm2) : sqrt(nrm2);
+        const double v0 = x0 - alpha;
+        const double t = -v0 / alpha;
+        for (int r = tid; r < m; r += blockDim.x) {
+            const double v = (r == 0) ? 1.0 : a[(j + 1 + r) + j * k] / v0;
+            vv[r] = v;
+            a[(j + 1 + r) + j * k] = v;     // keep the reflector
+        }
+        __syncthreads();
+        // p = t * A22 v, four threads per row
+        for (int base = 0; base < 4 * m; base += blockDim.x) {
+            const int x = base + tid;
+            const int r = x >> 2, part = x & 3;
+            double acc = 0.0;
+            if (r < m)
+                for (int c = part; c < m; c += 4) acc += a[(j + 1 + r) + (j + 1 + c) * k] * vv[c];
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            if (r < m && part == 0) pw[r] = t * acc;
+        }
+        __syncthreads();
+        double sp = 0.0;
+        for (int r = tid; r < m; r += blockDim.x) sp += vv[r] * pw[r];
+        const double K = 0.5 * t * td_block_sum(sp, red);
+        for (int r = tid; r < m; r += blockDim.x) pw[r] -= K * vv[r];
+        __syncthreads();
+        for (int x = tid; x < m * m; x += blockDim.x) {
+            const int r = x % m, c = x / m;
+            a[(j + 1 + r) + (j + 1 + c) * k] -= vv[r] * pw[c] + pw[r] * vv[c];
+        }
+        if (tid == 0) { d[j] = a[j + j * k]; e[j] = alpha; tau[j] = t; }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        d[k - 2] = a[(k - 2) + (k - 2) * k];
+        d[k - 1] = a[(k - 1) + (k - 1) * k];
+        e[k - 2] = a[(k - 1) + (k - 2) * k];
+        tau[k - 2] = 0.0;
+    }
+    __syncthreads();
+    // 2. eigenvalues by bisection (thread i: i-th largest)
+    double lo = 0.0, hi = 0.0, tnorm = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < k ? fabs(e[i]) : 0.0);
+        lo = (i == 0) ? d[i] - r : fmin(lo, d[i] - r);
+        hi = (i == 0) ? d[i] + r : fmax(hi, d[i] + r);
+    }
+    tnorm = fmax(fabs(lo), fabs(hi));
+    const double pivmin = fmax(1e-300, 1e-30 * tnorm * tnorm);
+    if (tid < k) {
+        const int want = k - 1 - tid;   // number of eigenvalues below the target
+        double l = lo - 1e-14 * tnorm - 1e-300, h = hi + 1e-14 * tnorm + 1e-300;
+        for (int it = 0; it < 64; ++it) {
+            const double mid = 0.5 * (l + h);
+            if (sturm_count(k, d, e, mid, pivmin) > want) h = mid; else l = mid;
+        }
+        lam[tid] = 0.5 * (l + h);
+    }
+    __syncthreads();
+    // 3. inverse iteration, thread i owns eigenvector i (coalesced scratch)
+    double* X = J.scratch;                    // X[i + j k]: element j of vector i
+    double* U0 = X + (long)k * k;             // pivoted LU factors
+    double* U1 = U0 + (long)k * k;
+    double* U2 = U1 + (long)k * k;
+    double* ML = U2 + (long)k * k;            // multipliers, sign encodes the interchange
+    const double smallpiv = 1e-15 * fmax(tnorm, 1e-300);
+    if (tid < k) {
+        const int i = tid;
+        const double lm = lam[i] + 4e-16 * tnorm * (1 + (i % 3));
+        // factor T - lm I (rows: sub c_j = e[j-1], diag, super e[j])
+        double ad = d[0] - lm, bd = (k > 1) ? e[0] : 0.0, fd = 0.0;
+        for (int j = 0; j + 1 < k; ++j) {
+            const double c = e[j];
+            const double an = d[j + 1] - lm;
+            const double bn = (j + 2 < k) ? e[j + 1] : 0.0;
+            if (fabs(ad) >= fabs(c)) {
+                const double mlt = (ad != 0.0) ? c / ad : 0.0;
+                U0[i + (long)j * k] = (fabs(ad) < smallpiv) ? copysign(smallpiv, ad) : ad;
+                U1[i + (long)j * k] = bd;
+                U2[i + (long)j * k] = fd;
+                ML[i + (long)j * k] = mlt;
+                ML[i + (long)j * k + (long)k * k] = 0.0;
+                ad = an - mlt * bd;
+                bd = bn - mlt * fd;
+                fd = 0.0;
+            } else {
+                const double mlt = ad / c;
+                U0[i + (long)j * k] = c;
+                U1[i + (long)j * k] = an;
+                U2[i + (long)j * k] = bn;
+                ML[i + (long)j * k] = mlt;
+                ML[i + (long)j * k + (long)k * k] = 1.0;
+                const double na = bd - mlt * an;
+                const double nb = fd - mlt * bn;
+                ad = na;
+                bd = nb;
+                fd = 0.0;
+            }
+        }
+        U0[i + (long)(k - 1) * k] = (fabs(ad) < smallpiv) ? copysign(smallpiv, ad) : ad;
+        U1[i + (long)(k - 1) * k] = 0.0;
+        U2[i + (long)(k - 1) * k] = 0.0;
+        // start vector
+        for (int j = 0; j < k; ++j) X[i + (long)j * k] = 1.0 + 0.37 * ((j * 7 + i * 13) % 11) / 11.0;
+        const long KK = (long)k * k;
+        for (int it = 0; it < 3; ++it) {
+            // forward: apply the row operations to the right-hand side
+            double carry = X[i];
+            for (int j0 = 0; j0 + 1 < k; j0 += 8) {
+                const int jn = min(8, k - 1 - j0);
+                double ml[8], sw[8], xs[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q < jn) {
+                        ml[q] = ML[i + (long)(j0 + q) * k];
+                        sw[q] = ML[i + (long)(j0 + q) * k + KK];
+                        xs[q] = X[i + (long)(j0 + q + 1) * k];
+                    }
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q < jn) {
+                        double r0 = carry, r1 = xs[q];
+                        if (sw[q] != 0.0) { const double t2 = r0; r0 = r1; r1 = t2; }
+                        r1 -= ml[q] * r0;
+                        X[i + (long)(j0 + q) * k] = r0;
+                        carry = r1;
+                    }
+            }
+            X[i + (long)(k - 1) * k] = carry;
+            // back substitution
+            double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+            for (int j1 = k - 1; j1 >= 0; j1 -= 8) {
+                const int jn = min(8, j1 + 1);
+                double u0[8], u1[8], u2[8], rh[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q < jn) {
+                        const long o = i + (long)(j1 - q) * k;
+                        u0[q] = U0[o]; u1[q] = U1[o]; u2[q] = U2[o]; rh[q] = X[o];
+                    }
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q < jn) {
+                        const double v = (rh[q] - u1[q] * x1 - u2[q] * x2) / u0[q];
+                        X[i + (long)(j1 - q) * k] = v;
+                        x2 = x1;
+                        x1 = v;
+                        nrm += v * v;
+                    }
+            }
+            const double inv = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
+            for (int j = 0; j < k; ++j) X[i + (long)j * k] *= inv;
+        }
+    }
+    __syncthreads();
+    // re-orthogonalise within clusters of close eigenvalues (descending order):
+    // all dot products of vector i with its cluster predecessors in one sweep
+    // (one wavefront per predecessor), then one subtraction sweep; two passes.
+    const double lmax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
+    {
+        const int lane = tid & 63, wv = tid >> 6;
+        int j0 = 0;
+        for (int i = 1; i < k; ++i) {
+            if (lam[i - 1] - lam[i] >= 1e-9 * lmax) { j0 = i; continue; }
+            const int cnt = i - j0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int c = wv; c < cnt; c += TD_THREADS / 64) {
+                    double acc = 0.0;
+                    for (int r = lane; r < k; r += 64)
+                        acc += X[(j0 + c) + (long)r * k] * X[i + (long)r * k];
+                    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+                    if (lane == 0) pw[c] = acc;
+                }
+                __syncthreads();
+                for (int r = tid; r < k; r += blockDim.x) {
+                    double v = X[i + (long)r * k];
+                    for (int c = 0; c < cnt; ++c) v -= pw[c] * X[(j0 + c) + (long)r * k];
+                    X[i + (long)r * k] = v;
+                }
+                __syncthreads();
+            }
+            double s3 = 0.0;
+            for (int r = tid; r < k; r += blockDim.x) s3 += X[i + (long)r * k] * X[i + (long)r * k];
+            const double nn = sqrt(td_block_sum(s3, red));
+            for (int r = tid; r < k; r += blockDim.x) X[i + (long)r * k] *= (nn > 0 ? 1.0 / nn : 0.0);
+            __syncthreads();
+        }
+    }
+    // 4. back-transformation: V = H_0 ... H_{k-3} X; reflector j acts on rows j+1..k-1
+    for (int x = tid; x < k * k; x += blockDim.x) {
+        const int r = x % k, i = x / k;
+        J.V[r + (long)i * J.ldv] = X[i + (long)r * k];
+    }
+    __syncthreads();
+    for (int j = k - 3; j >= 0; --j) {
+        const double t = tau[j];
+        if (t == 0.0) continue;
+        const int m = k - j - 1;
+        // s_i = t * v^T V[j+1:, i], four threads per column
+        for (int base = 0; base < 4 * k; base += blockDim.x) {
+            const int x = base + tid;
+            const int i = x >> 2, part = x & 3;
+            double acc = 0.0;
+            if (i < k) {
+                const double* col = J.V + (long)i * J.ldv + (j + 1);
+                for (int r = part; r < m; r += 4) acc += a[(j + 1 + r) + j * k] * col[r];
+            }
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            if (i < k && part == 0) pw[i] = t * acc;
+        }
+        __syncthreads();
+        for (int x = tid; x < m * k; x += blockDim.x) {
+            const int r = x % m, i = x / m;
+            J.V[(j + 1 + r) + (long)i * J.ldv] -= pw[i] * a[(j + 1 + r) + j * k];
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < k; i += blockDim.x) J.evals[i] = lam[i];
+}
+
 hipError_t sym_eig_multi(const EigJobs& jobs, hipStream_t s) {
     int kmax = 0;
     for (int i = 0; i < jobs.count; ++i) {
@@ -281,11 +582,16 @@ hipError_t sym_eig_multi(const EigJobs& jobs, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr = true;
     }
-    EigJobs j2 = jobs;
-    j2.kpmax = kp;
-    const int vlds = (2L * kp * kp * sizeof(double) <= 150L * 1024) ? 1 : 0;
-    hipLaunchKernelGGL(jacobi_multi_kernel, dim3(jobs.count), dim3(JAC_THREADS),
-                       sizeof(double) * kp * kp * (vlds ? 2 : 1), s, j2, vlds);
+    static bool attr2 = false;
+    if (!attr2) {
+        hipError_t e = hipFuncSetAttribute((const void*)tdeig_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        if (e != hipSuccess) return e;
+        attr2 = true;
+    }
+    (void)kp;
+    hipLaunchKernelGGL(tdeig_kernel, dim3(jobs.count), dim3(TD_THREADS),
+                       sizeof(double) * ((size_t)kmax * kmax + 6 * kmax), s, jobs);
     return hipGetLastError();
 }
 
@@ -671,24 +977,27 @@ hipError_t transpose(int rows, int cols, const double* src, long lds, double* ds
     return hipGetLastError();
 }
 
-// Two-pass classical Gram-Schmidt inside a panel: for column j, all dot
-// products against the kept panel columns are formed in one sweep (one
-// wavefront per column, 16 wavefronts), then subtracted in one sweep.
+// Two-pass classical Gram-Schmidt inside a panel held in LDS: for column j,
+// all dot products against the kept panel columns are formed in one sweep
+// (one wavefront per column), then subtracted in one sweep.
 __global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, int b, double* Y,
                                                          const double* norm0, double drop,
                                                          int* keep) {
+    extern __shared__ double P[];   // n x b
     __shared__ double red[32];
     __shared__ double dots[32];
     __shared__ int kp[32];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (long x = tid; x < (long)n * b; x += 1024) P[x] = Y[x];
+    __syncthreads();
     for (int j = 0; j < b; ++j) {
-        double* y = Y + (long)j * n;
+        double* y = P + (long)j * n;
         for (int pass = 0; pass < 2; ++pass) {
             if (j > 0) {
                 for (int c = w; c < j; c += 16) {
                     double acc = 0.0;
                     if (kp[c]) {
-                        const double* q = Y + (long)c * n;
+                        const double* q = P + (long)c * n;
                         for (int i = lane; i < n; i += 64) acc += q[i] * y[i];
                     }
                     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
@@ -697,7 +1006,7 @@ __global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, int b, double* Y
                 __syncthreads();
                 for (int i = tid; i < n; i += 1024) {
                     double v = y[i];
-                    for (int c = 0; c < j; ++c) v -= dots[c] * Y[(long)c * n + i];
+                    for (int c = 0; c < j; ++c) v -= dots[c] * P[(long)c * n + i];
                     y[i] = v;
                 }
                 __syncthreads();
@@ -712,12 +1021,22 @@ __global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, int b, double* Y
         if (tid == 0) { kp[j] = ok ? 1 : 0; keep[j] = ok ? 1 : 0; }
         __syncthreads();
     }
+    for (long x = tid; x < (long)n * b; x += 1024) Y[x] = P[x];
 }
 
 hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, int* keep,
                      hipStream_t s) {
     if (b <= 0) return hipSuccess;
-    hipLaunchKernelGGL(panel_mgs_kernel, dim3(1), dim3(1024), 0, s, n, b, Y, norm0, drop, keep);
+    if ((long)n * b * sizeof(double) > 144L * 1024 || b > 32) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)panel_mgs_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(panel_mgs_kernel, dim3(1), dim3(1024), sizeof(double) * n * b, s, n, b, Y,
+                       norm0, drop, keep);
     return hipGetLastError();
 }
 

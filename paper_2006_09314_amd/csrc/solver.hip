@@ -87,6 +87,14 @@ struct Separable {
     std::vector<double> F[3];                     // host copies of unweighted factors n x Q
 };
 
+enum { SITE_Z = 0, SITE_S, SITE_X, SITE_R, SITE_P, SITE_MISC, NSITES };
+
+struct WarmBasis {
+    double* W[3] = {nullptr, nullptr, nullptr};
+    int pk[3] = {0, 0, 0};
+    bool valid = false;
+};
+
 struct fc_plan_s {
     int n = 0;
     double alpha = 0, beta = 1, gamma = 1, eps = 1e-6, tol = 1e-6, op_acc = 0;
@@ -108,6 +116,7 @@ struct fc_plan_s {
     double *cw = nullptr, *cf[3] = {}, *Yh[3] = {};
     int* icount = nullptr;
     double* jac = nullptr;
+    WarmBasis warm[NSITES];
     double *qrN = nullptr, *qrC = nullptr, *qrTmp = nullptr;
     double *Xs3[3] = {}, *HX3[3] = {}, *Bp3 = nullptr, *Ev3 = nullptr, *Evec3 = nullptr;
     int* qrKeep = nullptr;
@@ -234,7 +243,8 @@ int orthonormalize(const Ctx& c, int m, double* Y, double drop, int slot = 0) {
     double* norms = p->qrN;
     int* keep = p->qrKeep;
     HIPCHK(fc::col_norms(n, m, Y, n, norms, c.s));
-    const int b = 16;
+    // panel width: the panel lives in LDS (<= 144 KiB)
+    const int b = std::max(1, std::min(16, (int)((144L * 1024 / 8) / n)));
     for (int j0 = 0; j0 < m; j0 += b) {
         const int bw = std::min(b, m - j0);
         double* P = Y + (long)j0 * n;
@@ -283,7 +293,7 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
             fc::EigJob& J = jobs.job[l];
             J.A = p->Cg + (long)l * KM * KM; J.lda = k[l]; J.k = k[l];
             J.evals = p->Cev + l * KM; J.V = p->Cvec + (long)l * KM * KM; J.ldv = k[l];
-            J.scratch = p->jac + (long)l * KM * KM;
+            J.scratch = p->jac + (long)l * 6 * KM * KM;
         }
         HIPCHK(fc::sym_eig_multi(jobs, c.s));
     }
@@ -300,7 +310,10 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
             tail += std::max(ev[l * KM + i], 0.0);
             if (tail <= thr2 / 3.0) rr = i; else break;
         }
-        r[l] = rr;
+        int numrank = 0;
+        const double tmax = std::max(ev[l * KM], 0.0);
+        while (numrank < k[l] && ev[l * KM + numrank] > 1e-17 * tmax) ++numrank;
+        r[l] = std::min(rr, numrank);
     }
     if (r[0] == 0 || r[1] == 0 || r[2] == 0 || tot <= thr2) {
         out.r[0] = out.r[1] = out.r[2] = 0;
@@ -330,13 +343,57 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
     p->max_seen_rank = std::max({p->max_seen_rank, r[0], r[1], r[2]});
 }
 
-// Rayleigh-Ritz on the three orthonormal subspaces X_l (n x kk_l, in Xs3):
-// eigenpairs of X_l^T H_l X_l in one batched launch, then W_l = X_l V_l[:, :pk_l]
-// with pk_l = (smallest rank whose Ritz tail is <= tail_budget) + margin.
+// Dominant subspaces of the three mode Grams H_l (given by `apply`, which
+// writes H_l X to its output), the three modes in lockstep:
+//  * start: the previous basis found at the same place of the iteration (a
+//    warm start, within one solve) padded with random columns, or random
+//    columns alone; orthonormalised;
+//  * power steps (1 from a random start, none from a warm start), each
+//    followed by a rank-revealing orthonormalisation;
+//  * Rayleigh-Ritz: eigenpairs of X_l^T H_l X_l in one batched launch, then
+//    W_l = X_l V_l[:, :pk_l] with pk_l = (smallest rank whose Ritz tail is
+//    <= tail_budget) + margin, capped by the numerical rank.
+// Returns false if some H_l is zero.
+// span[l] (optional, n x kcap[l]): columns spanning the whole range of H_l;
+// then the start is exactly that span and no power step is needed.
 template <class Apply>
-void ritz(const Ctx& c, const int kk[3], double tail_budget, int margin, Apply& apply, int pk[3]) {
+bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, double tail_budget,
+                    int margin, int pk[3], const double* const* span = nullptr) {
     fc_plan_s* p = c.p;
     const int n = c.n;
+    int kk[3];
+    WarmBasis& wb = p->warm[site];
+    const bool warm = wb.valid;
+    bool all_exact = true;
+    for (int l = 0; l < 3; ++l) {
+        kk[l] = kcap[l];
+        int off = 0;
+        if (span && span[l]) {
+            HIPCHK(fc::copy2d(n, kk[l], span[l], n, p->Xs3[l], n, c.s));
+            off = kk[l];
+        } else {
+            all_exact = false;
+            if (warm) {
+                off = std::min(wb.pk[l], kk[l]);
+                HIPCHK(fc::copy2d(n, off, wb.W[l], n, p->Xs3[l], n, c.s));
+            }
+        }
+        if (kk[l] > off)
+            HIPCHK(fc::fill_random(n * (long)(kk[l] - off), 1234u + 7u * l + 101u * site,
+                                   p->Xs3[l] + (long)off * n, c.s));
+        kk[l] = orthonormalize(c, kk[l], p->Xs3[l], 1e-13);
+        if (kk[l] == 0) return false;
+    }
+    // one power step moves a warm or random start into the range of H_l
+    const int power = all_exact ? 0 : 1;
+    for (int it = 0; it < power; ++it) {
+        for (int l = 0; l < 3; ++l) {
+            apply(l, p->Xs3[l], kk[l], p->HX3[l]);
+            kk[l] = orthonormalize(c, kk[l], p->HX3[l], 1e-13);
+            if (kk[l] == 0) return false;
+            std::swap(p->Xs3[l], p->HX3[l]);
+        }
+    }
     fc::EigJobs jobs;
     jobs.count = 3;
     for (int l = 0; l < 3; ++l) {
@@ -346,7 +403,7 @@ void ritz(const Ctx& c, const int kk[3], double tail_budget, int margin, Apply& 
         fc::EigJob& J = jobs.job[l];
         J.A = Bl; J.lda = kk[l]; J.k = kk[l];
         J.evals = p->Ev3 + l * KM; J.V = p->Evec3 + (long)l * KM * KM; J.ldv = kk[l];
-        J.scratch = p->jac + (long)l * KM * KM;
+        J.scratch = p->jac + (long)l * 6 * KM * KM;
     }
     HIPCHK(fc::sym_eig_multi(jobs, c.s));
     std::vector<double> th(3 * KM);
@@ -358,11 +415,18 @@ void ritz(const Ctx& c, const int kk[3], double tail_budget, int margin, Apply& 
             tail += std::max(th[l * KM + i], 0.0);
             if (tail <= tail_budget) rr = i; else break;
         }
-        const int use = std::min(kk[l], std::max(rr + margin, 1));
+        int numrank = 0;
+        const double tmax = std::max(th[l * KM], 0.0);
+        while (numrank < kk[l] && th[l * KM + numrank] > 1e-17 * tmax) ++numrank;
+        const int use = std::min(std::max(numrank, 1), std::max(rr + margin, 1));
         gemm(c, false, false, n, use, kk[l], 1.0, p->Xs3[l], n, p->Evec3 + (long)l * KM * KM, kk[l],
              0.0, p->W[l], n);
         pk[l] = use;
+        HIPCHK(fc::copy2d(n, use, p->W[l], n, wb.W[l], n, c.s));
+        wb.pk[l] = use;
     }
+    wb.valid = true;
+    return true;
 }
 
 // ---- exact truncation of a short sum of Tucker tensors ---------------------
@@ -375,7 +439,7 @@ void ritz(const Ctx& c, const int kk[3], double tail_budget, int margin, Apply& 
 // ||T||^2 = trace(M_l G_l) is exact, so the energy the subspace misses is
 // known and charged to the tolerance.
 void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>& terms_in,
-               double tol_rel, double floor_abs, Tucker& out, const char* what) {
+               double tol_rel, double floor_abs, Tucker& out, const char* what, int site) {
     fc_plan_s* p = c.p;
     const int n = c.n;
     std::vector<std::pair<double, const Tucker*>> terms;
@@ -434,26 +498,22 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
     if (!std::isfinite(n2)) throw FcError(FC_ERR_NUMERIC, std::string(what) + ": non-finite");
     const double thr2 = std::max(tol_rel * tol_rel * n2, floor_abs * floor_abs);
     if (n2 <= thr2) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
-    // dominant subspaces of H_l = B M B^T (the three modes in lockstep)
-    int pk[3], kk[3];
+    // dominant subspaces of H_l = B M B^T
+    int pk[3], kcap[3];
     auto apply = [&](int l, const double* X, int q, double* HXo) {
         gemm(c, true, false, k[l], q, n, 1.0, p->Phi[l], n, X, n, 0.0, p->Ys, k[l]);
         gemm(c, false, false, k[l], q, k[l], 1.0, p->SM[l], k[l], p->Ys, k[l], 0.0, p->Ts, k[l]);
         gemm(c, false, false, n, q, k[l], 1.0, p->Phi[l], n, p->Ts, k[l], 0.0, HXo, n);
     };
+    const double* span[3] = {nullptr, nullptr, nullptr};
     for (int l = 0; l < 3; ++l) {
-        kk[l] = std::min({p->pcap, n, k[l]});
-        HIPCHK(fc::fill_random(n * (long)kk[l], 4321u + 13u * l, p->Xs3[l], c.s));
+        kcap[l] = std::min({p->pcap, n, k[l]});
+        if (k[l] <= p->pcap && k[l] <= n) span[l] = p->Phi[l];   // range(H_l) within span(B_l)
     }
-    for (int it = 0; it < 3; ++it) {
-        for (int l = 0; l < 3; ++l) {
-            apply(l, p->Xs3[l], kk[l], p->HX3[l]);
-            kk[l] = orthonormalize(c, kk[l], p->HX3[l], 1e-13);
-            if (kk[l] == 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
-            std::swap(p->Xs3[l], p->HX3[l]);
-        }
+    if (!find_subspaces(c, site, kcap, apply, thr2 / 6.0, 8, pk, span)) {
+        out.r[0] = out.r[1] = out.r[2] = 0;
+        return;
     }
-    ritz(c, kk, thr2 / 6.0, 8, apply, pk);
     // exact projection C = sum_t c_t core_t x_l (W_l^T Z_l^t)
     for (int l = 0; l < 3; ++l)
         gemm(c, true, false, pk[l], k[l], n, 1.0, p->W[l], n, p->Phi[l], n, 0.0, p->Map + (long)l * KM * 256,
@@ -485,7 +545,7 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
 // block reduced HOSVD (sum over q of the unfolding Grams of the terms),
 // exact projection of T onto it, then HOSVD of the projected core.
 void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_rel,
-               double floor_abs, Tucker& out, const char* what) {
+               double floor_abs, Tucker& out, const char* what, int site) {
     fc_plan_s* p = c.p;
     const int n = c.n;
     const int Q = op.Q;
@@ -530,9 +590,8 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     if (!std::isfinite(trH)) throw FcError(FC_ERR_NUMERIC, std::string(what) + ": non-finite");
     if (trH <= 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
     const double tau2_est = std::max(tol_rel * tol_rel * trH, floor_abs * floor_abs);
-    // 3. dominant subspaces of Hh_l = sum_q D^q Z M^q Z^T D^q by subspace iteration
-    //    (the three modes in lockstep)
-    int pk[3], kk[3];
+    // 3. dominant subspaces of Hh_l = sum_q D^q Z M^q Z^T D^q
+    int pk[3], kcap[3];
     auto apply = [&](int l, const double* X, int q, double* HXo) {
         // Y^q = Z^T D^q X  (stack: r*q x Q)
         HIPCHK(fc::rowkron(n, r[l], q, P.Z[l], n, X, n, p->E, c.s));
@@ -544,19 +603,11 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
         gemm(c, false, true, n, r[l] * q, Q, 1.0, op.D[l], n, p->Ts, (long)r[l] * q, 0.0, p->F, n);
         HIPCHK(fc::rowcontract(n, r[l], q, P.Z[l], n, p->F, HXo, n, c.s));
     };
-    for (int l = 0; l < 3; ++l) {
-        kk[l] = std::min({p->pcap, n, Q * r[l]});
-        HIPCHK(fc::fill_random(n * (long)kk[l], 1234u + 7u * l, p->Xs3[l], c.s));
+    for (int l = 0; l < 3; ++l) kcap[l] = std::min({p->pcap, n, Q * r[l]});
+    if (!find_subspaces(c, site, kcap, apply, tau2_est / 3.0, 16, pk)) {
+        out.r[0] = out.r[1] = out.r[2] = 0;
+        return;
     }
-    for (int it = 0; it < 3; ++it) {
-        for (int l = 0; l < 3; ++l) {
-            apply(l, p->Xs3[l], kk[l], p->HX3[l]);
-            kk[l] = orthonormalize(c, kk[l], p->HX3[l], 1e-13);
-            if (kk[l] == 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
-            std::swap(p->Xs3[l], p->HX3[l]);
-        }
-    }
-    ritz(c, kk, tau2_est / 3.0, 16, apply, pk);
     // 4. projection A_l^q = W_l^T D^q Z_l -> stack (pk*r x Q)
     for (int l = 0; l < 3; ++l) {
         HIPCHK(fc::rowkron(n, pk[l], r[l], p->W[l], n, P.Z[l], n, p->E, c.s));
@@ -744,6 +795,10 @@ int tucker_to_canon_out(const Ctx& c, const Tucker& X, double budget2, bool to_g
     return K;
 }
 
+void reset_warm(fc_plan_s* p) {
+    for (int st = 0; st < NSITES; ++st) p->warm[st].valid = false;
+}
+
 void alloc_workspace(fc_plan_s* p) {
     const int n = p->n;
     const long rc = p->rcap, pc = p->pcap;
@@ -792,7 +847,7 @@ void alloc_workspace(fc_plan_s* p) {
         p->SG[l] = A.alloc((size_t)256 * 256);
         p->SM[l] = A.alloc((size_t)256 * 256);
     }
-    p->jac = A.alloc((size_t)std::max<long>((long)(KM + 1) * (KM + 1), (long)rc * (rc + 1) * (rc + 1)));
+    p->jac = A.alloc((size_t)std::max<long>(3L * 6 * KM * KM, (long)rc * (rc + 1) * (rc + 1)));
     p->scal = A.alloc(64);
     p->tmpn = A.alloc((size_t)n * std::max<long>(rc, 256));
     p->tmpn2 = A.alloc((size_t)n * std::max<long>(rc, 256));
@@ -806,6 +861,8 @@ void alloc_workspace(fc_plan_s* p) {
         p->HX3[l] = A.alloc((size_t)n * pc);
     }
     p->Bp3 = A.alloc((size_t)3 * KM * KM);
+    for (int st = 0; st < NSITES; ++st)
+        for (int l = 0; l < 3; ++l) p->warm[st].W[l] = A.alloc((size_t)n * pc);
     p->Ev3 = A.alloc((size_t)3 * KM);
     p->Evec3 = A.alloc((size_t)3 * KM * KM);
     p->splitws_cap = 8L << 20;
@@ -986,30 +1043,30 @@ SolveOut pcg(const Ctx& c, const Tucker& Bt, Tucker& Xout) {
     const double bn = std::sqrt(tucker_norm2(c, Bt));
     X.r[0] = X.r[1] = X.r[2] = 0;
     tucker_copy(c, Bt, R);                 // R0 = B - fun(X0), X0 = 0
-    had_trunc(c, p->pc, R, eps, 0.0, Z, "Z0 = trunc(precond(R0))");
+    had_trunc(c, p->pc, R, eps, 0.0, Z, "Z0 = trunc(precond(R0))", SITE_Z);
     tucker_copy(c, Z, P);                  // P0 = Z0
     double rz = tucker_inner(c, R, Z);
     for (int k = 0; k < p->max_iter; ++k) {
-        had_trunc(c, p->op, P, eps, 0.1 * eps * bn, S, "S = trunc(fun(P))");
+        had_trunc(c, p->op, P, eps, 0.1 * eps * bn, S, "S = trunc(fun(P))", SITE_S);
         const double ps = tucker_inner(c, P, S);
         if (!(ps > 0) || !std::isfinite(ps) || !std::isfinite(rz))
             throw FcError(FC_ERR_NUMERIC, "PCG breakdown: <P,S> = " + std::to_string(ps));
         const double ak = rz / ps;
         // X = trunc(X + a P)
-        sum_trunc(c, {{1.0, &X}, {ak, &P}}, 0.1 * eps, 0.0, T1, "X = trunc(X + aP)");
+        sum_trunc(c, {{1.0, &X}, {ak, &P}}, 0.1 * eps, 0.0, T1, "X = trunc(X + aP)", SITE_X);
         std::swap(X, T1);
         // R = trunc(R - a S)
-        sum_trunc(c, {{1.0, &R}, {-ak, &S}}, 0.1 * eps, 0.1 * eps * bn, T2, "R = trunc(R - aS)");
+        sum_trunc(c, {{1.0, &R}, {-ak, &S}}, 0.1 * eps, 0.1 * eps * bn, T2, "R = trunc(R - aS)", SITE_R);
         std::swap(R, T2);
         so.iterations = k + 1;
         const double rn = std::sqrt(tucker_norm2(c, R));
         so.rel_res = bn > 0 ? rn / bn : 0.0;
         if (R.empty() || so.rel_res <= p->tol) { so.converged = true; break; }
-        had_trunc(c, p->pc, R, eps, 0.0, Z, "Z = trunc(precond(R))");
+        had_trunc(c, p->pc, R, eps, 0.0, Z, "Z = trunc(precond(R))", SITE_Z);
         const double rzn = tucker_inner(c, R, Z);
         const double bk = rzn / rz;
         rz = rzn;
-        sum_trunc(c, {{1.0, &Z}, {bk, &P}}, eps, 0.0, T1, "P = trunc(Z + bP)");
+        sum_trunc(c, {{1.0, &Z}, {bk, &P}}, eps, 0.0, T1, "P = trunc(Z + bP)", SITE_P);
         std::swap(P, T1);
         if (P.empty()) { so.converged = true; break; }
     }
@@ -1264,7 +1321,8 @@ fc_status fc_apply_separable(fc_plan p, int which, int m, const double* w, const
         Tucker& T = p->slot[8];
         Tucker& O = p->slot[9];
         canon_to_tucker(c, m, w, X, 1e-3 * eps, T, "input");
-        had_trunc(c, which == 0 ? p->op : p->pc, T, eps / std::sqrt(2.0), 0.0, O, "apply");
+        reset_warm(p);
+        had_trunc(c, which == 0 ? p->op : p->pc, T, eps / std::sqrt(2.0), 0.0, O, "apply", SITE_MISC);
         const double n2 = tucker_norm2(c, O);
         inner = canon_out(p, c, O, 0.5 * eps * eps * n2, false, cap, rank_out, w_out, O1, O2, O3);
     });
@@ -1281,6 +1339,7 @@ fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, c
     const int n = p->n;
     fc_status result = FC_OK;
     p->max_seen_rank = 0;
+    reset_warm(p);
     fc_status st = guard([&] {
         // NaN guard on the input
         static const int zero_flag = 0;
@@ -1375,6 +1434,26 @@ fc_status fc_profile_gemm_read(long* launches, double* total_ms, double* flops, 
     *flops = g_prof.flops;
     *bytes = g_prof.bytes;
     return FC_OK;
+}
+
+int fc_selftest_eig(int k, const double* A_host, double* evals_host, double* V_host) {
+    if (k < 1 || k > 128 || !A_host || !evals_host || !V_host) return 1;
+    double *A = nullptr, *ev = nullptr, *V = nullptr, *scr = nullptr;
+    if (hipMalloc(&A, sizeof(double) * k * k) != hipSuccess) return 2;
+    if (hipMalloc(&ev, sizeof(double) * k) != hipSuccess) return 2;
+    if (hipMalloc(&V, sizeof(double) * k * k) != hipSuccess) return 2;
+    if (hipMalloc(&scr, sizeof(double) * 6 * k * k) != hipSuccess) return 2;
+    int rc = 0;
+    if (hipMemcpy(A, A_host, sizeof(double) * k * k, hipMemcpyHostToDevice) != hipSuccess) rc = 3;
+    fc::EigJobs jobs;
+    jobs.count = 1;
+    jobs.job[0].A = A; jobs.job[0].lda = k; jobs.job[0].k = k;
+    jobs.job[0].evals = ev; jobs.job[0].V = V; jobs.job[0].ldv = k; jobs.job[0].scratch = scr;
+    if (!rc && fc::sym_eig_multi(jobs, nullptr) != hipSuccess) rc = 4;
+    if (!rc && hipMemcpy(evals_host, ev, sizeof(double) * k, hipMemcpyDeviceToHost) != hipSuccess) rc = 5;
+    if (!rc && hipMemcpy(V_host, V, sizeof(double) * k * k, hipMemcpyDeviceToHost) != hipSuccess) rc = 5;
+    (void)hipFree(A); (void)hipFree(ev); (void)hipFree(V); (void)hipFree(scr);
+    return rc;
 }
 
 int fc_selftest_mfma(double* host_out) {
