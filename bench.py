@@ -84,6 +84,71 @@ def cpu_baseline(prob, sample_slabs=8):
     }
 
 
+def measure_batched(args, api, torch, dev):
+    """Many independent solves in one fc_solve_batched call (concurrent
+    streams): `batch` problems of the sine family at n = 1024 with seeds
+    100.. (or the uneven-size family), plans built beforehand."""
+    import numpy as np
+    import threading
+    import workloads as wl
+    from oracle import solve as osolve
+    if args.batch_workload == "mixed":
+        probs = wl.workload_batched(count=args.batch)
+    else:
+        probs = wl.workload_batched_uniform(count=args.batch, n=1024)
+    log(f"[bench] batched: {len(probs)} problems ({args.batch_workload}); building plans ...")
+    t0 = time.perf_counter()
+    plans = [None] * len(probs)
+
+    def build(i):
+        p = probs[i]
+        plans[i] = api.Plan(p.n, p.a, p.alpha, p.beta, p.gamma, p.eps)
+
+    idx = list(range(len(probs)))
+    th = []
+    for t in range(8):
+        th.append(threading.Thread(target=lambda t=t: [build(i) for i in idx[t::8]]))
+        th[-1].start()
+    for x in th:
+        x.join()
+    setup_s = time.perf_counter() - t0
+    log(f"[bench] batched setup {setup_s:.1f}s")
+    inputs = [(torch.from_numpy(np.asarray(p.w)).to(dev),
+               [api.to_device_colmajor(y, dev) for y in p.Y]) for p in probs]
+    cap = 1024
+    outs = [(torch.empty(cap, dtype=torch.float64, device=dev),
+             [torch.empty((cap, p.n), dtype=torch.float64, device=dev).t() for _ in range(3)])
+            for p in probs]
+    res = api.solve_batched(plans, inputs, cap_u=cap, outs=outs)     # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.batch_steps):
+        res = api.solve_batched(plans, inputs, cap_u=cap, outs=outs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rate = args.batch_steps * len(probs) / el
+    log(f"[bench] batched: {args.batch_steps} x {len(probs)} solves in {el:.2f}s -> {rate:.2f} solves/s")
+    checks = []
+    if not args.no_check:
+        rng = np.random.default_rng(1)
+        for i in [0, len(probs) - 1]:
+            p = probs[i]
+            w_u, U, info, st = res[i]
+            slabs = sorted(set(list(range(8)) + list(rng.choice(p.n, size=8, replace=False))))
+            rep = osolve.rel_error(p, w_u.cpu().numpy(), [u.cpu().numpy() for u in U], slabs=slabs)
+            checks.append({"problem": i, "n": p.n, "rel_l2_sampled": rep["rel_l2"],
+                           "slabs": rep["slabs"], "iterations": info["iterations"],
+                           "pass": bool(rep["rel_l2"] <= 10 * p.eps)})
+        log(f"[bench] batched checks {checks}")
+    for p in plans:
+        p.close()
+    iters = [r[2]["iterations"] for r in res]
+    return {"workload": args.batch_workload, "problems": len(probs), "steps": args.batch_steps,
+            "solves_per_s": rate, "s_per_batch": el / args.batch_steps, "setup_s": setup_s,
+            "streams": int(os.environ.get("FC_BATCH_STREAMS", "8")),
+            "iterations_min_max": [min(iters), max(iters)], "checks": checks}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +158,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--check-slabs", type=int, default=24)
+    ap.add_argument("--batch", type=int, default=64,
+                    help="problems in the batched measurement (0 disables it)")
+    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--batch-workload", default="sine1024x64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -157,6 +226,10 @@ def main():
                  "flops_per_launch": fl_launch, "bytes_per_launch": by_launch,
                  "gemm_share_of_step": (ms.value / 1e3) / elapsed})
 
+    batched = None
+    if args.batch > 0:
+        batched = measure_batched(args, api, torch, dev)
+
     parity = None
     if not args.no_check:
         from oracle import solve as osolve
@@ -180,15 +253,24 @@ def main():
         cpu = cpu_baseline(prob)
         log(f"[bench] cpu baseline {cpu}")
 
+    fp64_value = value
+    if batched is not None:
+        value = batched["solves_per_s"]
+        batched["vs_fp64_single"] = value / fp64_value
     rec = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wname, "n": prob.n, "rank_y": prob.rank, "alpha": prob.alpha,
-                   "beta": prob.beta, "gamma": prob.gamma, "eps": prob.eps, "path": "fp64",
+        "config": {"workload": (f"{args.batch}x sine_n1024_rank10 batched (seeds 100..)"
+                                if batched is not None else wname),
+                   "n": prob.n, "rank_y": prob.rank, "alpha": prob.alpha,
+                   "beta": prob.beta, "gamma": prob.gamma, "eps": prob.eps,
+                   "path": "fp64, concurrent streams" if batched is not None else "fp64",
                    "setup_s": setup_s},
         "roofline": roof, "cpu_baseline": cpu, "parity": parity, "solve_info": info,
+        "fp64_single": {"solves_per_s": fp64_value, "ms_per_solve": 1e3 * elapsed / args.steps},
+        "batched": batched,
     }
     print(json.dumps(rec), flush=True)
     plan.close()

@@ -149,6 +149,47 @@ class Plan:
                                 cap, stream)
 
 
+def solve_batched(plans: Sequence["Plan"], problems: Sequence, cap_u: int = 4096, stream=None,
+                  outs=None, raise_on_error: bool = True):
+    """Concurrent solves (fc_solve_batched): problems[i] = (w_y, [Y1, Y2, Y3]) on
+    plans[i].  Returns a list of (w_u, [U1, U2, U3], info, status)."""
+    import torch
+    from ._lib import Info, STATUS
+    count = len(plans)
+    VP = C.c_void_p
+    arr = lambda xs: (VP * count)(*xs)
+    Ys = [[_colmajor(y) for y in p[1]] for p in problems]
+    if outs is None:
+        outs = []
+        for i in range(count):
+            dev = Ys[i][0].device
+            n = plans[i].n
+            outs.append((torch.empty(cap_u, dtype=torch.float64, device=dev),
+                         [torch.empty((cap_u, n), dtype=torch.float64, device=dev).t()
+                          for _ in range(3)]))
+    rank_y = (C.c_int * count)(*[Ys[i][0].shape[1] for i in range(count)])
+    capa = (C.c_int * count)(*[outs[i][0].shape[0] for i in range(count)])
+    rank_u = (C.c_int * count)()
+    status = (C.c_int * count)()
+    infos = (Info * count)()
+    st = lib().fc_solve_batched(
+        count, arr([p.handle.value for p in plans]), rank_y,
+        arr([_ptr(p[0]) for p in problems]),
+        arr([_ptr(Ys[i][0]) for i in range(count)]), arr([_ptr(Ys[i][1]) for i in range(count)]),
+        arr([_ptr(Ys[i][2]) for i in range(count)]), capa, rank_u,
+        arr([_ptr(o[0]) for o in outs]), arr([_ptr(o[1][0]) for o in outs]),
+        arr([_ptr(o[1][1]) for o in outs]), arr([_ptr(o[1][2]) for o in outs]),
+        status, infos, _stream_ptr(stream))
+    res = []
+    for i in range(count):
+        k = rank_u[i]
+        w_u, U = outs[i]
+        res.append((w_u[:k], [u[:, :k] for u in U], infos[i].as_dict(), STATUS.get(status[i])))
+    if st != 0 and raise_on_error:
+        check(st, "fc_solve_batched")
+    return res
+
+
 def _colmajor(t):
     """A (rows, cols) tensor laid out column-major (its transpose contiguous)."""
     if t.dim() != 2:

@@ -3,6 +3,7 @@
 #include "kernels.h"
 
 #include <cstdint>
+#include <mutex>
 
 namespace fc {
 
@@ -256,15 +257,6 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double
                 scratch + (long)b * kp * kp, sm);
 }
 
-__global__ __launch_bounds__(JAC_THREADS) void jacobi_multi_kernel(EigJobs jobs, int vlds) {
-    extern __shared__ double sm[];
-    const EigJob& J = jobs.job[blockIdx.x];
-    const int kp = J.k + (J.k & 1);
-    // rotations accumulate in LDS when both matrices fit, else in global scratch
-    double* v = vlds ? sm + jobs.kpmax * jobs.kpmax : J.scratch;
-    jacobi_body(J.k, J.A, J.lda, J.evals, J.V, J.ldv, v, sm);
-    (void)kp;
-}
 
 // ---------------------------------------------------------------------------
 // Dense symmetric eigensolver for k <= 128, one workgroup per matrix:
@@ -575,20 +567,13 @@ hipError_t sym_eig_multi(const EigJobs& jobs, hipStream_t s) {
     }
     if (jobs.count <= 0 || kmax <= 0) return hipSuccess;
     const int kp = kmax + (kmax & 1);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)jacobi_multi_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    static bool attr2 = false;
-    if (!attr2) {
-        hipError_t e = hipFuncSetAttribute((const void*)tdeig_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-        if (e != hipSuccess) return e;
-        attr2 = true;
-    }
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [] {
+        attr_err = hipFuncSetAttribute((const void*)tdeig_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    });
+    if (attr_err != hipSuccess) return attr_err;
     (void)kp;
     hipLaunchKernelGGL(tdeig_kernel, dim3(jobs.count), dim3(TD_THREADS),
                        sizeof(double) * ((size_t)kmax * kmax + 6 * kmax), s, jobs);
@@ -601,13 +586,13 @@ hipError_t sym_eig(int k, int batch, const double* A, long lda, long strideA, do
     if (k > 128) return hipErrorInvalidValue;
     const int kp = k + (k & 1);
     const size_t shm = sizeof(double) * kp * kp;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)jacobi_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [] {
+        attr_err = hipFuncSetAttribute((const void*)jacobi_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+    });
+    if (attr_err != hipSuccess) return attr_err;
     hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(JAC_THREADS), shm, s, k, A, lda, strideA,
                        evals, V, ldv, strideV, scratch);
     return hipGetLastError();
@@ -1028,13 +1013,13 @@ hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, 
                      hipStream_t s) {
     if (b <= 0) return hipSuccess;
     if ((long)n * b * sizeof(double) > 144L * 1024 || b > 32) return hipErrorInvalidValue;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)panel_mgs_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [] {
+        attr_err = hipFuncSetAttribute((const void*)panel_mgs_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    });
+    if (attr_err != hipSuccess) return attr_err;
     hipLaunchKernelGGL(panel_mgs_kernel, dim3(1), dim3(1024), sizeof(double) * n * b, s, n, b, Y,
                        norm0, drop, keep);
     return hipGetLastError();

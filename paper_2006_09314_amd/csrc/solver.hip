@@ -12,6 +12,9 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <atomic>
+#include <cstdlib>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -129,6 +132,7 @@ struct fc_plan_s {
     hipStream_t stream = nullptr;
     // statistics of the last solve
     int max_seen_rank = 0;
+    std::mutex use_mu;   // one solve at a time per plan
 };
 
 namespace {
@@ -145,6 +149,8 @@ struct GemmProfile {
     long launches = 0;
 };
 GemmProfile g_prof;
+std::mutex g_prof_mu;
+thread_local bool t_no_profile = false;   // set in batch workers
 
 struct Ctx {
     fc_plan_s* p;
@@ -164,7 +170,8 @@ void gemm(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, con
     g.C = C; g.ldc = ldc; g.strideC = sC; g.strideCin = sCi;
     g.d = d; g.strideD = sD;
     g.part = c.p->splitws; g.part_cap = c.p->splitws_cap;
-    if (g_prof.on && M > 0 && N > 0 && K > 0 && batch > 0) {
+    if (g_prof.on && !t_no_profile && M > 0 && N > 0 && K > 0 && batch > 0) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
         if (g_prof.used + 2 > g_prof.ev.size()) {
             for (int i = 0; i < 256; ++i) {
                 hipEvent_t e;
@@ -1396,13 +1403,49 @@ fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
     if (count < 0 || (count > 0 && (!plans || !rank_y || !Y1 || !Y2 || !Y3 || !cap_u || !rank_u ||
                                     !w_u || !U1 || !U2 || !U3 || !status)))
         return fail(FC_ERR_INVALID_ARG, "fc_solve_batched: bad arguments");
+    for (int i = 0; i < count; ++i)
+        if (!plans[i]) return fail(FC_ERR_INVALID_ARG, "fc_solve_batched: NULL plan");
+    if (count == 0) return FC_OK;
+    // Problems run concurrently: worker threads, each with its own stream,
+    // take problems in order from a shared counter.  The caller's stream is
+    // joined at the start (its pending work completes before any solve
+    // starts); every solve synchronises its own stream before it returns.
+    int workers = 8;
+    if (const char* env = std::getenv("FC_BATCH_STREAMS")) workers = std::max(1, std::atoi(env));
+    workers = std::min(workers, count);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(FC_ERR_HIP, "hipGetDevice failed");
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return fail(FC_ERR_HIP, "hipStreamSynchronize failed");
+    std::atomic<int> next(0);
+    std::vector<std::string> errs(count);
+    auto work = [&]() {
+        t_no_profile = true;
+        if (hipSetDevice(dev) != hipSuccess) return;
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
+        for (;;) {
+            const int i = next.fetch_add(1);
+            if (i >= count) break;
+            std::lock_guard<std::mutex> lk(plans[i]->use_mu);
+            status[i] = fc_solve(plans[i], rank_y[i], w_y ? w_y[i] : nullptr, Y1[i], Y2[i], Y3[i],
+                                 cap_u[i], &rank_u[i], w_u[i], U1[i], U2[i], U3[i],
+                                 info ? &info[i] : nullptr, s);
+            if (status[i] != FC_OK) errs[i] = g_last_error;
+        }
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    };
+    for (int i = 0; i < count; ++i) status[i] = FC_ERR_INTERNAL;
+    std::vector<std::thread> pool;
+    for (int t = 0; t < workers; ++t) pool.emplace_back(work);
+    for (auto& t : pool) t.join();
     fc_status first = FC_OK;
-    for (int i = 0; i < count; ++i) {
-        status[i] = fc_solve(plans[i], rank_y[i], w_y ? w_y[i] : nullptr, Y1[i], Y2[i], Y3[i],
-                             cap_u[i], &rank_u[i], w_u[i], U1[i], U2[i], U3[i],
-                             info ? &info[i] : nullptr, stream);
-        if (status[i] != FC_OK && first == FC_OK) first = status[i];
-    }
+    for (int i = 0; i < count; ++i)
+        if (status[i] != FC_OK && first == FC_OK) {
+            first = status[i];
+            g_last_error = "problem " + std::to_string(i) + ": " + errs[i];
+        }
     return first;
 }
 

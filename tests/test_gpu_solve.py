@@ -119,3 +119,36 @@ def test_max_iter_reports_not_converged():
     with pytest.raises(FcError) as ei:
         solve(plan, prob)
     assert ei.value.status == 3
+
+
+def test_batched_matches_single_and_isolates_failures():
+    """fc_solve_batched runs the problems concurrently; every result equals
+    the single solve of the same problem bit for bit, passes the oracle gate,
+    and a failing problem (NaN design) does not disturb the others."""
+    import torch
+    from paper_2006_09314_amd import api
+    from tests.gpu_util import dev, host, plan_for, solve
+    probs = [wl.workload_small(n=24), wl.workload_quadratic(n=48, alpha=0.3, seed=7),
+             wl.workload_sine(n=40, seed=11, rank=3), wl.workload_quadratic(n=56, alpha=0.7)]
+    plans = [plan_for(p) for p in probs]
+    inputs = [(torch.from_numpy(p.w).cuda(), [dev(y) for y in p.Y]) for p in probs]
+    bad_Y = [y.copy() for y in probs[2].Y]
+    bad_Y[0][5, 1] = np.nan
+    inputs_bad = list(inputs)
+    inputs_bad[2] = (inputs[2][0], [dev(y) for y in bad_Y])
+    res = api.solve_batched(plans, inputs, cap_u=2048)
+    for p, plan, r in zip(probs, plans, res):
+        w_u, U, info, st = r
+        assert st == "FC_OK"
+        w1, U1, info1 = solve(plan, p)
+        assert np.array_equal(host(w_u), w1)
+        assert all(np.array_equal(host(a), b) for a, b in zip(U, U1))
+        rep = osolve.rel_error(p, host(w_u), [host(u) for u in U])
+        assert rep["rel_l2"] <= GATE * p.eps, (p.name, rep)
+    from paper_2006_09314_amd._lib import FcError
+    with pytest.raises(FcError):
+        api.solve_batched(plans, inputs_bad, cap_u=2048)
+    res2 = api.solve_batched(plans, inputs_bad, cap_u=2048, raise_on_error=False)
+    assert [r[3] for r in res2] == ["FC_OK", "FC_OK", "FC_ERR_NUMERIC", "FC_OK"]
+    for i in (0, 1, 3):
+        assert np.array_equal(host(res2[i][0]), host(res[i][0]))
