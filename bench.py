@@ -162,6 +162,7 @@ def main():
                     help="problems in the batched measurement (0 disables it)")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--batch-workload", default="sine1024x64")
+    ap.add_argument("--mixed-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -226,6 +227,29 @@ def main():
                  "flops_per_launch": fl_launch, "bytes_per_launch": by_launch,
                  "gemm_share_of_step": (ms.value / 1e3) / elapsed})
 
+    mixed = None
+    if args.mixed_steps > 0:
+        mplan = api.Plan(prob.n, prob.a, prob.alpha, prob.beta, prob.gamma, prob.eps, precision=1)
+        res_m = mplan.solve(w, Y, cap_u=cap, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.mixed_steps):
+            res_m = mplan.solve(w, Y, cap_u=cap, out=out)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        mixed = {"solves_per_s": args.mixed_steps / el, "ms_per_solve": 1e3 * el / args.mixed_steps,
+                 "info": res_m[2]}
+        if not args.no_check:
+            from oracle import solve as osolve
+            rng = np.random.default_rng(2)
+            slabs = sorted(set(list(range(12)) + list(rng.choice(prob.n, size=8, replace=False))))
+            rep = osolve.rel_error(prob, res_m[0].cpu().numpy(), [u.cpu().numpy() for u in res_m[1]],
+                                   slabs=slabs)
+            mixed["rel_l2_sampled"] = rep["rel_l2"]
+            mixed["pass"] = bool(rep["rel_l2"] <= 10 * prob.eps)
+        log(f"[bench] mixed FP32/FP64-refinement: {mixed}")
+        mplan.close()
+
     batched = None
     if args.batch > 0:
         batched = measure_batched(args, api, torch, dev)
@@ -270,7 +294,7 @@ def main():
                    "setup_s": setup_s},
         "roofline": roof, "cpu_baseline": cpu, "parity": parity, "solve_info": info,
         "fp64_single": {"solves_per_s": fp64_value, "ms_per_solve": 1e3 * elapsed / args.steps},
-        "batched": batched,
+        "batched": batched, "mixed_single": mixed,
     }
     print(json.dumps(rec), flush=True)
     plan.close()

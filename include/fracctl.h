@@ -55,7 +55,13 @@ typedef enum {
     FC_ERR_INTERNAL = 7       /* internal capacity exceeded (Tucker rank > max)   */
 } fc_status;
 
-typedef enum { FC_FP64 = 0 } fc_precision;
+/* FC_FP64: every operation in FP64.  FC_MIXED_FP32: outer FP64 iterative
+ * refinement of the true residual around an inner PCG whose bulk
+ * contractions (mode transforms of the subspace iteration, Hadamard
+ * projections, core contractions) run on the FP32 matrix cores with FP32
+ * accumulation; Grams, eigensolves, PCG scalars and the refinement residual
+ * stay FP64. */
+typedef enum { FC_FP64 = 0, FC_MIXED_FP32 = 1 } fc_precision;
 
 /* Setup parameters.  Zero-valued optional fields select the defaults. */
 typedef struct {
@@ -69,12 +75,13 @@ typedef struct {
     int max_iter;           /* 0 -> 100                                                        */
     int max_rank;           /* Tucker rank capacity per mode; 0 -> 64, at most 96              */
     int precond_rank;       /* Kronecker rank of the preconditioner; 0 -> 6 (Section 4)        */
-    fc_precision precision; /* FC_FP64                                                         */
+    fc_precision precision; /* FC_FP64 or FC_MIXED_FP32                                        */
 } fc_setup_params;
 
 /* Per-solve report (HOST struct). */
 typedef struct {
-    int iterations;         /* PCG iterations taken (Algorithm 1 loop count)                   */
+    int iterations;         /* PCG iterations taken (Algorithm 1 loop count, all sweeps)       */
+    int refinements;        /* outer refinement sweeps (FC_MIXED_FP32), else 0                 */
     int rank_u;             /* canonical rank of the result                                    */
     int tucker_rank[3];     /* Tucker rank of the final iterate                                */
     int max_tucker_rank;    /* largest Tucker rank met during the iteration                    */
@@ -209,8 +216,9 @@ fc_status fc_host_separable(const fc_setup_params* p, int which, int cap, int* r
 fc_status fc_profile_gemm(int enable);
 fc_status fc_profile_gemm_read(long* launches, double* total_ms, double* flops, double* bytes);
 
-/* Self-test of the matrix-core operand layout: one 16x16x4 FP64 product of
- * fixed matrices, 256 values written row-major to HOST out.  Returns 0 on
+/* Self-test of the matrix-core operand layouts: one 16x16x4 product of fixed
+ * matrices on the FP64 matrix core (out[0..255], row-major) and on the FP32
+ * matrix core (out[256..511]); 512 values written to HOST out.  Returns 0 on
  * success. */
 int fc_selftest_mfma(double* host_out);
 

@@ -44,6 +44,7 @@ class SetupParams(C.Structure):
 class Info(C.Structure):
     _fields_ = [
         ("iterations", C.c_int),
+        ("refinements", C.c_int),
         ("rank_u", C.c_int),
         ("tucker_rank", C.c_int * 3),
         ("max_tucker_rank", C.c_int),
@@ -56,7 +57,8 @@ class Info(C.Structure):
 
     def as_dict(self):
         return {
-            "iterations": self.iterations, "rank_u": self.rank_u,
+            "iterations": self.iterations, "refinements": self.refinements,
+            "rank_u": self.rank_u,
             "tucker_rank": list(self.tucker_rank), "max_tucker_rank": self.max_tucker_rank,
             "op_rank": self.op_rank, "precond_rank": self.precond_rank,
             "rel_residual": self.rel_residual, "op_max_rel_err": self.op_max_rel_err,

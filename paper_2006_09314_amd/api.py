@@ -35,7 +35,7 @@ class Plan:
     def __init__(self, n: int, a: Sequence[np.ndarray], alpha: float, beta: float,
                  gamma: float = 1.0, eps: float = 1e-6, tol: float = 0.0,
                  op_accuracy: float = 0.0, max_iter: int = 0, max_rank: int = 0,
-                 precond_rank: int = 0, stream=None):
+                 precond_rank: int = 0, precision: int = 0, stream=None):
         self._a = [_host_array(x) for x in a]
         for x in self._a:
             if x.shape != (n + 1,):
@@ -46,7 +46,8 @@ class Plan:
             p.a[l] = self._a[l].ctypes.data_as(C.POINTER(C.c_double))
         p.alpha, p.beta, p.gamma, p.eps, p.tol = alpha, beta, gamma, eps, tol
         p.op_accuracy = op_accuracy
-        p.max_iter, p.max_rank, p.precond_rank, p.precision = max_iter, max_rank, precond_rank, 0
+        p.max_iter, p.max_rank, p.precond_rank, p.precision = (max_iter, max_rank, precond_rank,
+                                                                precision)
         h = C.c_void_p()
         check(lib().fc_setup_ex(C.byref(p), _stream_ptr(stream), C.byref(h)), "fc_setup_ex")
         self.handle = h

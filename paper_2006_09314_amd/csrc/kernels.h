@@ -20,6 +20,9 @@ struct GemmArgs {
     // split over extra workgroups whose partial products land here and are
     // summed in a fixed order by a second kernel (deterministic).
     double* part = nullptr; long part_cap = 0;
+    // FP32 matrix cores (operands rounded to FP32, FP32 accumulation, FP64
+    // in and out) instead of FP64
+    bool lowp = false;
 };
 
 hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s);

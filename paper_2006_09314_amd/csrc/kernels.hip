@@ -8,6 +8,9 @@
 namespace fc {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+// accumulator row of register v in lane l for v_mfma_f32_16x16x4f32
+#define F32_ROW(l, v) (4 * ((l) >> 4) + (v))
 
 // ---------------------------------------------------------------------------
 // Batched FP64 GEMM on the matrix cores.
@@ -97,6 +100,85 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g, int kchu
             }
 }
 
+template <bool TA, bool TB, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void gemm32_kernel(GemmArgs g, int kchunk) {
+    constexpr int BM = 32 * WM, BN = 32 * WN, BK = 16, NT = 64 * WM * WN;
+    __shared__ float As[BK][BM + 1];
+    __shared__ float Bs[BK][BN + 1];
+    const int tilesM = (g.M + BM - 1) / BM;
+    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
+    const int b = blockIdx.y;
+    const long bo = b / g.inner, bi = b % g.inner;
+    const double* __restrict__ A = g.A + bo * g.strideA + bi * g.strideAin;
+    const double* __restrict__ B = g.B + bo * g.strideB + bi * g.strideBin;
+    const double* __restrict__ d = g.d ? g.d + bo * g.strideD : nullptr;
+    double* __restrict__ C = g.C + bo * g.strideC + bi * g.strideCin;
+    long ldc = g.ldc;
+    double alpha = g.alpha, beta = g.beta;
+    const int kz = blockIdx.z;
+    const int kbeg = kz * kchunk, kend = min(g.K, kbeg + kchunk);
+    if (gridDim.z > 1) {
+        // partial product of this K slice -> part[kz][b] (M x N, ld M)
+        C = g.part + ((long)kz * g.batch + b) * (long)g.M * g.N;
+        ldc = g.M;
+        alpha = 1.0;
+        beta = 0.0;
+    }
+    const int row0 = tm * BM, col0 = tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    flt4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        for (int e = tid; e < BM * BK; e += NT) {
+            int i, k;
+            if (!TA) { i = e % BM; k = e / BM; } else { k = e % BK; i = e / BK; }
+            const int gi = row0 + i, gk = k0 + k;
+            double v = 0.0;
+            if (gi < g.M && gk < kend) {
+                v = TA ? A[gk + (long)gi * g.lda] : A[gi + (long)gk * g.lda];
+                if (d) v *= d[gk];
+            }
+            As[k][i] = (float)v;
+        }
+        for (int e = tid; e < BK * BN; e += NT) {
+            int j, k;
+            if (!TB) { k = e % BK; j = e / BK; } else { j = e % BN; k = e / BN; }
+            const int gj = col0 + j, gk = k0 + k;
+            double v = 0.0;
+            if (gj < g.N && gk < kend) v = TB ? B[gj + (long)gk * g.ldb] : B[gk + (long)gj * g.ldb];
+            Bs[k][j] = (float)v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+            const int k = kk * 4 + (lane >> 4);
+            const float a0 = As[k][wm * 32 + (lane & 15)];
+            const float a1 = As[k][wm * 32 + 16 + (lane & 15)];
+            const float b0 = Bs[k][wn * 32 + (lane & 15)];
+            const float b1 = Bs[k][wn * 32 + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    for (int mi = 0; mi < 2; ++mi)
+        for (int ni = 0; ni < 2; ++ni)
+            for (int v = 0; v < 4; ++v) {
+                const int i = row0 + wm * 32 + mi * 16 + F32_ROW(lane, v);
+                const int j = col0 + wn * 32 + ni * 16 + (lane & 15);
+                if (i < g.M && j < g.N) {
+                    double r = alpha * (double)acc[mi][ni][v];
+                    if (beta != 0.0) r += beta * C[i + (long)j * ldc];
+                    C[i + (long)j * ldc] = r;
+                }
+            }
+}
+
 // sum of the split-K partial products: C = alpha sum_z part[z] + beta C
 __global__ void splitk_reduce_kernel(GemmArgs g, int ksplit) {
     const long mn = (long)g.M * g.N;
@@ -130,12 +212,20 @@ static hipError_t gemm_dispatch(const GemmArgs& g, hipStream_t s) {
     int kchunk = (g.K + ksplit - 1) / ksplit;
     kchunk = (kchunk + 15) / 16 * 16;
     ksplit = (g.K + kchunk - 1) / kchunk;
-    if (big)
+    if (g.lowp) {
+        if (big)
+            hipLaunchKernelGGL((gemm32_kernel<TA, TB, 2, 2>), dim3(tiles, g.batch, ksplit), dim3(256),
+                               0, s, g, kchunk);
+        else
+            hipLaunchKernelGGL((gemm32_kernel<TA, TB, 1, 1>), dim3(tiles, g.batch, ksplit), dim3(64),
+                               0, s, g, kchunk);
+    } else if (big) {
         hipLaunchKernelGGL((gemm_kernel<TA, TB, 2, 2>), dim3(tiles, g.batch, ksplit), dim3(256), 0, s,
                            g, kchunk);
-    else
+    } else {
         hipLaunchKernelGGL((gemm_kernel<TA, TB, 1, 1>), dim3(tiles, g.batch, ksplit), dim3(64), 0, s,
                            g, kchunk);
+    }
     if (ksplit > 1) {
         const long total = (long)g.M * g.N * g.batch;
         const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
@@ -1071,7 +1161,23 @@ __global__ void mfma_probe_kernel(double* out) {
     }
 }
 
+// The same product on the FP32 matrix core (v_mfma_f32_16x16x4f32); out[256..511]
+// receives the accumulator with the row mapping used by the FP32 GEMM.
+__global__ void mfma_probe_f32_kernel(double* out) {
+    const int lane = threadIdx.x;
+    const int i = lane & 15, k = lane >> 4;
+    const float a = 1.0f + i + 16.0f * k;
+    const float b = 1.0f + 0.5f * k - 0.25f * i;
+    flt4 acc = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    for (int v = 0; v < 4; ++v) {
+        const int row = F32_ROW(lane, v), col = lane & 15;
+        out[256 + row * 16 + col] = acc[v];
+    }
+}
+
 hipError_t mfma_probe(double* out, hipStream_t s) {
+    hipLaunchKernelGGL(mfma_probe_f32_kernel, dim3(1), dim3(64), 0, s, out);
     hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, s, out);
     return hipGetLastError();
 }

@@ -90,7 +90,7 @@ struct Separable {
     std::vector<double> F[3];                     // host copies of unweighted factors n x Q
 };
 
-enum { SITE_Z = 0, SITE_S, SITE_X, SITE_R, SITE_P, SITE_MISC, NSITES };
+enum { SITE_Z = 0, SITE_S, SITE_X, SITE_R, SITE_P, SITE_MISC, SITE_OS, SITE_OR, SITE_OU, NSITES };
 
 struct WarmBasis {
     double* W[3] = {nullptr, nullptr, nullptr};
@@ -109,7 +109,8 @@ struct fc_plan_s {
     double op_err = 0, pc_err = 0;
     Arena arena;
     // workspace
-    Tucker slot[10];
+    Tucker slot[12];
+    fc_precision precision = FC_FP64;
     double *E = nullptr, *Gd[3] = {}, *Mq = nullptr, *c1 = nullptr, *c2 = nullptr;
     double *Xs = nullptr, *HX = nullptr, *Ys = nullptr, *Ts = nullptr, *F = nullptr;
     double *Bp = nullptr, *Ev = nullptr, *Evec = nullptr, *W[3] = {}, *As[3] = {};
@@ -139,6 +140,17 @@ namespace {
 
 using fc::GemmArgs;
 
+// Convergence trace on stderr (ranks and residuals per iteration and per
+// refinement sweep), switched on by the environment variable FC_TRACE.
+const bool g_trace = std::getenv("FC_TRACE") != nullptr;
+#define FC_TRACE_PRINT(...)                         \
+    do {                                            \
+        if (g_trace) {                              \
+            std::fprintf(stderr, "[fc] " __VA_ARGS__); \
+            std::fflush(stderr);                    \
+        }                                           \
+    } while (0)
+
 // Optional timing of every matrix-core GEMM launch with HIP events on the
 // launching stream (for roofline reporting); off unless enabled.
 struct GemmProfile {
@@ -156,13 +168,15 @@ struct Ctx {
     fc_plan_s* p;
     hipStream_t s;
     int n;
+    bool lowp = false;   // bulk contractions on the FP32 matrix cores
 };
 
 void gemm(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
           long lda, const double* B, long ldb, double beta, double* C, long ldc, int batch = 1,
           long sA = 0, long sB = 0, long sC = 0, int inner = 1, long sAi = 0, long sBi = 0,
-          long sCi = 0, const double* d = nullptr, long sD = 0) {
+          long sCi = 0, const double* d = nullptr, long sD = 0, bool bulk = false) {
     GemmArgs g;
+    g.lowp = c.lowp && bulk;
     g.M = M; g.N = N; g.K = K; g.batch = batch; g.inner = inner;
     g.alpha = alpha; g.beta = beta;
     g.A = A; g.lda = lda; g.strideA = sA; g.strideAin = sAi;
@@ -191,6 +205,15 @@ void gemm(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, con
     HIPCHK(fc::gemm(ta, tb, g, c.s));
 }
 
+// bulk contraction: runs on the FP32 matrix cores when the context asks for it
+void gemmb(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+           long lda, const double* B, long ldb, double beta, double* C, long ldc, int batch = 1,
+           long sA = 0, long sB = 0, long sC = 0, int inner = 1, long sAi = 0, long sBi = 0,
+           long sCi = 0) {
+    gemm(c, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, batch, sA, sB, sC, inner, sAi,
+         sBi, sCi, nullptr, 0, true);
+}
+
 void sync(const Ctx& c) { HIPCHK(hipStreamSynchronize(c.s)); }
 
 template <class T>
@@ -209,16 +232,17 @@ void h2d(const Ctx& c, T* dst, const T* src, size_t count) {
 // With transM the stored matrix is r_mode x m and op(M) = M^T.
 void mode_product(const Ctx& c, const double* core, const int r[3], int mode, const double* M,
                   long ldm, int m, double* out, double alpha = 1.0, double beta = 0.0,
-                  bool transM = false) {
+                  bool transM = false, bool bulk = false) {
     if (mode == 0) {
-        gemm(c, transM, false, m, r[1] * r[2], r[0], alpha, M, ldm, core, r[0], beta, out, m);
+        gemm(c, transM, false, m, r[1] * r[2], r[0], alpha, M, ldm, core, r[0], beta, out, m, 1, 0,
+             0, 0, 1, 0, 0, 0, nullptr, 0, bulk);
     } else if (mode == 1) {
         // for each k: (r0 x r1) * op(M)^T (r1 x m)
         gemm(c, false, !transM, r[0], m, r[1], alpha, core, r[0], M, ldm, beta, out, r[0], r[2],
-             (long)r[0] * r[1], 0, (long)r[0] * m);
+             (long)r[0] * r[1], 0, (long)r[0] * m, 1, 0, 0, 0, nullptr, 0, bulk);
     } else {
         gemm(c, false, !transM, r[0] * r[1], m, r[2], alpha, core, (long)r[0] * r[1], M, ldm,
-             beta, out, (long)r[0] * r[1]);
+             beta, out, (long)r[0] * r[1], 1, 0, 0, 0, 1, 0, 0, 0, nullptr, 0, bulk);
     }
 }
 
@@ -337,7 +361,8 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
     for (int l = 0; l < 3; ++l) {
         double* dst = (l == 2) ? out.core : bufs[l & 1];
         // C x_l U_l[:, :r_l]^T
-        mode_product(c, src, cur, l, p->Cvec + (long)l * KM * KM, k[l], r[l], dst, 1.0, 0.0, true);
+        mode_product(c, src, cur, l, p->Cvec + (long)l * KM * KM, k[l], r[l], dst, 1.0, 0.0, true,
+                     true);
         cur[l] = r[l];
         src = dst;
     }
@@ -523,8 +548,8 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
     }
     // exact projection C = sum_t c_t core_t x_l (W_l^T Z_l^t)
     for (int l = 0; l < 3; ++l)
-        gemm(c, true, false, pk[l], k[l], n, 1.0, p->W[l], n, p->Phi[l], n, 0.0, p->Map + (long)l * KM * 256,
-             pk[l]);
+        gemmb(c, true, false, pk[l], k[l], n, 1.0, p->W[l], n, p->Phi[l], n, 0.0,
+              p->Map + (long)l * KM * 256, pk[l]);
     const long Csz = (long)pk[0] * pk[1] * pk[2];
     for (int t = 0; t < m; ++t) {
         const Tucker& T = *terms[t].second;
@@ -535,7 +560,8 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
             const bool last = (l == 2);
             double* dst = last ? p->C : bufs[l & 1];
             mode_product(c, src, cur, l, p->Map + (long)l * KM * 256 + (long)off[t][l] * pk[l], pk[l],
-                         pk[l], dst, last ? terms[t].first : 1.0, (last && t > 0) ? 1.0 : 0.0);
+                         pk[l], dst, last ? terms[t].first : 1.0, (last && t > 0) ? 1.0 : 0.0, false,
+                         true);
             cur[l] = pk[l];
             src = dst;
         }
@@ -618,8 +644,8 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     // 4. projection A_l^q = W_l^T D^q Z_l -> stack (pk*r x Q)
     for (int l = 0; l < 3; ++l) {
         HIPCHK(fc::rowkron(n, pk[l], r[l], p->W[l], n, P.Z[l], n, p->E, c.s));
-        gemm(c, true, false, pk[l] * r[l], Q, n, 1.0, p->E, n, op.D[l], n, 0.0, p->As[l],
-             (long)pk[l] * r[l]);
+        gemmb(c, true, false, pk[l] * r[l], Q, n, 1.0, p->E, n, op.D[l], n, 0.0, p->As[l],
+              (long)pk[l] * r[l]);
     }
     // 5. C = sum_q core x_1 A_0^q x_2 A_1^q x_3 A_2^q
     const long csz = (long)r[0] * r[1] * r[2];
@@ -628,16 +654,16 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     for (long q0 = 0; q0 < Q; q0 += p->qchunk) {
         const int qc = (int)std::min<long>(p->qchunk, Q - q0);
         // T1^q = A_0^q core_(1): (pk0 x r0)(r0 x r1 r2)
-        gemm(c, false, false, pk[0], r[1] * r[2], r[0], 1.0, p->As[0] + q0 * pk[0] * (long)r[0],
-             pk[0], P.core, r[0], 0.0, p->T1, pk[0], qc, (long)pk[0] * r[0], 0, t1sz);
+        gemmb(c, false, false, pk[0], r[1] * r[2], r[0], 1.0, p->As[0] + q0 * pk[0] * (long)r[0],
+              pk[0], P.core, r[0], 0.0, p->T1, pk[0], qc, (long)pk[0] * r[0], 0, t1sz);
         // T2^q = T1^q x_2 A_1^q: batch (q, k)
-        gemm(c, false, true, pk[0], pk[1], r[1], 1.0, p->T1, pk[0],
-             p->As[1] + q0 * pk[1] * (long)r[1], pk[1], 0.0, p->T2, pk[0], qc * r[2], t1sz,
-             (long)pk[1] * r[1], t2sz, r[2], (long)pk[0] * r[1], 0, (long)pk[0] * pk[1]);
+        gemmb(c, false, true, pk[0], pk[1], r[1], 1.0, p->T1, pk[0],
+              p->As[1] + q0 * pk[1] * (long)r[1], pk[1], 0.0, p->T2, pk[0], qc * r[2], t1sz,
+              (long)pk[1] * r[1], t2sz, r[2], (long)pk[0] * r[1], 0, (long)pk[0] * pk[1]);
         // C += [T2^q]_q [A_2^q]_q^T  ((pk0 pk1) x (qc r2)) ((qc r2) x pk2)
-        gemm(c, false, true, pk[0] * pk[1], pk[2], qc * r[2], 1.0, p->T2, (long)pk[0] * pk[1],
-             p->As[2] + q0 * pk[2] * (long)r[2], pk[2], q0 == 0 ? 0.0 : 1.0, p->C,
-             (long)pk[0] * pk[1]);
+        gemmb(c, false, true, pk[0] * pk[1], pk[2], qc * r[2], 1.0, p->T2, (long)pk[0] * pk[1],
+              p->As[2] + q0 * pk[2] * (long)r[2], pk[2], q0 == 0 ? 0.0 : 1.0, p->C,
+              (long)pk[0] * pk[1]);
     }
     const long Csz = (long)pk[0] * pk[1] * pk[2];
     const double n2 = host_dot(c, Csz, p->C, p->C);
@@ -811,7 +837,7 @@ void alloc_workspace(fc_plan_s* p) {
     const long rc = p->rcap, pc = p->pcap;
     const int Q = std::max(p->op.Q, p->pc.Q);
     Arena& A = p->arena;
-    for (int s = 0; s < 10; ++s) {
+    for (int s = 0; s < 12; ++s) {
         for (int l = 0; l < 3; ++l) p->slot[s].Z[l] = A.alloc((size_t)n * rc);
         p->slot[s].core = A.alloc((size_t)rc * rc * rc);
     }
@@ -1036,9 +1062,12 @@ struct SolveOut {
     bool converged = false;
 };
 
-SolveOut pcg(const Ctx& c, const Tucker& Bt, Tucker& Xout) {
+// floor_abs: absolute accuracy to which S and R are resolved (the plain solve
+// uses eps/10 of ||B||; a refinement correction needs no more than the outer
+// solve's absolute level).
+SolveOut pcg(const Ctx& c, const Tucker& Bt, Tucker& Xout, double eps, double tol, int max_iter,
+             double floor_abs, double stop_abs = 0.0) {
     fc_plan_s* p = c.p;
-    const double eps = p->eps;
     Tucker& X = p->slot[1];
     Tucker& R = p->slot[2];
     Tucker& Z = p->slot[3];
@@ -1053,8 +1082,8 @@ SolveOut pcg(const Ctx& c, const Tucker& Bt, Tucker& Xout) {
     had_trunc(c, p->pc, R, eps, 0.0, Z, "Z0 = trunc(precond(R0))", SITE_Z);
     tucker_copy(c, Z, P);                  // P0 = Z0
     double rz = tucker_inner(c, R, Z);
-    for (int k = 0; k < p->max_iter; ++k) {
-        had_trunc(c, p->op, P, eps, 0.1 * eps * bn, S, "S = trunc(fun(P))", SITE_S);
+    for (int k = 0; k < max_iter; ++k) {
+        had_trunc(c, p->op, P, eps, floor_abs, S, "S = trunc(fun(P))", SITE_S);
         const double ps = tucker_inner(c, P, S);
         if (!(ps > 0) || !std::isfinite(ps) || !std::isfinite(rz))
             throw FcError(FC_ERR_NUMERIC, "PCG breakdown: <P,S> = " + std::to_string(ps));
@@ -1063,12 +1092,15 @@ SolveOut pcg(const Ctx& c, const Tucker& Bt, Tucker& Xout) {
         sum_trunc(c, {{1.0, &X}, {ak, &P}}, 0.1 * eps, 0.0, T1, "X = trunc(X + aP)", SITE_X);
         std::swap(X, T1);
         // R = trunc(R - a S)
-        sum_trunc(c, {{1.0, &R}, {-ak, &S}}, 0.1 * eps, 0.1 * eps * bn, T2, "R = trunc(R - aS)", SITE_R);
+        sum_trunc(c, {{1.0, &R}, {-ak, &S}}, 0.1 * eps, floor_abs, T2, "R = trunc(R - aS)", SITE_R);
         std::swap(R, T2);
         so.iterations = k + 1;
         const double rn = std::sqrt(tucker_norm2(c, R));
         so.rel_res = bn > 0 ? rn / bn : 0.0;
-        if (R.empty() || so.rel_res <= p->tol) { so.converged = true; break; }
+        FC_TRACE_PRINT("pcg%s it %d |R|/|B| %.3e ranks X %d,%d,%d R %d,%d,%d S %d,%d,%d P %d,%d,%d\n",
+                       c.lowp ? "(fp32)" : "", k + 1, so.rel_res, X.r[0], X.r[1], X.r[2], R.r[0],
+                       R.r[1], R.r[2], S.r[0], S.r[1], S.r[2], P.r[0], P.r[1], P.r[2]);
+        if (R.empty() || so.rel_res <= tol || rn <= stop_abs) { so.converged = true; break; }
         had_trunc(c, p->pc, R, eps, 0.0, Z, "Z = trunc(precond(R))", SITE_Z);
         const double rzn = tucker_inner(c, R, Z);
         const double bk = rzn / rz;
@@ -1082,6 +1114,84 @@ SolveOut pcg(const Ctx& c, const Tucker& Bt, Tucker& Xout) {
     p->slot[1] = X; p->slot[2] = R; p->slot[3] = Z; p->slot[4] = P; p->slot[5] = S;
     p->slot[6] = T1; p->slot[7] = T2;
     return so;
+}
+
+// Mixed precision: outer FP64 iterative refinement on the true residual
+// B - D~ (.) U (FP64 truncations), inner rank-truncated PCG on D~ C = R with the
+// projection contractions on the FP32 matrix cores and a loose tolerance; the
+// correction is added in FP64.  Subspace searches (whose Rayleigh-Ritz values
+// square the precision), Grams, eigensolves, PCG scalars and the refinement
+// residual stay FP64.  The sweeps stop on the preconditioned residual ratio
+// ||D~_p (.) R|| / ||D~_p (.) B|| <= tol (an error estimate), or when it
+// stagnates.
+SolveOut mixed_solve(const Ctx& c0, const Tucker& Bt, Tucker& Uout, int& sweeps_out) {
+    fc_plan_s* p = c0.p;
+    Ctx cf = c0; cf.lowp = false;
+    Ctx cl = c0; cl.lowp = true;
+    const double eps = p->eps;
+    Tucker& U = p->slot[8];
+    Tucker& Rh = p->slot[9];
+    Tucker& Un = p->slot[10];
+    Tucker& S = p->slot[11];
+    U.r[0] = U.r[1] = U.r[2] = 0;
+    const double bn = std::sqrt(tucker_norm2(cf, Bt));
+    // error estimate: || D~_p (.) R || relative to || D~_p (.) B || (D~_p ~ D~^-1)
+    Tucker& Zh = p->slot[3];
+    had_trunc(cf, p->pc, Bt, 1e-2, 0.0, Zh, "refinement: precond(B)", SITE_Z);
+    const double zbn = std::sqrt(tucker_norm2(cf, Zh));
+    SolveOut total;
+    int sweep = 0;
+    double prev_est = 1e300;
+    for (; sweep < 12; ++sweep) {
+        double est;
+        if (U.empty()) {
+            tucker_copy(cf, Bt, Rh);
+            est = 1.0;
+        } else {
+            had_trunc(cf, p->op, U, 0.1 * eps, 0.1 * eps * bn, S, "refinement: D~ (.) U", SITE_OS);
+            sum_trunc(cf, {{1.0, &Bt}, {-1.0, &S}}, 0.1 * eps, 0.05 * eps * bn, Rh,
+                      "refinement: B - D~ (.) U", SITE_OR);
+            if (Rh.empty()) {
+                est = 0.0;
+            } else {
+                // an estimate: two digits suffice
+                had_trunc(cf, p->pc, Rh, 1e-2, 0.0, Zh, "refinement: precond(R)", SITE_Z);
+                est = std::sqrt(tucker_norm2(cf, Zh)) / zbn;
+            }
+            total.rel_res = Rh.empty() ? 0.0 : std::sqrt(tucker_norm2(cf, Rh)) / bn;
+        }
+        FC_TRACE_PRINT("refine sweep %d est %.3e |R|/|B| %.3e ranks U %d,%d,%d R %d,%d,%d\n", sweep,
+                       est, total.rel_res, U.r[0], U.r[1], U.r[2], Rh.r[0], Rh.r[1], Rh.r[2]);
+        if (est <= p->tol || Rh.empty()) { total.converged = true; break; }
+        if (est > 0.5 * prev_est) {            // stagnation at the truncation floor
+            total.converged = est <= 3.0 * p->tol;
+            break;
+        }
+        prev_est = est;
+        Tucker C;
+        SolveOut in;
+        try {
+            // The correction needs absolute accuracy ~eps ||B|| only: the inner
+            // tolerances (2 eps ||B|| / ||R||, clamped) are relative to ||R|| and
+            // loosen as R shrinks, never below 1e-4, well above the FP32 rounding
+            // of the bulk contractions.
+            const double rhn = std::sqrt(tucker_norm2(cf, Rh));
+            const double ratio = bn / rhn;
+            const double eps_in = std::min(1e-2, std::max(1e-4, 2.0 * eps * ratio));
+            const double tol_in = std::min(1e-1, std::max(1e-3, 2.0 * p->tol * ratio));
+            FC_TRACE_PRINT("refine sweep %d inner eps %.2e tol %.2e\n", sweep, eps_in, tol_in);
+            in = pcg(cl, Rh, C, eps_in, tol_in, p->max_iter, 0.1 * eps_in * rhn);
+        } catch (const FcError& e) {
+            throw FcError(e.status, e.msg + " (refinement sweep " + std::to_string(sweep) + ")");
+        }
+        total.iterations += in.iterations;
+        if (C.empty()) break;
+        sum_trunc(cf, {{1.0, &U}, {1.0, &C}}, 0.1 * eps, 0.0, Un, "refinement: U + C", SITE_OU);
+        std::swap(U, Un);
+    }
+    sweeps_out = sweep;
+    Uout = U;
+    return total;
 }
 
 fc_status guard(const std::function<void()>& fn) {
@@ -1194,7 +1304,8 @@ static fc_status validate_params(const fc_setup_params* prm) {
         return fail(FC_ERR_INVALID_ARG, "negative option");
     if (prm->max_rank > 96) return fail(FC_ERR_INVALID_ARG, "max_rank must be <= 96");
     if (prm->precond_rank > 32) return fail(FC_ERR_INVALID_ARG, "precond_rank must be <= 32");
-    if (prm->precision != FC_FP64) return fail(FC_ERR_INVALID_ARG, "unsupported precision");
+    if (prm->precision != FC_FP64 && prm->precision != FC_MIXED_FP32)
+        return fail(FC_ERR_INVALID_ARG, "unsupported precision");
     return FC_OK;
 }
 
@@ -1207,6 +1318,7 @@ static void apply_defaults(fc_plan_s* p, const fc_setup_params* prm) {
     p->rcap = prm->max_rank > 0 ? prm->max_rank : 96;
     p->pcap = 128;
     p->precond_rank = prm->precond_rank > 0 ? prm->precond_rank : 6;
+    p->precision = prm->precision;
 }
 
 fc_status fc_setup_ex(const fc_setup_params* prm, void* hip_stream, fc_plan* out) {
@@ -1366,10 +1478,14 @@ fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, c
         canon_to_tucker(c, rank_y, w_y, Yc, 1e-2 * p->eps, B, "B = C2T(Y_hat)");
         Tucker X;
         SolveOut so;
+        int sweeps = 0;
         if (B.empty()) {
             so.converged = true;
+        } else if (p->precision == FC_MIXED_FP32) {
+            so = mixed_solve(c, B, X, sweeps);
         } else {
-            so = pcg(c, B, X);
+            const double bn = std::sqrt(tucker_norm2(c, B));
+            so = pcg(c, B, X, p->eps, p->tol, p->max_iter, 0.1 * p->eps * bn);
         }
         // T2C of the result and exit transform U_l = V_l (Z_l coef)
         const double xn2 = X.empty() ? 0.0 : tucker_norm2(c, X);
@@ -1385,6 +1501,7 @@ fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, c
             info->op_rank = p->op.Q;
             info->precond_rank = p->pc.Q;
             info->rel_residual = so.rel_res;
+            info->refinements = sweeps;
             info->op_max_rel_err = p->op_err;
             info->precond_max_rel_err = p->pc_err;
         }
@@ -1501,11 +1618,12 @@ int fc_selftest_eig(int k, const double* A_host, double* evals_host, double* V_h
 
 int fc_selftest_mfma(double* host_out) {
     double* d = nullptr;
-    if (hipMalloc(&d, 256 * sizeof(double)) != hipSuccess) return 1;
-    fc::mfma_probe(d, nullptr);
-    hipMemcpy(host_out, d, 256 * sizeof(double), hipMemcpyDeviceToHost);
-    hipFree(d);
-    return 0;
+    if (hipMalloc(&d, 512 * sizeof(double)) != hipSuccess) return 1;
+    int rc = 0;
+    if (fc::mfma_probe(d, nullptr) != hipSuccess) rc = 2;
+    if (!rc && hipMemcpy(host_out, d, 512 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) rc = 3;
+    (void)hipFree(d);
+    return rc;
 }
 
 }  // extern "C"

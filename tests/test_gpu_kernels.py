@@ -19,13 +19,14 @@ def _gpu():
 def test_mfma_operand_layout():
     import ctypes as C
     from paper_2006_09314_amd._lib import lib
-    out = np.zeros(256)
+    out = np.zeros(512)
     assert lib().fc_selftest_mfma(out.ctypes.data_as(C.POINTER(C.c_double))) == 0
     i = np.arange(16)[:, None]
     k = np.arange(4)[None, :]
     A = 1.0 + i + 16.0 * k
     B = 1.0 + 0.5 * np.arange(4)[:, None] - 0.25 * np.arange(16)[None, :]
-    np.testing.assert_allclose(out.reshape(16, 16), A @ B, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(out[:256].reshape(16, 16), A @ B, rtol=0, atol=1e-12)   # FP64 core
+    np.testing.assert_allclose(out[256:].reshape(16, 16), A @ B, rtol=0, atol=1e-3)    # FP32 core
 
 
 @pytest.mark.parametrize("k,kind", [(1, "rand"), (2, "rand"), (7, "rand"), (64, "psd"),

@@ -152,3 +152,13 @@ def test_batched_matches_single_and_isolates_failures():
     assert [r[3] for r in res2] == ["FC_OK", "FC_OK", "FC_ERR_NUMERIC", "FC_OK"]
     for i in (0, 1, 3):
         assert np.array_equal(host(res2[i][0]), host(res[i][0]))
+
+
+@pytest.mark.parametrize("maker", [lambda: wl.workload_small(),
+                                   lambda: wl.workload_quadratic(n=64, alpha=0.5),
+                                   lambda: wl.workload_sine(n=128, seed=3)])
+def test_mixed_precision_refinement(maker):
+    """FP32 matrix cores inside, FP64 refinement outside: same 10 eps gate."""
+    prob = maker()
+    rep, info, w, U = _check(prob, precision=1)
+    assert info["refinements"] >= 1
