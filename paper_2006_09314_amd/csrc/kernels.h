@@ -79,6 +79,12 @@ hipError_t col_norms(int n, int m, const double* X, long ldx, double* out, hipSt
 hipError_t fill_random(long n, unsigned seed, double* x, hipStream_t s);
 // zero a buffer with a fill kernel (graph-safe)
 hipError_t zero(long n, double* x, hipStream_t s);
+// x[0..n) = v
+hipError_t fill_int(int n, int* x, int v, hipStream_t s);
+// Scale the columns of the three n x K factors (ld) to unit length and
+// multiply w[t] by the product of the three column norms.
+hipError_t normalize_factors(int n, int K, double* U0, double* U1, double* U2, long ld, double* w,
+                             hipStream_t s);
 // copy a column-major m x n block
 hipError_t copy2d(int rows, int cols, const double* src, long lds, double* dst, long ldd,
                   hipStream_t s);
@@ -97,10 +103,11 @@ hipError_t cp_inner_reduce(int ra, int rb, const double* G0, const double* G1, c
 hipError_t mgs_qr(int n, int m, double* Y, double drop, int* count, hipStream_t s);
 
 // Panel step of a blocked Gram-Schmidt: orthonormalise the n x b panel Y
-// (ld n, b <= 32) in place with two-pass MGS; a column whose norm after
-// projection is <= drop * norm0[j] is set to zero and flagged 0 in keep[j].
+// (ld n, b <= 32) in place with `passes`-pass MGS; a column whose norm after
+// projection is <= drop * norm0[j] (norm0 null: drop * 1) is set to zero and
+// flagged 0 in keep[j].
 hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, int* keep,
-                     hipStream_t s);
+                     int passes, hipStream_t s);
 // Move the kept columns (keep[j] != 0) of the n x m matrix Y to the front, in
 // order, and write their number to *count.  tmp: n x m scratch.
 hipError_t compact_cols(int n, int m, double* Y, const int* keep, double* tmp, int* count,

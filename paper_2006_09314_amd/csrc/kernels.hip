@@ -583,15 +583,19 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
         }
     }
     __syncthreads();
-    // re-orthogonalise within clusters of close eigenvalues (descending order):
-    // all dot products of vector i with its cluster predecessors in one sweep
-    // (one wavefront per predecessor), then one subtraction sweep; two passes.
+    // Vectors of clusters of close eigenvalues (descending order) are
+    // re-orthogonalised against ALL their predecessors: inverse iteration
+    // returns nearly parallel vectors inside a cluster, and normalising what
+    // is left after removing the cluster alone would magnify their rounding
+    // components along the other eigenvectors.  All dot products of vector i
+    // with its predecessors in one sweep (one wavefront per predecessor), then
+    // one subtraction sweep; two passes.
     const double lmax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
     {
         const int lane = tid & 63, wv = tid >> 6;
-        int j0 = 0;
+        const int j0 = 0;
         for (int i = 1; i < k; ++i) {
-            if (lam[i - 1] - lam[i] >= 1e-9 * lmax) { j0 = i; continue; }
+            if (lam[i - 1] - lam[i] >= 1e-9 * lmax) continue;
             const int cnt = i - j0;
             for (int pass = 0; pass < 2; ++pass) {
                 for (int c = wv; c < cnt; c += TD_THREADS / 64) {
@@ -901,6 +905,47 @@ hipError_t zero(long n, double* x, hipStream_t s) {
     return hipGetLastError();
 }
 
+// One workgroup per column t: U_l[:, t] /= ||U_l[:, t]|| for l = 0..2 and
+// w[t] *= the product of the three norms.
+__global__ void normalize_factors_kernel(int n, double* U0, double* U1, double* U2, long ld,
+                                         double* w) {
+    __shared__ double red[4];
+    const int t = blockIdx.x, tid = threadIdx.x;
+    double* U[3] = {U0 + (long)t * ld, U1 + (long)t * ld, U2 + (long)t * ld};
+    double prod = 1.0;
+    for (int l = 0; l < 3; ++l) {
+        double s = 0.0;
+        for (int i = tid; i < n; i += 256) s += U[l][i] * U[l][i];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = s;
+        __syncthreads();
+        const double nrm = sqrt(red[0] + red[1] + red[2] + red[3]);
+        __syncthreads();
+        const double f = nrm > 0 ? 1.0 / nrm : 0.0;
+        for (int i = tid; i < n; i += 256) U[l][i] *= f;
+        prod *= nrm;
+    }
+    if (tid == 0) w[t] *= prod;
+}
+
+hipError_t normalize_factors(int n, int K, double* U0, double* U1, double* U2, long ld, double* w,
+                             hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    hipLaunchKernelGGL(normalize_factors_kernel, dim3(K), dim3(256), 0, s, n, U0, U1, U2, ld, w);
+    return hipGetLastError();
+}
+
+__global__ void fill_int_kernel(int n, int* x, int v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = v;
+}
+
+hipError_t fill_int(int n, int* x, int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = std::min((n + 255) / 256, 256);
+    hipLaunchKernelGGL(fill_int_kernel, dim3(blocks), dim3(256), 0, s, n, x, v);
+    return hipGetLastError();
+}
+
 __global__ void copy2d_kernel(int rows, int cols, const double* __restrict__ src, long lds,
                               double* __restrict__ dst, long ldd) {
     const long total = (long)rows * cols;
@@ -1057,7 +1102,7 @@ hipError_t transpose(int rows, int cols, const double* src, long lds, double* ds
 // (one wavefront per column), then subtracted in one sweep.
 __global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, int b, double* Y,
                                                          const double* norm0, double drop,
-                                                         int* keep) {
+                                                         int* keep, int passes) {
     extern __shared__ double P[];   // n x b
     __shared__ double red[32];
     __shared__ double dots[32];
@@ -1067,7 +1112,7 @@ __global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, int b, double* Y
     __syncthreads();
     for (int j = 0; j < b; ++j) {
         double* y = P + (long)j * n;
-        for (int pass = 0; pass < 2; ++pass) {
+        for (int pass = 0; pass < passes; ++pass) {
             if (j > 0) {
                 for (int c = w; c < j; c += 16) {
                     double acc = 0.0;
@@ -1090,7 +1135,7 @@ __global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, int b, double* Y
         double s = 0.0;
         for (int i = tid; i < n; i += 1024) s += y[i] * y[i];
         const double nrm = sqrt(block_sum_1024(s, red));
-        const bool ok = nrm > drop * norm0[j] && nrm > 1e-300;
+        const bool ok = nrm > drop * (norm0 ? norm0[j] : 1.0) && nrm > 1e-300;
         const double f = ok ? 1.0 / nrm : 0.0;
         for (int i = tid; i < n; i += 1024) y[i] *= f;
         if (tid == 0) { kp[j] = ok ? 1 : 0; keep[j] = ok ? 1 : 0; }
@@ -1100,7 +1145,7 @@ __global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, int b, double* Y
 }
 
 hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, int* keep,
-                     hipStream_t s) {
+                     int passes, hipStream_t s) {
     if (b <= 0) return hipSuccess;
     if ((long)n * b * sizeof(double) > 144L * 1024 || b > 32) return hipErrorInvalidValue;
     static std::once_flag once;
@@ -1111,7 +1156,7 @@ hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, 
     });
     if (attr_err != hipSuccess) return attr_err;
     hipLaunchKernelGGL(panel_mgs_kernel, dim3(1), dim3(1024), sizeof(double) * n * b, s, n, b, Y,
-                       norm0, drop, keep);
+                       norm0, drop, keep, passes);
     return hipGetLastError();
 }
 

@@ -267,30 +267,60 @@ double host_dot(const Ctx& c, long n, const double* x, const double* y) {
 // then orthonormalised by a two-pass MGS panel kernel.  Columns whose norm
 // after projection drops below `drop` times their input norm are removed.
 // Returns the number of kept columns (compacted to the front).
-int orthonormalize(const Ctx& c, int m, double* Y, double drop, int slot = 0) {
+// `done` leading columns are already orthonormal and are kept as they are.
+int orthonormalize(const Ctx& c, int m, double* Y, double drop, int done = 0, int slot = 0) {
     fc_plan_s* p = c.p;
     const int n = c.n;
     if (m <= 0) return 0;
+    done = std::max(0, std::min(done, m));
     double* norms = p->qrN;
     int* keep = p->qrKeep;
     HIPCHK(fc::col_norms(n, m, Y, n, norms, c.s));
+    HIPCHK(fc::fill_int(done, keep, 1, c.s));
     // panel width: the panel lives in LDS (<= 144 KiB)
     const int b = std::max(1, std::min(16, (int)((144L * 1024 / 8) / n)));
-    for (int j0 = 0; j0 < m; j0 += b) {
+    // BCGS2: block projection, panel MGS, then a second block projection and
+    // panel pass.  The second round removes what normalising a nearly
+    // dependent column magnified of its rounding components along the earlier
+    // columns; a column with less than half its length left after it was
+    // rounding noise and is dropped.
+    for (int j0 = done; j0 < m; j0 += b) {
         const int bw = std::min(b, m - j0);
         double* P = Y + (long)j0 * n;
         if (j0 > 0) {
-            for (int pass = 0; pass < 2; ++pass) {
-                gemm(c, true, false, j0, bw, n, 1.0, Y, n, P, n, 0.0, p->qrC, j0);
-                gemm(c, false, false, n, bw, j0, -1.0, Y, n, p->qrC, j0, 1.0, P, n);
-            }
+            gemm(c, true, false, j0, bw, n, 1.0, Y, n, P, n, 0.0, p->qrC, j0);
+            gemm(c, false, false, n, bw, j0, -1.0, Y, n, p->qrC, j0, 1.0, P, n);
         }
-        HIPCHK(fc::panel_mgs(n, bw, P, norms + j0, drop, keep + j0, c.s));
+        HIPCHK(fc::panel_mgs(n, bw, P, norms + j0, drop, keep + j0, 2, c.s));
+        if (j0 > 0) {
+            gemm(c, true, false, j0, bw, n, 1.0, Y, n, P, n, 0.0, p->qrC, j0);
+            gemm(c, false, false, n, bw, j0, -1.0, Y, n, p->qrC, j0, 1.0, P, n);
+            HIPCHK(fc::panel_mgs(n, bw, P, nullptr, 0.5, keep + j0, 1, c.s));
+        }
     }
     HIPCHK(fc::compact_cols(n, m, Y, keep, p->qrTmp, p->icount + 4 + slot, c.s));
     int cnt = 0;
     d2h(c, &cnt, p->icount + 4 + slot, 1);
     return cnt;
+}
+
+// Diagnostic (environment variable FC_CHECK): largest deviation of M^T M
+// from the identity for an m x k matrix, printed when above 1e-10.
+const bool g_check = std::getenv("FC_CHECK") != nullptr;
+void check_cols(const Ctx& c, const double* M, long ld, int m, int k, const char* what, int tag) {
+    if (!g_check || k <= 0) return;
+    fc_plan_s* p = c.p;
+    double* G = p->Bp3 + 2L * KM * KM;   // scratch for k <= 128
+    gemm(c, true, false, k, k, m, 1.0, M, ld, M, ld, 0.0, G, k);
+    std::vector<double> g((size_t)k * k);
+    d2h(c, g.data(), G, g.size());
+    double worst = 0;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j)
+            worst = std::max(worst, std::fabs(g[i + (size_t)j * k] - (i == j ? 1.0 : 0.0)));
+    if (worst > 1e-10)
+        std::fprintf(stderr, "[fc] check %s[%d]: max |M^T M - I| = %.3e (%d x %d)\n", what, tag,
+                     worst, m, k);
 }
 
 // ---- HOSVD truncation of a dense core in given bases ----------------------
@@ -327,6 +357,8 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
             J.scratch = p->jac + (long)l * 6 * KM * KM;
         }
         HIPCHK(fc::sym_eig_multi(jobs, c.s));
+        for (int l = 0; l < 3; ++l)
+            check_cols(c, p->Cvec + (long)l * KM * KM, k[l], k[l], k[l], "core eigenvectors", l);
     }
     std::vector<double> ev(3 * KM);
     d2h(c, ev.data(), p->Cev, 3 * KM);
@@ -377,85 +409,117 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
 
 // Dominant subspaces of the three mode Grams H_l (given by `apply`, which
 // writes H_l X to its output), the three modes in lockstep:
-//  * start: the previous basis found at the same place of the iteration (a
-//    warm start, within one solve) padded with random columns, or random
-//    columns alone; orthonormalised;
-//  * power steps (1 from a random start, none from a warm start), each
-//    followed by a rank-revealing orthonormalisation;
+//  * start: the basis found at the same place of the previous iteration (a
+//    warm start, within one solve) padded with 2 * margin random columns, or
+//    kcap random columns; orthonormalised;
+//  * one power step followed by a rank-revealing orthonormalisation;
 //  * Rayleigh-Ritz: eigenpairs of X_l^T H_l X_l in one batched launch, then
 //    W_l = X_l V_l[:, :pk_l] with pk_l = (smallest rank whose Ritz tail is
 //    <= tail_budget) + margin, capped by the numerical rank.
+//  * If a mode's Ritz tail leaves less than `margin` spare columns, its
+//    subspace is enlarged (Ritz vectors plus random columns) and the power
+//    step and Rayleigh-Ritz are repeated for that mode.
 // Returns false if some H_l is zero.
 // span[l] (optional, n x kcap[l]): columns spanning the whole range of H_l;
-// then the start is exactly that span and no power step is needed.
+// then the start is exactly that span and no power step is needed;
+// span_ortho[l] of its leading columns are already orthonormal.
 template <class Apply>
 bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, double tail_budget,
-                    int margin, int pk[3], const double* const* span = nullptr) {
+                    int margin, int pk[3], const double* const* span = nullptr,
+                    const int* span_ortho = nullptr) {
     fc_plan_s* p = c.p;
     const int n = c.n;
-    int kk[3];
     WarmBasis& wb = p->warm[site];
-    const bool warm = wb.valid;
-    bool all_exact = true;
+    int kk[3], have[3], first_cols[3] = {0, 0, 0};
+    bool exact[3], active[3], dropped[3] = {false, false, false};
     for (int l = 0; l < 3; ++l) {
-        kk[l] = kcap[l];
-        int off = 0;
-        if (span && span[l]) {
+        exact[l] = span && span[l];
+        active[l] = true;
+        if (exact[l]) {
+            kk[l] = have[l] = kcap[l];
+            first_cols[l] = span_ortho ? span_ortho[l] : 0;
             HIPCHK(fc::copy2d(n, kk[l], span[l], n, p->Xs3[l], n, c.s));
-            off = kk[l];
+        } else if (wb.valid) {
+            have[l] = std::min(wb.pk[l], kcap[l]);
+            kk[l] = std::min(kcap[l], have[l] + 2 * margin);
+            HIPCHK(fc::copy2d(n, have[l], wb.W[l], n, p->Xs3[l], n, c.s));
         } else {
-            all_exact = false;
-            if (warm) {
-                off = std::min(wb.pk[l], kk[l]);
-                HIPCHK(fc::copy2d(n, off, wb.W[l], n, p->Xs3[l], n, c.s));
-            }
+            have[l] = 0;
+            kk[l] = kcap[l];
         }
-        if (kk[l] > off)
-            HIPCHK(fc::fill_random(n * (long)(kk[l] - off), 1234u + 7u * l + 101u * site,
-                                   p->Xs3[l] + (long)off * n, c.s));
-        kk[l] = orthonormalize(c, kk[l], p->Xs3[l], 1e-13);
-        if (kk[l] == 0) return false;
     }
-    // one power step moves a warm or random start into the range of H_l
-    const int power = all_exact ? 0 : 1;
-    for (int it = 0; it < power; ++it) {
+    std::vector<double> th(3 * KM);
+    for (int round = 0;; ++round) {
         for (int l = 0; l < 3; ++l) {
+            if (!active[l]) continue;
+            if (kk[l] > have[l])
+                HIPCHK(fc::fill_random(n * (long)(kk[l] - have[l]),
+                                       1234u + 7u * l + 101u * site + 7919u * round,
+                                       p->Xs3[l] + (long)have[l] * n, c.s));
+            kk[l] = orthonormalize(c, kk[l], p->Xs3[l], 1e-13, exact[l] ? first_cols[l] : have[l]);
+            if (kk[l] == 0) return false;
+            check_cols(c, p->Xs3[l], n, n, kk[l], "start basis", l);
+            if (exact[l]) continue;
+            // one power step moves the start into the range of H_l
+            const int before = kk[l];
             apply(l, p->Xs3[l], kk[l], p->HX3[l]);
             kk[l] = orthonormalize(c, kk[l], p->HX3[l], 1e-13);
+            dropped[l] = kk[l] < before;
             if (kk[l] == 0) return false;
             std::swap(p->Xs3[l], p->HX3[l]);
+            check_cols(c, p->Xs3[l], n, n, kk[l], "power-step basis", l);
         }
-    }
-    fc::EigJobs jobs;
-    jobs.count = 3;
-    for (int l = 0; l < 3; ++l) {
-        apply(l, p->Xs3[l], kk[l], p->HX3[l]);
-        double* Bl = p->Bp3 + (long)l * KM * KM;
-        gemm(c, true, false, kk[l], kk[l], n, 1.0, p->Xs3[l], n, p->HX3[l], n, 0.0, Bl, kk[l]);
-        fc::EigJob& J = jobs.job[l];
-        J.A = Bl; J.lda = kk[l]; J.k = kk[l];
-        J.evals = p->Ev3 + l * KM; J.V = p->Evec3 + (long)l * KM * KM; J.ldv = kk[l];
-        J.scratch = p->jac + (long)l * 6 * KM * KM;
-    }
-    HIPCHK(fc::sym_eig_multi(jobs, c.s));
-    std::vector<double> th(3 * KM);
-    d2h(c, th.data(), p->Ev3, 3 * KM);
-    for (int l = 0; l < 3; ++l) {
-        double tail = 0;
-        int rr = kk[l];
-        for (int i = kk[l] - 1; i >= 0; --i) {
-            tail += std::max(th[l * KM + i], 0.0);
-            if (tail <= tail_budget) rr = i; else break;
+        fc::EigJobs jobs;
+        jobs.count = 0;
+        for (int l = 0; l < 3; ++l) {
+            if (!active[l]) continue;
+            apply(l, p->Xs3[l], kk[l], p->HX3[l]);
+            double* Bl = p->Bp3 + (long)l * KM * KM;
+            gemm(c, true, false, kk[l], kk[l], n, 1.0, p->Xs3[l], n, p->HX3[l], n, 0.0, Bl, kk[l]);
+            fc::EigJob& J = jobs.job[jobs.count++];
+            J.A = Bl; J.lda = kk[l]; J.k = kk[l];
+            J.evals = p->Ev3 + l * KM; J.V = p->Evec3 + (long)l * KM * KM; J.ldv = kk[l];
+            J.scratch = p->jac + (long)l * 6 * KM * KM;
         }
-        int numrank = 0;
-        const double tmax = std::max(th[l * KM], 0.0);
-        while (numrank < kk[l] && th[l * KM + numrank] > 1e-17 * tmax) ++numrank;
-        const int use = std::min(std::max(numrank, 1), std::max(rr + margin, 1));
-        gemm(c, false, false, n, use, kk[l], 1.0, p->Xs3[l], n, p->Evec3 + (long)l * KM * KM, kk[l],
-             0.0, p->W[l], n);
-        pk[l] = use;
-        HIPCHK(fc::copy2d(n, use, p->W[l], n, wb.W[l], n, c.s));
-        wb.pk[l] = use;
+        HIPCHK(fc::sym_eig_multi(jobs, c.s));
+        d2h(c, th.data(), p->Ev3, 3 * KM);
+        bool again = false;
+        for (int l = 0; l < 3; ++l) {
+            if (!active[l]) continue;
+            double tail = 0;
+            int rr = kk[l];
+            for (int i = kk[l] - 1; i >= 0; --i) {
+                tail += std::max(th[l * KM + i], 0.0);
+                if (tail <= tail_budget) rr = i; else break;
+            }
+            int numrank = 0;
+            const double tmax = std::max(th[l * KM], 0.0);
+            while (numrank < kk[l] && th[l * KM + numrank] > 1e-17 * tmax) ++numrank;
+            const double* Vl = p->Evec3 + (long)l * KM * KM;
+            FC_TRACE_PRINT("subspace site %d round %d mode %d kk %d/%d rr %d numrank %d\n", site,
+                           round, l, kk[l], kcap[l], rr, numrank);
+            // Too few spare columns: restart from all Ritz vectors, enlarged.  Not
+            // when the power step dropped columns: then the subspace already holds
+            // the numerical range of H_l.
+            if (!dropped[l] && !exact[l] && rr + margin > kk[l] && kk[l] < kcap[l] &&
+                numrank == kk[l] && round < 3) {
+                gemm(c, false, false, n, kk[l], kk[l], 1.0, p->Xs3[l], n, Vl, kk[l], 0.0, p->W[l], n);
+                HIPCHK(fc::copy2d(n, kk[l], p->W[l], n, p->Xs3[l], n, c.s));
+                have[l] = kk[l];
+                kk[l] = std::min(kcap[l], std::max(kk[l], rr) + 2 * margin);
+                again = true;
+                continue;
+            }
+            const int use = std::min(std::max(numrank, 1), std::max(rr + margin, 1));
+            check_cols(c, Vl, kk[l], kk[l], kk[l], "Ritz vectors", l);
+            gemm(c, false, false, n, use, kk[l], 1.0, p->Xs3[l], n, Vl, kk[l], 0.0, p->W[l], n);
+            check_cols(c, p->W[l], n, n, use, "subspace W", l);
+            pk[l] = use;
+            HIPCHK(fc::copy2d(n, use, p->W[l], n, wb.W[l], n, c.s));
+            wb.pk[l] = use;
+            active[l] = false;
+        }
+        if (!again) break;
     }
     wb.valid = true;
     return true;
@@ -542,7 +606,9 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
         kcap[l] = std::min({p->pcap, n, k[l]});
         if (k[l] <= p->pcap && k[l] <= n) span[l] = p->Phi[l];   // range(H_l) within span(B_l)
     }
-    if (!find_subspaces(c, site, kcap, apply, thr2 / 6.0, 8, pk, span)) {
+    int span_ortho[3];
+    for (int l = 0; l < 3; ++l) span_ortho[l] = terms[0].second->r[l];
+    if (!find_subspaces(c, site, kcap, apply, thr2 / 6.0, 8, pk, span, span_ortho)) {
         out.r[0] = out.r[1] = out.r[2] = 0;
         return;
     }
@@ -742,6 +808,11 @@ double tucker_norm2(const Ctx& c, const Tucker& A) {
     return host_dot(c, A.csize(), A.core, A.core);
 }
 
+void check_orth(const Ctx& c, const Tucker& T, const char* what) {
+    if (!g_check || T.empty()) return;
+    for (int l = 0; l < 3; ++l) check_cols(c, T.Z[l], c.n, c.n, T.r[l], what, l);
+}
+
 void tucker_copy(const Ctx& c, const Tucker& src, Tucker& dst, double scale = 1.0) {
     for (int l = 0; l < 3; ++l) {
         HIPCHK(fc::copy2d(c.n, src.r[l], src.Z[l], c.n, dst.Z[l], c.n, c.s));
@@ -824,6 +895,8 @@ int tucker_to_canon_out(const Ctx& c, const Tucker& X, double budget2, bool to_g
         gemm(c, false, false, n, K, rr[l], 1.0, Zl, n, p->cf[l], rr[l], 0.0, U[l], n);
     }
     h2d(c, w_u, wh.data(), K);
+    // exact unit columns (the bases are orthonormal only to rounding)
+    HIPCHK(fc::normalize_factors(n, K, U[0], U[1], U[2], n, w_u, c.s));
     sync(c);
     return K;
 }
@@ -1080,19 +1153,23 @@ SolveOut pcg(const Ctx& c, const Tucker& Bt, Tucker& Xout, double eps, double to
     X.r[0] = X.r[1] = X.r[2] = 0;
     tucker_copy(c, Bt, R);                 // R0 = B - fun(X0), X0 = 0
     had_trunc(c, p->pc, R, eps, 0.0, Z, "Z0 = trunc(precond(R0))", SITE_Z);
+    check_orth(c, Z, "Z0");
     tucker_copy(c, Z, P);                  // P0 = Z0
     double rz = tucker_inner(c, R, Z);
     for (int k = 0; k < max_iter; ++k) {
         had_trunc(c, p->op, P, eps, floor_abs, S, "S = trunc(fun(P))", SITE_S);
+        check_orth(c, S, "S");
         const double ps = tucker_inner(c, P, S);
         if (!(ps > 0) || !std::isfinite(ps) || !std::isfinite(rz))
             throw FcError(FC_ERR_NUMERIC, "PCG breakdown: <P,S> = " + std::to_string(ps));
         const double ak = rz / ps;
         // X = trunc(X + a P)
         sum_trunc(c, {{1.0, &X}, {ak, &P}}, 0.1 * eps, 0.0, T1, "X = trunc(X + aP)", SITE_X);
+        check_orth(c, T1, "X");
         std::swap(X, T1);
         // R = trunc(R - a S)
         sum_trunc(c, {{1.0, &R}, {-ak, &S}}, 0.1 * eps, floor_abs, T2, "R = trunc(R - aS)", SITE_R);
+        check_orth(c, T2, "R");
         std::swap(R, T2);
         so.iterations = k + 1;
         const double rn = std::sqrt(tucker_norm2(c, R));
@@ -1102,10 +1179,12 @@ SolveOut pcg(const Ctx& c, const Tucker& Bt, Tucker& Xout, double eps, double to
                        R.r[1], R.r[2], S.r[0], S.r[1], S.r[2], P.r[0], P.r[1], P.r[2]);
         if (R.empty() || so.rel_res <= tol || rn <= stop_abs) { so.converged = true; break; }
         had_trunc(c, p->pc, R, eps, 0.0, Z, "Z = trunc(precond(R))", SITE_Z);
+        check_orth(c, Z, "Z");
         const double rzn = tucker_inner(c, R, Z);
         const double bk = rzn / rz;
         rz = rzn;
         sum_trunc(c, {{1.0, &Z}, {bk, &P}}, eps, 0.0, T1, "P = trunc(Z + bP)", SITE_P);
+        check_orth(c, T1, "P");
         std::swap(P, T1);
         if (P.empty()) { so.converged = true; break; }
     }

@@ -172,6 +172,30 @@ def test_cp_truncate_cancellation():
     assert np.linalg.norm(To - TA) <= 1e-6 * np.linalg.norm(TA) + 1e-10 * np.linalg.norm(wb)
 
 
+def test_cp_truncate_nearly_dependent_columns():
+    """Factors whose second half repeats the first up to 1e-9: the
+    orthonormalisation must keep the bases orthonormal although those
+    columns are nearly dependent (their components along the first half,
+    magnified by normalisation, are removed by the second Gram-Schmidt
+    round)."""
+    import torch
+    from tests.gpu_util import dev, host, plan_for
+    rng = np.random.default_rng(21)
+    n, m = 40, 12
+    A = [rng.standard_normal((n, m)) for _ in range(3)]
+    F = [np.hstack([a, a + 1e-9 * rng.standard_normal((n, m))]) for a in A]
+    w = np.concatenate([rng.uniform(0.5, 1.5, m), rng.uniform(0.5, 1.5, m)])
+    T = ot.cp_full(w, F)
+    plan = plan_for(wl.workload_small(n=n))
+    for eps in (1e-8, 1e-12):
+        wo, O = plan.cp_truncate(torch.from_numpy(w).cuda(), [dev(f) for f in F], eps)
+        To = ot.cp_full(host(wo), [host(o) for o in O])
+        err = np.linalg.norm(To - T) / np.linalg.norm(T)
+        assert err <= eps * (1 + 1e-6) + 1e-14, (eps, err)
+        for o in O:
+            np.testing.assert_allclose(np.linalg.norm(host(o), axis=0), 1.0, rtol=1e-10)
+
+
 @pytest.mark.parametrize("which", [0, 1])
 def test_apply_separable_matches_full_grid(which):
     import torch

@@ -162,3 +162,50 @@ def test_mixed_precision_refinement(maker):
     prob = maker()
     rep, info, w, U = _check(prob, precision=1)
     assert info["refinements"] >= 1
+
+
+# ---- the benchmark configuration: n = 1024 per mode -----------------------
+
+def _sampled_slabs(n, k=8, seed=0):
+    rng = np.random.default_rng(seed)
+    return sorted(set([0, 1, n // 2, n - 1] + list(rng.choice(n, size=k - 4, replace=False))))
+
+
+def test_full_size_sine1024_fp64_sampled():
+    """The benchmark workload (n = 1024, rank-10 design, eps = 1e-6) in FP64,
+    checked against the oracle's exact solution on sampled mode-1 slabs."""
+    prob = wl.workload_sine(n=1024, seed=3)
+    rep, info, w, U = _check(prob, slabs=_sampled_slabs(prob.n))
+    assert info["iterations"] <= 15
+    for u in U:
+        np.testing.assert_allclose(np.linalg.norm(u, axis=0), 1.0, rtol=1e-10)
+
+
+def test_full_size_sine1024_mixed_sampled():
+    prob = wl.workload_sine(n=1024, seed=3)
+    rep, info, w, U = _check(prob, slabs=_sampled_slabs(prob.n, seed=1), precision=1)
+    assert info["refinements"] >= 1
+
+
+def test_full_size_batched_n1024_matches_single():
+    """Concurrent solves of four n = 1024 problems (the batched benchmark's
+    family) equal the single solves bit for bit and pass the oracle gate on
+    sampled slabs."""
+    import torch
+    from paper_2006_09314_amd import api
+    from tests.gpu_util import dev, host, plan_for, solve
+    probs = wl.workload_batched_uniform(count=4, n=1024)
+    plans = [plan_for(p) for p in probs]
+    inputs = [(torch.from_numpy(np.asarray(p.w)).cuda(), [dev(y) for y in p.Y]) for p in probs]
+    res = api.solve_batched(plans, inputs, cap_u=2048)
+    for i, (p, plan, r) in enumerate(zip(probs, plans, res)):
+        w_u, U, info, st = r
+        assert st == "FC_OK"
+        w1, U1, info1 = solve(plan, p)
+        assert np.array_equal(host(w_u), w1)
+        assert all(np.array_equal(host(a), b) for a, b in zip(U, U1))
+        if i in (0, 3):
+            rep = osolve.rel_error(p, w1, U1, slabs=_sampled_slabs(p.n, k=6, seed=i))
+            assert rep["rel_l2"] <= GATE * p.eps, (p.name, rep)
+    for plan in plans:
+        plan.close()
