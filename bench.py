@@ -1,18 +1,24 @@
 #!/usr/bin/env python
 """Throughput of the rank-truncated PCG solve on one MI355X.
 
-A step is one complete solve (Algorithm 1 of the paper with the entry and
-exit transforms and the Tucker-to-canonical output) of the control equation
-(beta A^-alpha + (gamma/beta) A^alpha) u = y for one design function, with the
+A solve is Algorithm 1 of the paper (with the entry and exit transforms and
+the Tucker-to-canonical output) for the control equation
+(beta A^-alpha + (gamma/beta) A^alpha) u = y and one design function, with the
 plan (eigenpairs, separable operator and preconditioner) built beforehand and
-the inputs resident in HBM.  Default workload: n = 1024 per mode,
-a_l(x) = 1 + 0.9 sin(4 pi x + phi_l), rank-10 Gaussian-bump design, alpha = 0.5,
-beta = 1e-4, gamma = 1, eps = 1e-6, FP64.
+the inputs resident in HBM.
 
-Prints one JSON line (rank 0) with the solves/sec, the roofline of the
-dominant kernel (the FP64 matrix-core GEMM, timed with HIP events on its
-stream inside the timed region), the CPU oracle timed on a bounded sample on
-this host, and the oracle error of the last solve on sampled slabs.
+The headline value: a step is one batched call (fc_solve_batched, concurrent
+streams) solving 64 independent problems at n = 1024 per mode,
+a_l(x) = 1 + 0.9 sin(4 pi x + phi_l) with seeded phases, rank-10 Gaussian-bump
+designs, alpha = 0.5, beta = 1e-4, gamma = 1, eps = 1e-6, FP64; value =
+solves/sec over the timed steps.  Also measured: the plain FP64 path one solve
+at a time, the mixed-precision path (single and batched), and a batch of
+uneven sizes (n from 64 to 2048).
+
+Prints one JSON line with the roofline of the dominant kernel (the FP64
+matrix-core GEMM, timed with HIP events on a sampled worker stream inside the
+timed region), the CPU oracle timed on a bounded sample on this host, and the
+oracle error of sampled results.
 """
 from __future__ import annotations
 
@@ -22,6 +28,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -84,136 +92,55 @@ def cpu_baseline(prob, sample_slabs=8):
     }
 
 
-def measure_batched(args, api, torch, dev):
-    """Many independent solves in one fc_solve_batched call (concurrent
-    streams): `batch` problems of the sine family at n = 1024 with seeds
-    100.. (or the uneven-size family), plans built beforehand."""
-    import numpy as np
+def build_plans(api, probs, precision=0, threads=8):
+    """Plans for `probs`, built concurrently on host threads."""
     import threading
-    import workloads as wl
-    from oracle import solve as osolve
-    if args.batch_workload == "mixed":
-        probs = wl.workload_batched(count=args.batch)
-    else:
-        probs = wl.workload_batched_uniform(count=args.batch, n=1024)
-    log(f"[bench] batched: {len(probs)} problems ({args.batch_workload}); building plans ...")
-    t0 = time.perf_counter()
     plans = [None] * len(probs)
+    errors = []
 
     def build(i):
         p = probs[i]
-        plans[i] = api.Plan(p.n, p.a, p.alpha, p.beta, p.gamma, p.eps)
+        try:
+            plans[i] = api.Plan(p.n, p.a, p.alpha, p.beta, p.gamma, p.eps, precision=precision)
+        except Exception as e:  # reported after the join
+            errors.append(e)
 
     idx = list(range(len(probs)))
-    th = []
-    for t in range(8):
-        th.append(threading.Thread(target=lambda t=t: [build(i) for i in idx[t::8]]))
-        th[-1].start()
+    th = [threading.Thread(target=lambda t=t: [build(i) for i in idx[t::threads]])
+          for t in range(threads)]
+    for x in th:
+        x.start()
     for x in th:
         x.join()
-    setup_s = time.perf_counter() - t0
-    log(f"[bench] batched setup {setup_s:.1f}s")
+    if errors:
+        raise errors[0]
+    return plans
+
+
+def batch_io(api, torch, dev, probs, cap):
     inputs = [(torch.from_numpy(np.asarray(p.w)).to(dev),
                [api.to_device_colmajor(y, dev) for y in p.Y]) for p in probs]
-    cap = 1024
     outs = [(torch.empty(cap, dtype=torch.float64, device=dev),
              [torch.empty((cap, p.n), dtype=torch.float64, device=dev).t() for _ in range(3)])
             for p in probs]
-    res = api.solve_batched(plans, inputs, cap_u=cap, outs=outs)     # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.batch_steps):
-        res = api.solve_batched(plans, inputs, cap_u=cap, outs=outs)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    rate = args.batch_steps * len(probs) / el
-    log(f"[bench] batched: {args.batch_steps} x {len(probs)} solves in {el:.2f}s -> {rate:.2f} solves/s")
-    checks = []
-    if not args.no_check:
-        rng = np.random.default_rng(1)
-        for i in [0, len(probs) - 1]:
-            p = probs[i]
-            w_u, U, info, st = res[i]
-            slabs = sorted(set(list(range(8)) + list(rng.choice(p.n, size=8, replace=False))))
-            rep = osolve.rel_error(p, w_u.cpu().numpy(), [u.cpu().numpy() for u in U], slabs=slabs)
-            checks.append({"problem": i, "n": p.n, "rel_l2_sampled": rep["rel_l2"],
-                           "slabs": rep["slabs"], "iterations": info["iterations"],
-                           "pass": bool(rep["rel_l2"] <= 10 * p.eps)})
-        log(f"[bench] batched checks {checks}")
-    for p in plans:
-        p.close()
-    iters = [r[2]["iterations"] for r in res]
-    return {"workload": args.batch_workload, "problems": len(probs), "steps": args.batch_steps,
-            "solves_per_s": rate, "s_per_batch": el / args.batch_steps, "setup_s": setup_s,
-            "streams": int(os.environ.get("FC_BATCH_STREAMS", "8")),
-            "iterations_min_max": [min(iters), max(iters)], "checks": checks}
+    return inputs, outs
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sine1024")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--check-slabs", type=int, default=24)
-    ap.add_argument("--batch", type=int, default=64,
-                    help="problems in the batched measurement (0 disables it)")
-    ap.add_argument("--batch-steps", type=int, default=2)
-    ap.add_argument("--batch-workload", default="sine1024x64")
-    ap.add_argument("--mixed-steps", type=int, default=3)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the method runs on a single device; see the multi-GPU design notes)",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    from paper_2006_09314_amd import api
-    from paper_2006_09314_amd._lib import check, lib
-
-    prob, wname = make_workload(args.workload)
-    log(f"[bench] workload {wname}: n={prob.n} rank_y={prob.rank} alpha={prob.alpha} "
-        f"beta={prob.beta} eps={prob.eps}")
-    torch.cuda.init()
-    dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
-    plan = api.Plan(prob.n, prob.a, prob.alpha, prob.beta, prob.gamma, prob.eps)
-    setup_s = time.perf_counter() - t0
-    log(f"[bench] setup {setup_s:.2f}s")
-    w = torch.from_numpy(np.asarray(prob.w)).to(dev)
-    Y = [api.to_device_colmajor(y, dev) for y in prob.Y]
-    cap = 8192
-    out = (torch.empty(cap, dtype=torch.float64, device=dev),
-           [torch.empty((cap, prob.n), dtype=torch.float64, device=dev).t() for _ in range(3)])
-    info = None
-    for i in range(args.warmup):
-        res = plan.solve(w, Y, cap_u=cap, out=out)
-        info = res[2]
-        log(f"[bench] warmup {i}: {info}")
-    torch.cuda.synchronize()
-    check(lib().fc_profile_gemm(1), "fc_profile_gemm")
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        res = plan.solve(w, Y, cap_u=cap, out=out)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    check(lib().fc_profile_gemm(0), "fc_profile_gemm")
-    info = res[2]
+def gemm_profile(lib, check):
     launches, ms, flops, byts = C.c_long(), C.c_double(), C.c_double(), C.c_double()
-    check(lib().fc_profile_gemm_read(C.byref(launches), C.byref(ms), C.byref(flops), C.byref(byts)),
-          "fc_profile_gemm_read")
-    elapsed = t1 - t0
-    value = args.steps / elapsed
-    log(f"[bench] timed {args.steps} solves in {elapsed:.3f}s -> {value:.2f} solves/s")
+    check(lib().fc_profile_gemm_read(C.byref(launches), C.byref(ms), C.byref(flops),
+                                     C.byref(byts)), "fc_profile_gemm_read")
+    return launches.value, ms.value, flops.value, byts.value
 
-    per_launch_s = (ms.value / 1e3) / max(launches.value, 1)
-    fl_launch = flops.value / max(launches.value, 1)
-    by_launch = byts.value / max(launches.value, 1)
-    ai = flops.value / max(byts.value, 1.0)
+
+def roofline(launches, ms, flops, byts):
+    """Roofline of the FP64 matrix-core GEMM from HIP-event timings: the
+    algorithmic work per launch over the mean launch duration, against the
+    HBM roof when the arithmetic intensity is below the ridge point."""
+    per_launch_s = (ms / 1e3) / max(launches, 1)
+    fl_launch = flops / max(launches, 1)
+    by_launch = byts / max(launches, 1)
+    ai = flops / max(byts, 1.0)
     if ai >= PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
         achieved = fl_launch / per_launch_s / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
@@ -222,54 +149,199 @@ def main():
         achieved = by_launch / per_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof.update({"kernel": "gemm_kernel (FP64 MFMA 16x16x4)", "launches_per_step":
-                 launches.value / args.steps, "avg_launch_us": per_launch_s * 1e6,
+    roof.update({"kernel": "gemm_kernel (FP64 MFMA 16x16x4, all tile variants)",
+                 "launches_timed": launches, "avg_launch_us": per_launch_s * 1e6,
                  "flops_per_launch": fl_launch, "bytes_per_launch": by_launch,
-                 "gemm_share_of_step": (ms.value / 1e3) / elapsed})
+                 "arith_intensity": ai})
+    return roof
 
+
+def sampled_parity(prob, w_u, U, k, seed):
+    from oracle import solve as osolve
+    n = prob.n
+    rng = np.random.default_rng(seed)
+    slabs = sorted(set(list(range(min(k // 2, n))) +
+                       list(rng.choice(n, size=min(n, k - k // 2), replace=False))))
+    rep = osolve.rel_error(prob, w_u.cpu().numpy(), [u.cpu().numpy() for u in U], slabs=slabs)
+    return {"rel_l2_sampled": rep["rel_l2"], "rel_residual_sampled": rep["rel_residual"],
+            "slabs": rep["slabs"], "gate": 10 * prob.eps,
+            "pass": bool(rep["rel_l2"] <= 10 * prob.eps)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2,
+                    help="timed batched steps (one step = one batched call over --batch problems)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--workload", default="sine1024", help="single-solve workload")
+    ap.add_argument("--single-steps", type=int, default=5)
+    ap.add_argument("--mixed-steps", type=int, default=3)
+    ap.add_argument("--no-mixed-batch", action="store_true")
+    ap.add_argument("--uneven", type=int, default=16,
+                    help="problems in the uneven-size batched measurement (0 disables it)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--check-slabs", type=int, default=24)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a "
+                         "known-size reference for hardware byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: each solve "
+              "runs on a single device, and independent problems would be spread over GPUs "
+              "one process per GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as wl
+    from paper_2006_09314_amd import api
+    from paper_2006_09314_amd._lib import check, lib
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    if args.copy_mib > 0:
+        nel = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] reference copy of {args.copy_mib} MiB done")
+        del src, dst
+
+    # ---- FP64, one solve at a time (the plain path) -------------------------
+    prob, wname = make_workload(args.workload)
+    log(f"[bench] single workload {wname}: n={prob.n} rank_y={prob.rank} alpha={prob.alpha} "
+        f"beta={prob.beta} eps={prob.eps}")
+    t0 = time.perf_counter()
+    plan = api.Plan(prob.n, prob.a, prob.alpha, prob.beta, prob.gamma, prob.eps)
+    setup_s = time.perf_counter() - t0
+    w = torch.from_numpy(np.asarray(prob.w)).to(dev)
+    Y = [api.to_device_colmajor(y, dev) for y in prob.Y]
+    cap = 8192
+    out = (torch.empty(cap, dtype=torch.float64, device=dev),
+           [torch.empty((cap, prob.n), dtype=torch.float64, device=dev).t() for _ in range(3)])
+    res = plan.solve(w, Y, cap_u=cap, out=out)
+    log(f"[bench] setup {setup_s:.2f}s; warm-up solve {res[2]}")
+    torch.cuda.synchronize()
+    check(lib().fc_profile_gemm(1), "fc_profile_gemm")
+    t0 = time.perf_counter()
+    for _ in range(args.single_steps):
+        res = plan.solve(w, Y, cap_u=cap, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    check(lib().fc_profile_gemm(0), "fc_profile_gemm")
+    sl, sms, sfl, sby = gemm_profile(lib, check)
+    single = {"solves_per_s": args.single_steps / el, "ms_per_solve": 1e3 * el / args.single_steps,
+              "info": res[2], "gemm_launches_per_solve": sl / args.single_steps,
+              "gemm_share_of_solve": (sms / 1e3) / el}
+    log(f"[bench] FP64 single: {single['solves_per_s']:.2f} solves/s")
+    if not args.no_check:
+        single["parity"] = sampled_parity(prob, res[0], res[1], args.check_slabs, 0)
+        log(f"[bench] FP64 single parity {single['parity']}")
+
+    # ---- mixed precision, one solve at a time --------------------------------
     mixed = None
     if args.mixed_steps > 0:
         mplan = api.Plan(prob.n, prob.a, prob.alpha, prob.beta, prob.gamma, prob.eps, precision=1)
         res_m = mplan.solve(w, Y, cap_u=cap, out=out)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(args.mixed_steps):
+        for _ in range(args.mixed_steps):
             res_m = mplan.solve(w, Y, cap_u=cap, out=out)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        mixed = {"solves_per_s": args.mixed_steps / el, "ms_per_solve": 1e3 * el / args.mixed_steps,
-                 "info": res_m[2]}
+        mixed = {"solves_per_s": args.mixed_steps / el,
+                 "ms_per_solve": 1e3 * el / args.mixed_steps, "info": res_m[2]}
         if not args.no_check:
-            from oracle import solve as osolve
-            rng = np.random.default_rng(2)
-            slabs = sorted(set(list(range(12)) + list(rng.choice(prob.n, size=8, replace=False))))
-            rep = osolve.rel_error(prob, res_m[0].cpu().numpy(), [u.cpu().numpy() for u in res_m[1]],
-                                   slabs=slabs)
-            mixed["rel_l2_sampled"] = rep["rel_l2"]
-            mixed["pass"] = bool(rep["rel_l2"] <= 10 * prob.eps)
-        log(f"[bench] mixed FP32/FP64-refinement: {mixed}")
+            mixed["parity"] = sampled_parity(prob, res_m[0], res_m[1], 20, 2)
+        log(f"[bench] mixed single: {mixed}")
         mplan.close()
+    plan.close()
 
-    batched = None
-    if args.batch > 0:
-        batched = measure_batched(args, api, torch, dev)
-
-    parity = None
+    # ---- batched FP64 at n = 1024: the timed region of the headline value ----
+    probs = wl.workload_batched_uniform(count=args.batch, n=1024)
+    log(f"[bench] batched: {len(probs)} problems at n=1024 (sine family, seeds 100..); "
+        "building plans ...")
+    t0 = time.perf_counter()
+    plans = build_plans(api, probs)
+    bsetup = time.perf_counter() - t0
+    inputs, outs = batch_io(api, torch, dev, probs, 1024)
+    check(lib().fc_profile_gemm(1), "fc_profile_gemm")      # sizes the event pool
+    for _ in range(args.warmup):
+        res_b = api.solve_batched(plans, inputs, cap_u=1024, outs=outs)
+    torch.cuda.synchronize()
+    check(lib().fc_profile_gemm(1), "fc_profile_gemm")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res_b = api.solve_batched(plans, inputs, cap_u=1024, outs=outs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    check(lib().fc_profile_gemm(0), "fc_profile_gemm")
+    roof = roofline(*gemm_profile(lib, check))
+    roof["sampled_stream"] = "first worker stream of the batched call"
+    value = args.steps * len(probs) / elapsed
+    iters = [r[2]["iterations"] for r in res_b]
+    batched = {"problems": len(probs), "setup_s": bsetup, "solves_per_s": value,
+               "streams": int(os.environ.get("FC_BATCH_STREAMS", "8")),
+               "iterations_min_max": [min(iters), max(iters)],
+               "vs_fp64_single": value / single["solves_per_s"]}
+    log(f"[bench] batched FP64: {args.steps} x {len(probs)} solves in {elapsed:.2f}s -> "
+        f"{value:.2f} solves/s")
     if not args.no_check:
-        from oracle import solve as osolve
-        w_u, U, _ = res
-        n = prob.n
-        rng = np.random.default_rng(0)
-        k = min(args.check_slabs, n)
-        slabs = sorted(set(list(range(min(16, k))) + list(rng.choice(n, size=max(0, k - 16),
-                                                                            replace=False))))
+        batched["parity"] = [dict(problem=i, **sampled_parity(probs[i], res_b[i][0], res_b[i][1],
+                                                              16, 10 + i))
+                             for i in (0, len(probs) - 1)]
+        log(f"[bench] batched parity {batched['parity']}")
+    for p_ in plans:
+        p_.close()
+
+    # ---- batched mixed precision on the same problems ------------------------
+    mixed_batched = None
+    if not args.no_mixed_batch:
+        plans = build_plans(api, probs, precision=1)
+        res_mb = api.solve_batched(plans, inputs, cap_u=1024, outs=outs)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rep = osolve.rel_error(prob, w_u.cpu().numpy(), [u.cpu().numpy() for u in U], slabs=slabs)
-        parity = {"rel_l2_sampled": rep["rel_l2"], "rel_residual_sampled": rep["rel_residual"],
-                  "slabs": rep["slabs"], "gate": 10 * prob.eps,
-                  "pass": bool(rep["rel_l2"] <= 10 * prob.eps)}
-        log(f"[bench] oracle check on {rep['slabs']} slabs: {parity} "
-            f"({time.perf_counter() - t0:.1f}s)")
+        for _ in range(args.steps):
+            res_mb = api.solve_batched(plans, inputs, cap_u=1024, outs=outs)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        mixed_batched = {"problems": len(probs), "solves_per_s": args.steps * len(probs) / el,
+                         "refinements_min_max": [min(r[2]["refinements"] for r in res_mb),
+                                                 max(r[2]["refinements"] for r in res_mb)]}
+        if not args.no_check:
+            mixed_batched["parity"] = sampled_parity(probs[0], res_mb[0][0], res_mb[0][1], 16, 20)
+        log(f"[bench] batched mixed: {mixed_batched}")
+        for p_ in plans:
+            p_.close()
+    del inputs, outs
+
+    # ---- batched FP64, uneven sizes and ranks (n in 64..2048) ----------------
+    uneven = None
+    if args.uneven > 0:
+        uprobs = wl.workload_batched(count=args.uneven)
+        plans = build_plans(api, uprobs)
+        uin, uout = batch_io(api, torch, dev, uprobs, 2048)
+        res_u = api.solve_batched(plans, uin, cap_u=2048, outs=uout)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res_u = api.solve_batched(plans, uin, cap_u=2048, outs=uout)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ns = [p.n for p in uprobs]
+        uneven = {"problems": len(uprobs), "n_values": sorted(set(ns)),
+                  "solves_per_s": len(uprobs) / el, "s_per_batch": el}
+        if not args.no_check:
+            big = int(np.argmax(ns))
+            uneven["parity_largest"] = dict(problem=big, n=ns[big], **sampled_parity(
+                uprobs[big], res_u[big][0], res_u[big][1], 8, 30))
+        log(f"[bench] batched uneven: {uneven}")
+        for p_ in plans:
+            p_.close()
+        del uin, uout
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -277,27 +349,20 @@ def main():
         cpu = cpu_baseline(prob)
         log(f"[bench] cpu baseline {cpu}")
 
-    fp64_value = value
-    if batched is not None:
-        value = batched["solves_per_s"]
-        batched["vs_fp64_single"] = value / fp64_value
     rec = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": (f"{args.batch}x sine_n1024_rank10 batched (seeds 100..)"
-                                if batched is not None else wname),
-                   "n": prob.n, "rank_y": prob.rank, "alpha": prob.alpha,
-                   "beta": prob.beta, "gamma": prob.gamma, "eps": prob.eps,
-                   "path": "fp64, concurrent streams" if batched is not None else "fp64",
-                   "setup_s": setup_s},
-        "roofline": roof, "cpu_baseline": cpu, "parity": parity, "solve_info": info,
-        "fp64_single": {"solves_per_s": fp64_value, "ms_per_solve": 1e3 * elapsed / args.steps},
-        "batched": batched, "mixed_single": mixed,
+        "config": {"workload": f"{len(probs)}x sine_n1024_rank10 batched (seeds 100..)",
+                   "step": f"one batched call solving {len(probs)} problems",
+                   "n": 1024, "rank_y": 10, "alpha": 0.5, "beta": 1e-4, "gamma": 1.0,
+                   "eps": 1e-6, "path": "fp64, concurrent streams"},
+        "roofline": roof, "cpu_baseline": cpu,
+        "fp64_single": single, "batched": batched, "mixed_single": mixed,
+        "mixed_batched": mixed_batched, "batched_uneven": uneven,
     }
     print(json.dumps(rec), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

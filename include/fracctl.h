@@ -208,7 +208,10 @@ fc_status fc_host_separable(const fc_setup_params* p, int which, int cap, int* r
 /* Timing of the FP64 matrix-core GEMM kernel (the dominant kernel of the
  * path) for roofline reporting.  fc_profile_gemm(1) clears the counters and
  * brackets every subsequent GEMM launch of the library with a pair of HIP
- * events on its stream; fc_profile_gemm(0) stops recording.
+ * events on its stream (inside fc_solve_batched: the launches of its first
+ * worker stream only, a sample); fc_profile_gemm(0) stops recording.  The
+ * event pool grows as needed and is kept, so a profiled warm-up run sizes it
+ * for a later profiled run.
  * fc_profile_gemm_read waits for the recorded events and returns the launch
  * count, the summed kernel time (ms), and the algorithmic work of those
  * launches: 2 M N K flops and 8 (M K + K N + M N) bytes per GEMM.

@@ -1615,8 +1615,8 @@ fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
         return fail(FC_ERR_HIP, "hipStreamSynchronize failed");
     std::atomic<int> next(0);
     std::vector<std::string> errs(count);
-    auto work = [&]() {
-        t_no_profile = true;
+    auto work = [&](int t) {
+        t_no_profile = (t != 0);   // GEMM timing (when enabled) samples worker 0
         if (hipSetDevice(dev) != hipSuccess) return;
         hipStream_t s = nullptr;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
@@ -1634,7 +1634,7 @@ fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
     };
     for (int i = 0; i < count; ++i) status[i] = FC_ERR_INTERNAL;
     std::vector<std::thread> pool;
-    for (int t = 0; t < workers; ++t) pool.emplace_back(work);
+    for (int t = 0; t < workers; ++t) pool.emplace_back(work, t);
     for (auto& t : pool) t.join();
     fc_status first = FC_OK;
     for (int i = 0; i < count; ++i)
