@@ -16,9 +16,9 @@ at a time, the mixed-precision path (single and batched), and a batch of
 uneven sizes (n from 64 to 2048).
 
 Prints one JSON line with the roofline of the dominant kernel (the FP64
-matrix-core GEMM, timed with HIP events on a sampled worker stream inside the
-timed region), the CPU oracle timed on a bounded sample on this host, and the
-oracle error of sampled results.
+matrix-core GEMM, each launch timed with HIP events on its stream in the
+single-solve timed region), the CPU oracle timed on a bounded sample on this
+host, and the oracle error of sampled results.
 """
 from __future__ import annotations
 
@@ -156,6 +156,26 @@ def roofline(launches, ms, flops, byts):
     return roof
 
 
+def recorded_traffic():
+    """HBM bytes per GEMM launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, if the GEMM source is unchanged since it was taken
+    (the record carries the SHA-256 of the kernel source); else None."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2006_09314_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic-record: "):
+                    rec = json.loads(line[len("traffic-record: "):])
+                    if rec.get("kernel_source_sha256") == digest:
+                        return rec["gemm_hbm_bytes_per_launch"], os.path.basename(path)
+                    return None, f"{os.path.basename(path)} (stale: kernel source changed)"
+    return None, "no counter record"
+
+
 def sampled_parity(prob, w_u, U, k, seed):
     from oracle import solve as osolve
     n = prob.n
@@ -234,6 +254,11 @@ def main():
     el = time.perf_counter() - t0
     check(lib().fc_profile_gemm(0), "fc_profile_gemm")
     sl, sms, sfl, sby = gemm_profile(lib, check)
+    roof = roofline(sl, sms, sfl, sby)
+    roof["measured_in"] = ("FP64 single-solve timed region, one stream (under concurrent streams "
+                           "HIP events time queueing, not kernel duration)")
+    roof["gemm_bytes_per_solve"] = sby / args.single_steps
+    roof["traffic"], roof["traffic_source"] = recorded_traffic()
     single = {"solves_per_s": args.single_steps / el, "ms_per_solve": 1e3 * el / args.single_steps,
               "info": res[2], "gemm_launches_per_solve": sl / args.single_steps,
               "gemm_share_of_solve": (sms / 1e3) / el}
@@ -269,20 +294,18 @@ def main():
     plans = build_plans(api, probs)
     bsetup = time.perf_counter() - t0
     inputs, outs = batch_io(api, torch, dev, probs, 1024)
-    check(lib().fc_profile_gemm(1), "fc_profile_gemm")      # sizes the event pool
     for _ in range(args.warmup):
         res_b = api.solve_batched(plans, inputs, cap_u=1024, outs=outs)
     torch.cuda.synchronize()
-    check(lib().fc_profile_gemm(1), "fc_profile_gemm")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res_b = api.solve_batched(plans, inputs, cap_u=1024, outs=outs)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    check(lib().fc_profile_gemm(0), "fc_profile_gemm")
-    roof = roofline(*gemm_profile(lib, check))
-    roof["sampled_stream"] = "first worker stream of the batched call"
     value = args.steps * len(probs) / elapsed
+    # GEMM bytes moved per second of the batched steps (all streams together),
+    # from the per-solve algorithmic GEMM bytes of the single-solve profile
+    roof["aggregate_gemm_gbs_batched"] = roof["gemm_bytes_per_solve"] * value / 1e9
     iters = [r[2]["iterations"] for r in res_b]
     batched = {"problems": len(probs), "setup_s": bsetup, "solves_per_s": value,
                "streams": int(os.environ.get("FC_BATCH_STREAMS", "8")),
