@@ -490,7 +490,12 @@ bool fit_expsum_nnls(const std::function<double(double)>& h,
     }
     std::vector<double> wl(M, 1.0), coef, colscale(N);
     std::vector<double> A(size_t(M) * N), b(M);
-    for (int round = 0; round < 5; ++round) {
+    // Lawson reweighting rounds; the round with the smallest maximum
+    // relative error on the sample grid is kept (the iteration need not be
+    // monotone on a nearly dependent exponential basis)
+    std::vector<double> best;
+    double best_err = 1e300;
+    for (int round = 0; round < 10; ++round) {
         for (int j = 0; j < N; ++j) {
             double nrm = 0.0;
             for (int i = 0; i < M; ++i) {
@@ -518,11 +523,13 @@ bool fit_expsum_nnls(const std::function<double(double)>& h,
             e[i] = std::fabs(v - hv[i]) / rf[i];
             emax = std::max(emax, e[i]);
         }
+        if (emax < best_err) { best_err = emax; best = coef; }
         if (!(emax > 0)) break;
         for (int i = 0; i < M; ++i) wl[i] *= std::sqrt(std::max(e[i] / emax, 1e-3));
         const double wm = *std::max_element(wl.begin(), wl.end());
         for (double& v : wl) v /= wm;
     }
+    if (!best.empty()) coef = best;
     t.clear(); c.clear(); c0 = 0.0;
     for (int j = 0; j < int(nodes.size()); ++j)
         if (coef[j] > 0) { t.push_back(nodes[j]); c.push_back(coef[j]); }

@@ -41,6 +41,13 @@ def test_quadratic_coefficients(alpha):
     _check(wl.workload_quadratic(n=64, alpha=alpha))
 
 
+@pytest.mark.parametrize("alpha", [0.25, 0.5, 0.75])
+def test_quadratic_n256_full_grid(alpha):
+    """The n = 256 quadratic-coefficient configuration, error over the whole
+    n^3 grid."""
+    _check(wl.workload_quadratic(n=256, alpha=alpha))
+
+
 def test_sine_coefficients_n128():
     _check(wl.workload_sine(n=128, seed=3))
 

@@ -157,6 +157,18 @@ def test_operator_matches_exact_symbol(maker):
     assert err <= max(gate, 1e-14) * 1.05 + 1e-13, (err, gate)
 
 
+@pytest.mark.parametrize("n", [64, 256, 1024])
+@pytest.mark.parametrize("alpha", [0.25, 0.5, 0.75])
+def test_operator_gate_holds_on_the_configurations(n, alpha):
+    """The setup's accuracy gate (max |D~/f - 1| <= eps over the spectrum)
+    holds for the quadratic-coefficient family at every alpha of its
+    configuration and at the sizes the tests and benchmark use."""
+    prob = wl.workload_quadratic(n=n, alpha=alpha)
+    w, F, gate = _host_separable(prob, 0)
+    assert 0 < gate <= prob.eps
+    assert np.all(w > 0)
+
+
 def test_alpha0_operator_is_exact_constant():
     prob = wl.workload_small(n=20)
     prob.alpha = 0.0
