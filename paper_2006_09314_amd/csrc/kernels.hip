@@ -351,61 +351,41 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double
 // ---------------------------------------------------------------------------
 // Dense symmetric eigensolver for k <= 128, one workgroup per matrix:
 //  1. Householder reduction to tridiagonal form in LDS (reflectors kept in
-//     the lower triangle);
-//  2. eigenvalues by bisection on Sturm counts, one eigenvalue per thread;
+//     the lower triangle), four barriers per step;
+//  2. eigenvalues by multisection on Sturm counts: four lanes per
+//     eigenvalue, eight points per step;
 //  3. eigenvectors of the tridiagonal matrix by inverse iteration with a
 //     partially pivoted tridiagonal LU, one vector per thread (factors in a
-//     coalesced global scratch), re-orthogonalised within clusters of close
-//     eigenvalues;
-//  4. back-transformation by the reflectors.
+//     coalesced global scratch);
+//  4. the eigenvectors move to LDS (one padded column each; the reflectors
+//     to global scratch) and vectors of clusters of close eigenvalues are
+//     re-orthogonalised against all their predecessors;
+//  5. back-transformation by the reflectors in LDS.
 // Eigenvalues are returned in descending order.  Eigenvectors belonging to
-// eigenvalues below 1e-17 of the largest in magnitude are not computed
-// accurately (callers do not use them).
+// eigenvalues at most 1e-17 of the largest in magnitude are neither refined
+// nor back-transformed (callers do not use them).  Scratch: 6 k^2 doubles.
 constexpr int TD_THREADS = 512;
 
-__device__ inline double td_block_sum(double v, double* red) {
-    const int tid = threadIdx.x;
+__device__ inline double td_wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((tid & 63) == 0) red[tid >> 6] = v;
-    __syncthreads();
-    if (tid == 0) {
-        double s = 0.0;
-        for (int w = 0; w < TD_THREADS / 64; ++w) s += red[w];
-        red[15] = s;
-    }
-    __syncthreads();
-    const double r = red[15];
-    __syncthreads();
-    return r;
-}
-
-__device__ int sturm_count(int k, const double* d, const double* e, double x, double pivmin) {
-    // number of eigenvalues < x
-    int cnt = 0;
-    double q = d[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    if (q < 0) ++cnt;
-    for (int i = 1; i < k; ++i) {
-        q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        if (q < 0) ++cnt;
-    }
-    return cnt;
+    return __shfl(v, 0, 64);
 }
 
 __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
     extern __shared__ double sm[];
-    __shared__ double red[16];
+    __shared__ double sc[2];
     const EigJob& J = jobs.job[blockIdx.x];
     const int k = J.k;
-    const int tid = threadIdx.x;
-    double* a = sm;              // k x k, ld k
-    double* d = a + k * k;       // diagonal
-    double* e = d + k;           // off-diagonal
-    double* tau = e + k;         // reflector scalars
-    double* vv = tau + k;        // current reflector
-    double* pw = vv + k;         // p / w
-    double* lam = pw + k;        // eigenvalues, descending
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int kp = k + 1;            // padded leading dimension of the eigenvector block
+    double* a = sm;                  // phase 1: the matrix (ld k); phases 4-5: eigenvectors (ld kp)
+    double* d = sm + (long)k * kp;   // diagonal
+    double* e = d + k;               // off-diagonal
+    double* tau = e + k;             // reflector scalars
+    double* vv = tau + k;            // current reflector
+    double* pw = vv + k;             // p / w / dot products
+    double* lam = pw + k;            // eigenvalues, descending
+    double* e2 = lam + k;            // squared off-diagonal
     for (int x = tid; x < k * k; x += blockDim.x) {
         const int i = x % k, j = x / k;
         a[x] = 0.5 * (J.A[i + (long)j * J.lda] + J.A[j + (long)i * J.lda]);
@@ -415,28 +395,32 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
         if (tid == 0) { J.evals[0] = a[0]; J.V[0] = 1.0; }
         return;
     }
-    // 1. tridiagonalisation
+    // 1. tridiagonalisation; the first wavefront forms each reflector and the
+    //    scalar products, so a step costs four barriers
     for (int j = 0; j + 2 < k; ++j) {
         const int m = k - j - 1;
-        double s = 0.0;
-        for (int r = tid; r < m; r += blockDim.x) { const double x = a[(j + 1 + r) + j * k]; s += x * x; }
-        const double nrm2 = td_block_sum(s, red);
-        const double x0 = a[(j + 1) + j * k];
-        const double sub = sqrt(nrm2 - x0 * x0 > 0 ? nrm2 - x0 * x0 : 0.0);
-        if (sub == 0.0) {
-            if (tid == 0) { d[j] = a[j + j * k]; e[j] = x0; tau[j] = 0.0; }
-            __syncthreads();
-            continue;
-        }
-        const double alpha = x0 > 0 ? -sqrt(nrm2) : sqrt(nrm2);
-        const double v0 = x0 - alpha;
-        const double t = -v0 / alpha;
-        for (int r = tid; r < m; r += blockDim.x) {
-            const double v = (r == 0) ? 1.0 : a[(j + 1 + r) + j * k] / v0;
-            vv[r] = v;
-            a[(j + 1 + r) + j * k] = v;     // keep the reflector
+        if (wv == 0) {
+            double s = 0.0;
+            for (int r = lane; r < m; r += 64) { const double x = a[(j + 1 + r) + j * k]; s += x * x; }
+            const double nrm2 = td_wave_sum(s);
+            const double x0 = a[(j + 1) + j * k];
+            const double sub = sqrt(nrm2 - x0 * x0 > 0 ? nrm2 - x0 * x0 : 0.0);
+            if (sub == 0.0) {
+                if (lane == 0) { d[j] = a[j + j * k]; e[j] = x0; tau[j] = 0.0; sc[j & 1] = 0.0; }
+            } else {
+                const double alpha = x0 > 0 ? -sqrt(nrm2) : sqrt(nrm2);
+                const double v0 = x0 - alpha;
+                for (int r = lane; r < m; r += 64) {
+                    const double v = (r == 0) ? 1.0 : a[(j + 1 + r) + j * k] / v0;
+                    vv[r] = v;
+                    a[(j + 1 + r) + j * k] = v;     // keep the reflector
+                }
+                if (lane == 0) { d[j] = a[j + j * k]; e[j] = alpha; tau[j] = -v0 / alpha; sc[j & 1] = -v0 / alpha; }
+            }
         }
         __syncthreads();
+        const double t = sc[j & 1];
+        if (t == 0.0) continue;
         // p = t * A22 v, four threads per row
         for (int base = 0; base < 4 * m; base += blockDim.x) {
             const int x = base + tid;
@@ -449,16 +433,17 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
             if (r < m && part == 0) pw[r] = t * acc;
         }
         __syncthreads();
-        double sp = 0.0;
-        for (int r = tid; r < m; r += blockDim.x) sp += vv[r] * pw[r];
-        const double K = 0.5 * t * td_block_sum(sp, red);
-        for (int r = tid; r < m; r += blockDim.x) pw[r] -= K * vv[r];
+        if (wv == 0) {
+            double sp = 0.0;
+            for (int r = lane; r < m; r += 64) sp += vv[r] * pw[r];
+            const double K = 0.5 * t * td_wave_sum(sp);
+            for (int r = lane; r < m; r += 64) pw[r] -= K * vv[r];
+        }
         __syncthreads();
         for (int x = tid; x < m * m; x += blockDim.x) {
             const int r = x % m, c = x / m;
             a[(j + 1 + r) + (j + 1 + c) * k] -= vv[r] * pw[c] + pw[r] * vv[c];
         }
-        if (tid == 0) { d[j] = a[j + j * k]; e[j] = alpha; tau[j] = t; }
         __syncthreads();
     }
     if (tid == 0) {
@@ -468,7 +453,12 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
         tau[k - 2] = 0.0;
     }
     __syncthreads();
-    // 2. eigenvalues by bisection (thread i: i-th largest)
+    for (int i = tid; i + 1 < k; i += blockDim.x) e2[i] = e[i] * e[i];
+    __syncthreads();
+    // 2. eigenvalues by multisection: four lanes per eigenvalue, each
+    //    evaluating Sturm counts at two of eight interior points (two
+    //    independent recurrences per lane), so every step shrinks the bracket
+    //    nine-fold
     double lo = 0.0, hi = 0.0, tnorm = 0.0;
     for (int i = 0; i < k; ++i) {
         const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < k ? fabs(e[i]) : 0.0);
@@ -477,14 +467,42 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
     }
     tnorm = fmax(fabs(lo), fabs(hi));
     const double pivmin = fmax(1e-300, 1e-30 * tnorm * tnorm);
-    if (tid < k) {
-        const int want = k - 1 - tid;   // number of eigenvalues below the target
+    {
+        const int grp = tid >> 2, q = tid & 3;
+        const bool act = grp < k;
+        const int want = k - 1 - grp;   // number of eigenvalues below the target
         double l = lo - 1e-14 * tnorm - 1e-300, h = hi + 1e-14 * tnorm + 1e-300;
-        for (int it = 0; it < 64; ++it) {
-            const double mid = 0.5 * (l + h);
-            if (sturm_count(k, d, e, mid, pivmin) > want) h = mid; else l = mid;
+        for (int it = 0; it < 18; ++it) {   // 9^-18 of 2 |T| is below 1e-16 |T|
+            const double w = (h - l) / 9.0;
+            const double x1 = l + w * (2 * q + 1), x2 = l + w * (2 * q + 2);
+            int c1 = 0, c2 = 0;
+            if (act) {
+                double qa = d[0] - x1, qb = d[0] - x2;
+                if (fabs(qa) < pivmin) qa = -pivmin;
+                if (fabs(qb) < pivmin) qb = -pivmin;
+                c1 = qa < 0;
+                c2 = qb < 0;
+                for (int i = 1; i < k; ++i) {
+                    const double di = d[i], ee = e2[i - 1];
+                    qa = (di - x1) - ee / qa;
+                    qb = (di - x2) - ee / qb;
+                    if (fabs(qa) < pivmin) qa = -pivmin;
+                    if (fabs(qb) < pivmin) qb = -pivmin;
+                    c1 += qa < 0;
+                    c2 += qb < 0;
+                }
+            }
+            // Sturm counts are monotone in x: the first z of the eight points
+            // have at most `want` eigenvalues below them
+            int z = (c1 <= want) + (c2 <= want);
+            z += __shfl_xor(z, 1, 64);
+            z += __shfl_xor(z, 2, 64);
+            const double nl = (z == 0) ? l : l + w * z;
+            const double nh = (z == 8) ? h : l + w * (z + 1);
+            l = nl;
+            h = nh;
         }
-        lam[tid] = 0.5 * (l + h);
+        if (act && q == 0) lam[grp] = 0.5 * (l + h);
     }
     __syncthreads();
     // 3. inverse iteration, thread i owns eigenvector i (coalesced scratch)
@@ -583,61 +601,80 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
         }
     }
     __syncthreads();
-    // Vectors of clusters of close eigenvalues (descending order) are
-    // re-orthogonalised against ALL their predecessors: inverse iteration
-    // returns nearly parallel vectors inside a cluster, and normalising what
-    // is left after removing the cluster alone would magnify their rounding
-    // components along the other eigenvectors.  All dot products of vector i
-    // with its predecessors in one sweep (one wavefront per predecessor), then
-    // one subtraction sweep; two passes.
-    const double lmax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
-    {
-        const int lane = tid & 63, wv = tid >> 6;
-        const int j0 = 0;
-        for (int i = 1; i < k; ++i) {
-            if (lam[i - 1] - lam[i] >= 1e-9 * lmax) continue;
-            const int cnt = i - j0;
-            for (int pass = 0; pass < 2; ++pass) {
-                for (int c = wv; c < cnt; c += TD_THREADS / 64) {
-                    double acc = 0.0;
-                    for (int r = lane; r < k; r += 64)
-                        acc += X[(j0 + c) + (long)r * k] * X[i + (long)r * k];
-                    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-                    if (lane == 0) pw[c] = acc;
-                }
-                __syncthreads();
-                for (int r = tid; r < k; r += blockDim.x) {
-                    double v = X[i + (long)r * k];
-                    for (int c = 0; c < cnt; ++c) v -= pw[c] * X[(j0 + c) + (long)r * k];
-                    X[i + (long)r * k] = v;
-                }
-                __syncthreads();
-            }
-            double s3 = 0.0;
-            for (int r = tid; r < k; r += blockDim.x) s3 += X[i + (long)r * k] * X[i + (long)r * k];
-            const double nn = sqrt(td_block_sum(s3, red));
-            for (int r = tid; r < k; r += blockDim.x) X[i + (long)r * k] *= (nn > 0 ? 1.0 / nn : 0.0);
-            __syncthreads();
-        }
-    }
-    // 4. back-transformation: V = H_0 ... H_{k-3} X; reflector j acts on rows j+1..k-1
+    // The reflectors move to global scratch (the LU factors are no longer
+    // needed) and the eigenvectors of T into LDS, one contiguous column per
+    // vector (ld kp).
+    double* Rf = U0;
+    for (int x = tid; x < k * k; x += blockDim.x) Rf[x] = a[x];
+    __syncthreads();
+    double* Xl = a;
     for (int x = tid; x < k * k; x += blockDim.x) {
-        const int r = x % k, i = x / k;
-        J.V[r + (long)i * J.ldv] = X[i + (long)r * k];
+        const int i = x % k, j = x / k;
+        Xl[j + (long)i * kp] = X[i + (long)j * k];
     }
     __syncthreads();
+    // 4. Vectors of clusters of close eigenvalues (descending order) are
+    //    re-orthogonalised against ALL their predecessors: inverse iteration
+    //    returns nearly parallel vectors inside a cluster, and normalising what
+    //    is left after removing the cluster alone would magnify their rounding
+    //    components along the other eigenvectors.  Dot products one wavefront
+    //    per predecessor, one subtraction sweep, two passes, then normalise.
+    //    Vectors of eigenvalues at most 1e-17 of the largest in magnitude are
+    //    not refined (callers never use them) and are skipped as predecessors.
+    const double lmax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
+    double* used = e2;   // no longer needed: 1 for a vector that is refined
+    for (int i = tid; i < k; i += blockDim.x) used[i] = fabs(lam[i]) > 1e-17 * lmax ? 1.0 : 0.0;
+    __syncthreads();
+    for (int i = 1; i < k; ++i) {
+        if (used[i] == 0.0 || lam[i - 1] - lam[i] >= 1e-9 * lmax) continue;
+        double* xi = Xl + (long)i * kp;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int c = wv; c < i; c += TD_THREADS / 64) {
+                const double* xc = Xl + (long)c * kp;
+                double acc = 0.0;
+                for (int r = lane; r < k; r += 64) acc += xc[r] * xi[r];
+                acc = td_wave_sum(acc);
+                if (lane == 0) pw[c] = acc * used[c];
+            }
+            __syncthreads();
+            // four threads per row, each over a quarter of the predecessors
+            for (int base = 0; base < 4 * k; base += blockDim.x) {
+                const int x = base + tid;
+                const int r = x >> 2, part = x & 3;
+                double acc = 0.0;
+                if (r < k)
+                    for (int c = part; c < i; c += 4) acc += pw[c] * Xl[r + (long)c * kp];
+                acc += __shfl_xor(acc, 1, 64);
+                acc += __shfl_xor(acc, 2, 64);
+                if (r < k && part == 0) xi[r] -= acc;
+            }
+            __syncthreads();
+        }
+        if (wv == 0) {
+            double s3 = 0.0;
+            for (int r = lane; r < k; r += 64) s3 += xi[r] * xi[r];
+            const double nn = sqrt(td_wave_sum(s3));
+            const double f = nn > 0 ? 1.0 / nn : 0.0;
+            for (int r = lane; r < k; r += 64) xi[r] *= f;
+        }
+        __syncthreads();
+    }
+    // 5. back-transformation in LDS: V = H_0 ... H_{k-3} X; reflector j acts
+    //    on rows j+1..k-1
     for (int j = k - 3; j >= 0; --j) {
         const double t = tau[j];
         if (t == 0.0) continue;
         const int m = k - j - 1;
+        for (int r = tid; r < m; r += blockDim.x) vv[r] = Rf[(j + 1 + r) + j * k];
+        __syncthreads();
         // s_i = t * v^T V[j+1:, i], four threads per column
         for (int base = 0; base < 4 * k; base += blockDim.x) {
             const int x = base + tid;
             const int i = x >> 2, part = x & 3;
             double acc = 0.0;
-            if (i < k) {
-                const double* col = J.V + (long)i * J.ldv + (j + 1);
-                for (int r = part; r < m; r += 4) acc += a[(j + 1 + r) + j * k] * col[r];
+            if (i < k && used[i] != 0.0) {
+                const double* col = Xl + (long)i * kp + (j + 1);
+                for (int r = part; r < m; r += 4) acc += vv[r] * col[r];
             }
             acc += __shfl_xor(acc, 1, 64);
             acc += __shfl_xor(acc, 2, 64);
@@ -646,9 +683,13 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
         __syncthreads();
         for (int x = tid; x < m * k; x += blockDim.x) {
             const int r = x % m, i = x / m;
-            J.V[(j + 1 + r) + (long)i * J.ldv] -= pw[i] * a[(j + 1 + r) + j * k];
+            Xl[(j + 1 + r) + (long)i * kp] -= pw[i] * vv[r];
         }
         __syncthreads();
+    }
+    for (int x = tid; x < k * k; x += blockDim.x) {
+        const int r = x % k, i = x / k;
+        J.V[r + (long)i * J.ldv] = Xl[r + (long)i * kp];
     }
     for (int i = tid; i < k; i += blockDim.x) J.evals[i] = lam[i];
 }
@@ -670,7 +711,7 @@ hipError_t sym_eig_multi(const EigJobs& jobs, hipStream_t s) {
     if (attr_err != hipSuccess) return attr_err;
     (void)kp;
     hipLaunchKernelGGL(tdeig_kernel, dim3(jobs.count), dim3(TD_THREADS),
-                       sizeof(double) * ((size_t)kmax * kmax + 6 * kmax), s, jobs);
+                       sizeof(double) * ((size_t)kmax * (kmax + 1) + 7 * kmax), s, jobs);
     return hipGetLastError();
 }
 

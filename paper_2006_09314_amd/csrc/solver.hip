@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -133,6 +134,8 @@ struct fc_plan_s {
     hipStream_t stream = nullptr;
     // statistics of the last solve
     int max_seen_rank = 0;
+    double site_ms[16] = {};   // wall time per truncation site (with FC_TRACE)
+    int site_calls[16] = {};
     std::mutex use_mu;   // one solve at a time per plan
 };
 
@@ -153,9 +156,15 @@ const bool g_trace = std::getenv("FC_TRACE") != nullptr;
 
 // Optional timing of every matrix-core GEMM launch with HIP events on the
 // launching stream (for roofline reporting); off unless enabled.
+struct GemmShape {
+    bool ta, tb;
+    int M, N, K, batch, inner;
+    bool lowp;
+};
 struct GemmProfile {
     bool on = false;
     std::vector<hipEvent_t> ev;   // pairs
+    std::vector<GemmShape> shapes;
     size_t used = 0;
     double flops = 0, bytes = 0;
     long launches = 0;
@@ -197,6 +206,7 @@ void gemm(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, con
         HIPCHK(fc::gemm(ta, tb, g, c.s));
         HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], c.s));
         g_prof.used += 2;
+        g_prof.shapes.push_back({ta, tb, M, N, K, batch, inner, g.lowp});
         g_prof.flops += 2.0 * M * N * (double)K * batch;
         g_prof.bytes += 8.0 * ((double)M * K + (double)K * N + (double)M * N) * batch;
         g_prof.launches += 1;
@@ -215,6 +225,27 @@ void gemmb(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, co
 }
 
 void sync(const Ctx& c) { HIPCHK(hipStreamSynchronize(c.s)); }
+
+// With FC_TRACE: wall time of one truncation, stream drained at both ends.
+struct SiteClock {
+    const Ctx& c;
+    int site;
+    std::chrono::steady_clock::time_point t0;
+    SiteClock(const Ctx& c_, int site_) : c(c_), site(site_) {
+        if (g_trace) {
+            (void)hipStreamSynchronize(c.s);
+            t0 = std::chrono::steady_clock::now();
+        }
+    }
+    ~SiteClock() {
+        if (!g_trace) return;
+        (void)hipStreamSynchronize(c.s);
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        c.p->site_ms[site] += ms;
+        c.p->site_calls[site] += 1;
+    }
+};
 
 template <class T>
 void d2h(const Ctx& c, T* dst, const T* src, size_t count) {
@@ -536,6 +567,7 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
 // known and charged to the tolerance.
 void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>& terms_in,
                double tol_rel, double floor_abs, Tucker& out, const char* what, int site) {
+    SiteClock clock(c, site);
     fc_plan_s* p = c.p;
     const int n = c.n;
     std::vector<std::pair<double, const Tucker*>> terms;
@@ -645,6 +677,7 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
 // exact projection of T onto it, then HOSVD of the projected core.
 void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_rel,
                double floor_abs, Tucker& out, const char* what, int site) {
+    SiteClock clock(c, site);
     fc_plan_s* p = c.p;
     const int n = c.n;
     const int Q = op.Q;
@@ -1538,6 +1571,8 @@ fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, c
     fc_status result = FC_OK;
     p->max_seen_rank = 0;
     reset_warm(p);
+    for (int i = 0; i < 16; ++i) { p->site_ms[i] = 0; p->site_calls[i] = 0; }
+    const auto t_solve = std::chrono::steady_clock::now();
     fc_status st = guard([&] {
         // NaN guard on the input
         static const int zero_flag = 0;
@@ -1586,6 +1621,19 @@ fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, c
         }
         if (K > cap_u) result = fail(FC_ERR_RANK_OVERFLOW, "result rank exceeds cap_u");
         else if (!so.converged) result = fail(FC_ERR_NOT_CONVERGED, "max_iter reached");
+        if (g_trace) {
+            sync(c);
+            const double tot = std::chrono::duration<double, std::milli>(
+                                   std::chrono::steady_clock::now() - t_solve).count();
+            static const char* names[NSITES] = {"Z", "S", "X", "R", "P", "misc", "ref-S", "ref-R",
+                                                "ref-U"};
+            std::string line = "[fc] solve " + std::to_string(tot) + " ms; truncations:";
+            for (int i = 0; i < NSITES; ++i)
+                if (p->site_calls[i])
+                    line += std::string(" ") + names[i] + " " + std::to_string(p->site_calls[i]) +
+                            "x " + std::to_string(p->site_ms[i]) + " ms;";
+            std::fprintf(stderr, "%s\n", line.c_str());
+        }
     });
     return st != FC_OK ? st : result;
 }
@@ -1649,6 +1697,7 @@ fc_status fc_profile_gemm(int enable) {
     if (enable) {
         g_prof.on = true;
         g_prof.used = 0;
+        g_prof.shapes.clear();
         g_prof.flops = g_prof.bytes = 0;
         g_prof.launches = 0;
     } else {
@@ -1667,6 +1716,20 @@ fc_status fc_profile_gemm_read(long* launches, double* total_ms, double* flops, 
         if (hipEventElapsedTime(&t, g_prof.ev[i], g_prof.ev[i + 1]) != hipSuccess)
             return fail(FC_ERR_HIP, "hipEventElapsedTime failed");
         ms += t;
+    }
+    // diagnostic: per-launch shapes and times as CSV (environment FC_GEMMLOG = path)
+    if (const char* path = std::getenv("FC_GEMMLOG")) {
+        if (FILE* f = std::fopen(path, "w")) {
+            std::fprintf(f, "ta,tb,M,N,K,batch,inner,lowp,us\n");
+            for (size_t i = 0; i + 1 < g_prof.used && i / 2 < g_prof.shapes.size(); i += 2) {
+                float t = 0;
+                (void)hipEventElapsedTime(&t, g_prof.ev[i], g_prof.ev[i + 1]);
+                const GemmShape& g = g_prof.shapes[i / 2];
+                std::fprintf(f, "%d,%d,%d,%d,%d,%d,%d,%d,%.2f\n", g.ta, g.tb, g.M, g.N, g.K, g.batch,
+                             g.inner, g.lowp, 1000.0 * t);
+            }
+            std::fclose(f);
+        }
     }
     *launches = g_prof.launches;
     *total_ms = ms;
