@@ -163,3 +163,68 @@ def rel_error(prob, w_u: np.ndarray, U_u: Sequence[np.ndarray], sp: Optional[Spe
                       rel_residual=float(np.sqrt(rnum / rden)) if rden > 0 else float("nan"),
                       slabs=len(idx), n=n)
     return rep
+
+
+# ---- state recovery and the cost functional (Section 3.1) -----------------
+#
+# The state equation y = beta A^-alpha u (eqn `State`) is diagonal in the
+# tensor eigenbasis with the symbol f_state(s) = beta s^-alpha.  The discrete
+# cost functional of Section 3.1 with the finite-difference mass matrix M = I
+# is J(y, u) = 1/2 ||y - y_Omega||^2 + gamma/2 ||u||^2 (Euclidean norms,
+# Section 2); the control equation (1) is its stationarity condition after
+# eliminating y, so J is smallest at the exact control.
+
+def cost_full(prob, u: np.ndarray, y: np.ndarray) -> float:
+    """J(y, u) on the full grid."""
+    from .tensor import cp_full
+    yom = cp_full(prob.w, prob.Y)
+    return 0.5 * float(np.sum((y - yom) ** 2)) + 0.5 * prob.gamma * float(np.sum(u * u))
+
+
+def cost_from_factors(prob, w_u, U_u: Sequence[np.ndarray], w_y, Y_y: Sequence[np.ndarray]) -> float:
+    """J(y, u) for canonical u and y, from canonical inner products only
+    (Appendix 1): ||y - y_Omega||^2 = <y,y> - 2 <y,y_Omega> + <y_Omega,y_Omega>."""
+    from .tensor import cp_inner
+    yy = cp_inner(w_y, Y_y, w_y, Y_y)
+    yo = cp_inner(w_y, Y_y, prob.w, prob.Y)
+    oo = cp_inner(prob.w, prob.Y, prob.w, prob.Y)
+    uu = cp_inner(w_u, U_u, w_u, U_u)
+    return 0.5 * (yy - 2.0 * yo + oo) + 0.5 * prob.gamma * uu
+
+
+def state_rel_error(prob, w_y: np.ndarray, Y_y: Sequence[np.ndarray],
+                    sp: Optional[Spectral] = None, slabs: Optional[Iterable[int]] = None,
+                    block: int = 8) -> ErrorReport:
+    """Relative L2 error of a canonical candidate state y against the exact
+    state beta A^-alpha u* of the exact control u* (eigen-coordinates, slab by
+    slab; with `slabs` a sampled estimate)."""
+    sp = sp or Spectral(prob)
+    n = prob.n
+    Yy = sp.to_eig(Y_y)
+    w_y = np.asarray(w_y, dtype=np.float64)
+    idx = sorted(set(int(i) for i in slabs)) if slabs is not None else list(range(n))
+    num = den = 0.0
+    for i0 in idx:
+        i1 = i0 + 1
+        D = sp.D_block(i0, i1)
+        s = (sp.lam[0][i0:i1, None, None] + sp.lam[1][None, :, None]
+             + sp.lam[2][None, None, :])
+        Ex = f_state(s, prob.alpha, prob.beta) * cp_block(prob.w, sp.Yh, i0, i1) / D
+        Yb = cp_block(w_y, Yy, i0, i1)
+        num += float(np.sum((Yb - Ex) ** 2))
+        den += float(np.sum(Ex ** 2))
+    return ErrorReport(rel_l2=float(np.sqrt(num / den)) if den > 0 else float("nan"),
+                       slabs=len(idx), n=n)
+
+
+def optimal_cost(prob, sp: Optional[Spectral] = None) -> float:
+    """J at the exact control, evaluated on the full grid in eigen-coordinates
+    (small and moderate n)."""
+    sp = sp or Spectral(prob)
+    n = prob.n
+    s = (sp.lam[0][:, None, None] + sp.lam[1][None, :, None] + sp.lam[2][None, None, :])
+    Yh = cp_block(prob.w, sp.Yh, 0, n)
+    Uh = Yh / f_control(s, prob.alpha, prob.beta, prob.gamma)
+    Yst = f_state(s, prob.alpha, prob.beta) * Uh
+    return 0.5 * float(np.sum((Yst - Yh) ** 2)) + 0.5 * prob.gamma * float(np.sum(Uh * Uh))
+

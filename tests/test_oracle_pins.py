@@ -12,7 +12,11 @@ by mathematics, never against itself.
 * an eigenvector-triple design function (rank-1 exact solution);
 * symmetry, positivity and linearity of the solution operator;
 * the canonical-format definitions (Appendix 1) against full-grid evaluation;
-* the slab-streamed error evaluator against a full-grid evaluation.
+* the slab-streamed error evaluator against a full-grid evaluation;
+* the state and the cost functional: hand-solved n = 1 values, the dense
+  matrix function, and the optimality of the exact control (J is stationary
+  there, its second variation is the quadratic form of the problem, and
+  J* = 1/2 <y_Omega, y_Omega - y*>).
 """
 import os
 
@@ -261,3 +265,79 @@ def test_workload_shapes_and_determinism():
     assert len(b) == 8 and all(1 <= x.rank <= 10 and 0.2 <= x.alpha <= 0.8 for x in b)
     s = wl.workload_small()
     assert s.n == 32 and s.rank == 1
+
+
+def test_golden_state_and_cost_n1():
+    seen = 0
+    for rest in _golden_lines("state"):
+        lhs, rhs = rest.split(":")
+        head, m2, m3 = lhs.split("|")
+        h = head.split()
+        alpha, beta, gamma = float(h[0]), float(h[1]), float(h[2])
+        a = [np.array([float(v) for v in h[3:]]), np.array([float(v) for v in m2.split()]),
+             np.array([float(v) for v in m3.split()])]
+        one = np.ones((1, 1), order="F")
+        prob = wl.Problem("golden", 1, a, alpha, beta, gamma, 1e-6, np.ones(1), [one, one, one])
+        u = solve.solve_full(prob)
+        y = solve.state_full(prob, u)
+        want_y, want_J = (float(v) for v in rhs.split())
+        np.testing.assert_allclose(y.reshape(-1), [want_y], rtol=1e-14)
+        assert solve.cost_full(prob, u, y) == pytest.approx(want_J, rel=1e-14)
+        assert solve.optimal_cost(prob) == pytest.approx(want_J, rel=1e-14)
+        seen += 1
+    assert seen >= 2
+
+
+@pytest.mark.parametrize("alpha", [0.3, 1.0])
+def test_cost_is_minimal_at_the_exact_control(alpha):
+    """Second variation from the dense matrix function (no 1D eigenbases):
+    J(u* + t w) - J(u*) = t^2/2 (||beta A^-alpha w||^2 + gamma ||w||^2) exactly,
+    which holds only if the oracle's u* is stationary."""
+    prob = _tiny_problem(5, alpha)
+    u = solve.solve_full(prob)
+    y = solve.state_full(prob, u)
+    J0 = solve.cost_full(prob, u, y)
+    A = brute.kron_sum_dense(prob)
+    mu, Q = np.linalg.eigh(A)
+    S = (Q * (prob.beta * mu ** (-prob.alpha))[None, :]) @ Q.T
+    rng = np.random.default_rng(4)
+    for t in (1e-2, 1e-1, 1.0):
+        w = rng.standard_normal(u.shape)
+        uw = u + t * w
+        yw = (S @ uw.reshape(-1)).reshape(u.shape)
+        Sw = S @ w.reshape(-1)
+        quad = 0.5 * t * t * (float(Sw @ Sw) + prob.gamma * float(np.sum(w * w)))
+        assert solve.cost_full(prob, uw, yw) - J0 == pytest.approx(quad, rel=1e-8, abs=1e-13)
+    yom = tensor.cp_full(prob.w, prob.Y)
+    assert J0 == pytest.approx(0.5 * float(np.sum(yom * (yom - y))), rel=1e-11)
+
+
+def test_cost_and_state_evaluators_against_full_grid():
+    prob = wl.workload_quadratic(n=12, alpha=0.6, rank=3)
+    u = solve.solve_full(prob)
+    y = solve.state_full(prob, u)
+    # canonical-factor cost on a perturbed canonical pair
+    rng = np.random.default_rng(8)
+    Fu = [rng.standard_normal((12, 4)) for _ in range(3)]
+    wu = rng.standard_normal(4)
+    Fy = [rng.standard_normal((12, 5)) for _ in range(3)]
+    wy = rng.standard_normal(5)
+    uf = tensor.cp_full(wu, Fu)
+    yf = tensor.cp_full(wy, Fy)
+    assert solve.cost_from_factors(prob, wu, Fu, wy, Fy) == pytest.approx(
+        solve.cost_full(prob, uf, yf), rel=1e-12)
+    assert solve.optimal_cost(prob) == pytest.approx(solve.cost_full(prob, u, y), rel=1e-12)
+    # state evaluator: a candidate with known full-grid error, all slabs and sampled
+    cand = y + 1e-3 * yf / np.linalg.norm(yf) * np.linalg.norm(y)
+    sp = solve.Spectral(prob)
+    # the candidate written exactly as a canonical tensor: its core in a full
+    # orthonormal basis, one term per core entry
+    Qc = [np.linalg.qr(rng.standard_normal((12, 12)))[0] for _ in range(3)]
+    core = solve.mode_products(cand, [q.T for q in Qc])
+    idx = np.array(np.unravel_index(np.arange(12 ** 3), (12, 12, 12)))
+    wc = core.reshape(-1)
+    Fc = [Qc[l][:, idx[l]] for l in range(3)]
+    rep = solve.state_rel_error(prob, wc, Fc, sp=sp)
+    want = np.linalg.norm(cand - y) / np.linalg.norm(y)
+    assert rep["rel_l2"] == pytest.approx(want, rel=1e-8)
+
