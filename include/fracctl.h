@@ -90,6 +90,8 @@ typedef struct {
     double rel_residual;    /* ||R|| / ||Y|| of the recursively updated residual at exit       */
     double op_max_rel_err;  /* max over the spectrum of |D~/D - 1| (setup gate value)          */
     double precond_max_rel_err; /* max over the spectrum of |D~_p D - 1|                       */
+    int state_rank;         /* Kronecker rank of the state map beta A^-alpha                   */
+    double state_max_rel_err; /* max over the spectrum of its relative error (setup gate)      */
 } fc_info;
 
 /* Plan with gamma = 1, FP64 and defaults; see fc_setup_ex.  a1..a3 are HOST. */
@@ -108,7 +110,7 @@ fc_status fc_setup(int n, const double* a1, const double* a2, const double* a3,
 fc_status fc_setup_ex(const fc_setup_params* p, void* hip_stream, fc_plan* out);
 
 /* Solve F(A) u = y for one design function given in canonical format.
- *   rank_y            number of terms of y, 1 <= rank_y <= 4 * max_rank
+ *   rank_y            number of terms of y, 1 <= rank_y <= 256
  *   w_y               DEVICE, rank_y weights, or NULL for all ones
  *   Y1, Y2, Y3        DEVICE, n x rank_y column-major factors of y
  *   cap_u             capacity (columns) of the output buffers
@@ -124,6 +126,24 @@ fc_status fc_solve(fc_plan plan, int rank_y, const double* w_y,
                    const double* Y1, const double* Y2, const double* Y3,
                    int cap_u, int* rank_u, double* w_u, double* U1, double* U2, double* U3,
                    fc_info* info, void* hip_stream);
+
+/* fc_solve, then the state y = beta A^-alpha u (eqn `State`, Section 3.1) and
+ * the cost functional J = 1/2 ||y - y_Omega||^2 + gamma/2 ||u||^2 (Section 3.1
+ * with the finite-difference mass matrix M = I, Euclidean norms).  The state
+ * is the Hadamard product of the Tucker solution with the separable state
+ * map (an exponential sum for beta s^-alpha, gated like the operator),
+ * truncated to relative accuracy eps, then converted to canonical format and
+ * transformed to the grid like u.  J is evaluated from exact Tucker inner
+ * products of y, u and the design in eigen-coordinates.
+ *   cap_s, rank_s, w_s, S1..S3   as cap_u, rank_u, w_u, U1..U3, for y
+ *   J                            HOST out, may be NULL
+ * Other arguments, synchronisation and errors as fc_solve; FC_ERR_RANK_OVERFLOW
+ * when either output exceeds its capacity. */
+fc_status fc_solve_state(fc_plan plan, int rank_y, const double* w_y, const double* Y1,
+                         const double* Y2, const double* Y3, int cap_u, int* rank_u, double* w_u,
+                         double* U1, double* U2, double* U3, int cap_s, int* rank_s, double* w_s,
+                         double* S1, double* S2, double* S3, double* J, fc_info* info,
+                         void* hip_stream);
 
 /* Solve a batch of independent problems, one plan per problem (plans may
  * differ in n and alpha).  Arrays are HOST arrays of length `count`; the
@@ -144,8 +164,8 @@ void fc_destroy(fc_plan plan);
  * after mode; V (may be NULL): 3 n x n column-major eigenvector matrices. */
 fc_status fc_plan_spectrum(fc_plan plan, double* lam, double* V);
 
-/* Separable factors of the operator (which = 0) or the preconditioner
- * (which = 1) in eigen-coordinates: *rank terms, w (HOST, capacity cap) and
+/* Separable factors of the operator (which = 0), the preconditioner
+ * (which = 1) or the state map (which = 2) in eigen-coordinates: *rank terms, w (HOST, capacity cap) and
  * F (HOST, 3 consecutive n x cap column-major matrices, may be NULL). */
 fc_status fc_plan_separable(fc_plan plan, int which, int cap, int* rank, double* w, double* F);
 
@@ -173,7 +193,8 @@ fc_status fc_cp_truncate(fc_plan plan, int m, const double* w, const double* X1,
                          int* rank_out, double* w_out, double* O1, double* O2, double* O3,
                          void* hip_stream);
 
-/* Apply the operator (which = 0) or preconditioner (which = 1) to a canonical
+/* Apply the operator (which = 0), preconditioner (which = 1) or state map
+ * (which = 2) to a canonical
  * tensor given in eigen-coordinates, with truncation to relative accuracy eps
  * (Section 3.3, eqn. Gen3DtimesX, evaluated in eigen-coordinates).  DEVICE
  * buffers as in fc_cp_truncate. */
@@ -198,8 +219,8 @@ fc_status fc_host_expsum(int kind, double p1, double p2, double p3, double s_min
                          int terms, double* t, double* c, double* max_rel_err);
 
 /* Host-only construction of the setup phase (no device needed): the
- * eigenpairs and the separable operator (which = 0) or preconditioner
- * (which = 1) exactly as fc_setup_ex builds them, returned like
+ * eigenpairs and the separable operator (which = 0), preconditioner
+ * (which = 1) or state map (which = 2) exactly as fc_setup_ex builds them, returned like
  * fc_plan_separable; *max_rel_err (may be NULL) receives the gate value
  * max over [s_min, s_max] of |D~/f - 1| (operator) or |D~_p f - 1|. */
 fc_status fc_host_separable(const fc_setup_params* p, int which, int cap, int* rank, double* w,

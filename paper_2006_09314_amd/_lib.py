@@ -53,6 +53,8 @@ class Info(C.Structure):
         ("rel_residual", C.c_double),
         ("op_max_rel_err", C.c_double),
         ("precond_max_rel_err", C.c_double),
+        ("state_rank", C.c_int),
+        ("state_max_rel_err", C.c_double),
     ]
 
     def as_dict(self):
@@ -63,6 +65,7 @@ class Info(C.Structure):
             "op_rank": self.op_rank, "precond_rank": self.precond_rank,
             "rel_residual": self.rel_residual, "op_max_rel_err": self.op_max_rel_err,
             "precond_max_rel_err": self.precond_max_rel_err,
+            "state_rank": self.state_rank, "state_max_rel_err": self.state_max_rel_err,
         }
 
 
@@ -77,6 +80,8 @@ PROTOTYPES = {
     "fc_setup_ex": (_I, [C.POINTER(SetupParams), _VP, C.POINTER(_VP)]),
     "fc_solve": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _I, _PI, _VP, _VP, _VP, _VP,
                       C.POINTER(Info), _VP]),
+    "fc_solve_state": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _I, _PI, _VP, _VP, _VP, _VP,
+                            _I, _PI, _VP, _VP, _VP, _VP, _PD, C.POINTER(Info), _VP]),
     "fc_solve_batched": (_I, [_I, C.POINTER(_VP), _PI, C.POINTER(_VP), C.POINTER(_VP),
                               C.POINTER(_VP), C.POINTER(_VP), _PI, _PI, C.POINTER(_VP),
                               C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP), _PI,

@@ -113,6 +113,28 @@ class Plan:
         k = rank_u.value
         return w_u[:k], [u[:, :k] for u in U], info.as_dict()
 
+    def solve_state(self, w_y, Y: Sequence, cap_u: int = 4096, cap_s: int = 4096, stream=None):
+        """fc_solve_state: the control u, the state y = beta A^-alpha u and the
+        cost J.  Returns (w_u, [U1, U2, U3], w_s, [S1, S2, S3], J, info)."""
+        import torch
+        n = self.n
+        Yc = [_colmajor(y) for y in Y]
+        dev = Yc[0].device
+        w_u = torch.empty(cap_u, dtype=torch.float64, device=dev)
+        U = [torch.empty((cap_u, n), dtype=torch.float64, device=dev).t() for _ in range(3)]
+        w_s = torch.empty(cap_s, dtype=torch.float64, device=dev)
+        S = [torch.empty((cap_s, n), dtype=torch.float64, device=dev).t() for _ in range(3)]
+        info = Info()
+        rank_u, rank_s, J = C.c_int(), C.c_int(), C.c_double()
+        st = lib().fc_solve_state(self.handle, Yc[0].shape[1], _ptr(w_y), *[_ptr(y) for y in Yc],
+                                  cap_u, C.byref(rank_u), _ptr(w_u), *[_ptr(u) for u in U],
+                                  cap_s, C.byref(rank_s), _ptr(w_s), *[_ptr(x) for x in S],
+                                  C.byref(J), C.byref(info), _stream_ptr(stream))
+        check(st, "fc_solve_state")
+        k, ks = rank_u.value, rank_s.value
+        return (w_u[:k], [u[:, :k] for u in U], w_s[:ks], [x[:, :ks] for x in S], J.value,
+                info.as_dict())
+
     def mode_transform(self, mode: int, transpose: bool, X, stream=None):
         import torch
         Xc = _colmajor(X)

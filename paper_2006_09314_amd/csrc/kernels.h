@@ -26,6 +26,12 @@ struct GemmArgs {
 };
 
 hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
+// C = alpha op(A) op(B) + beta C for M, N <= 128 and a long reduction
+// (op(A) op(B) = A^T B, A B^T or A B; batched over g.batch with strides;
+// inner == 1, no diagonal, FP64): the Gram-type products of the
+// truncations, one workgroup per 32 x 32 output tile, K split over its
+// wavefronts.
+hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
 
 // Symmetric eigen-decomposition of a batch of k x k matrices (k <= 128),
 // cyclic Jacobi with the matrix in LDS.  A (column-major, leading dimension

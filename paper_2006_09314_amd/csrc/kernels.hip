@@ -234,6 +234,114 @@ static hipError_t gemm_dispatch(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Products with a small result (M, N <= 128) and a long reduction:
+// C = alpha op(A) op(B) + beta C with op(A) op(B) = A^T B (L = 0), A B^T
+// (L = 1) or A B (L = 2), column-major operands.  One workgroup per 32 x 32
+// output tile; its sixteen wavefronts split K in interleaved chunks of 16 on
+// the FP64 matrix core (16x16x4), each loading the operands of a chunk
+// (four steps) before issuing their products, so that the sixteen
+// wavefronts keep sixteen chunks in flight; operands go straight from
+// memory into the
+// matrix-core lane layout (lane l: row/column l % 16, k = l / 16), and the
+// partial tiles are summed in LDS in a fixed order (deterministic).
+// Batched over blockIdx.z with strides.
+constexpr int GR_WAVES = 16;
+constexpr int GR_DEPTH = 1;   // chunks loaded per wavefront before computing
+
+template <int L>
+__global__ __launch_bounds__(64 * GR_WAVES) void gram_kernel(GemmArgs g) {
+    extern __shared__ double gram_red[];   // [GR_WAVES][4 blocks][4 regs][64 lanes]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tilesM = (g.M + 31) / 32;
+    const int i0 = (blockIdx.x % tilesM) * 32, j0 = (blockIdx.x / tilesM) * 32;
+    const long b = blockIdx.z;
+    const double* __restrict__ A = g.A + b * g.strideA;
+    const double* __restrict__ B = g.B + b * g.strideB;
+    double* __restrict__ C = g.C + b * g.strideC;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int ia0 = i0 + r16, ia1 = i0 + 16 + r16;
+    const int jb0 = j0 + r16, jb1 = j0 + 16 + r16;
+    const bool va0 = ia0 < g.M, va1 = ia1 < g.M, vb0 = jb0 < g.N, vb1 = jb1 < g.N;
+    // element (row i of op(A), k) is A[k + i lda] for L = 0, else A[i + k lda];
+    // element (k, column j of op(B)) is B[j + k ldb] for L = 1, else B[k + j ldb]
+    const long sa = (L == 0) ? 1 : g.lda, sb = (L == 1) ? g.ldb : 1;
+    const double* a0p = A + (va0 ? ((L == 0) ? (long)ia0 * g.lda : ia0) : 0);
+    const double* a1p = A + (va1 ? ((L == 0) ? (long)ia1 * g.lda : ia1) : 0);
+    const double* b0p = B + (vb0 ? ((L == 1) ? jb0 : (long)jb0 * g.ldb) : 0);
+    const double* b1p = B + (vb1 ? ((L == 1) ? jb1 : (long)jb1 * g.ldb) : 0);
+    dbl4 acc[2][2];
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int chunks = (g.K + 15) / 16;
+    for (int base = wave; base < chunks; base += GR_WAVES * GR_DEPTH) {
+        double a0[4 * GR_DEPTH], a1[4 * GR_DEPTH], b0[4 * GR_DEPTH], b1[4 * GR_DEPTH];
+#pragma unroll
+        for (int u = 0; u < 4 * GR_DEPTH; ++u) {
+            const int k = 16 * (base + GR_WAVES * (u >> 2)) + 4 * (u & 3) + kq;
+            const bool vk = k < g.K;
+            a0[u] = (vk && va0) ? a0p[k * sa] : 0.0;
+            a1[u] = (vk && va1) ? a1p[k * sa] : 0.0;
+            b0[u] = (vk && vb0) ? b0p[k * sb] : 0.0;
+            b1[u] = (vk && vb1) ? b1p[k * sb] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4 * GR_DEPTH; ++u) {
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u], acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b1[u], acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b0[u], acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u], acc[1][1], 0, 0, 0);
+        }
+    }
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y)
+            for (int v = 0; v < 4; ++v)
+                gram_red[((wave * 4 + 2 * x + y) * 4 + v) * 64 + lane] = acc[x][y][v];
+    __syncthreads();
+    // 32 x 32 outputs, two per thread; accumulator v of lane l holds
+    // row (l >> 4) + 4 v, column l & 15 of its 16 x 16 block
+    for (int e = threadIdx.x; e < 2 * 2 * 4 * 64; e += 64 * GR_WAVES) {
+        const int l = e & 63, v = (e >> 6) & 3, blk = e >> 8;
+        const int x = blk >> 1, y = blk & 1;
+        double sum = 0.0;
+        for (int w = 0; w < GR_WAVES; ++w) sum += gram_red[((w * 4 + blk) * 4 + v) * 64 + l];
+        const int i = i0 + 16 * x + (l >> 4) + 4 * v, j = j0 + 16 * y + (l & 15);
+        if (i < g.M && j < g.N) {
+            double r = g.alpha * sum;
+            if (g.beta != 0.0) r += g.beta * C[i + (long)j * g.ldc];
+            C[i + (long)j * g.ldc] = r;
+        }
+    }
+}
+
+hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if (g.M > 128 || g.N > 128 || g.inner != 1 || g.d || g.lowp || g.K <= 0 || (transA && transB))
+        return hipErrorInvalidValue;
+    const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
+    const dim3 grid(tiles, 1, g.batch), block(64 * GR_WAVES);
+    const size_t lds = sizeof(double) * GR_WAVES * 4 * 4 * 64;   // 128 KiB
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [lds] {
+        const void* fns[3] = {(const void*)gram_kernel<0>, (const void*)gram_kernel<1>,
+                              (const void*)gram_kernel<2>};
+        for (const void* f : fns) {
+            const hipError_t e =
+                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) attr_err = e;
+        }
+    });
+    if (attr_err != hipSuccess) return attr_err;
+    if (transA)
+        hipLaunchKernelGGL(gram_kernel<0>, grid, block, lds, s, g);
+    else if (transB)
+        hipLaunchKernelGGL(gram_kernel<1>, grid, block, lds, s, g);
+    else
+        hipLaunchKernelGGL(gram_kernel<2>, grid, block, lds, s, g);
+    return hipGetLastError();
+}
+
 hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     if (g.K <= 0) {

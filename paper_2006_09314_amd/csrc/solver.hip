@@ -6,6 +6,7 @@
 // rank) positive tensors, and Algorithm 1 (Appendix 2) runs on Tucker iterates
 // (orthonormal bases Z_l, n x r_l, dense core r0 x r1 x r2).
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -91,7 +92,7 @@ struct Separable {
     std::vector<double> F[3];                     // host copies of unweighted factors n x Q
 };
 
-enum { SITE_Z = 0, SITE_S, SITE_X, SITE_R, SITE_P, SITE_MISC, SITE_OS, SITE_OR, SITE_OU, NSITES };
+enum { SITE_Z = 0, SITE_S, SITE_X, SITE_R, SITE_P, SITE_MISC, SITE_OS, SITE_OR, SITE_OU, SITE_ST, NSITES };
 
 struct WarmBasis {
     double* W[3] = {nullptr, nullptr, nullptr};
@@ -106,11 +107,11 @@ struct fc_plan_s {
     std::vector<double> lam[3];   // host eigenvalues
     std::vector<double> Vh[3];    // host eigenvectors
     double* V[3] = {nullptr, nullptr, nullptr};
-    Separable op, pc;
-    double op_err = 0, pc_err = 0;
+    Separable op, pc, st;   // operator ~ f, preconditioner ~ 1/f, state map ~ beta s^-alpha
+    double op_err = 0, pc_err = 0, st_err = 0;
     Arena arena;
     // workspace
-    Tucker slot[12];
+    Tucker slot[13];
     fc_precision precision = FC_FP64;
     double *E = nullptr, *Gd[3] = {}, *Mq = nullptr, *c1 = nullptr, *c2 = nullptr;
     double *Xs = nullptr, *HX = nullptr, *Ys = nullptr, *Ts = nullptr, *F = nullptr;
@@ -137,6 +138,10 @@ struct fc_plan_s {
     double site_ms[16] = {};   // wall time per truncation site (with FC_TRACE)
     int site_calls[16] = {};
     std::mutex use_mu;   // one solve at a time per plan
+    rocblas_handle blas = nullptr;   // plain FP64 GEMMs (own workspace, no atomics)
+    ~fc_plan_s() {
+        if (blas) rocblas_destroy_handle(blas);
+    }
 };
 
 namespace {
@@ -180,6 +185,35 @@ struct Ctx {
     bool lowp = false;   // bulk contractions on the FP32 matrix cores
 };
 
+// Route one product: Gram-type (a small result: any A^T B, and A B^T or A B
+// over a long reduction) to the hand-written split-over-waves kernel, other
+// plain FP64 products to
+// rocBLAS, and the rest (diagonal scaling, two-level batches, FP32 cores)
+// to the library's MFMA GEMM.
+hipError_t run_gemm(const Ctx& c, bool ta, bool tb, const GemmArgs& g) {
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    const bool plain = !g.lowp && !g.d && g.inner == 1 && g.K > 0;
+    if (plain && g.M <= 128 && g.N <= 128 && !(ta && tb) && (ta || g.K >= 256))
+        return fc::gram(ta, tb, g, c.s);
+    if (plain && c.p->blas) {
+        rocblas_handle h = c.p->blas;
+        if (rocblas_set_stream(h, c.s) != rocblas_status_success) return hipErrorUnknown;
+        const rocblas_operation oa = ta ? rocblas_operation_transpose : rocblas_operation_none;
+        const rocblas_operation ob = tb ? rocblas_operation_transpose : rocblas_operation_none;
+        rocblas_status st;
+        if (g.batch == 1)
+            st = rocblas_dgemm(h, oa, ob, g.M, g.N, g.K, &g.alpha, g.A, (rocblas_int)g.lda, g.B,
+                               (rocblas_int)g.ldb, &g.beta, g.C, (rocblas_int)g.ldc);
+        else
+            st = rocblas_dgemm_strided_batched(h, oa, ob, g.M, g.N, g.K, &g.alpha, g.A,
+                                               (rocblas_int)g.lda, g.strideA, g.B,
+                                               (rocblas_int)g.ldb, g.strideB, &g.beta, g.C,
+                                               (rocblas_int)g.ldc, g.strideC, g.batch);
+        return st == rocblas_status_success ? hipSuccess : hipErrorUnknown;
+    }
+    return fc::gemm(ta, tb, g, c.s);
+}
+
 void gemm(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
           long lda, const double* B, long ldb, double beta, double* C, long ldc, int batch = 1,
           long sA = 0, long sB = 0, long sC = 0, int inner = 1, long sAi = 0, long sBi = 0,
@@ -203,7 +237,7 @@ void gemm(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, con
             }
         }
         HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], c.s));
-        HIPCHK(fc::gemm(ta, tb, g, c.s));
+        HIPCHK(run_gemm(c, ta, tb, g));
         HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], c.s));
         g_prof.used += 2;
         g_prof.shapes.push_back({ta, tb, M, N, K, batch, inner, g.lowp});
@@ -212,7 +246,7 @@ void gemm(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, con
         g_prof.launches += 1;
         return;
     }
-    HIPCHK(fc::gemm(ta, tb, g, c.s));
+    HIPCHK(run_gemm(c, ta, tb, g));
 }
 
 // bulk contraction: runs on the FP32 matrix cores when the context asks for it
@@ -941,9 +975,9 @@ void reset_warm(fc_plan_s* p) {
 void alloc_workspace(fc_plan_s* p) {
     const int n = p->n;
     const long rc = p->rcap, pc = p->pcap;
-    const int Q = std::max(p->op.Q, p->pc.Q);
+    const int Q = std::max({p->op.Q, p->pc.Q, p->st.Q});
     Arena& A = p->arena;
-    for (int s = 0; s < 12; ++s) {
+    for (int s = 0; s < 13; ++s) {
         for (int l = 0; l < 3; ++l) p->slot[s].Z[l] = A.alloc((size_t)n * rc);
         p->slot[s].core = A.alloc((size_t)rc * rc * rc);
     }
@@ -1128,6 +1162,42 @@ void build_preconditioner(fc_plan_s* p, double smin, double smax) {
     p->pc_err = err;
 }
 
+// State map y = beta A^-alpha u (eqn `State`): beta s^-alpha is completely
+// monotone, so it is an exponential sum with positive weights on the same
+// geometric node grid as the operator (one separable term per node; the
+// constant beta when alpha = 0), gated like the operator.
+void build_state_map(fc_plan_s* p, double smin, double smax) {
+    const int n = p->n;
+    const double a = p->alpha, b = p->beta;
+    Separable& S = p->st;
+    auto add = [&](double w, double t) {
+        S.w.push_back(w);
+        for (int l = 0; l < 3; ++l)
+            for (int i = 0; i < n; ++i) S.F[l].push_back(t > 0 ? std::exp(-t * p->lam[l][i]) : 1.0);
+        S.Q++;
+    };
+    if (a == 0.0) {
+        add(b, 0.0);
+        p->st_err = 0.0;
+        return;
+    }
+    auto h = [&](double s) { return b * std::pow(s, -a); };
+    const double t_hi = (std::log(1.0 / p->op_acc) + 10.0) / smin;
+    const double t_lo = std::pow(p->op_acc, 0.7) / smax;
+    std::vector<double> t, cc;
+    double c0 = 0.0, err = 1e300;
+    for (double hstep : {0.7, 0.6, 0.5, 0.42, 0.35}) {
+        if (!fc::fit_expsum_nnls(h, h, smin, smax, t_lo, t_hi, hstep, false, t, cc, c0, err))
+            continue;
+        if (err <= p->op_acc) break;
+    }
+    if (!(err <= p->op_acc))
+        throw FcError(FC_ERR_NUMERIC, "state-map exponential sum misses the accuracy gate (err " +
+                                          std::to_string(err) + ")");
+    for (size_t k = 0; k < t.size(); ++k) add(cc[k], t[k]);
+    p->st_err = err;
+}
+
 void host_spectra_and_separables(fc_plan_s* p, const fc_setup_params* prm) {
     const int n = p->n;
     // eigenpairs of the three 1D matrices (host, in parallel)
@@ -1146,6 +1216,7 @@ void host_spectra_and_separables(fc_plan_s* p, const fc_setup_params* prm) {
     for (int l = 0; l < 3; ++l) { smin += p->lam[l].front(); smax += p->lam[l].back(); }
     build_operator(p, smin, smax);
     build_preconditioner(p, smin, smax);
+    build_state_map(p, smin, smax);
 }
 
 void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
@@ -1157,7 +1228,22 @@ void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
     }
     upload_separable(p, p->op);
     upload_separable(p, p->pc);
+    upload_separable(p, p->st);
     alloc_workspace(p);
+    // rocBLAS for plain products: a fixed workspace from the plan (no device
+    // allocation during a solve), deterministic kernels only
+    if (rocblas_create_handle(&p->blas) != rocblas_status_success) {
+        p->blas = nullptr;
+        throw FcError(FC_ERR_HIP, "rocblas_create_handle failed");
+    }
+    if (rocblas_set_atomics_mode(p->blas, rocblas_atomics_not_allowed) != rocblas_status_success)
+        throw FcError(FC_ERR_HIP, "rocblas_set_atomics_mode failed");
+    {
+        const size_t wsz = size_t(32) << 20;
+        double* ws = p->arena.alloc(wsz / sizeof(double));
+        if (rocblas_set_workspace(p->blas, ws, wsz) != rocblas_status_success)
+            throw FcError(FC_ERR_HIP, "rocblas_set_workspace failed");
+    }
     HIPCHK(hipDeviceSynchronize());
 }
 
@@ -1380,16 +1466,16 @@ static void apply_defaults(fc_plan_s* p, const fc_setup_params* prm);
 
 fc_status fc_host_separable(const fc_setup_params* prm, int which, int cap, int* rank, double* w,
                             double* F, double* max_rel_err) {
-    if (!prm || !rank || (which != 0 && which != 1)) return fail(FC_ERR_INVALID_ARG, "fc_host_separable: bad arguments");
+    if (!prm || !rank || which < 0 || which > 2) return fail(FC_ERR_INVALID_ARG, "fc_host_separable: bad arguments");
     fc_status v = validate_params(prm);
     if (v != FC_OK) return v;
     fc_plan_s p;
     apply_defaults(&p, prm);
     fc_status st = guard([&] { host_spectra_and_separables(&p, prm); });
     if (st != FC_OK) return st;
-    const Separable& S = which == 0 ? p.op : p.pc;
+    const Separable& S = which == 0 ? p.op : which == 1 ? p.pc : p.st;
     *rank = S.Q;
-    if (max_rel_err) *max_rel_err = which == 0 ? p.op_err : p.pc_err;
+    if (max_rel_err) *max_rel_err = which == 0 ? p.op_err : which == 1 ? p.pc_err : p.st_err;
     if (cap < S.Q) return fail(FC_ERR_RANK_OVERFLOW, "capacity too small");
     const int n = p.n;
     if (w) std::memcpy(w, S.w.data(), sizeof(double) * S.Q);
@@ -1470,8 +1556,8 @@ fc_status fc_plan_spectrum(fc_plan p, double* lam, double* V) {
 }
 
 fc_status fc_plan_separable(fc_plan p, int which, int cap, int* rank, double* w, double* F) {
-    if (!p || !rank || (which != 0 && which != 1)) return fail(FC_ERR_INVALID_ARG, "fc_plan_separable: bad arguments");
-    const Separable& S = which == 0 ? p->op : p->pc;
+    if (!p || !rank || which < 0 || which > 2) return fail(FC_ERR_INVALID_ARG, "fc_plan_separable: bad arguments");
+    const Separable& S = which == 0 ? p->op : which == 1 ? p->pc : p->st;
     *rank = S.Q;
     if (cap < S.Q) return fail(FC_ERR_RANK_OVERFLOW, "capacity too small");
     const int n = p->n;
@@ -1542,7 +1628,7 @@ fc_status fc_apply_separable(fc_plan p, int which, int m, const double* w, const
                              const double* X2, const double* X3, double eps, int cap,
                              int* rank_out, double* w_out, double* O1, double* O2, double* O3,
                              void* stream) {
-    if (!p || (which != 0 && which != 1) || m < 1 || m > 256 || !X1 || !X2 || !X3 ||
+    if (!p || which < 0 || which > 2 || m < 1 || m > 256 || !X1 || !X2 || !X3 ||
         !(eps > 0 && eps < 1) || cap < 0 || !rank_out || !w_out || !O1 || !O2 || !O3)
         return fail(FC_ERR_INVALID_ARG, "fc_apply_separable: bad arguments");
     Ctx c{p, (hipStream_t)stream, p->n};
@@ -1553,19 +1639,30 @@ fc_status fc_apply_separable(fc_plan p, int which, int m, const double* w, const
         Tucker& O = p->slot[9];
         canon_to_tucker(c, m, w, X, 1e-3 * eps, T, "input");
         reset_warm(p);
-        had_trunc(c, which == 0 ? p->op : p->pc, T, eps / std::sqrt(2.0), 0.0, O, "apply", SITE_MISC);
+        had_trunc(c, which == 0 ? p->op : which == 1 ? p->pc : p->st, T, eps / std::sqrt(2.0), 0.0, O,
+                  "apply", SITE_MISC);
         const double n2 = tucker_norm2(c, O);
         inner = canon_out(p, c, O, 0.5 * eps * eps * n2, false, cap, rank_out, w_out, O1, O2, O3);
     });
     return st != FC_OK ? st : inner;
 }
 
-fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, const double* Y2,
-                   const double* Y3, int cap_u, int* rank_u, double* w_u, double* U1,
-                   double* U2, double* U3, fc_info* info, void* stream) {
-    if (!p || rank_y < 1 || rank_y > 256 || !Y1 || !Y2 || !Y3 || cap_u < 0 || !rank_u ||
-        !w_u || !U1 || !U2 || !U3)
-        return fail(FC_ERR_INVALID_ARG, "fc_solve: bad arguments");
+}  // extern "C"
+
+namespace {
+
+// Output of the optional state recovery (fc_solve_state).
+struct StateOut {
+    int cap = 0;
+    int* rank = nullptr;
+    double* w = nullptr;
+    double* F[3] = {nullptr, nullptr, nullptr};
+    double* J = nullptr;
+};
+
+fc_status solve_impl(fc_plan p, int rank_y, const double* w_y, const double* Y1, const double* Y2,
+                     const double* Y3, int cap_u, int* rank_u, double* w_u, double* U1,
+                     double* U2, double* U3, fc_info* info, void* stream, const StateOut* so_out) {
     Ctx c{p, (hipStream_t)stream, p->n};
     const int n = p->n;
     fc_status result = FC_OK;
@@ -1601,6 +1698,29 @@ fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, c
             const double bn = std::sqrt(tucker_norm2(c, B));
             so = pcg(c, B, X, p->eps, p->tol, p->max_iter, 0.1 * p->eps * bn);
         }
+        // state y = beta A^-alpha u (eqn `State`) from the Tucker solution, and
+        // the cost J = 1/2 ||y - y_Omega||^2 + gamma/2 ||u||^2 (Section 3.1,
+        // M = I) from exact Tucker inner products in eigen-coordinates
+        int Ks = 0;
+        if (so_out) {
+            Tucker& Ys = p->slot[12];
+            if (X.empty()) {
+                Ys.r[0] = Ys.r[1] = Ys.r[2] = 0;
+            } else {
+                p->warm[SITE_ST].valid = false;
+                had_trunc(c, p->st, X, p->eps, 0.0, Ys, "state: trunc(beta A^-alpha u)", SITE_ST);
+            }
+            if (so_out->J) {
+                const double yy = tucker_norm2(c, Ys), bb = tucker_norm2(c, B);
+                const double yb = (Ys.empty() || B.empty()) ? 0.0 : tucker_inner(c, Ys, B);
+                const double uu = tucker_norm2(c, X);
+                *so_out->J = 0.5 * (yy - 2.0 * yb + bb) + 0.5 * p->gamma * uu;
+            }
+            const double yn2 = Ys.empty() ? 0.0 : tucker_norm2(c, Ys);
+            Ks = Ys.empty() ? 0 : tucker_to_canon_out(c, Ys, 0.01 * p->eps * p->eps * yn2, true,
+                                                      so_out->cap, so_out->w, so_out->F);
+            *so_out->rank = Ks;
+        }
         // T2C of the result and exit transform U_l = V_l (Z_l coef)
         const double xn2 = X.empty() ? 0.0 : tucker_norm2(c, X);
         double* U[3] = {U1, U2, U3};
@@ -1618,15 +1738,18 @@ fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, c
             info->refinements = sweeps;
             info->op_max_rel_err = p->op_err;
             info->precond_max_rel_err = p->pc_err;
+            info->state_rank = p->st.Q;
+            info->state_max_rel_err = p->st_err;
         }
         if (K > cap_u) result = fail(FC_ERR_RANK_OVERFLOW, "result rank exceeds cap_u");
+        else if (so_out && Ks > so_out->cap) result = fail(FC_ERR_RANK_OVERFLOW, "state rank exceeds cap_s");
         else if (!so.converged) result = fail(FC_ERR_NOT_CONVERGED, "max_iter reached");
         if (g_trace) {
             sync(c);
             const double tot = std::chrono::duration<double, std::milli>(
                                    std::chrono::steady_clock::now() - t_solve).count();
             static const char* names[NSITES] = {"Z", "S", "X", "R", "P", "misc", "ref-S", "ref-R",
-                                                "ref-U"};
+                                                "ref-U", "state"};
             std::string line = "[fc] solve " + std::to_string(tot) + " ms; truncations:";
             for (int i = 0; i < NSITES; ++i)
                 if (p->site_calls[i])
@@ -1636,6 +1759,38 @@ fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, c
         }
     });
     return st != FC_OK ? st : result;
+}
+
+}  // namespace
+
+extern "C" {
+
+fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, const double* Y2,
+                   const double* Y3, int cap_u, int* rank_u, double* w_u, double* U1,
+                   double* U2, double* U3, fc_info* info, void* stream) {
+    if (!p || rank_y < 1 || rank_y > 256 || !Y1 || !Y2 || !Y3 || cap_u < 0 || !rank_u ||
+        !w_u || !U1 || !U2 || !U3)
+        return fail(FC_ERR_INVALID_ARG, "fc_solve: bad arguments");
+    return solve_impl(p, rank_y, w_y, Y1, Y2, Y3, cap_u, rank_u, w_u, U1, U2, U3, info, stream,
+                      nullptr);
+}
+
+fc_status fc_solve_state(fc_plan p, int rank_y, const double* w_y, const double* Y1,
+                         const double* Y2, const double* Y3, int cap_u, int* rank_u, double* w_u,
+                         double* U1, double* U2, double* U3, int cap_s, int* rank_s, double* w_s,
+                         double* S1, double* S2, double* S3, double* J, fc_info* info,
+                         void* stream) {
+    if (!p || rank_y < 1 || rank_y > 256 || !Y1 || !Y2 || !Y3 || cap_u < 0 || !rank_u ||
+        !w_u || !U1 || !U2 || !U3 || cap_s < 0 || !rank_s || !w_s || !S1 || !S2 || !S3)
+        return fail(FC_ERR_INVALID_ARG, "fc_solve_state: bad arguments");
+    StateOut so;
+    so.cap = cap_s;
+    so.rank = rank_s;
+    so.w = w_s;
+    so.F[0] = S1; so.F[1] = S2; so.F[2] = S3;
+    so.J = J;
+    return solve_impl(p, rank_y, w_y, Y1, Y2, Y3, cap_u, rank_u, w_u, U1, U2, U3, info, stream,
+                      &so);
 }
 
 fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,

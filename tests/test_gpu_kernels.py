@@ -196,7 +196,7 @@ def test_cp_truncate_nearly_dependent_columns():
             np.testing.assert_allclose(np.linalg.norm(host(o), axis=0), 1.0, rtol=1e-10)
 
 
-@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("which", [0, 1, 2])
 def test_apply_separable_matches_full_grid(which):
     import torch
     from tests.gpu_util import dev, host, plan_for
@@ -216,6 +216,10 @@ def test_apply_separable_matches_full_grid(which):
     if which == 0:
         # operator: the separable tensor is the exact symbol to its gate accuracy
         assert np.abs(Dt / D - 1).max() <= 1.01 * prob.eps
+    if which == 2:
+        # state map: beta s^-alpha to its gate accuracy
+        Ds = osolve.f_state(s, prob.alpha, prob.beta)
+        assert np.abs(Dt / Ds - 1).max() <= 1.01 * prob.eps
     got = ot.cp_full(host(wo), [host(o) for o in O])
     want = Dt * T
     assert np.linalg.norm(got - want) <= 1.01 * eps * np.linalg.norm(want)

@@ -216,3 +216,49 @@ def test_full_size_batched_n1024_matches_single():
             assert rep["rel_l2"] <= GATE * p.eps, (p.name, rep)
     for plan in plans:
         plan.close()
+
+
+# ---- state recovery y = beta A^-alpha u and the cost functional ----------
+
+def _check_state(prob, slabs=None, cost=True):
+    from tests.gpu_util import plan_for
+    import torch
+    print(f"[case] state {prob.name} n={prob.n} alpha={prob.alpha}", flush=True)
+    plan = plan_for(prob)
+    w = torch.from_numpy(np.asarray(prob.w, dtype=np.float64)).cuda()
+    from tests.gpu_util import dev
+    w_u, U, w_s, S, J, info = plan.solve_state(w, [dev(y) for y in prob.Y])
+    h = lambda t: t.detach().cpu().numpy()
+    rep_u = osolve.rel_error(prob, h(w_u), [h(u) for u in U], slabs=slabs)
+    rep_y = osolve.state_rel_error(prob, h(w_s), [h(x) for x in S], slabs=slabs)
+    print(f"[result] state {prob.name}: u err {rep_u['rel_l2']:.3e} y err {rep_y['rel_l2']:.3e} "
+          f"J {J!r} info {info}", flush=True)
+    assert rep_u["rel_l2"] <= GATE * prob.eps, rep_u
+    assert rep_y["rel_l2"] <= GATE * prob.eps, rep_y
+    if cost:
+        Jx = osolve.optimal_cost(prob)
+        print(f"[result] J exact {Jx!r} rel diff {abs(J - Jx) / Jx:.3e}", flush=True)
+        assert abs(J - Jx) <= GATE * prob.eps * Jx
+    plan.close()
+    return J, info
+
+
+@pytest.mark.parametrize("maker", [lambda: wl.workload_small(),
+                                   lambda: wl.workload_quadratic(n=64, alpha=0.25),
+                                   lambda: wl.workload_quadratic(n=64, alpha=0.75),
+                                   lambda: wl.workload_paper_shaped(40, 1.0),
+                                   lambda: wl.workload_quadratic(n=256, alpha=0.5)])
+def test_state_and_cost_against_oracle(maker):
+    _check_state(maker())
+
+
+def test_state_alpha0_is_beta_u():
+    """alpha = 0: y = beta u exactly, u = y_Omega / (beta + gamma/beta)."""
+    prob = wl.workload_quadratic(n=24, alpha=0.0, rank=2)
+    J, info = _check_state(prob)
+    assert info["state_rank"] == 1 and info["state_max_rel_err"] == 0.0
+
+
+def test_state_full_size_sine1024_sampled():
+    prob = wl.workload_sine(n=1024, seed=3)
+    _check_state(prob, slabs=_sampled_slabs(prob.n, seed=5), cost=False)

@@ -169,6 +169,37 @@ def test_operator_gate_holds_on_the_configurations(n, alpha):
     assert np.all(w > 0)
 
 
+@pytest.mark.parametrize("maker", [
+    lambda: wl.workload_small(),
+    lambda: wl.workload_quadratic(n=128, alpha=0.25),
+    lambda: wl.workload_quadratic(n=256, alpha=0.75),
+    lambda: wl.workload_sine(n=1024, seed=3),
+    lambda: wl.workload_paper_shaped(48, 1.0),
+])
+def test_state_map_matches_exact_symbol(maker):
+    """Separable state map vs beta s^-alpha (eqn State) on sampled entries,
+    within its setup gate (<= eps); weights and factors positive."""
+    prob = maker()
+    w, F, gate = _host_separable(prob, 2)
+    assert np.all(w > 0) and all(np.all(f >= 0) for f in F)
+    assert gate <= prob.eps
+    sp = osolve.Spectral(prob)
+    rng = np.random.default_rng(2)
+    idx = rng.integers(0, prob.n, size=(3, 20000))
+    idx[:, :2000] = rng.integers(0, min(prob.n, 12), size=(3, 2000))
+    s = sp.lam[0][idx[0]] + sp.lam[1][idx[1]] + sp.lam[2][idx[2]]
+    want = osolve.f_state(s, prob.alpha, prob.beta)
+    got = np.prod([F[l][idx[l]] for l in range(3)], axis=0) @ w
+    assert np.abs(got / want - 1).max() <= max(gate, 1e-14) * 1.05 + 1e-13
+
+
+def test_alpha0_state_map_is_beta():
+    prob = wl.workload_quadratic(n=20, alpha=0.0)
+    w, F, gate = _host_separable(prob, 2)
+    assert len(w) == 1 and w[0] == prob.beta and gate == 0.0
+    assert all(np.all(f == 1.0) for f in F)
+
+
 def test_alpha0_operator_is_exact_constant():
     prob = wl.workload_small(n=20)
     prob.alpha = 0.0
