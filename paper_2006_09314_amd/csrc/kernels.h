@@ -71,6 +71,10 @@ hipError_t permute_core(int r0, int r1, int r2, int mode, int batch, const doubl
 // y[i] = a * x[i] (+ y[i] if accumulate)
 hipError_t axpby(long n, double a, const double* x, double b, double* y, hipStream_t s);
 // out[b] = sum_i x[b*stride + i] * y[b*stride + i] for i < n (deterministic tree)
+// out[0] = x . y for a long vector: 256-thread partial sums in up to 256
+// blocks (part: 256 doubles of scratch), then one block sums them (fixed order)
+hipError_t dot_long(long n, const double* x, const double* y, double* part, double* out,
+                    hipStream_t s);
 hipError_t dot_batched(long n, int batch, const double* x, const double* y, long stride,
                        double* out, hipStream_t s);
 // sum of `count` arrays of length n with coefficients: y = sum_t coef[t] * x[t*stride .. ]

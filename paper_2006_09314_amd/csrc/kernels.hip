@@ -8,6 +8,28 @@
 namespace fc {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Wavefront sum of a double through DPP moves (row shifts and row
+// broadcasts, both 32-bit halves), the total read from lane 63 and returned
+// to every lane.  Lanes whose DPP source is absent or masked add zero.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline double dpp_take(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double wave_sum(double v) {
+    v += dpp_take<0xb1>(v);          // quad_perm [1,0,3,2]
+    v += dpp_take<0x4e>(v);          // quad_perm [2,3,0,1]: every lane holds its quad sum
+    v += dpp_take<0x114>(v);         // row_shr:4
+    v += dpp_take<0x118>(v);         // row_shr:8: lane 15 of a row holds the row sum
+    v += dpp_take<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_take<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
 typedef float flt4 __attribute__((ext_vector_type(4)));
 // accumulator row of register v in lane l for v_mfma_f32_16x16x4f32
 #define F32_ROW(l, v) (4 * ((l) >> 4) + (v))
@@ -474,10 +496,7 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double
 // nor back-transformed (callers do not use them).  Scratch: 6 k^2 doubles.
 constexpr int TD_THREADS = 512;
 
-__device__ inline double td_wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return __shfl(v, 0, 64);
-}
+__device__ inline double td_wave_sum(double v) { return wave_sum(v); }
 
 __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
     extern __shared__ double sm[];
@@ -947,10 +966,42 @@ __global__ __launch_bounds__(256) void dot_kernel(long n, const double* __restri
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+__global__ __launch_bounds__(256) void dot_partial_kernel(long n, const double* __restrict__ x,
+                                                          const double* __restrict__ y,
+                                                          double* part) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+        acc += x[i] * y[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void dot_final_kernel(int parts, const double* part,
+                                                        double* out) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < parts; i += 256) acc += part[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
+}
+
 hipError_t dot_batched(long n, int batch, const double* x, const double* y, long stride,
                        double* out, hipStream_t s) {
     if (batch <= 0) return hipSuccess;
     hipLaunchKernelGGL(dot_kernel, dim3(batch), dim3(256), 0, s, n, x, y, stride, out);
+    return hipGetLastError();
+}
+
+hipError_t dot_long(long n, const double* x, const double* y, double* part, double* out,
+                    hipStream_t s) {
+    const int parts = (int)std::min<long>(256, std::max<long>(1, (n + 4095) / 4096));
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(parts), dim3(256), 0, s, n, x, y, part);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(256), 0, s, parts, part, out);
     return hipGetLastError();
 }
 
@@ -1065,7 +1116,7 @@ __global__ void normalize_factors_kernel(int n, double* U0, double* U1, double* 
     for (int l = 0; l < 3; ++l) {
         double s = 0.0;
         for (int i = tid; i < n; i += 256) s += U[l][i] * U[l][i];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        s = wave_sum(s);
         if ((tid & 63) == 0) red[tid >> 6] = s;
         __syncthreads();
         const double nrm = sqrt(red[0] + red[1] + red[2] + red[3]);
@@ -1157,18 +1208,11 @@ hipError_t cp_inner_reduce(int ra, int rb, const double* G0, const double* G1, c
 // Block-wide sum of one value per thread (blockDim.x == 1024).
 __device__ inline double block_sum_1024(double v, double* red) {
     const int tid = threadIdx.x;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    v = wave_sum(v);
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
-    double r = 0.0;
-    if (tid < 64) {
-        r = tid < 16 ? red[tid] : 0.0;
-        for (int off = 8; off > 0; off >>= 1) r += __shfl_down(r, off, 64);
-    }
-    __syncthreads();
-    if (tid == 0) red[16] = r;
-    __syncthreads();
-    r = red[16];
+    // every wavefront sums the 16 partials itself (no second barrier pair)
+    const double r = wave_sum((tid & 63) < 16 ? red[tid & 63] : 0.0);
     __syncthreads();
     return r;
 }
@@ -1195,7 +1239,7 @@ __global__ __launch_bounds__(1024) void mgs_kernel(int n, int m, double* Y, doub
                     const double* q = Y + (long)c * n;
                     for (int i = lane; i < n; i += 64) acc += q[i] * y[i];
                 }
-                for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+                acc = wave_sum(acc);
                 if (lane == 0) dots[w] = acc;
                 __syncthreads();
                 const int nc = min(16, kept - c0);
@@ -1269,7 +1313,7 @@ __global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, int b, double* Y
                         const double* q = P + (long)c * n;
                         for (int i = lane; i < n; i += 64) acc += q[i] * y[i];
                     }
-                    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+                    acc = wave_sum(acc);
                     if (lane == 0) dots[c] = acc;
                 }
                 __syncthreads();

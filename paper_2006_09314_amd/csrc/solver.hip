@@ -320,7 +320,7 @@ void perm_dims(const int r[3], int mode, int out[3]) {
 
 double host_dot(const Ctx& c, long n, const double* x, const double* y) {
     fc_plan_s* p = c.p;
-    HIPCHK(fc::dot_batched(n, 1, x, y, 0, p->scal, c.s));
+    HIPCHK(fc::dot_long(n, x, y, p->scal + 256, p->scal, c.s));
     double v = 0;
     d2h(c, &v, p->scal, 1);
     return v;
@@ -1021,7 +1021,7 @@ void alloc_workspace(fc_plan_s* p) {
         p->SM[l] = A.alloc((size_t)256 * 256);
     }
     p->jac = A.alloc((size_t)std::max<long>(3L * 6 * KM * KM, (long)rc * (rc + 1) * (rc + 1)));
-    p->scal = A.alloc(64);
+    p->scal = A.alloc(512);
     p->tmpn = A.alloc((size_t)n * std::max<long>(rc, 256));
     p->tmpn2 = A.alloc((size_t)n * std::max<long>(rc, 256));
     p->icount = A.alloc_int(16);
