@@ -47,6 +47,13 @@ hipError_t sym_eig(int k, int batch, const double* A, long lda, long strideA, do
 struct EigJob {
     const double* A = nullptr; long lda = 0; int k = 0;
     double* evals = nullptr; double* V = nullptr; long ldv = 0; double* scratch = nullptr;
+    // Eigenvectors wanted: all when budget < 0; else the first
+    // min(max(numrank, 1), max(rr + margin, 1)), rr the smallest count whose
+    // tail sum of positive eigenvalues is <= budget and numrank the count
+    // above 1e-17 of the largest (the rank rule of the truncations, applied
+    // to the same eigenvalues in the same order).  The other columns of V are
+    // left as they are.
+    double budget = -1.0; int margin = 0;
 };
 struct EigJobs {
     EigJob job[4];

@@ -632,6 +632,26 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
         if (act && q == 0) lam[grp] = 0.5 * (l + h);
     }
     __syncthreads();
+    __shared__ int nvec_s;
+    if (tid == 0) {
+        int nv = k;
+        if (J.budget >= 0.0) {
+            double tail = 0.0;
+            int rr = k;
+            for (int i = k - 1; i >= 0; --i) {
+                tail += fmax(lam[i], 0.0);
+                if (tail <= J.budget) rr = i; else break;
+            }
+            int numrank = 0;
+            const double tmax = fmax(lam[0], 0.0);
+            while (numrank < k && lam[numrank] > 1e-17 * tmax) ++numrank;
+            nv = min(max(numrank, 1), max(rr + J.margin, 1));
+            nv = min(nv, k);
+        }
+        nvec_s = nv;
+    }
+    __syncthreads();
+    const int nvec = nvec_s;
     // 3. inverse iteration, thread i owns eigenvector i (coalesced scratch)
     double* X = J.scratch;                    // X[i + j k]: element j of vector i
     double* U0 = X + (long)k * k;             // pivoted LU factors
@@ -639,7 +659,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
     double* U2 = U1 + (long)k * k;
     double* ML = U2 + (long)k * k;            // multipliers, sign encodes the interchange
     const double smallpiv = 1e-15 * fmax(tnorm, 1e-300);
-    if (tid < k) {
+    if (tid < nvec) {
         const int i = tid;
         const double lm = lam[i] + 4e-16 * tnorm * (1 + (i % 3));
         // factor T - lm I (rows: sub c_j = e[j-1], diag, super e[j])
@@ -735,8 +755,8 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
     for (int x = tid; x < k * k; x += blockDim.x) Rf[x] = a[x];
     __syncthreads();
     double* Xl = a;
-    for (int x = tid; x < k * k; x += blockDim.x) {
-        const int i = x % k, j = x / k;
+    for (int x = tid; x < nvec * k; x += blockDim.x) {
+        const int i = x % nvec, j = x / nvec;
         Xl[j + (long)i * kp] = X[i + (long)j * k];
     }
     __syncthreads();
@@ -752,7 +772,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
     double* used = e2;   // no longer needed: 1 for a vector that is refined
     for (int i = tid; i < k; i += blockDim.x) used[i] = fabs(lam[i]) > 1e-17 * lmax ? 1.0 : 0.0;
     __syncthreads();
-    for (int i = 1; i < k; ++i) {
+    for (int i = 1; i < nvec; ++i) {
         if (used[i] == 0.0 || lam[i - 1] - lam[i] >= 1e-9 * lmax) continue;
         double* xi = Xl + (long)i * kp;
         for (int pass = 0; pass < 2; ++pass) {
@@ -795,26 +815,26 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
         for (int r = tid; r < m; r += blockDim.x) vv[r] = Rf[(j + 1 + r) + j * k];
         __syncthreads();
         // s_i = t * v^T V[j+1:, i], four threads per column
-        for (int base = 0; base < 4 * k; base += blockDim.x) {
+        for (int base = 0; base < 4 * nvec; base += blockDim.x) {
             const int x = base + tid;
             const int i = x >> 2, part = x & 3;
             double acc = 0.0;
-            if (i < k && used[i] != 0.0) {
+            if (i < nvec && used[i] != 0.0) {
                 const double* col = Xl + (long)i * kp + (j + 1);
                 for (int r = part; r < m; r += 4) acc += vv[r] * col[r];
             }
             acc += __shfl_xor(acc, 1, 64);
             acc += __shfl_xor(acc, 2, 64);
-            if (i < k && part == 0) pw[i] = t * acc;
+            if (i < nvec && part == 0) pw[i] = t * acc;
         }
         __syncthreads();
-        for (int x = tid; x < m * k; x += blockDim.x) {
+        for (int x = tid; x < m * nvec; x += blockDim.x) {
             const int r = x % m, i = x / m;
             Xl[(j + 1 + r) + (long)i * kp] -= pw[i] * vv[r];
         }
         __syncthreads();
     }
-    for (int x = tid; x < k * k; x += blockDim.x) {
+    for (int x = tid; x < k * nvec; x += blockDim.x) {
         const int r = x % k, i = x / k;
         J.V[r + (long)i * J.ldv] = Xl[r + (long)i * kp];
     }

@@ -420,10 +420,10 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
             J.A = p->Cg + (long)l * KM * KM; J.lda = k[l]; J.k = k[l];
             J.evals = p->Cev + l * KM; J.V = p->Cvec + (long)l * KM * KM; J.ldv = k[l];
             J.scratch = p->jac + (long)l * 6 * KM * KM;
+            J.budget = thr2 / 3.0;   // vectors for the kept rank only
+            J.margin = 0;
         }
         HIPCHK(fc::sym_eig_multi(jobs, c.s));
-        for (int l = 0; l < 3; ++l)
-            check_cols(c, p->Cvec + (long)l * KM * KM, k[l], k[l], k[l], "core eigenvectors", l);
     }
     std::vector<double> ev(3 * KM);
     d2h(c, ev.data(), p->Cev, 3 * KM);
@@ -545,6 +545,8 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
             J.A = Bl; J.lda = kk[l]; J.k = kk[l];
             J.evals = p->Ev3 + l * KM; J.V = p->Evec3 + (long)l * KM * KM; J.ldv = kk[l];
             J.scratch = p->jac + (long)l * 6 * KM * KM;
+            J.budget = tail_budget;   // vectors for the rank rule below only
+            J.margin = margin;
         }
         HIPCHK(fc::sym_eig_multi(jobs, c.s));
         d2h(c, th.data(), p->Ev3, 3 * KM);
@@ -576,7 +578,7 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
                 continue;
             }
             const int use = std::min(std::max(numrank, 1), std::max(rr + margin, 1));
-            check_cols(c, Vl, kk[l], kk[l], kk[l], "Ritz vectors", l);
+            check_cols(c, Vl, kk[l], kk[l], use, "Ritz vectors", l);
             gemm(c, false, false, n, use, kk[l], 1.0, p->Xs3[l], n, Vl, kk[l], 0.0, p->W[l], n);
             check_cols(c, p->W[l], n, n, use, "subspace W", l);
             pk[l] = use;
