@@ -33,6 +33,15 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The batched call runs 16 solves on 16 streams; HIP maps streams onto its
+# hardware queues (4 by default), so ask for at least one queue per stream.
+# Read by the HIP runtime when it initialises, i.e. before torch touches the GPU.
+try:
+    _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+except ValueError:
+    _hwq = 0
+if _hwq < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "rank-truncated PCG solves/sec at n=1024, ε=1e-6: mixed/batched vs FP64"
 PEAK_FP64_TFLOPS = 78.6
@@ -126,40 +135,49 @@ def batch_io(api, torch, dev, probs, cap):
     return inputs, outs
 
 
-def gemm_profile(lib, check):
+KERNELS = {0: "GEMM family (hand-written Gram-type and MFMA kernels, rocBLAS dgemm)",
+           1: "panel_mgs_kernel (Gram-Schmidt panel, one workgroup)",
+           2: "tdeig_kernel (symmetric eigensolver, one workgroup per matrix)"}
+
+
+def kernel_profile(lib, check, kind):
     launches, ms, flops, byts = C.c_long(), C.c_double(), C.c_double(), C.c_double()
-    check(lib().fc_profile_gemm_read(C.byref(launches), C.byref(ms), C.byref(flops),
-                                     C.byref(byts)), "fc_profile_gemm_read")
+    check(lib().fc_profile_kernel_read(kind, C.byref(launches), C.byref(ms), C.byref(flops),
+                                       C.byref(byts)), "fc_profile_kernel_read")
     return launches.value, ms.value, flops.value, byts.value
 
 
-def roofline(launches, ms, flops, byts):
-    """Roofline of the FP64 matrix-core GEMM from HIP-event timings: the
-    algorithmic work per launch over the mean launch duration, against the
-    HBM roof when the arithmetic intensity is below the ridge point."""
+def roofline(kind, launches, ms, flops, byts):
+    """Roofline of one kernel family from HIP-event timings: the algorithmic
+    work per launch over the mean launch duration, against the HBM roof when
+    the arithmetic intensity is below the FP64 ridge point, else the FP64
+    matrix-core roof."""
     per_launch_s = (ms / 1e3) / max(launches, 1)
     fl_launch = flops / max(launches, 1)
     by_launch = byts / max(launches, 1)
     ai = flops / max(byts, 1.0)
     if ai >= PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
+        # above the ridge: the FP64 matrix cores for the GEMMs; the eigensolver
+        # computes on the FP64 vector units (same 78.6 TFLOP/s peak)
         achieved = fl_launch / per_launch_s / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
+        roof = {"bound": "alu" if kind == 2 else "mfma", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": None}
     else:
         achieved = by_launch / per_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof.update({"kernel": "gemm_kernel (FP64 MFMA 16x16x4, all tile variants)",
-                 "launches_timed": launches, "avg_launch_us": per_launch_s * 1e6,
-                 "flops_per_launch": fl_launch, "bytes_per_launch": by_launch,
-                 "arith_intensity": ai})
+    roof.update({"kernel": KERNELS[kind], "launches_timed": launches,
+                 "avg_launch_us": per_launch_s * 1e6, "flops_per_launch": fl_launch,
+                 "bytes_per_launch": by_launch, "arith_intensity": ai})
     return roof
 
 
-def recorded_traffic():
-    """HBM bytes per GEMM launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, if the GEMM source is unchanged since it was taken
-    (the record carries the SHA-256 of the kernel source); else None."""
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, if the kernel source is unchanged since
+    it was taken (the record carries the SHA-256 of the kernel source); else
+    None."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_2006_09314_amd", "csrc", "kernels.hip")
@@ -170,8 +188,10 @@ def recorded_traffic():
             for line in f:
                 if line.startswith("traffic-record: "):
                     rec = json.loads(line[len("traffic-record: "):])
+                    if rec.get("kernel") != kernel:
+                        continue
                     if rec.get("kernel_source_sha256") == digest:
-                        return rec["gemm_hbm_bytes_per_launch"], os.path.basename(path)
+                        return rec["hbm_bytes_per_launch"], os.path.basename(path)
                     return None, f"{os.path.basename(path)} (stale: kernel source changed)"
     return None, "no counter record"
 
@@ -253,12 +273,23 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     check(lib().fc_profile_gemm(0), "fc_profile_gemm")
-    sl, sms, sfl, sby = gemm_profile(lib, check)
-    roof = roofline(sl, sms, sfl, sby)
+    profs = {k: kernel_profile(lib, check, k) for k in (0, 1, 2)}
+    # the dominant single kernel of the solve (largest share of kernel time in
+    # the rocprofv3 trace) is the Gram-Schmidt panel kernel
+    roof = roofline(1, *profs[1])
     roof["measured_in"] = ("FP64 single-solve timed region, one stream (under concurrent streams "
                            "HIP events time queueing, not kernel duration)")
-    roof["gemm_bytes_per_solve"] = sby / args.single_steps
-    roof["traffic"], roof["traffic_source"] = recorded_traffic()
+    roof["share_of_solve"] = (profs[1][1] / 1e3) / el
+    roof["traffic"], roof["traffic_source"] = recorded_traffic("panel_mgs_kernel")
+    others = {}
+    for k, name in ((0, "gemm_family"), (2, "eigensolver")):
+        r = roofline(k, *profs[k])
+        r["share_of_solve"] = (profs[k][1] / 1e3) / el
+        r["per_solve_bytes"] = profs[k][3] / args.single_steps
+        others[name] = r
+    roof["other_kernels"] = others
+    sl = profs[0][0]
+    sms = profs[0][1]
     single = {"solves_per_s": args.single_steps / el, "ms_per_solve": 1e3 * el / args.single_steps,
               "info": res[2], "gemm_launches_per_solve": sl / args.single_steps,
               "gemm_share_of_solve": (sms / 1e3) / el}
@@ -305,10 +336,12 @@ def main():
     value = args.steps * len(probs) / elapsed
     # GEMM bytes moved per second of the batched steps (all streams together),
     # from the per-solve algorithmic GEMM bytes of the single-solve profile
-    roof["aggregate_gemm_gbs_batched"] = roof["gemm_bytes_per_solve"] * value / 1e9
+    roof["other_kernels"]["gemm_family"]["aggregate_gbs_batched"] = (
+        roof["other_kernels"]["gemm_family"]["per_solve_bytes"] * value / 1e9)
     iters = [r[2]["iterations"] for r in res_b]
     batched = {"problems": len(probs), "setup_s": bsetup, "solves_per_s": value,
-               "streams": int(os.environ.get("FC_BATCH_STREAMS", "8")),
+               "streams": int(os.environ.get("FC_BATCH_STREAMS", "16")),
+               "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                "iterations_min_max": [min(iters), max(iters)],
                "vs_fp64_single": value / single["solves_per_s"]}
     log(f"[bench] batched FP64: {args.steps} x {len(probs)} solves in {elapsed:.2f}s -> "

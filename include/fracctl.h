@@ -149,7 +149,11 @@ fc_status fc_solve_state(fc_plan plan, int rank_y, const double* w_y, const doub
  * differ in n and alpha).  Arrays are HOST arrays of length `count`; the
  * per-problem pointers follow fc_solve.  status[i] receives each problem's
  * own status; the return value is FC_OK if every problem succeeded, else the
- * first failing status.  Problems run concurrently on the given stream. */
+ * first failing status.  Problems run concurrently: worker threads (16, or
+ * the environment variable FC_BATCH_STREAMS) each solve on a stream of their
+ * own after the given stream's pending work; the call returns when all are
+ * done.  The HIP runtime maps streams onto GPU_MAX_HW_QUEUES hardware queues
+ * (4 unless set before the runtime starts), which bounds the concurrency. */
 fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
                            const double* const* w_y, const double* const* Y1,
                            const double* const* Y2, const double* const* Y3,
@@ -239,6 +243,14 @@ fc_status fc_host_separable(const fc_setup_params* p, int which, int cap, int* r
  * Process-wide; not thread-safe; meant for benchmarks. */
 fc_status fc_profile_gemm(int enable);
 fc_status fc_profile_gemm_read(long* launches, double* total_ms, double* flops, double* bytes);
+
+/* The same for another kernel family timed while fc_profile_gemm is on:
+ * kind 0 the GEMMs (as fc_profile_gemm_read), 1 the Gram-Schmidt panel kernel
+ * (16 n b bytes: its n x b panel read and written once; 4 n b^2 flops per two
+ * passes), 2 the symmetric eigensolver (16 k^2 bytes and (4/3 + 2) k^3 flops
+ * per matrix). */
+fc_status fc_profile_kernel_read(int kind, long* launches, double* total_ms, double* flops,
+                                 double* bytes);
 
 /* Self-test of the matrix-core operand layouts: one 16x16x4 product of fixed
  * matrices on the FP64 matrix core (out[0..255], row-major) and on the FP32

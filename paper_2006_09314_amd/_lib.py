@@ -100,6 +100,7 @@ PROTOTYPES = {
     "fc_selftest_mfma": (_I, [_PD]),
     "fc_selftest_eig": (_I, [_I, _PD, _PD, _PD]),
     "fc_profile_gemm": (_I, [_I]),
+    "fc_profile_kernel_read": (_I, [_I, C.POINTER(C.c_long), _PD, _PD, _PD]),
     "fc_profile_gemm_read": (_I, [C.POINTER(C.c_long), _PD, _PD, _PD]),
     "fc_status_string": (C.c_char_p, [_I]),
     "fc_last_error": (C.c_char_p, []),

@@ -178,6 +178,52 @@ GemmProfile g_prof;
 std::mutex g_prof_mu;
 thread_local bool t_no_profile = false;   // set in batch workers
 
+// The same HIP-event timing for the Gram-Schmidt panel kernel (kind 1) and
+// the eigensolver (kind 2), enabled together with the GEMM timing.
+struct KernelProfile {
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    double flops = 0, bytes = 0;
+    long launches = 0;
+};
+KernelProfile k_prof[3];
+
+// algorithmic work of a batch of symmetric eigenproblems: Householder
+// tridiagonalisation 4/3 k^3 and back-transformation 2 k^2 k flops per
+// matrix; the matrix read and the vectors written once
+double eig_flops(const fc::EigJobs& j) {
+    double f = 0;
+    for (int i = 0; i < j.count; ++i) f += (4.0 / 3.0 + 2.0) * std::pow((double)j.job[i].k, 3);
+    return f;
+}
+double eig_bytes(const fc::EigJobs& j) {
+    double b = 0;
+    for (int i = 0; i < j.count; ++i) b += 16.0 * (double)j.job[i].k * j.job[i].k;
+    return b;
+}
+
+template <class F>
+hipError_t timed_launch(int kind, hipStream_t s, double flops, double bytes, F&& launch) {
+    if (!g_prof.on || t_no_profile) return launch();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    KernelProfile& kp = k_prof[kind];
+    if (kp.used + 2 > kp.ev.size())
+        for (int i = 0; i < 256; ++i) {
+            hipEvent_t e;
+            hipError_t er = hipEventCreate(&e);
+            if (er != hipSuccess) return er;
+            kp.ev.push_back(e);
+        }
+    hipError_t e = hipEventRecord(kp.ev[kp.used], s);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(kp.ev[kp.used + 1], s);
+    kp.used += 2;
+    kp.flops += flops;
+    kp.bytes += bytes;
+    kp.launches += 1;
+    return e;
+}
+
 struct Ctx {
     fc_plan_s* p;
     hipStream_t s;
@@ -356,11 +402,16 @@ int orthonormalize(const Ctx& c, int m, double* Y, double drop, int done = 0, in
             gemm(c, true, false, j0, bw, n, 1.0, Y, n, P, n, 0.0, p->qrC, j0);
             gemm(c, false, false, n, bw, j0, -1.0, Y, n, p->qrC, j0, 1.0, P, n);
         }
-        HIPCHK(fc::panel_mgs(n, bw, P, norms + j0, drop, keep + j0, 2, c.s));
+        // algorithmic work: the panel read and written once, two MGS passes
+        HIPCHK(timed_launch(1, c.s, 4.0 * n * bw * bw, 16.0 * n * bw, [&] {
+            return fc::panel_mgs(n, bw, P, norms + j0, drop, keep + j0, 2, c.s);
+        }));
         if (j0 > 0) {
             gemm(c, true, false, j0, bw, n, 1.0, Y, n, P, n, 0.0, p->qrC, j0);
             gemm(c, false, false, n, bw, j0, -1.0, Y, n, p->qrC, j0, 1.0, P, n);
-            HIPCHK(fc::panel_mgs(n, bw, P, nullptr, 0.5, keep + j0, 1, c.s));
+            HIPCHK(timed_launch(1, c.s, 2.0 * n * bw * bw, 16.0 * n * bw, [&] {
+                return fc::panel_mgs(n, bw, P, nullptr, 0.5, keep + j0, 1, c.s);
+            }));
         }
     }
     HIPCHK(fc::compact_cols(n, m, Y, keep, p->qrTmp, p->icount + 4 + slot, c.s));
@@ -423,7 +474,8 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
             J.budget = thr2 / 3.0;   // vectors for the kept rank only
             J.margin = 0;
         }
-        HIPCHK(fc::sym_eig_multi(jobs, c.s));
+        HIPCHK(timed_launch(2, c.s, eig_flops(jobs), eig_bytes(jobs),
+                            [&] { return fc::sym_eig_multi(jobs, c.s); }));
     }
     std::vector<double> ev(3 * KM);
     d2h(c, ev.data(), p->Cev, 3 * KM);
@@ -548,7 +600,8 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
             J.budget = tail_budget;   // vectors for the rank rule below only
             J.margin = margin;
         }
-        HIPCHK(fc::sym_eig_multi(jobs, c.s));
+        HIPCHK(timed_launch(2, c.s, eig_flops(jobs), eig_bytes(jobs),
+                            [&] { return fc::sym_eig_multi(jobs, c.s); }));
         d2h(c, th.data(), p->Ev3, 3 * KM);
         bool again = false;
         for (int l = 0; l < 3; ++l) {
@@ -1811,7 +1864,7 @@ fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
     // take problems in order from a shared counter.  The caller's stream is
     // joined at the start (its pending work completes before any solve
     // starts); every solve synchronises its own stream before it returns.
-    int workers = 8;
+    int workers = 16;
     if (const char* env = std::getenv("FC_BATCH_STREAMS")) workers = std::max(1, std::atoi(env));
     workers = std::min(workers, count);
     int dev = 0;
@@ -1855,11 +1908,38 @@ fc_status fc_profile_gemm(int enable) {
         g_prof.on = true;
         g_prof.used = 0;
         g_prof.shapes.clear();
+        for (KernelProfile& kp : k_prof) {
+            kp.used = 0;
+            kp.flops = kp.bytes = 0;
+            kp.launches = 0;
+        }
         g_prof.flops = g_prof.bytes = 0;
         g_prof.launches = 0;
     } else {
         g_prof.on = false;
     }
+    return FC_OK;
+}
+
+fc_status fc_profile_kernel_read(int kind, long* launches, double* total_ms, double* flops,
+                                 double* bytes) {
+    if (kind == 0) return fc_profile_gemm_read(launches, total_ms, flops, bytes);
+    if (kind < 1 || kind > 2 || !launches || !total_ms || !flops || !bytes)
+        return fail(FC_ERR_INVALID_ARG, "fc_profile_kernel_read: bad arguments");
+    KernelProfile& kp = k_prof[kind];
+    double ms = 0;
+    for (size_t i = 0; i + 1 < kp.used; i += 2) {
+        if (hipEventSynchronize(kp.ev[i + 1]) != hipSuccess)
+            return fail(FC_ERR_HIP, "hipEventSynchronize failed");
+        float t = 0;
+        if (hipEventElapsedTime(&t, kp.ev[i], kp.ev[i + 1]) != hipSuccess)
+            return fail(FC_ERR_HIP, "hipEventElapsedTime failed");
+        ms += t;
+    }
+    *launches = kp.launches;
+    *total_ms = ms;
+    *flops = kp.flops;
+    *bytes = kp.bytes;
     return FC_OK;
 }
 
