@@ -16,7 +16,11 @@ by mathematics, never against itself.
 * the state and the cost functional: hand-solved n = 1 values, the dense
   matrix function, and the optimality of the exact control (J is stationary
   there, its second variation is the quadratic form of the problem, and
-  J* = 1/2 <y_Omega, y_Omega - y*>).
+  J* = 1/2 <y_Omega, y_Omega - y*>);
+* preconditioner case (A): the sine matrix against SciPy's DST-I, the sine
+  diagonalisation of the finite-difference Laplacian, hand-solved n = 1
+  values, the dense n^3 x n^3 matrix function of the anisotropic Laplacian,
+  and exactness for constant coefficients (P F(A) = I).
 """
 import os
 
@@ -24,7 +28,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from oracle import brute, fd, solve, tensor
+from oracle import brute, fd, precond, solve, tensor
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fd_hand_values.txt")
 
@@ -341,3 +345,121 @@ def test_cost_and_state_evaluators_against_full_grid():
     want = np.linalg.norm(cand - y) / np.linalg.norm(y)
     assert rep["rel_l2"] == pytest.approx(want, rel=1e-8)
 
+
+
+# ---- preconditioner case (A), Section 3.5 ----------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 1000])
+def test_dst1_matrix_matches_library_dst(n):
+    """S x equals SciPy's orthonormal DST-I; S is symmetric and its own inverse."""
+    import scipy.fft
+    S = precond.dst1_matrix(n)
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, 3))
+    want = scipy.fft.dst(X, type=1, norm="ortho", axis=0)
+    np.testing.assert_allclose(S @ X, want, rtol=0, atol=1e-13 * np.abs(want).max())
+    np.testing.assert_allclose(S, S.T, rtol=0, atol=0)
+    np.testing.assert_allclose(S @ S, np.eye(n), rtol=0, atol=1e-13 * max(1, n) ** 0.5)
+
+
+@pytest.mark.parametrize("n", [2, 7, 50])
+def test_sine_basis_diagonalises_the_fd_laplacian(n):
+    """S Delta S = diag(mu) with Delta the finite-difference matrix of a = 1
+    (Section 3.2) and mu ascending (eqn DiagLaplace)."""
+    S = precond.dst1_matrix(n)
+    Delta = fd.stiffness_dense(np.ones(n + 1))
+    mu = precond.laplace_eigenvalues(n)
+    D = S @ Delta @ S
+    np.testing.assert_allclose(D, np.diag(mu), rtol=0, atol=1e-12 * mu.max())
+    assert np.all(np.diff(mu) > 0)
+
+
+def test_golden_case_a_n1():
+    seen = 0
+    for rest in _golden_lines("precond"):
+        lhs, rhs = rest.split(":")
+        v = [float(x) for x in lhs.split()]
+        alpha, beta, gamma, b0 = v[0], v[1], v[2], v[3:6]
+        one = np.ones((1, 1), order="F")
+        prob = wl.Problem("golden", 1, [np.ones(2)] * 3, alpha, beta, gamma, 1e-6, np.ones(1),
+                          [one, one, one])
+        z = precond.apply_full(prob, np.ones((1, 1, 1)), b0)
+        np.testing.assert_allclose(z.reshape(-1), [float(rhs)], rtol=1e-14)
+        seen += 1
+    assert seen >= 2
+
+
+def test_b0_midrange():
+    """eqn modcoeff: the mid-range of the samples; positive overrides win."""
+    prob = _tiny_problem(3, 0.5)
+    prob.a = [np.array([0.1, 2.0, 0.5, 1.0]), np.array([3.0, 3.0, 3.0, 3.0]),
+              np.array([1.0, 5.0, 2.0, 4.0])]
+    np.testing.assert_allclose(precond.b0_for(prob), [1.05, 3.0, 3.0])
+    np.testing.assert_allclose(precond.b0_for(prob, [0.0, 1.0, -1.0]), [1.05, 1.0, 3.0])
+
+
+@pytest.mark.parametrize("alpha", [0.1, 0.5, 1.0])
+def test_case_a_dense_brute_force(alpha):
+    """P r against the dense n^3 x n^3 matrix function: B = Kronecker sum of
+    b0_l Delta assembled densely, B0 = beta B^-alpha + (gamma/beta) B^alpha
+    from its dense eigendecomposition, z = B0^-1 r by a dense solve."""
+    n = 4
+    b0 = [1.7, 0.4, 2.3]
+    prob = _tiny_problem(n, alpha)
+    prob.beta, prob.gamma = 1.3, 0.6
+    I = np.eye(n)
+    Delta = fd.stiffness_dense(np.ones(n + 1))
+    B = (np.kron(np.kron(b0[0] * Delta, I), I) + np.kron(np.kron(I, b0[1] * Delta), I)
+         + np.kron(np.kron(I, I), b0[2] * Delta))
+    mu, Q = np.linalg.eigh(B)
+    B0 = (Q * (prob.beta * mu ** (-alpha) + prob.gamma / prob.beta * mu ** alpha)[None, :]) @ Q.T
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal((n, n, n))
+    want = np.linalg.solve(B0, r.reshape(-1)).reshape(n, n, n)
+    got = precond.apply_full(prob, r, b0)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("alpha", [0.25, 1.0])
+def test_case_a_is_exact_for_constant_coefficients(alpha):
+    """With a_l = c_l constant, A = B for b0_l = c_l (the default mid-range),
+    so P F(A) x = x: F(A) x from the oracle's eigen-path (LAPACK eigenpairs of
+    the finite-difference matrices), P from the sine path."""
+    n = 9
+    c = [0.7, 1.9, 3.1]
+    prob = _tiny_problem(n, alpha)
+    prob.a = [np.full(n + 1, cl) for cl in c]
+    b0 = precond.b0_for(prob)
+    np.testing.assert_allclose(b0, c)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((n, n, n))
+    Fx = brute.dense_operator_apply(prob, x)
+    np.testing.assert_allclose(precond.apply_full(prob, Fx, b0), x, rtol=0, atol=1e-11)
+    sp = solve.Spectral(prob)
+    xh = solve.mode_products(x, [V.T for V in sp.V])
+    Fxh = solve.mode_products(Fx, [V.T for V in sp.V])
+    np.testing.assert_allclose(precond.apply_eig(prob, sp, Fxh, b0), xh, rtol=0, atol=1e-11)
+
+
+def test_case_a_spectral_bound_for_variable_coefficients():
+    """Section 3.5 (the condition bound of case (A)): c1 B <= A <= c2 B in the
+    Loewner order with c1 = min_l min a_l/b0_l, c2 = max_l max a_l/b0_l (the
+    finite-difference matrix is monotone in its coefficient), so by the
+    Loewner-Heinz inequality the spectrum of P F(A) lies in
+    [min(c1^alpha, c2^-alpha), max(c1^-alpha, c2^alpha)].  Checked densely at
+    n = 4 with the paper's coefficients."""
+    n = 4
+    prob = wl.workload_paper_shaped(n, 0.5)
+    b0 = precond.b0_for(prob)
+    Fx = np.stack([brute.dense_operator_apply(prob, e.reshape(n, n, n)).reshape(-1)
+                   for e in np.eye(n ** 3)], axis=1)
+    Pm = np.stack([precond.apply_full(prob, e.reshape(n, n, n), b0).reshape(-1)
+                   for e in np.eye(n ** 3)], axis=1)
+    ev = np.linalg.eigvals(Pm @ Fx)
+    assert np.abs(ev.imag).max() < 1e-9
+    ev = ev.real
+    lo = min(float(np.min(a)) / b for a, b in zip(prob.a, b0))
+    hi = max(float(np.max(a)) / b for a, b in zip(prob.a, b0))
+    # f(t s)/f(s) lies in [min(t^-alpha, t^alpha), max(t^-alpha, t^alpha)]
+    k = max(lo ** -prob.alpha, hi ** prob.alpha, lo ** prob.alpha, hi ** -prob.alpha)
+    assert ev.min() > 1.0 / k - 1e-9 and ev.max() < k + 1e-9
