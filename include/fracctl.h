@@ -63,6 +63,20 @@ typedef enum {
  * stay FP64. */
 typedef enum { FC_FP64 = 0, FC_MIXED_FP32 = 1 } fc_precision;
 
+/* Preconditioner (Section 3.5).
+ * FC_PRECOND_EIGEN (case (B)): D~_p ~ 1/f(lambda1 + lambda2 + lambda3) in the
+ *   eigenbasis of the variable-coefficient matrices, no transforms.
+ * FC_PRECOND_LAPLACE (case (A)): P = (beta B^-alpha + (gamma/beta) B^alpha)^-1
+ *   (eqn Precond_var) for the constant-coefficient anisotropic Laplacian
+ *   B = sum_l b0_l Delta_l (eqn PrecClassA), diagonal in the sine (DST-I)
+ *   basis (eqn DiagLaplace) with entries 1/f(b0_1 mu_i + b0_2 mu_j + b0_3 mu_k),
+ *   mu_k = (4/h^2) sin^2(k pi h/2).  Each application maps the iterate's
+ *   factors from the eigenbasis of A_l to the sine basis with the dense
+ *   orthogonal W_l = S V_l (S the orthonormal DST-I matrix, formed at setup),
+ *   applies the separable symbol there and maps back with W_l^T.  b0_l = 1 in
+ *   every mode is the classical Laplacian of the paper's 3D tests (Section 4). */
+typedef enum { FC_PRECOND_EIGEN = 0, FC_PRECOND_LAPLACE = 1 } fc_precond_kind;
+
 /* Setup parameters.  Zero-valued optional fields select the defaults. */
 typedef struct {
     int n;                  /* interior nodes per mode, 2 <= n <= 4096                        */
@@ -76,6 +90,9 @@ typedef struct {
     int max_rank;           /* Tucker rank capacity per mode; 0 -> 64, at most 96              */
     int precond_rank;       /* Kronecker rank of the preconditioner; 0 -> 6 (Section 4)        */
     fc_precision precision; /* FC_FP64 or FC_MIXED_FP32                                        */
+    fc_precond_kind precond; /* FC_PRECOND_EIGEN (0, default) or FC_PRECOND_LAPLACE             */
+    double precond_b0[3];   /* case (A) constants b0_l; <= 0 -> (max a_l + min a_l)/2 over the
+                               samples (eqn modcoeff); finite                                  */
 } fc_setup_params;
 
 /* Per-solve report (HOST struct). */
@@ -89,7 +106,8 @@ typedef struct {
     int precond_rank;       /* Kronecker rank of the preconditioner                            */
     double rel_residual;    /* ||R|| / ||Y|| of the recursively updated residual at exit       */
     double op_max_rel_err;  /* max over the spectrum of |D~/D - 1| (setup gate value)          */
-    double precond_max_rel_err; /* max over the spectrum of |D~_p D - 1|                       */
+    double precond_max_rel_err; /* max over the preconditioner's spectrum (of A, case (B); of B,
+                                   case (A)) of |D~_p f - 1|                                   */
     int state_rank;         /* Kronecker rank of the state map beta A^-alpha                   */
     double state_max_rel_err; /* max over the spectrum of its relative error (setup gate)      */
 } fc_info;
@@ -101,8 +119,9 @@ fc_status fc_setup(int n, const double* a1, const double* a2, const double* a3,
 /* Build a plan (paper Sections 3.2-3.5): the three 1D FD matrices, their
  * eigenpairs (host, tridiagonal QL), the separable operator
  * D~ ~ f(lambda1+lambda2+lambda3), f(s) = beta s^-alpha + (gamma/beta) s^alpha, and
- * the rank-precond_rank preconditioner D~_p ~ 1/f (preconditioner case (B),
- * Section 3.5), both as exponential sums with positive weights (sinc-type
+ * the rank-precond_rank preconditioner (case (B): D~_p ~ 1/f in the same
+ * eigenbasis; case (A): 1/f on the spectrum of the anisotropic Laplacian in
+ * the sine basis, see fc_precond_kind), both as exponential sums with positive weights (sinc-type
  * quadrature of the Laplace transform, Section 3.4, refined by least squares).
  * Uploads everything and allocates the solve workspace.  Fails with
  * FC_ERR_NUMERIC if the operator misses op_accuracy anywhere on
@@ -170,7 +189,9 @@ fc_status fc_plan_spectrum(fc_plan plan, double* lam, double* V);
 
 /* Separable factors of the operator (which = 0), the preconditioner
  * (which = 1) or the state map (which = 2) in eigen-coordinates: *rank terms, w (HOST, capacity cap) and
- * F (HOST, 3 consecutive n x cap column-major matrices, may be NULL). */
+ * F (HOST, 3 consecutive n x cap column-major matrices, may be NULL).  For
+ * FC_PRECOND_LAPLACE the preconditioner's rows are indexed by the sine mode k
+ * (ascending mu_k), not by the eigenpairs of A_l. */
 fc_status fc_plan_separable(fc_plan plan, int which, int cap, int* rank, double* w, double* F);
 
 /* ---- building blocks of the path, exposed for testing (DEVICE buffers) ---- */
@@ -200,8 +221,10 @@ fc_status fc_cp_truncate(fc_plan plan, int m, const double* w, const double* X1,
 /* Apply the operator (which = 0), preconditioner (which = 1) or state map
  * (which = 2) to a canonical
  * tensor given in eigen-coordinates, with truncation to relative accuracy eps
- * (Section 3.3, eqn. Gen3DtimesX, evaluated in eigen-coordinates).  DEVICE
- * buffers as in fc_cp_truncate. */
+ * (Section 3.3, eqn. Gen3DtimesX, evaluated in eigen-coordinates; for
+ * FC_PRECOND_LAPLACE eqn Lap3DtimesX with the sine-basis maps W_l, W_l^T
+ * around the separable symbol, result in eigen-coordinates).  DEVICE buffers
+ * as in fc_cp_truncate. */
 fc_status fc_apply_separable(fc_plan plan, int which, int m, const double* w, const double* X1,
                              const double* X2, const double* X3, double eps, int cap,
                              int* rank_out, double* w_out, double* O1, double* O2, double* O3,

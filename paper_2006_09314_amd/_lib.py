@@ -38,6 +38,8 @@ class SetupParams(C.Structure):
         ("max_rank", C.c_int),
         ("precond_rank", C.c_int),
         ("precision", C.c_int),
+        ("precond", C.c_int),
+        ("precond_b0", C.c_double * 3),
     ]
 
 
@@ -117,6 +119,11 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise LibraryMissing(
                 f"{LIB_PATH} not found; build it with `python -m paper_2006_09314_amd.build`")
+        # torch first: its HIP runtime (the one that owns the device buffers
+        # this binding passes) is then the one the library binds to by soname;
+        # loading the library first would bring in a second runtime that
+        # torch's own initialisation cannot share.
+        import torch  # noqa: F401
         h = C.CDLL(LIB_PATH)
         for name, (res, args) in PROTOTYPES.items():
             f = getattr(h, name)

@@ -35,7 +35,8 @@ class Plan:
     def __init__(self, n: int, a: Sequence[np.ndarray], alpha: float, beta: float,
                  gamma: float = 1.0, eps: float = 1e-6, tol: float = 0.0,
                  op_accuracy: float = 0.0, max_iter: int = 0, max_rank: int = 0,
-                 precond_rank: int = 0, precision: int = 0, stream=None):
+                 precond_rank: int = 0, precision: int = 0, stream=None, precond: int = 0,
+                 precond_b0: Optional[Sequence[float]] = None):
         self._a = [_host_array(x) for x in a]
         for x in self._a:
             if x.shape != (n + 1,):
@@ -48,6 +49,10 @@ class Plan:
         p.op_accuracy = op_accuracy
         p.max_iter, p.max_rank, p.precond_rank, p.precision = (max_iter, max_rank, precond_rank,
                                                                 precision)
+        p.precond = precond
+        if precond_b0 is not None:
+            for l in range(3):
+                p.precond_b0[l] = float(precond_b0[l])
         h = C.c_void_p()
         check(lib().fc_setup_ex(C.byref(p), _stream_ptr(stream), C.byref(h)), "fc_setup_ex")
         self.handle = h

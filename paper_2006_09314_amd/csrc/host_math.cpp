@@ -362,11 +362,19 @@ bool fit_expsum(const std::function<double(double)>& h, const std::function<doub
         P.wl.push_back(1.0);
     }
     std::vector<double> x(K);
-    // initial nodes: geometric between the scales of the interval ends
-    const double x0 = std::log(0.5 / s_max) - 2.0, x1 = std::log(30.0 / s_min);
-    for (int k = 0; k < K; ++k) x[k] = K == 1 ? 0.5 * (x0 + x1) : x0 + (x1 - x0) * double(k) / (K - 1);
+    // initial nodes: geometric between the scales of the interval ends.  The
+    // fastest node starts at 30/s_min; on wide intervals its column can fall
+    // below the rank test of the weighted design (it is ~exp(-30) at s_min
+    // against columns of size ~s_max), and then a slower start is taken.
     std::vector<double> cc;
-    if (!vp_lm(P, x, cc, 150)) return false;
+    bool started = false;
+    for (double fast : {30.0, 3.0, 1.0}) {
+        const double x0 = std::log(0.5 / s_max) - 2.0, x1 = std::log(fast / s_min);
+        for (int k = 0; k < K; ++k)
+            x[k] = K == 1 ? 0.5 * (x0 + x1) : x0 + (x1 - x0) * double(k) / (K - 1);
+        if (vp_lm(P, x, cc, 150)) { started = true; break; }
+    }
+    if (!started) return false;
     std::vector<double> bx = x, bc = cc;
     std::vector<double> tt(K);
     for (int k = 0; k < K; ++k) tt[k] = std::exp(x[k]);

@@ -75,8 +75,16 @@ struct Arena {
         blocks.push_back(p);
         return (int*)p;
     }
+    void release(void* q) {
+        for (size_t i = 0; i < blocks.size(); ++i)
+            if (blocks[i] == q) {
+                (void)hipFree(q);
+                blocks.erase(blocks.begin() + (long)i);
+                return;
+            }
+    }
     ~Arena() {
-        for (void* p : blocks) hipFree(p);
+        for (void* p : blocks) (void)hipFree(p);
     }
 };
 
@@ -92,7 +100,10 @@ struct Separable {
     std::vector<double> F[3];                     // host copies of unweighted factors n x Q
 };
 
-enum { SITE_Z = 0, SITE_S, SITE_X, SITE_R, SITE_P, SITE_MISC, SITE_OS, SITE_OR, SITE_OU, SITE_ST, NSITES };
+enum {
+    SITE_Z = 0, SITE_S, SITE_X, SITE_R, SITE_P, SITE_MISC, SITE_OS, SITE_OR, SITE_OU, SITE_ST, SITE_ZE,
+    NSITES
+};
 
 struct WarmBasis {
     double* W[3] = {nullptr, nullptr, nullptr};
@@ -109,9 +120,17 @@ struct fc_plan_s {
     double* V[3] = {nullptr, nullptr, nullptr};
     Separable op, pc, st;   // operator ~ f, preconditioner ~ 1/f, state map ~ beta s^-alpha
     double op_err = 0, pc_err = 0, st_err = 0;
+    // preconditioner case (A): 1/f on the spectrum of the anisotropic
+    // Laplacian in the sine basis, and the maps W_l = S V_l into that basis
+    int pc_kind = FC_PRECOND_EIGEN;
+    double b0[3] = {1.0, 1.0, 1.0};
+    std::vector<double> mu[3];    // host: b0_l (4/h^2) sin^2(k pi h/2), ascending
+    Separable pcA;
+    double pcA_err = 0;
+    double* Wsin[3] = {nullptr, nullptr, nullptr};
     Arena arena;
     // workspace
-    Tucker slot[13];
+    Tucker slot[14];
     fc_precision precision = FC_FP64;
     double *E = nullptr, *Gd[3] = {}, *Mq = nullptr, *c1 = nullptr, *c2 = nullptr;
     double *Xs = nullptr, *HX = nullptr, *Ys = nullptr, *Ts = nullptr, *F = nullptr;
@@ -229,6 +248,7 @@ struct Ctx {
     hipStream_t s;
     int n;
     bool lowp = false;   // bulk contractions on the FP32 matrix cores
+    bool clamp = false;  // search directions: cap HOSVD ranks at max_rank instead of failing
 };
 
 // Route one product: Gram-type (a small result: any A^T B, and A B^T or A B
@@ -500,9 +520,16 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
         return;
     }
     for (int l = 0; l < 3; ++l)
-        if (r[l] > p->rcap)
-            throw FcError(FC_ERR_INTERNAL, std::string(what) + ": Tucker rank " +
-                                               std::to_string(r[l]) + " exceeds max_rank");
+        if (r[l] > p->rcap) {
+            // a search direction (Z, P) only steers the iteration: its best
+            // rank-max_rank approximation keeps every recursion consistent
+            // (S is the operator applied to the P actually used)
+            if (!c.clamp)
+                throw FcError(FC_ERR_INTERNAL, std::string(what) + ": Tucker rank " +
+                                                   std::to_string(r[l]) + " exceeds max_rank");
+            FC_TRACE_PRINT("%s: mode %d rank %d capped at %d\n", what, l, r[l], p->rcap);
+            r[l] = p->rcap;
+        }
     // core projection: C x_l U_l^T
     int cur[3] = {k[0], k[1], k[2]};
     const double* src = C;
@@ -863,6 +890,44 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     (void)csz;
 }
 
+const Separable& active_pc(const fc_plan_s* p) {
+    return p->pc_kind == FC_PRECOND_LAPLACE ? p->pcA : p->pc;
+}
+
+double active_pc_err(const fc_plan_s* p) {
+    return p->pc_kind == FC_PRECOND_LAPLACE ? p->pcA_err : p->pc_err;
+}
+
+// Z = trunc(precond(R)) for an iterate in eigen-coordinates.  Case (B): the
+// Hadamard product with D~_p in the same coordinates.  Case (A) (eqn
+// Lap3DtimesX): the factors go to the sine basis (W_l Z_l, still
+// orthonormal), the Hadamard product with the Laplacian's symbol is truncated
+// there, and the result's factors come back with W_l^T.
+void apply_precond(const Ctx& c, const Tucker& R, double tol_rel, Tucker& Z, const char* what,
+                   int site) {
+    fc_plan_s* p = c.p;
+    if (p->pc_kind != FC_PRECOND_LAPLACE) {
+        had_trunc(c, p->pc, R, tol_rel, 0.0, Z, what, site);
+        return;
+    }
+    if (R.empty()) { Z.r[0] = Z.r[1] = Z.r[2] = 0; return; }
+    const int n = c.n;
+    Tucker& tmp = p->slot[13];
+    Tucker Rs;
+    for (int l = 0; l < 3; ++l) {
+        Rs.r[l] = R.r[l];
+        Rs.Z[l] = tmp.Z[l];
+        gemm(c, false, false, n, R.r[l], n, 1.0, p->Wsin[l], n, R.Z[l], n, 0.0, Rs.Z[l], n);
+    }
+    Rs.core = R.core;
+    had_trunc(c, p->pcA, Rs, tol_rel, 0.0, Z, what, site);
+    if (Z.empty()) return;
+    for (int l = 0; l < 3; ++l) {
+        gemm(c, true, false, n, Z.r[l], n, 1.0, p->Wsin[l], n, Z.Z[l], n, 0.0, tmp.Z[l], n);
+        std::swap(Z.Z[l], tmp.Z[l]);
+    }
+}
+
 // ---- canonical -> Tucker (exact unfolding spectra) ------------------------
 // Factors X_l (n x m, ld n) and weights w (m, device, may be null).
 void canon_to_tucker(const Ctx& c, int m, const double* w, const double* const X[3],
@@ -1030,9 +1095,9 @@ void reset_warm(fc_plan_s* p) {
 void alloc_workspace(fc_plan_s* p) {
     const int n = p->n;
     const long rc = p->rcap, pc = p->pcap;
-    const int Q = std::max({p->op.Q, p->pc.Q, p->st.Q});
+    const int Q = std::max({p->op.Q, p->pc.Q, p->st.Q, p->pcA.Q});
     Arena& A = p->arena;
-    for (int s = 0; s < 13; ++s) {
+    for (int s = 0; s < 14; ++s) {
         for (int l = 0; l < 3; ++l) p->slot[s].Z[l] = A.alloc((size_t)n * rc);
         p->slot[s].core = A.alloc((size_t)rc * rc * rc);
     }
@@ -1185,20 +1250,22 @@ void build_operator(fc_plan_s* p, double smin, double smax) {
         throw FcError(FC_ERR_NUMERIC, "operator gate failed: max rel err " + std::to_string(emax));
 }
 
-// Preconditioner case (B): D~_p ~ 1/f with precond_rank positive exponentials.
-void build_preconditioner(fc_plan_s* p, double smin, double smax) {
+// Preconditioner: 1/f with precond_rank positive exponentials on [smin, smax],
+// separable over the per-mode spectra lam[l] (case (B): the eigenvalues of
+// A_l; case (A): those of b0_l Delta_l).
+void build_preconditioner(fc_plan_s* p, double smin, double smax, const std::vector<double>* lam,
+                          Separable& S, double& err_out) {
     const int n = p->n;
     const double a = p->alpha, b = p->beta, gm = p->gamma;
-    Separable& S = p->pc;
     auto add = [&](double w, double t) {
         S.w.push_back(w);
         for (int l = 0; l < 3; ++l)
-            for (int i = 0; i < n; ++i) S.F[l].push_back(std::exp(-t * p->lam[l][i]));
+            for (int i = 0; i < n; ++i) S.F[l].push_back(std::exp(-t * lam[l][i]));
         S.Q++;
     };
     if (a == 0.0) {
         add(1.0 / (b + gm / b), 0.0);
-        p->pc_err = 0.0;
+        err_out = 0.0;
         return;
     }
     auto pf = [&](double s) { return 1.0 / f_control(s, a, b, gm); };
@@ -1214,7 +1281,25 @@ void build_preconditioner(fc_plan_s* p, double smin, double smax) {
     }
     if (!ok) throw FcError(FC_ERR_NUMERIC, "preconditioner fit failed");
     for (int k = 0; k < K; ++k) add(cc[k], t[k]);
-    p->pc_err = err;
+    err_out = err;
+}
+
+// Spectrum of the case (A) preconditioner: mu_l[k] = b0_l (4/h^2) sin^2(k pi h/2)
+// (eqn DiagLaplace, Section 3.4), b0_l the mid-range of the samples unless
+// given (eqn modcoeff).
+void laplace_spectrum(fc_plan_s* p, const fc_setup_params* prm) {
+    const int n = p->n;
+    const double h = 1.0 / (n + 1);
+    for (int l = 0; l < 3; ++l) {
+        double lo = prm->a[l][0], hi = prm->a[l][0];
+        for (int i = 1; i <= n; ++i) { lo = std::min(lo, prm->a[l][i]); hi = std::max(hi, prm->a[l][i]); }
+        p->b0[l] = prm->precond_b0[l] > 0 ? prm->precond_b0[l] : 0.5 * (lo + hi);
+        p->mu[l].resize(n);
+        for (int k = 1; k <= n; ++k) {
+            const double sn = std::sin(k * M_PI * h / 2.0);
+            p->mu[l][k - 1] = p->b0[l] * 4.0 / (h * h) * sn * sn;
+        }
+    }
 }
 
 // State map y = beta A^-alpha u (eqn `State`): beta s^-alpha is completely
@@ -1270,8 +1355,37 @@ void host_spectra_and_separables(fc_plan_s* p, const fc_setup_params* prm) {
     double smin = 0, smax = 0;
     for (int l = 0; l < 3; ++l) { smin += p->lam[l].front(); smax += p->lam[l].back(); }
     build_operator(p, smin, smax);
-    build_preconditioner(p, smin, smax);
+    build_preconditioner(p, smin, smax, p->lam, p->pc, p->pc_err);
     build_state_map(p, smin, smax);
+    if (p->pc_kind == FC_PRECOND_LAPLACE) {
+        laplace_spectrum(p, prm);
+        double mmin = 0, mmax = 0;
+        for (int l = 0; l < 3; ++l) { mmin += p->mu[l].front(); mmax += p->mu[l].back(); }
+        build_preconditioner(p, mmin, mmax, p->mu, p->pcA, p->pcA_err);
+    }
+}
+
+// W_l = S V_l: eigen-coordinates of A_l -> sine coordinates.  S[i,k] =
+// sqrt(2/(n+1)) sin(pi i k/(n+1)) with the integer i k reduced modulo
+// 2(n+1) before the sine; the product runs on the device.
+void build_sine_maps(fc_plan_s* p) {
+    const int n = p->n;
+    std::vector<double> S((size_t)n * n);
+    const double sc = std::sqrt(2.0 / (n + 1));
+    for (int k = 1; k <= n; ++k)
+        for (int i = 1; i <= n; ++i) {
+            const long m = ((long)i * k) % (2L * (n + 1));
+            S[(size_t)(k - 1) * n + (i - 1)] = sc * std::sin(M_PI * (double)m / (n + 1));
+        }
+    double* Sd = p->arena.alloc((size_t)n * n);
+    HIPCHK(hipMemcpy(Sd, S.data(), sizeof(double) * n * n, hipMemcpyHostToDevice));
+    Ctx c{p, p->stream, n};
+    for (int l = 0; l < 3; ++l) {
+        p->Wsin[l] = p->arena.alloc((size_t)n * n);
+        gemm(c, false, false, n, n, n, 1.0, Sd, n, p->V[l], n, 0.0, p->Wsin[l], n);
+    }
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->arena.release(Sd);
 }
 
 void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
@@ -1284,6 +1398,7 @@ void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
     upload_separable(p, p->op);
     upload_separable(p, p->pc);
     upload_separable(p, p->st);
+    if (p->pc_kind == FC_PRECOND_LAPLACE) upload_separable(p, p->pcA);
     alloc_workspace(p);
     // rocBLAS for plain products: a fixed workspace from the plan (no device
     // allocation during a solve), deterministic kernels only
@@ -1299,6 +1414,7 @@ void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
         if (rocblas_set_workspace(p->blas, ws, wsz) != rocblas_status_success)
             throw FcError(FC_ERR_HIP, "rocblas_set_workspace failed");
     }
+    if (p->pc_kind == FC_PRECOND_LAPLACE) build_sine_maps(p);
     HIPCHK(hipDeviceSynchronize());
 }
 
@@ -1323,10 +1439,12 @@ SolveOut pcg(const Ctx& c, const Tucker& Bt, Tucker& Xout, double eps, double to
     Tucker& T1 = p->slot[6];
     Tucker& T2 = p->slot[7];
     SolveOut so;
+    Ctx cd = c;
+    cd.clamp = true;                       // for the search directions Z and P
     const double bn = std::sqrt(tucker_norm2(c, Bt));
     X.r[0] = X.r[1] = X.r[2] = 0;
     tucker_copy(c, Bt, R);                 // R0 = B - fun(X0), X0 = 0
-    had_trunc(c, p->pc, R, eps, 0.0, Z, "Z0 = trunc(precond(R0))", SITE_Z);
+    apply_precond(cd, R, eps, Z, "Z0 = trunc(precond(R0))", SITE_Z);
     check_orth(c, Z, "Z0");
     tucker_copy(c, Z, P);                  // P0 = Z0
     double rz = tucker_inner(c, R, Z);
@@ -1352,12 +1470,12 @@ SolveOut pcg(const Ctx& c, const Tucker& Bt, Tucker& Xout, double eps, double to
                        c.lowp ? "(fp32)" : "", k + 1, so.rel_res, X.r[0], X.r[1], X.r[2], R.r[0],
                        R.r[1], R.r[2], S.r[0], S.r[1], S.r[2], P.r[0], P.r[1], P.r[2]);
         if (R.empty() || so.rel_res <= tol || rn <= stop_abs) { so.converged = true; break; }
-        had_trunc(c, p->pc, R, eps, 0.0, Z, "Z = trunc(precond(R))", SITE_Z);
+        apply_precond(cd, R, eps, Z, "Z = trunc(precond(R))", SITE_Z);
         check_orth(c, Z, "Z");
         const double rzn = tucker_inner(c, R, Z);
         const double bk = rzn / rz;
         rz = rzn;
-        sum_trunc(c, {{1.0, &Z}, {bk, &P}}, eps, 0.0, T1, "P = trunc(Z + bP)", SITE_P);
+        sum_trunc(cd, {{1.0, &Z}, {bk, &P}}, eps, 0.0, T1, "P = trunc(Z + bP)", SITE_P);
         check_orth(c, T1, "P");
         std::swap(P, T1);
         if (P.empty()) { so.converged = true; break; }
@@ -1390,7 +1508,11 @@ SolveOut mixed_solve(const Ctx& c0, const Tucker& Bt, Tucker& Uout, int& sweeps_
     const double bn = std::sqrt(tucker_norm2(cf, Bt));
     // error estimate: || D~_p (.) R || relative to || D~_p (.) B || (D~_p ~ D~^-1)
     Tucker& Zh = p->slot[3];
-    had_trunc(cf, p->pc, Bt, 1e-2, 0.0, Zh, "refinement: precond(B)", SITE_Z);
+    // the estimate always uses the case (B) symbol (no transforms); with case
+    // (A) in the inner solves its subspaces live in other coordinates, so it
+    // keeps warm starts of its own
+    const int est_site = p->pc_kind == FC_PRECOND_LAPLACE ? SITE_ZE : SITE_Z;
+    had_trunc(cf, p->pc, Bt, 1e-2, 0.0, Zh, "refinement: precond(B)", est_site);
     const double zbn = std::sqrt(tucker_norm2(cf, Zh));
     SolveOut total;
     int sweep = 0;
@@ -1408,7 +1530,7 @@ SolveOut mixed_solve(const Ctx& c0, const Tucker& Bt, Tucker& Uout, int& sweeps_
                 est = 0.0;
             } else {
                 // an estimate: two digits suffice
-                had_trunc(cf, p->pc, Rh, 1e-2, 0.0, Zh, "refinement: precond(R)", SITE_Z);
+                had_trunc(cf, p->pc, Rh, 1e-2, 0.0, Zh, "refinement: precond(R)", est_site);
                 est = std::sqrt(tucker_norm2(cf, Zh)) / zbn;
             }
             total.rel_res = Rh.empty() ? 0.0 : std::sqrt(tucker_norm2(cf, Rh)) / bn;
@@ -1528,9 +1650,9 @@ fc_status fc_host_separable(const fc_setup_params* prm, int which, int cap, int*
     apply_defaults(&p, prm);
     fc_status st = guard([&] { host_spectra_and_separables(&p, prm); });
     if (st != FC_OK) return st;
-    const Separable& S = which == 0 ? p.op : which == 1 ? p.pc : p.st;
+    const Separable& S = which == 0 ? p.op : which == 1 ? active_pc(&p) : p.st;
     *rank = S.Q;
-    if (max_rel_err) *max_rel_err = which == 0 ? p.op_err : which == 1 ? p.pc_err : p.st_err;
+    if (max_rel_err) *max_rel_err = which == 0 ? p.op_err : which == 1 ? active_pc_err(&p) : p.st_err;
     if (cap < S.Q) return fail(FC_ERR_RANK_OVERFLOW, "capacity too small");
     const int n = p.n;
     if (w) std::memcpy(w, S.w.data(), sizeof(double) * S.Q);
@@ -1559,6 +1681,11 @@ static fc_status validate_params(const fc_setup_params* prm) {
     if (prm->precond_rank > 32) return fail(FC_ERR_INVALID_ARG, "precond_rank must be <= 32");
     if (prm->precision != FC_FP64 && prm->precision != FC_MIXED_FP32)
         return fail(FC_ERR_INVALID_ARG, "unsupported precision");
+    if (prm->precond != FC_PRECOND_EIGEN && prm->precond != FC_PRECOND_LAPLACE)
+        return fail(FC_ERR_INVALID_ARG, "unknown preconditioner");
+    for (int l = 0; l < 3; ++l)
+        if (!std::isfinite(prm->precond_b0[l]))
+            return fail(FC_ERR_INVALID_ARG, "precond_b0 must be finite");
     return FC_OK;
 }
 
@@ -1572,6 +1699,7 @@ static void apply_defaults(fc_plan_s* p, const fc_setup_params* prm) {
     p->pcap = 128;
     p->precond_rank = prm->precond_rank > 0 ? prm->precond_rank : 6;
     p->precision = prm->precision;
+    p->pc_kind = prm->precond;
 }
 
 fc_status fc_setup_ex(const fc_setup_params* prm, void* hip_stream, fc_plan* out) {
@@ -1612,7 +1740,7 @@ fc_status fc_plan_spectrum(fc_plan p, double* lam, double* V) {
 
 fc_status fc_plan_separable(fc_plan p, int which, int cap, int* rank, double* w, double* F) {
     if (!p || !rank || which < 0 || which > 2) return fail(FC_ERR_INVALID_ARG, "fc_plan_separable: bad arguments");
-    const Separable& S = which == 0 ? p->op : which == 1 ? p->pc : p->st;
+    const Separable& S = which == 0 ? p->op : which == 1 ? active_pc(p) : p->st;
     *rank = S.Q;
     if (cap < S.Q) return fail(FC_ERR_RANK_OVERFLOW, "capacity too small");
     const int n = p->n;
@@ -1694,8 +1822,11 @@ fc_status fc_apply_separable(fc_plan p, int which, int m, const double* w, const
         Tucker& O = p->slot[9];
         canon_to_tucker(c, m, w, X, 1e-3 * eps, T, "input");
         reset_warm(p);
-        had_trunc(c, which == 0 ? p->op : which == 1 ? p->pc : p->st, T, eps / std::sqrt(2.0), 0.0, O,
-                  "apply", SITE_MISC);
+        if (which == 1)
+            apply_precond(c, T, eps / std::sqrt(2.0), O, "apply", SITE_MISC);
+        else
+            had_trunc(c, which == 0 ? p->op : p->st, T, eps / std::sqrt(2.0), 0.0, O, "apply",
+                      SITE_MISC);
         const double n2 = tucker_norm2(c, O);
         inner = canon_out(p, c, O, 0.5 * eps * eps * n2, false, cap, rank_out, w_out, O1, O2, O3);
     });
@@ -1788,11 +1919,11 @@ fc_status solve_impl(fc_plan p, int rank_y, const double* w_y, const double* Y1,
             for (int l = 0; l < 3; ++l) info->tucker_rank[l] = X.r[l];
             info->max_tucker_rank = p->max_seen_rank;
             info->op_rank = p->op.Q;
-            info->precond_rank = p->pc.Q;
+            info->precond_rank = active_pc(p).Q;
             info->rel_residual = so.rel_res;
             info->refinements = sweeps;
             info->op_max_rel_err = p->op_err;
-            info->precond_max_rel_err = p->pc_err;
+            info->precond_max_rel_err = active_pc_err(p);
             info->state_rank = p->st.Q;
             info->state_max_rel_err = p->st_err;
         }
@@ -1804,7 +1935,7 @@ fc_status solve_impl(fc_plan p, int rank_y, const double* w_y, const double* Y1,
             const double tot = std::chrono::duration<double, std::milli>(
                                    std::chrono::steady_clock::now() - t_solve).count();
             static const char* names[NSITES] = {"Z", "S", "X", "R", "P", "misc", "ref-S", "ref-R",
-                                                "ref-U", "state"};
+                                                "ref-U", "state", "ref-Z"};
             std::string line = "[fc] solve " + std::to_string(tot) + " ms; truncations:";
             for (int i = 0; i < NSITES; ++i)
                 if (p->site_calls[i])

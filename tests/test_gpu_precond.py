@@ -1,0 +1,151 @@
+"""Preconditioner case (A) (Section 3.5) on the GPU: the sine-basis
+application against the oracle, solves with it against the exact solution
+(relative L2 error <= 10 eps), and the iteration counts of the paper's
+anisotropic-preconditioning experiment (Section 4, Table 4.6: flat in n)."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import precond as opc
+from oracle import solve as osolve
+from oracle import tensor as ot
+
+pytestmark = pytest.mark.gpu
+
+GATE = 10.0  # error gate in units of eps
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    from tests.gpu_util import require_gpu
+    require_gpu()
+
+
+def _solve(prob, slabs=None, **kw):
+    from tests.gpu_util import plan_for, solve
+    print(f"[case] {prob.name} n={prob.n} rank={prob.rank} alpha={prob.alpha} {kw}", flush=True)
+    plan = plan_for(prob, **kw)
+    w_u, U, info = solve(plan, prob)
+    rep = osolve.rel_error(prob, w_u, U, slabs=slabs)
+    print(f"[result] {prob.name}: rel_l2={rep['rel_l2']:.3e} iterations={info['iterations']} "
+          f"precond_err={info['precond_max_rel_err']:.3e}", flush=True)
+    return rep, info
+
+
+def _check(prob, slabs=None, **kw):
+    rep, info = _solve(prob, slabs=slabs, **kw)
+    assert rep["rel_l2"] <= GATE * prob.eps, rep
+    return rep, info
+
+
+@pytest.mark.parametrize("b0", [None, (1.0, 1.0, 1.0)])
+def test_apply_case_a_matches_oracle(b0):
+    """fc_apply_separable(which = 1) with case (A): W_l^T (D~_A (.) (W_l X))
+    for a canonical X in eigen-coordinates.  Checked (1) against the same
+    separable symbol applied through the oracle's sine matrix, to the
+    truncation accuracy, and (2) against the oracle's exact B0^-1, to the
+    symbol's fit error."""
+    import torch
+    from tests.gpu_util import dev, host, plan_for
+    n = 24
+    prob = wl.workload_paper_shaped(n, 0.5)
+    plan = plan_for(prob, precond=1, precond_b0=b0)
+    lam, V = plan.spectrum(with_vectors=True)
+    sp = osolve.Spectral(prob)
+    for l in range(3):   # the plan's eigenvectors are the oracle's up to column signs
+        np.testing.assert_allclose(np.abs(V[l].T @ sp.V[l]), np.eye(n), rtol=0, atol=1e-9)
+    rng = np.random.default_rng(21)
+    F = [np.exp(-np.arange(n)[:, None] / 5.0) * rng.standard_normal((n, 3)) for _ in range(3)]
+    w = np.array([1.0, 0.4, -0.3])
+    eps = 1e-8
+    wo, O = plan.apply_separable(1, torch.from_numpy(w).cuda(), [dev(f) for f in F], eps)
+    got = ot.cp_full(host(wo), [host(o) for o in O])
+    T = ot.cp_full(w, F)
+    S = opc.dst1_matrix(n)
+    W = [S @ V[l] for l in range(3)]
+    ws, Fs = plan.separable(1)
+    Dt = ot.cp_full(ws, Fs)
+    want = osolve.mode_products(Dt * osolve.mode_products(T, W), [Wl.T for Wl in W])
+    assert np.linalg.norm(got - want) <= 1.01 * eps * np.linalg.norm(want) + 1e-12 * np.linalg.norm(want)
+    bb = opc.b0_for(prob, b0)
+    P = opc.symbol(prob, bb)
+    fit = np.abs(Dt / P - 1).max()
+    assert fit < 0.1
+    grid = osolve.mode_products(T, V)
+    exact = osolve.mode_products(opc.apply_full(prob, grid, bb), [Vl.T for Vl in V])
+    assert np.linalg.norm(got - exact) <= (1.01 * fit + 2 * eps) * np.linalg.norm(exact)
+
+
+@pytest.mark.parametrize("maker,b0", [
+    (lambda: wl.workload_small(), None),
+    (lambda: wl.workload_quadratic(n=64, alpha=0.25), None),
+    (lambda: wl.workload_quadratic(n=64, alpha=0.75), None),
+    (lambda: wl.workload_paper_shaped(64, 1.0), None),
+    (lambda: wl.workload_paper_shaped(64, 0.5), (1.0, 1.0, 1.0)),
+    (lambda: wl.workload_paper_shaped(64, 0.1), None),
+    (lambda: wl.workload_sine(n=128, seed=3), None),
+    (lambda: wl.workload_quadratic(n=24, alpha=0.0, rank=2), None),
+])
+def test_solve_with_case_a(maker, b0):
+    _check(maker(), precond=1, precond_b0=b0)
+
+
+def test_solve_with_case_a_mixed():
+    rep, info = _check(wl.workload_sine(n=128, seed=3), precond=1, precision=1)
+    assert info["refinements"] >= 1
+
+
+def test_case_a_equals_case_b_for_constant_coefficients():
+    """With a_l = c_l constant the sine basis is the eigenbasis of A_l and the
+    Laplacian's spectrum is A's, so both preconditioners are the same symbol:
+    the same iteration count and both within the gate."""
+    n = 48
+    base = wl.workload_quadratic(n=n, alpha=0.5)
+    base.a = [np.full(n + 1, c) for c in (0.6, 1.7, 2.9)]
+    base.name = "const_n48"
+    repA, infoA = _check(base, precond=1)
+    repB, infoB = _check(base)
+    assert abs(infoA["iterations"] - infoB["iterations"]) <= 1
+    assert infoA["precond_max_rel_err"] == pytest.approx(infoB["precond_max_rel_err"], rel=1e-6)
+
+
+def test_case_a_iterations_flat_in_n_alpha01():
+    """Table 4.6 setting (the paper's coefficients with a_2 shifted by 0.1),
+    alpha = 1/10: with the anisotropic Laplacian (mid-range constants) and
+    with the classical one the iteration count stays flat from n = 32 to 256."""
+    for b0 in (None, (1.0, 1.0, 1.0)):
+        its = []
+        for n in (32, 64, 128, 256):
+            prob = wl.workload_paper_shaped(n, 0.1)
+            slabs = None if n <= 64 else [0, 1, n // 2, n - 1]
+            rep, info = _check(prob, slabs=slabs, precond=1, precond_b0=b0)
+            its.append(info["iterations"])
+        print(f"[iterations] alpha=0.1 b0={b0}: {its}", flush=True)
+        assert max(its) - min(its) <= 1, its
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.5])
+def test_anisotropic_laplacian_beats_classical(alpha):
+    """Table 4.6: replacing the classical Laplacian by the anisotropic one with
+    the mid-range constants lowers the iteration count (n = 32, 64); the
+    eigenbasis preconditioner (case (B)) needs fewer still."""
+    for n in (32, 64):
+        prob = wl.workload_paper_shaped(n, alpha)
+        _, aniso = _check(prob, precond=1)
+        _, classic = _check(prob, precond=1, precond_b0=(1.0, 1.0, 1.0))
+        _, eig = _check(prob)
+        print(f"[iterations] alpha={alpha} n={n}: classical {classic['iterations']} "
+              f"anisotropic {aniso['iterations']} eigenbasis {eig['iterations']}", flush=True)
+        assert eig["iterations"] < aniso["iterations"] < classic["iterations"]
+
+
+def _sampled_slabs(n, k=8, seed=0):
+    rng = np.random.default_rng(seed)
+    return sorted(set([0, 1, n // 2, n - 1] + list(rng.choice(n, size=k - 4, replace=False))))
+
+
+def test_case_a_full_size_sine1024_sampled():
+    """The n = 1024 sine workload with case (A), sampled mode-1 slabs."""
+    prob = wl.workload_sine(n=1024, seed=3)
+    rep, info = _check(prob, slabs=_sampled_slabs(prob.n, seed=2), precond=1)
+    assert info["iterations"] <= 20
