@@ -32,6 +32,7 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocblas",
+                                                                                  "-lrocsolver",
                                                                                   "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -7,12 +7,14 @@
 // (orthonormal bases Z_l, n x r_l, dense core r0 x r1 x r2).
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <string>
 #include <atomic>
 #include <cstdlib>
@@ -1338,9 +1340,41 @@ void build_state_map(fc_plan_s* p, double smin, double smax) {
     p->st_err = err;
 }
 
+// The separable factors from the spectra (Sections 3.4, 3.5, 3.1): the
+// exponential-sum fits are independent host problems, run on threads of
+// their own.
+void build_separables(fc_plan_s* p, const fc_setup_params* prm) {
+    double smin = 0, smax = 0;
+    for (int l = 0; l < 3; ++l) { smin += p->lam[l].front(); smax += p->lam[l].back(); }
+    if (p->pc_kind == FC_PRECOND_LAPLACE) laplace_spectrum(p, prm);
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    const auto t0 = now();
+    std::exception_ptr err[4];
+    auto run = [&](int i, auto fn) {
+        try { fn(); } catch (...) { err[i] = std::current_exception(); }
+    };
+    std::vector<std::thread> th;
+    th.emplace_back([&] { run(0, [&] { build_operator(p, smin, smax); }); });
+    th.emplace_back([&] { run(1, [&] { build_state_map(p, smin, smax); }); });
+    if (p->pc_kind == FC_PRECOND_LAPLACE)
+        th.emplace_back([&] {
+            run(2, [&] {
+                double mmin = 0, mmax = 0;
+                for (int l = 0; l < 3; ++l) { mmin += p->mu[l].front(); mmax += p->mu[l].back(); }
+                build_preconditioner(p, mmin, mmax, p->mu, p->pcA, p->pcA_err);
+            });
+        });
+    run(3, [&] { build_preconditioner(p, smin, smax, p->lam, p->pc, p->pc_err); });
+    for (auto& t : th) t.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+    FC_TRACE_PRINT("setup fits: %.1f ms (operator Q %d)\n",
+                   std::chrono::duration<double, std::milli>(now() - t0).count(), p->op.Q);
+}
+
+// Host construction (no device): implicit-QL eigenpairs, then the fits.
 void host_spectra_and_separables(fc_plan_s* p, const fc_setup_params* prm) {
     const int n = p->n;
-    // eigenpairs of the three 1D matrices (host, in parallel)
     std::vector<std::thread> th;
     bool ok[3] = {false, false, false};
     for (int l = 0; l < 3; ++l) {
@@ -1352,16 +1386,50 @@ void host_spectra_and_separables(fc_plan_s* p, const fc_setup_params* prm) {
     for (int l = 0; l < 3; ++l)
         if (!ok[l] || !(p->lam[l][0] > 0))
             throw FcError(FC_ERR_NUMERIC, "tridiagonal eigensolver failed");
-    double smin = 0, smax = 0;
-    for (int l = 0; l < 3; ++l) { smin += p->lam[l].front(); smax += p->lam[l].back(); }
-    build_operator(p, smin, smax);
-    build_preconditioner(p, smin, smax, p->lam, p->pc, p->pc_err);
-    build_state_map(p, smin, smax);
-    if (p->pc_kind == FC_PRECOND_LAPLACE) {
-        laplace_spectrum(p, prm);
-        double mmin = 0, mmax = 0;
-        for (int l = 0; l < 3; ++l) { mmin += p->mu[l].front(); mmax += p->mu[l].back(); }
-        build_preconditioner(p, mmin, mmax, p->mu, p->pcA, p->pcA_err);
+    build_separables(p, prm);
+}
+
+// Eigenpairs of the three 1D matrices (Section 3.3) on the device: divide
+// and conquer on the symmetric tridiagonal matrices (rocSOLVER stedc, on a
+// handle of its own that manages its workspace), eigenvalues ascending,
+// eigenvectors straight into the plan's V_l.  The eigenvalues come back to
+// the host for the fits.
+void device_spectra(fc_plan_s* p, const fc_setup_params* prm) {
+    const int n = p->n;
+    std::vector<double> dh((size_t)3 * n), eh((size_t)3 * n, 0.0);
+    for (int l = 0; l < 3; ++l) fc::fd_tridiag(n, prm->a[l], &dh[(size_t)l * n], &eh[(size_t)l * n]);
+    double* D = p->arena.alloc((size_t)3 * n);
+    double* E = p->arena.alloc((size_t)3 * n);
+    int* info = p->arena.alloc_int(3);
+    HIPCHK(hipMemcpy(D, dh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(E, eh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success)
+        throw FcError(FC_ERR_HIP, "rocblas_create_handle failed");
+    struct HandleGuard {
+        rocblas_handle h;
+        ~HandleGuard() { rocblas_destroy_handle(h); }
+    } guard_h{h};
+    if (rocblas_set_stream(h, p->stream) != rocblas_status_success)
+        throw FcError(FC_ERR_HIP, "rocblas_set_stream failed");
+    for (int l = 0; l < 3; ++l) {
+        p->V[l] = p->arena.alloc((size_t)n * n);
+        if (rocsolver_dstedc(h, rocblas_evect_tridiagonal, n, D + (size_t)l * n, E + (size_t)l * n,
+                             p->V[l], n, info + l) != rocblas_status_success)
+            throw FcError(FC_ERR_HIP, "rocsolver_dstedc failed");
+    }
+    int ih[3];
+    HIPCHK(hipMemcpyAsync(dh.data(), D, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipMemcpyAsync(ih, info, sizeof(int) * 3, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->arena.release(D);
+    p->arena.release(E);
+    p->arena.release(info);
+    for (int l = 0; l < 3; ++l) {
+        p->lam[l].assign(dh.begin() + (long)l * n, dh.begin() + (long)(l + 1) * n);
+        if (ih[l] != 0 || !(p->lam[l][0] > 0))
+            throw FcError(FC_ERR_NUMERIC, "tridiagonal eigensolver failed (mode " +
+                                              std::to_string(l) + ", info " + std::to_string(ih[l]) + ")");
     }
 }
 
@@ -1389,12 +1457,12 @@ void build_sine_maps(fc_plan_s* p) {
 }
 
 void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
-    const int n = p->n;
-    host_spectra_and_separables(p, prm);
-    for (int l = 0; l < 3; ++l) {
-        p->V[l] = p->arena.alloc((size_t)n * n);
-        HIPCHK(hipMemcpy(p->V[l], p->Vh[l].data(), sizeof(double) * n * n, hipMemcpyHostToDevice));
-    }
+    const auto t0 = std::chrono::steady_clock::now();
+    device_spectra(p, prm);
+    const auto t1 = std::chrono::steady_clock::now();
+    build_separables(p, prm);
+    FC_TRACE_PRINT("setup eigenpairs on the device: %.1f ms\n",
+                   std::chrono::duration<double, std::milli>(t1 - t0).count());
     upload_separable(p, p->op);
     upload_separable(p, p->pc);
     upload_separable(p, p->st);
@@ -1731,11 +1799,14 @@ void fc_destroy(fc_plan plan) { delete plan; }
 fc_status fc_plan_spectrum(fc_plan p, double* lam, double* V) {
     if (!p || !lam) return fail(FC_ERR_INVALID_ARG, "fc_plan_spectrum: NULL argument");
     const int n = p->n;
-    for (int l = 0; l < 3; ++l) {
-        std::memcpy(lam + (size_t)l * n, p->lam[l].data(), sizeof(double) * n);
-        if (V) std::memcpy(V + (size_t)l * n * n, p->Vh[l].data(), sizeof(double) * n * n);
-    }
-    return FC_OK;
+    return guard([&] {
+        for (int l = 0; l < 3; ++l) {
+            std::memcpy(lam + (size_t)l * n, p->lam[l].data(), sizeof(double) * n);
+            if (V)
+                HIPCHK(hipMemcpy(V + (size_t)l * n * n, p->V[l], sizeof(double) * n * n,
+                                 hipMemcpyDeviceToHost));
+        }
+    });
 }
 
 fc_status fc_plan_separable(fc_plan p, int which, int cap, int* rank, double* w, double* F) {

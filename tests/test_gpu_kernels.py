@@ -223,3 +223,31 @@ def test_apply_separable_matches_full_grid(which):
     got = ot.cp_full(host(wo), [host(o) for o in O])
     want = Dt * T
     assert np.linalg.norm(got - want) <= 1.01 * eps * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("maker", [lambda: wl.workload_sine(n=1024, seed=3),
+                                   lambda: wl.workload_paper_shaped(512, 1.0),
+                                   lambda: wl.workload_quadratic(n=96, alpha=0.5)])
+def test_device_eigenpairs(maker):
+    """The plan's eigenpairs, computed on the device: eigenvalues equal
+    LAPACK's (oracle) to rounding, eigenvectors orthonormal and with residual
+    ||A_l v - lam v|| at rounding level.  The sine and paper coefficients have
+    (numerically) degenerate eigenvalues, so vectors are compared through the
+    residual, not one by one."""
+    from tests.gpu_util import plan_for
+    from oracle import fd
+    prob = maker()
+    plan = plan_for(prob)
+    lam, V = plan.spectrum(with_vectors=True)
+    n = prob.n
+    for l in range(3):
+        lo, Vo = fd.eig1d(prob.a[l])
+        scale = lo[-1]
+        np.testing.assert_allclose(lam[l], lo, rtol=0, atol=1e-13 * scale)
+        G = V[l].T @ V[l]
+        assert np.abs(G - np.eye(n)).max() <= 1e-12
+        d, e = fd.stiffness_tridiag(prob.a[l])
+        AV = d[:, None] * V[l]
+        AV[:-1] += e[:, None] * V[l][1:]
+        AV[1:] += e[:, None] * V[l][:-1]
+        assert np.abs(AV - V[l] * lam[l][None, :]).max() <= 1e-12 * scale
