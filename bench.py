@@ -379,7 +379,11 @@ def main():
     uneven = None
     if args.uneven > 0:
         uprobs = wl.workload_batched(count=args.uneven)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter()
         plans = build_plans(api, uprobs)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t_setup
         uin, uout = batch_io(api, torch, dev, uprobs, 2048)
         res_u = api.solve_batched(plans, uin, cap_u=2048, outs=uout)
         torch.cuda.synchronize()
@@ -389,7 +393,9 @@ def main():
         el = time.perf_counter() - t0
         ns = [p.n for p in uprobs]
         uneven = {"problems": len(uprobs), "n_values": sorted(set(ns)),
-                  "solves_per_s": len(uprobs) / el, "s_per_batch": el}
+                  "solves_per_s": len(uprobs) / el, "s_per_batch": el,
+                  "setup_s": t_setup,
+                  "solves_per_s_with_setup": len(uprobs) / (el + t_setup)}
         if not args.no_check:
             big = int(np.argmax(ns))
             uneven["parity_largest"] = dict(problem=big, n=ns[big], **sampled_parity(

@@ -59,3 +59,38 @@ def sparse_alpha1_solve(prob) -> np.ndarray:
     y = cp_full(prob.w, prob.Y).reshape(-1)
     u = spla.spsolve(M.tocsc(), A @ y)
     return u.reshape(n, n, n)
+
+
+# ---- d = 2 ------------------------------------------------------------------
+
+def kron_sum_dense_2d(prob) -> np.ndarray:
+    n = prob.n
+    I = np.eye(n)
+    A = [fd.stiffness_dense(prob.a[l]) for l in range(2)]
+    return np.kron(A[0], I) + np.kron(I, A[1])
+
+
+def dense_solve_2d(prob) -> np.ndarray:
+    """F(A) u = y with the n^2 x n^2 Kronecker sum eigendecomposed as one dense
+    symmetric matrix."""
+    n = prob.n
+    mu, Q = np.linalg.eigh(kron_sum_dense_2d(prob))
+    F = (Q * f_control(mu, prob.alpha, prob.beta, prob.gamma)[None, :]) @ Q.T
+    y = (prob.Y[0] * prob.w[None, :]) @ prob.Y[1].T
+    return np.linalg.solve(F, y.reshape(-1)).reshape(n, n)
+
+
+def sparse_alpha1_solve_2d(prob) -> np.ndarray:
+    """alpha = 1: (beta I + (gamma/beta) A^2) u = A y, no eigensolver."""
+    if prob.alpha != 1.0:
+        raise ValueError("identity holds for alpha = 1 only")
+    n = prob.n
+    I = sps.identity(n, format="csr")
+    A1 = []
+    for l in range(2):
+        d, e = fd.stiffness_tridiag(prob.a[l])
+        A1.append(sps.diags([e, d, e], [-1, 0, 1], format="csr"))
+    A = (sps.kron(A1[0], I) + sps.kron(I, A1[1])).tocsr()
+    M = prob.beta * sps.identity(n * n, format="csr") + (prob.gamma / prob.beta) * (A @ A)
+    y = ((prob.Y[0] * prob.w[None, :]) @ prob.Y[1].T).reshape(-1)
+    return spla.spsolve(M.tocsc(), A @ y).reshape(n, n)

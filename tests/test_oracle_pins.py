@@ -463,3 +463,76 @@ def test_case_a_spectral_bound_for_variable_coefficients():
     # f(t s)/f(s) lies in [min(t^-alpha, t^alpha), max(t^-alpha, t^alpha)]
     k = max(lo ** -prob.alpha, hi ** prob.alpha, lo ** prob.alpha, hi ** -prob.alpha)
     assert ev.min() > 1.0 / k - 1e-9 and ev.max() < k + 1e-9
+
+
+# ---- the d = 2 variant -------------------------------------------------------
+
+from oracle import solve2d  # noqa: E402
+
+
+def _tiny_problem_2d(n, alpha, beta=0.7, gamma=1.3, rank=2, seed=13):
+    rng = np.random.default_rng(seed)
+    xm = wl.midpoints(n)
+    a = [1.0 + 0.5 * np.sin(2 * np.pi * xm), 0.3 + xm ** 2]
+    w = rng.uniform(0.5, 1.5, rank)
+    Y = [np.asfortranarray(rng.standard_normal((n, rank))) for _ in range(2)]
+    return wl.Problem("tiny2d", n, a, alpha, beta, gamma, 1e-6, w, Y)
+
+
+def test_golden_control_2d_n1():
+    seen = 0
+    for rest in _golden_lines("control2d"):
+        lhs, rhs = rest.split(":")
+        head, m2 = lhs.split("|")
+        h = head.split()
+        alpha, beta, gamma = float(h[0]), float(h[1]), float(h[2])
+        a = [np.array([float(v) for v in h[3:]]), np.array([float(v) for v in m2.split()])]
+        one = np.ones((1, 1), order="F")
+        prob = wl.Problem("golden2d", 1, a, alpha, beta, gamma, 1e-6, np.ones(1), [one, one])
+        u = solve2d.solve_full_2d(prob)
+        np.testing.assert_allclose(u.reshape(-1), [float(rhs)], rtol=1e-14)
+        seen += 1
+    assert seen >= 2
+
+
+@pytest.mark.parametrize("alpha", [0.25, 0.5, 1.0])
+def test_dense_brute_force_2d(alpha):
+    """The n^2 x n^2 Kronecker sum eigendecomposed densely (distinct
+    coefficients per mode catch a transposed mode)."""
+    prob = _tiny_problem_2d(9, alpha)
+    np.testing.assert_allclose(solve2d.solve_full_2d(prob), brute.dense_solve_2d(prob),
+                               rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("n", [20, 60])
+def test_alpha1_sparse_identity_2d(n):
+    prob = _tiny_problem_2d(n, 1.0)
+    u = solve2d.solve_full_2d(prob)
+    np.testing.assert_allclose(u, brute.sparse_alpha1_solve_2d(prob), rtol=0,
+                               atol=1e-10 * np.abs(u).max())
+
+
+def test_constant_coefficients_2d_by_sine_transform():
+    """a_l = c_l: the eigenbasis is the sine basis with eigenvalues
+    c_l (4/h^2) sin^2(k pi h/2), so the solution is also the sine transform,
+    divide, sine transform back."""
+    n = 33
+    prob = _tiny_problem_2d(n, 0.5)
+    prob.a = [np.full(n + 1, 0.8), np.full(n + 1, 2.2)]
+    S = precond.dst1_matrix(n)
+    mu = precond.laplace_eigenvalues(n)
+    s = 0.8 * mu[:, None] + 2.2 * mu[None, :]
+    y = solve2d.cp_full_2d(prob.w, prob.Y)
+    u = S @ ((S @ y @ S) / solve.f_control(s, prob.alpha, prob.beta, prob.gamma)) @ S
+    np.testing.assert_allclose(solve2d.solve_full_2d(prob), u, rtol=0, atol=1e-12 * np.abs(u).max())
+
+
+def test_error_evaluator_2d():
+    prob = _tiny_problem_2d(12, 0.5)
+    u = solve2d.solve_full_2d(prob)
+    # an exact rank-n factorisation of u has zero error; a perturbed one its own
+    U, s, Vt = np.linalg.svd(u)
+    rep = solve2d.rel_error_2d(prob, s, [U, Vt.T])
+    assert rep["rel_l2"] < 1e-13 and rep["rel_residual"] < 1e-12
+    rep2 = solve2d.rel_error_2d(prob, s * (1 + 1e-3), [U, Vt.T])
+    assert rep2["rel_l2"] == pytest.approx(1e-3, rel=1e-6)

@@ -39,6 +39,8 @@ __all__ = [
     "workload_batched_uniform",
     "workload_paper_shaped",
     "eigvec_rhs_problem",
+    "workload_paper_2d",
+    "workload_quadratic_2d",
 ]
 
 
@@ -175,3 +177,26 @@ def eigvec_rhs_problem(base: Problem, vecs: Sequence[np.ndarray]) -> Problem:
     """Same operator as `base`, with the rank-1 design v1 (x) v2 (x) v3."""
     Y = [np.asfortranarray(np.asarray(v, dtype=np.float64).reshape(-1, 1)) for v in vecs]
     return dataclasses.replace(base, name=base.name + "_eigvec", w=np.ones(1), Y=Y)
+
+
+# ---- d = 2 (two-entry lists a and Y) ----------------------------------------
+
+def workload_paper_2d(n: int, alpha: float, gamma: float = 1.0) -> Problem:
+    """The paper's 2D tests: a_1 = sin(100 pi x) + 1.1, a_2 = sin x cos x,
+    beta = 1, a rank-1 box indicator on [0.25, 0.75]^2 standing in for the
+    box-type design."""
+    xm = midpoints(n)
+    a = [np.sin(100.0 * np.pi * xm) + 1.1, np.sin(xm) * np.cos(xm)]
+    x = nodes(n)
+    box = ((x >= 0.25) & (x <= 0.75)).astype(np.float64)[:, None]
+    return Problem(f"paper2d_n{n}_a{alpha:g}", n, a, float(alpha), 1.0, float(gamma), 1e-6,
+                   np.ones(1), [np.asfortranarray(box.copy()) for _ in range(2)])
+
+
+def workload_quadratic_2d(alpha: float = 0.5, n: int = 256, seed: int = 2, rank: int = 5,
+                          beta: float = 1e-3) -> Problem:
+    """The quadratic-coefficient family in two modes: the same draws as
+    `workload_quadratic` (three coefficient parameters, then per rank term a
+    weight and three bumps), of which the first two modes are used."""
+    p = workload_quadratic(alpha=alpha, n=n, seed=seed, rank=rank, beta=beta)
+    return dataclasses.replace(p, name=f"quadratic2d_n{n}_a{alpha:g}", a=p.a[:2], Y=p.Y[:2])
