@@ -93,6 +93,12 @@ typedef struct {
     fc_precond_kind precond; /* FC_PRECOND_EIGEN (0, default) or FC_PRECOND_LAPLACE             */
     double precond_b0[3];   /* case (A) constants b0_l; <= 0 -> (max a_l + min a_l)/2 over the
                                samples (eqn modcoeff); finite                                  */
+    int dims;               /* 3 (or 0) or 2: the d = 2 problem on (0,1)^2 (a[2] ignored), solved
+                               with fc_solve2d.  The plan then carries a third mode A_3 - sigma I
+                               (A_3 the Laplacian, sigma its smallest eigenvalue, so the third
+                               eigenvalues start at exactly 0) and every tensor is u (x) v_1 with
+                               v_1 the first eigenvector: the Tucker truncation of such a tensor
+                               is the reduced SVD truncation of the matrix u (Section 3.6).    */
 } fc_setup_params;
 
 /* Per-solve report (HOST struct). */
@@ -146,6 +152,15 @@ fc_status fc_solve(fc_plan plan, int rank_y, const double* w_y,
                    int cap_u, int* rank_u, double* w_u, double* U1, double* U2, double* U3,
                    fc_info* info, void* hip_stream);
 
+/* The d = 2 problem (Section 2 with d = 2, the 2D tests of Section 4): plan
+ * built with dims = 2.  y = sum_s w_y[s] Y1[:, s] Y2[:, s]^T, u returned as
+ * sum_k w_u[k] U1[:, k] U2[:, k]^T; arguments, ranks, synchronisation and
+ * errors as fc_solve (rank_u <= max_rank).  FC_ERR_INVALID_ARG if the plan
+ * is three-dimensional (and fc_solve, fc_solve_state reject d = 2 plans). */
+fc_status fc_solve2d(fc_plan plan, int rank_y, const double* w_y, const double* Y1,
+                     const double* Y2, int cap_u, int* rank_u, double* w_u, double* U1,
+                     double* U2, fc_info* info, void* hip_stream);
+
 /* fc_solve, then the state y = beta A^-alpha u (eqn `State`, Section 3.1) and
  * the cost functional J = 1/2 ||y - y_Omega||^2 + gamma/2 ||u||^2 (Section 3.1
  * with the finite-difference mass matrix M = I, Euclidean norms).  The state
@@ -184,7 +199,8 @@ fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
 void fc_destroy(fc_plan plan);
 
 /* Plan introspection (HOST outputs).  lam: 3*n ascending eigenvalues, mode
- * after mode; V (may be NULL): 3 n x n column-major eigenvector matrices. */
+ * after mode (d = 2: the third mode's shifted ones, starting at 0); V (may be
+ * NULL): 3 n x n column-major eigenvector matrices. */
 fc_status fc_plan_spectrum(fc_plan plan, double* lam, double* V);
 
 /* Separable factors of the operator (which = 0), the preconditioner

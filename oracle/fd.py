@@ -53,7 +53,12 @@ def eig1d(a_mid: np.ndarray):
     """(lam, V): ascending eigenvalues and orthonormal eigenvector columns
     of A_l (LAPACK tridiagonal solver via SciPy)."""
     d, e = stiffness_tridiag(a_mid)
-    lam, V = scipy.linalg.eigh_tridiagonal(d, e, lapack_driver="stemr")
+    try:
+        lam, V = scipy.linalg.eigh_tridiagonal(d, e, lapack_driver="stemr")
+    except np.linalg.LinAlgError:
+        # MRRR can fail on strongly graded matrices (a coefficient that
+        # nearly vanishes); implicit QL/QR (LAPACK stev) always converges there
+        lam, V = scipy.linalg.eigh_tridiagonal(d, e, lapack_driver="stev")
     return lam, np.asfortranarray(V)
 
 

@@ -29,11 +29,12 @@ from .solve import f_control
 class Spectral2D:
     """Eigenpairs of the two 1D matrices and the design in eigen-coordinates."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, eig=None):
+        """eig: optional [(lam, V), (lam, V)] of the same coefficients, reused."""
         self.prob = prob
         self.lam, self.V = [], []
         for l in range(2):
-            lam, V = fd.eig1d(prob.a[l])
+            lam, V = eig[l] if eig is not None else fd.eig1d(prob.a[l])
             self.lam.append(lam)
             self.V.append(V)
         self.Yh = [self.V[l].T @ prob.Y[l] for l in range(2)]

@@ -40,6 +40,7 @@ class SetupParams(C.Structure):
         ("precision", C.c_int),
         ("precond", C.c_int),
         ("precond_b0", C.c_double * 3),
+        ("dims", C.c_int),
     ]
 
 
@@ -82,6 +83,7 @@ PROTOTYPES = {
     "fc_setup_ex": (_I, [C.POINTER(SetupParams), _VP, C.POINTER(_VP)]),
     "fc_solve": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _I, _PI, _VP, _VP, _VP, _VP,
                       C.POINTER(Info), _VP]),
+    "fc_solve2d": (_I, [_VP, _I, _VP, _VP, _VP, _I, _PI, _VP, _VP, _VP, C.POINTER(Info), _VP]),
     "fc_solve_state": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _I, _PI, _VP, _VP, _VP, _VP,
                             _I, _PI, _VP, _VP, _VP, _VP, _PD, C.POINTER(Info), _VP]),
     "fc_solve_batched": (_I, [_I, C.POINTER(_VP), _PI, C.POINTER(_VP), C.POINTER(_VP),

@@ -36,15 +36,20 @@ class Plan:
                  gamma: float = 1.0, eps: float = 1e-6, tol: float = 0.0,
                  op_accuracy: float = 0.0, max_iter: int = 0, max_rank: int = 0,
                  precond_rank: int = 0, precision: int = 0, stream=None, precond: int = 0,
-                 precond_b0: Optional[Sequence[float]] = None):
-        self._a = [_host_array(x) for x in a]
+                 precond_b0: Optional[Sequence[float]] = None, dims: int = 3):
+        if dims not in (2, 3):
+            raise ValueError("dims must be 2 or 3")
+        self._a = [_host_array(x) for x in a[:dims]]
+        if len(self._a) != dims:
+            raise ValueError(f"need {dims} coefficient arrays")
         for x in self._a:
             if x.shape != (n + 1,):
                 raise ValueError("each coefficient needs n+1 midpoint samples")
         p = SetupParams()
         p.n = n
-        for l in range(3):
+        for l in range(dims):
             p.a[l] = self._a[l].ctypes.data_as(C.POINTER(C.c_double))
+        p.dims = dims
         p.alpha, p.beta, p.gamma, p.eps, p.tol = alpha, beta, gamma, eps, tol
         p.op_accuracy = op_accuracy
         p.max_iter, p.max_rank, p.precond_rank, p.precision = (max_iter, max_rank, precond_rank,
@@ -115,6 +120,24 @@ class Plan:
                             cap_u, C.byref(rank_u), _ptr(w_u), _ptr(U[0]), _ptr(U[1]), _ptr(U[2]),
                             C.byref(info), _stream_ptr(stream))
         check(st, "fc_solve")
+        k = rank_u.value
+        return w_u[:k], [u[:, :k] for u in U], info.as_dict()
+
+    def solve2d(self, w_y, Y: Sequence, cap_u: int = 256, stream=None):
+        """fc_solve2d on a dims=2 plan.  Y: two (n, rank) column-major device
+        tensors.  Returns (w_u, [U1, U2], info)."""
+        import torch
+        n = self.n
+        Yc = [_colmajor(y) for y in Y]
+        dev = Yc[0].device
+        w_u = torch.empty(cap_u, dtype=torch.float64, device=dev)
+        U = [torch.empty((cap_u, n), dtype=torch.float64, device=dev).t() for _ in range(2)]
+        info = Info()
+        rank_u = C.c_int()
+        st = lib().fc_solve2d(self.handle, Yc[0].shape[1], _ptr(w_y), _ptr(Yc[0]), _ptr(Yc[1]),
+                              cap_u, C.byref(rank_u), _ptr(w_u), _ptr(U[0]), _ptr(U[1]),
+                              C.byref(info), _stream_ptr(stream))
+        check(st, "fc_solve2d")
         k = rank_u.value
         return w_u[:k], [u[:, :k] for u in U], info.as_dict()
 

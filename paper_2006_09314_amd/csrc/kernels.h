@@ -98,6 +98,11 @@ hipError_t fill_random(long n, unsigned seed, double* x, hipStream_t s);
 hipError_t zero(long n, double* x, hipStream_t s);
 // x[0..n) = v
 hipError_t fill_int(int n, int* x, int v, hipStream_t s);
+// out[:, j] = v for j < m (out n x m, leading dimension ld).
+hipError_t fill_columns(int n, int m, const double* v, double* out, long ld, hipStream_t s);
+// w[k] *= <U[:, k], v> for k < K (U n x K, leading dimension ld).
+hipError_t scale_by_dot(int n, int K, const double* U, long ld, const double* v, double* w,
+                        hipStream_t s);
 // Scale the columns of the three n x K factors (ld) to unit length and
 // multiply w[t] by the product of the three column norms.
 hipError_t normalize_factors(int n, int K, double* U0, double* U1, double* U2, long ld, double* w,

@@ -1155,6 +1155,48 @@ hipError_t normalize_factors(int n, int K, double* U0, double* U1, double* U2, l
     return hipGetLastError();
 }
 
+// d = 2 plans carry the third mode as one fixed eigenvector v: the design's
+// mode-3 factor is v in every column, and the result's weights absorb the
+// mode-3 factor's component along v.
+__global__ void fill_columns_kernel(int n, int m, const double* __restrict__ v,
+                                    double* __restrict__ out, long ld) {
+    const long total = (long)n * m;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % n), j = int(e / n);
+        out[i + ld * j] = v[i];
+    }
+}
+
+hipError_t fill_columns(int n, int m, const double* v, double* out, long ld, hipStream_t s) {
+    if (n <= 0 || m <= 0) return hipSuccess;
+    const long total = (long)n * m;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 1024);
+    hipLaunchKernelGGL(fill_columns_kernel, dim3(blocks), dim3(256), 0, s, n, m, v, out, ld);
+    return hipGetLastError();
+}
+
+// w[k] *= <U[:, k], v>, one workgroup of 256 per column.
+__global__ void scale_by_dot_kernel(int n, const double* __restrict__ U, long ld,
+                                    const double* __restrict__ v, double* __restrict__ w) {
+    __shared__ double red[4];
+    const int k = blockIdx.x, tid = threadIdx.x;
+    const double* u = U + (long)k * ld;
+    double acc = 0.0;
+    for (int i = tid; i < n; i += 256) acc += u[i] * v[i];
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) w[k] *= (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+hipError_t scale_by_dot(int n, int K, const double* U, long ld, const double* v, double* w,
+                        hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_by_dot_kernel, dim3(K), dim3(256), 0, s, n, U, ld, v, w);
+    return hipGetLastError();
+}
+
 __global__ void fill_int_kernel(int n, int* x, int v) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = v;
 }

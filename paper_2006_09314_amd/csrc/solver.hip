@@ -125,6 +125,10 @@ struct fc_plan_s {
     // preconditioner case (A): 1/f on the spectrum of the anisotropic
     // Laplacian in the sine basis, and the maps W_l = S V_l into that basis
     int pc_kind = FC_PRECOND_EIGEN;
+    // d = 2: the third mode is a Laplacian shifted by its smallest eigenvalue,
+    // and designs and results carry its first eigenvector (Y3d, U3d: n x 256)
+    int dims = 3;
+    double *Y3d = nullptr, *U3d = nullptr;
     double b0[3] = {1.0, 1.0, 1.0};
     std::vector<double> mu[3];    // host: b0_l (4/h^2) sin^2(k pi h/2), ascending
     Separable pcA;
@@ -485,6 +489,11 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
         gemm(c, false, true, pd[0], pd[0], pd[1] * pd[2], 1.0, src, pd[0], src, pd[0], 0.0,
              p->Cg + (long)l * KM * KM, pd[0]);
     }
+    // per-mode share of the budget: the HOSVD bound sum_l tail_l <= thr2.  With
+    // d = 2 the core is a matrix (third rank 1, no tail) and cutting both
+    // modes at tails <= thr2 is the reduced SVD truncation, whose error is
+    // exactly the smaller of the two tails.
+    const double per_mode = p->dims == 2 ? thr2 : thr2 / 3.0;
     {
         fc::EigJobs jobs;
         jobs.count = 3;
@@ -493,7 +502,7 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
             J.A = p->Cg + (long)l * KM * KM; J.lda = k[l]; J.k = k[l];
             J.evals = p->Cev + l * KM; J.V = p->Cvec + (long)l * KM * KM; J.ldv = k[l];
             J.scratch = p->jac + (long)l * 6 * KM * KM;
-            J.budget = thr2 / 3.0;   // vectors for the kept rank only
+            J.budget = per_mode;   // vectors for the kept rank only
             J.margin = 0;
         }
         HIPCHK(timed_launch(2, c.s, eig_flops(jobs), eig_bytes(jobs),
@@ -505,12 +514,12 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
     for (int i = 0; i < k[0]; ++i) tot += std::max(ev[i], 0.0);
     int r[3];
     for (int l = 0; l < 3; ++l) {
-        // smallest r with tail(r) <= thr2/3
+        // smallest r with tail(r) <= the mode's share
         double tail = 0;
         int rr = k[l];
         for (int i = k[l] - 1; i >= 0; --i) {
             tail += std::max(ev[l * KM + i], 0.0);
-            if (tail <= thr2 / 3.0) rr = i; else break;
+            if (tail <= per_mode) rr = i; else break;
         }
         int numrank = 0;
         const double tmax = std::max(ev[l * KM], 0.0);
@@ -1344,9 +1353,23 @@ void build_state_map(fc_plan_s* p, double smin, double smax) {
 // exponential-sum fits are independent host problems, run on threads of
 // their own.
 void build_separables(fc_plan_s* p, const fc_setup_params* prm) {
+    if (p->dims == 2) {
+        // A_3 - lambda_3,1 I: its first eigenvector spans a null space, so a
+        // design y (x) v_1 has the solution u (x) v_1 with u the d = 2 control
+        const double sig = p->lam[2][0];
+        for (double& x : p->lam[2]) x -= sig;
+        p->lam[2][0] = 0.0;
+    }
     double smin = 0, smax = 0;
     for (int l = 0; l < 3; ++l) { smin += p->lam[l].front(); smax += p->lam[l].back(); }
-    if (p->pc_kind == FC_PRECOND_LAPLACE) laplace_spectrum(p, prm);
+    if (p->pc_kind == FC_PRECOND_LAPLACE) {
+        laplace_spectrum(p, prm);
+        if (p->dims == 2) {
+            const double sig = p->mu[2][0];
+            for (double& x : p->mu[2]) x -= sig;
+            p->mu[2][0] = 0.0;
+        }
+    }
     auto now = [] { return std::chrono::steady_clock::now(); };
     const auto t0 = now();
     std::exception_ptr err[4];
@@ -1483,6 +1506,10 @@ void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
             throw FcError(FC_ERR_HIP, "rocblas_set_workspace failed");
     }
     if (p->pc_kind == FC_PRECOND_LAPLACE) build_sine_maps(p);
+    if (p->dims == 2) {
+        p->Y3d = p->arena.alloc((size_t)p->n * 256);
+        p->U3d = p->arena.alloc((size_t)p->n * 256);
+    }
     HIPCHK(hipDeviceSynchronize());
 }
 
@@ -1708,6 +1735,7 @@ fc_status fc_host_expsum(int kind, double p1, double p2, double p3, double s_min
 
 static fc_status validate_params(const fc_setup_params* prm);
 static void apply_defaults(fc_plan_s* p, const fc_setup_params* prm);
+static fc_setup_params effective_params(const fc_setup_params* prm, std::vector<double>& ones);
 
 fc_status fc_host_separable(const fc_setup_params* prm, int which, int cap, int* rank, double* w,
                             double* F, double* max_rel_err) {
@@ -1716,7 +1744,9 @@ fc_status fc_host_separable(const fc_setup_params* prm, int which, int cap, int*
     if (v != FC_OK) return v;
     fc_plan_s p;
     apply_defaults(&p, prm);
-    fc_status st = guard([&] { host_spectra_and_separables(&p, prm); });
+    std::vector<double> ones;
+    const fc_setup_params q = effective_params(prm, ones);
+    fc_status st = guard([&] { host_spectra_and_separables(&p, &q); });
     if (st != FC_OK) return st;
     const Separable& S = which == 0 ? p.op : which == 1 ? active_pc(&p) : p.st;
     *rank = S.Q;
@@ -1733,7 +1763,9 @@ fc_status fc_host_separable(const fc_setup_params* prm, int which, int cap, int*
 static fc_status validate_params(const fc_setup_params* prm) {
     const int n = prm->n;
     if (n < 2 || n > 4096) return fail(FC_ERR_INVALID_ARG, "n must be in [2, 4096]");
-    for (int l = 0; l < 3; ++l) {
+    if (prm->dims != 0 && prm->dims != 2 && prm->dims != 3)
+        return fail(FC_ERR_INVALID_ARG, "dims must be 2 or 3");
+    for (int l = 0; l < (prm->dims == 2 ? 2 : 3); ++l) {
         if (!prm->a[l]) return fail(FC_ERR_INVALID_ARG, "coefficient pointer is NULL");
         if (!finite_pos(prm->a[l], n + 1))
             return fail(FC_ERR_INVALID_ARG, "coefficient samples must be finite and > 0");
@@ -1768,6 +1800,19 @@ static void apply_defaults(fc_plan_s* p, const fc_setup_params* prm) {
     p->precond_rank = prm->precond_rank > 0 ? prm->precond_rank : 6;
     p->precision = prm->precision;
     p->pc_kind = prm->precond;
+    p->dims = prm->dims == 2 ? 2 : 3;
+}
+
+// The parameters the construction runs on: with d = 2 the third mode is the
+// constant-coefficient Laplacian (samples all 1; `ones` keeps them alive).
+static fc_setup_params effective_params(const fc_setup_params* prm, std::vector<double>& ones) {
+    fc_setup_params q = *prm;
+    if (prm->dims == 2) {
+        ones.assign((size_t)prm->n + 1, 1.0);
+        q.a[2] = ones.data();
+        q.precond_b0[2] = 1.0;
+    }
+    return q;
 }
 
 fc_status fc_setup_ex(const fc_setup_params* prm, void* hip_stream, fc_plan* out) {
@@ -1778,7 +1823,9 @@ fc_status fc_setup_ex(const fc_setup_params* prm, void* hip_stream, fc_plan* out
     fc_plan_s* p = new fc_plan_s();
     apply_defaults(p, prm);
     p->stream = (hipStream_t)hip_stream;
-    fc_status st = guard([&] { setup_plan(p, prm); });
+    std::vector<double> ones;
+    const fc_setup_params q = effective_params(prm, ones);
+    fc_status st = guard([&] { setup_plan(p, &q); });
     if (st != FC_OK) { delete p; return st; }
     *out = p;
     return FC_OK;
@@ -2028,8 +2075,31 @@ fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, c
     if (!p || rank_y < 1 || rank_y > 256 || !Y1 || !Y2 || !Y3 || cap_u < 0 || !rank_u ||
         !w_u || !U1 || !U2 || !U3)
         return fail(FC_ERR_INVALID_ARG, "fc_solve: bad arguments");
+    if (p->dims == 2) return fail(FC_ERR_INVALID_ARG, "fc_solve: two-dimensional plan (use fc_solve2d)");
     return solve_impl(p, rank_y, w_y, Y1, Y2, Y3, cap_u, rank_u, w_u, U1, U2, U3, info, stream,
                       nullptr);
+}
+
+fc_status fc_solve2d(fc_plan p, int rank_y, const double* w_y, const double* Y1, const double* Y2,
+                     int cap_u, int* rank_u, double* w_u, double* U1, double* U2, fc_info* info,
+                     void* stream) {
+    if (!p || rank_y < 1 || rank_y > 256 || !Y1 || !Y2 || cap_u < 0 || !rank_u || !w_u || !U1 ||
+        !U2)
+        return fail(FC_ERR_INVALID_ARG, "fc_solve2d: bad arguments");
+    if (p->dims != 2) return fail(FC_ERR_INVALID_ARG, "fc_solve2d: plan is not two-dimensional");
+    const hipStream_t s = (hipStream_t)stream;
+    const double* v = p->V[2];   // first eigenvector of the third mode (its null direction)
+    fc_status st = guard([&] { HIPCHK(fc::fill_columns(p->n, rank_y, v, p->Y3d, p->n, s)); });
+    if (st != FC_OK) return st;
+    // the result's rank is at most min(r1, r2) <= max_rank (one core slice)
+    const int cap = std::min(cap_u, 256);
+    st = solve_impl(p, rank_y, w_y, Y1, Y2, p->Y3d, cap, rank_u, w_u, U1, U2, p->U3d, info, stream,
+                    nullptr);
+    if (st != FC_OK) return st;
+    return guard([&] {
+        HIPCHK(fc::scale_by_dot(p->n, *rank_u, p->U3d, p->n, v, w_u, s));
+        HIPCHK(hipStreamSynchronize(s));
+    });
 }
 
 fc_status fc_solve_state(fc_plan p, int rank_y, const double* w_y, const double* Y1,
@@ -2040,6 +2110,7 @@ fc_status fc_solve_state(fc_plan p, int rank_y, const double* w_y, const double*
     if (!p || rank_y < 1 || rank_y > 256 || !Y1 || !Y2 || !Y3 || cap_u < 0 || !rank_u ||
         !w_u || !U1 || !U2 || !U3 || cap_s < 0 || !rank_s || !w_s || !S1 || !S2 || !S3)
         return fail(FC_ERR_INVALID_ARG, "fc_solve_state: bad arguments");
+    if (p->dims == 2) return fail(FC_ERR_INVALID_ARG, "fc_solve_state: two-dimensional plan");
     StateOut so;
     so.cap = cap_s;
     so.rank = rank_s;

@@ -289,3 +289,49 @@ def test_library_shares_torch_hip_runtime():
     with open("/proc/self/maps") as fh:
         hip = {line.split()[-1] for line in fh if "libamdhip64" in line}
     assert len(hip) == 1, hip
+
+
+def _params_2d(prob, **kw):
+    p, keep = _params(wl.Problem(prob.name, prob.n, list(prob.a) + [prob.a[0]], prob.alpha,
+                                 prob.beta, prob.gamma, prob.eps, prob.w, prob.Y), dims=2, **kw)
+    p.a[2] = C.POINTER(C.c_double)()   # ignored for d = 2
+    return p, keep
+
+
+@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("alpha", [1.0, 0.5, 0.1])
+def test_two_dimensional_symbols(which, alpha):
+    """d = 2 plans: on the third mode's first index (its eigenvalue shifted to
+    exactly 0) the separable operator is the 2D symbol f(lam1_i + lam2_j) to
+    its gate, and the preconditioner approximates 1/f there."""
+    from oracle import solve2d
+    prob = wl.workload_paper_2d(96, alpha)
+    h = _lib()
+    p, keep = _params_2d(prob)
+    cap, n = 512, prob.n
+    w = np.zeros(cap)
+    F = np.zeros(3 * n * cap)
+    rank, gate = C.c_int(), C.c_double()
+    st = h.fc_host_separable(C.byref(p), which, cap, C.byref(rank),
+                             w.ctypes.data_as(C.POINTER(C.c_double)),
+                             F.ctypes.data_as(C.POINTER(C.c_double)), C.byref(gate))
+    assert st == 0, h.fc_last_error()
+    Q = rank.value
+    Fl = [F[l * n * cap:(l + 1) * n * cap].reshape(n, cap, order="F")[:, :Q] for l in range(3)]
+    sp = solve2d.Spectral2D(prob)
+    D = sp.D()
+    Dt = (Fl[0] * w[:Q][None, :] * Fl[2][0][None, :]) @ Fl[1].T
+    if which == 0:
+        assert np.abs(Dt / D - 1).max() <= max(gate.value, 1e-14) * 1.05 + 1e-13
+    else:
+        r = Dt * D
+        assert r.min() > 1 - gate.value - 1e-9 and r.max() < 1 + gate.value + 1e-9
+
+
+def test_setup_rejects_bad_dims():
+    h = _lib()
+    prob = wl.workload_small(n=16)
+    p, keep = _params(prob, dims=4)
+    rank = C.c_int()
+    st = h.fc_host_separable(C.byref(p), 0, 0, C.byref(rank), None, None, None)
+    assert st == 1 and b"dims" in h.fc_last_error()
