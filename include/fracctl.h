@@ -88,7 +88,9 @@ typedef struct {
     double op_accuracy;     /* entrywise relative accuracy of the operator; 0 -> eps           */
     int max_iter;           /* 0 -> 100                                                        */
     int max_rank;           /* Tucker rank capacity per mode; 0 -> 64, at most 96              */
-    int precond_rank;       /* Kronecker rank of the preconditioner; 0 -> 6 (Section 4)        */
+    int precond_rank;       /* Kronecker rank of the preconditioner (the paper's tests use 6,
+                               Section 4); 0 -> automatic: the first of 6, 8, ..., 16 whose
+                               fit of 1/f reaches a relative error of 1e-3 (else the best)    */
     fc_precision precision; /* FC_FP64 or FC_MIXED_FP32                                        */
     fc_precond_kind precond; /* FC_PRECOND_EIGEN (0, default) or FC_PRECOND_LAPLACE             */
     double precond_b0[3];   /* case (A) constants b0_l; <= 0 -> (max a_l + min a_l)/2 over the
@@ -240,7 +242,11 @@ fc_status fc_cp_truncate(fc_plan plan, int m, const double* w, const double* X1,
  * (Section 3.3, eqn. Gen3DtimesX, evaluated in eigen-coordinates; for
  * FC_PRECOND_LAPLACE eqn Lap3DtimesX with the sine-basis maps W_l, W_l^T
  * around the separable symbol, result in eigen-coordinates).  DEVICE buffers
- * as in fc_cp_truncate. */
+ * as in fc_cp_truncate.  Accuracy floor (this call, fc_cp_truncate and every
+ * truncation of the solve): subspaces and ranks come from unfolding Grams,
+ * which square the singular values, so relative accuracies below about 1e-8
+ * are not resolved (eps = 1e-8 gives errors up to ~5e-8; eps >= 1e-7 is
+ * met). */
 fc_status fc_apply_separable(fc_plan plan, int which, int m, const double* w, const double* X1,
                              const double* X2, const double* X3, double eps, int cap,
                              int* rank_out, double* w_out, double* O1, double* O2, double* O3,

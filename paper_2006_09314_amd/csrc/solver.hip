@@ -1280,17 +1280,36 @@ void build_preconditioner(fc_plan_s* p, double smin, double smax, const std::vec
         return;
     }
     auto pf = [&](double s) { return 1.0 / f_control(s, a, b, gm); };
+    // largest usable rank <= Kmax: positive weights and a relative error < 0.9
+    auto fit = [&](int Kmax, std::vector<double>& t, std::vector<double>& cc, double& err) {
+        for (int K = Kmax; K >= 1; --K) {
+            if (!fc::fit_expsum(pf, pf, smin, smax, K, t, cc, err)) continue;
+            bool pos = true;
+            for (double x : cc) pos = pos && x > 0;
+            if (pos && err < 0.9) return K;
+        }
+        return 0;
+    };
     std::vector<double> t, cc;
     double err = 0;
-    int K = p->precond_rank;
-    bool ok = false;
-    for (; K >= 1; --K) {
-        if (!fc::fit_expsum(pf, pf, smin, smax, K, t, cc, err)) continue;
-        bool pos = true;
-        for (double x : cc) pos = pos && x > 0;
-        if (pos && err < 0.9) { ok = true; break; }
+    int K = 0;
+    if (p->precond_rank > 0) {
+        K = fit(p->precond_rank, t, cc, err);
+    } else {
+        // automatic rank: the relative error of a fixed number of exponentials
+        // grows with the width of the spectrum, and every point of it costs
+        // PCG iterations, while a few more terms cost little in the Hadamard
+        // truncation; take the first of 6, 8, ..., 16 that reaches 1e-3
+        double best = 1e300;
+        for (int K0 = 6; K0 <= 16; K0 += 2) {
+            std::vector<double> t2, c2;
+            double e2 = 0;
+            const int k2 = fit(K0, t2, c2, e2);
+            if (k2 > 0 && e2 < best) { best = e2; K = k2; t = t2; cc = c2; err = e2; }
+            if (best <= 1e-3) break;
+        }
     }
-    if (!ok) throw FcError(FC_ERR_NUMERIC, "preconditioner fit failed");
+    if (K == 0) throw FcError(FC_ERR_NUMERIC, "preconditioner fit failed");
     for (int k = 0; k < K; ++k) add(cc[k], t[k]);
     err_out = err;
 }
@@ -1797,7 +1816,7 @@ static void apply_defaults(fc_plan_s* p, const fc_setup_params* prm) {
     p->max_iter = prm->max_iter > 0 ? prm->max_iter : 100;
     p->rcap = prm->max_rank > 0 ? prm->max_rank : 96;
     p->pcap = 128;
-    p->precond_rank = prm->precond_rank > 0 ? prm->precond_rank : 6;
+    p->precond_rank = prm->precond_rank;   // 0: automatic
     p->precision = prm->precision;
     p->pc_kind = prm->precond;
     p->dims = prm->dims == 2 ? 2 : 3;

@@ -74,20 +74,20 @@ def test_mixed_precision_2d():
 @pytest.mark.parametrize("alpha", [1.0, 0.5, 0.1])
 def test_paper_2d_iterations_flat_in_n(alpha):
     """Table 4.3 setting (a_1 = sin(100 pi x) + 1.1, a_2 = sin x cos x, box
-    design, beta = gamma = 1), n = 64 to 2048.  With the rank-6 preconditioner
-    the counts stay small; they can rise slowly with n because a fixed number
-    of exponentials fits 1/f less closely (relative error) as the spectrum
-    widens with n^2; a rank-12 preconditioner brings the largest case back
-    down."""
+    design, beta = gamma = 1), n = 64 to 2048, with the automatic
+    preconditioner rank: counts flat in n.  With the paper's fixed rank 6 the
+    counts rise slowly with n (a fixed number of exponentials fits 1/f less
+    closely, in relative error, as the spectrum widens with n^2), never
+    below the automatic rank's."""
     its = []
     for n in (64, 256, 1024, 2048):
         rep, info, w, U = _solve2d(wl.workload_paper_2d(n, alpha))
         its.append(info["iterations"])
     print(f"[iterations] 2D alpha={alpha}: {its}", flush=True)
-    assert max(its) <= 10, its
-    rep, info, w, U = _solve2d(wl.workload_paper_2d(2048, alpha), precond_rank=12)
-    print(f"[iterations] 2D alpha={alpha} n=2048 precond_rank=12: {info['iterations']}", flush=True)
-    assert info["iterations"] <= its[-1]
+    assert max(its) <= 5 and max(its) - min(its) <= 2, its
+    rep, info, w, U = _solve2d(wl.workload_paper_2d(2048, alpha), precond_rank=6)
+    print(f"[iterations] 2D alpha={alpha} n=2048 precond_rank=6: {info['iterations']}", flush=True)
+    assert info["iterations"] >= its[-1]
 
 
 def test_three_dimensional_entry_points_reject_2d_plans():
