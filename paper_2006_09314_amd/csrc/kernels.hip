@@ -1415,12 +1415,20 @@ hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, 
     return hipGetLastError();
 }
 
+// Destination of every kept column: an exclusive prefix count of keep[],
+// one wavefront, 64 flags per step (ballot + popcount).
 __global__ void compact_pos_kernel(int m, const int* keep, int* pos, int* count) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int c = 0;
-        for (int j = 0; j < m; ++j) { pos[j] = keep[j] ? c : -1; c += keep[j] ? 1 : 0; }
-        *count = c;
+    const int lane = threadIdx.x;
+    int carry = 0;
+    for (int base = 0; base < m; base += 64) {
+        const int j = base + lane;
+        const bool k = j < m && keep[j] != 0;
+        const unsigned long long mask = __ballot(k);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (j < m) pos[j] = k ? carry + before : -1;
+        carry += __popcll(mask);
     }
+    if (lane == 0) *count = carry;
 }
 
 __global__ void compact_copy_kernel(int n, int m, const double* __restrict__ src,
