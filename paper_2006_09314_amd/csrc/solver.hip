@@ -164,8 +164,13 @@ struct fc_plan_s {
     int site_calls[16] = {};
     std::mutex use_mu;   // one solve at a time per plan
     rocblas_handle blas = nullptr;   // plain FP64 GEMMs (own workspace, no atomics)
+    // pinned host landing area for the small device-to-host reads of a solve
+    // (ranks, spectra, scalars): a direct copy, no pageable staging
+    static constexpr size_t kPinnedBytes = 64 * 1024;
+    void* pinned = nullptr;
     ~fc_plan_s() {
         if (blas) rocblas_destroy_handle(blas);
+        if (pinned) (void)hipHostFree(pinned);
     }
 };
 
@@ -355,7 +360,15 @@ struct SiteClock {
 
 template <class T>
 void d2h(const Ctx& c, T* dst, const T* src, size_t count) {
-    HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, c.s));
+    const size_t bytes = count * sizeof(T);
+    void* pin = c.p->pinned;
+    if (pin && bytes <= fc_plan_s::kPinnedBytes) {
+        HIPCHK(hipMemcpyAsync(pin, src, bytes, hipMemcpyDeviceToHost, c.s));
+        sync(c);
+        std::memcpy(dst, pin, bytes);
+        return;
+    }
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.s));
     sync(c);
 }
 template <class T>
@@ -1525,6 +1538,7 @@ void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
             throw FcError(FC_ERR_HIP, "rocblas_set_workspace failed");
     }
     if (p->pc_kind == FC_PRECOND_LAPLACE) build_sine_maps(p);
+    HIPCHK(hipHostMalloc(&p->pinned, fc_plan_s::kPinnedBytes, hipHostMallocDefault));
     if (p->dims == 2) {
         p->Y3d = p->arena.alloc((size_t)p->n * 256);
         p->U3d = p->arena.alloc((size_t)p->n * 256);

@@ -262,3 +262,17 @@ def test_state_alpha0_is_beta_u():
 def test_state_full_size_sine1024_sampled():
     prob = wl.workload_sine(n=1024, seed=3)
     _check_state(prob, slabs=_sampled_slabs(prob.n, seed=5), cost=False)
+
+
+def test_max_size_n4096_sampled():
+    """The largest grid the library accepts (n = 4096 per mode, 6.9e10
+    unknowns), sampled mode-1 slabs against the oracle."""
+    prob = wl.workload_sine(n=4096, seed=7, rank=3)
+    rep, info, w, U = _check(prob, slabs=[0, 1, 2048, 4095])
+    for u in U:
+        np.testing.assert_allclose(np.linalg.norm(u, axis=0), 1.0, rtol=1e-10)
+
+
+def test_max_design_rank_256():
+    """A design with the largest accepted canonical rank (256 terms)."""
+    _check(wl.workload_quadratic(n=48, alpha=0.5, rank=256, seed=4))
