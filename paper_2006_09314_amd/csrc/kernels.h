@@ -77,16 +77,10 @@ hipError_t permute_core(int r0, int r1, int r2, int mode, int batch, const doubl
 
 // y[i] = a * x[i] (+ y[i] if accumulate)
 hipError_t axpby(long n, double a, const double* x, double b, double* y, hipStream_t s);
-// out[b] = sum_i x[b*stride + i] * y[b*stride + i] for i < n (deterministic tree)
 // out[0] = x . y for a long vector: 256-thread partial sums in up to 256
 // blocks (part: 256 doubles of scratch), then one block sums them (fixed order)
 hipError_t dot_long(long n, const double* x, const double* y, double* part, double* out,
                     hipStream_t s);
-hipError_t dot_batched(long n, int batch, const double* x, const double* y, long stride,
-                       double* out, hipStream_t s);
-// sum of `count` arrays of length n with coefficients: y = sum_t coef[t] * x[t*stride .. ]
-hipError_t sum_strided(long n, int count, const double* coef, const double* x, long stride,
-                       double* y, hipStream_t s);
 // X[:, c] *= scale[c] (or /= if divide) for an n x m column-major matrix
 hipError_t scale_cols(int n, int m, double* X, long ldx, const double* scale, int divide,
                       hipStream_t s);
@@ -94,10 +88,6 @@ hipError_t scale_cols(int n, int m, double* X, long ldx, const double* scale, in
 hipError_t col_norms(int n, int m, const double* X, long ldx, double* out, hipStream_t s);
 // fill with a deterministic pseudo-random normal-like sequence (counter hash)
 hipError_t fill_random(long n, unsigned seed, double* x, hipStream_t s);
-// zero a buffer with a fill kernel (graph-safe)
-hipError_t zero(long n, double* x, hipStream_t s);
-// x[0..n) = v
-hipError_t fill_int(int n, int* x, int v, hipStream_t s);
 // out[:, j] = v for j < m (out n x m, leading dimension ld).
 hipError_t fill_columns(int n, int m, const double* v, double* out, long ld, hipStream_t s);
 // w[k] *= <U[:, k], v> for k < K (U n x K, leading dimension ld).
@@ -117,22 +107,16 @@ hipError_t check_finite(long n, const double* x, int* flag, hipStream_t s);
 hipError_t cp_inner_reduce(int ra, int rb, const double* G0, const double* G1, const double* G2,
                            const double* wa, const double* wb, double* out, hipStream_t s);
 
-// Rank-revealing modified Gram-Schmidt (two passes per column) on the n x m
-// column-major matrix Y (ld n), in place, one workgroup.  Columns whose norm
-// after projection falls below drop * (their input norm) are removed; the
-// kept orthonormal columns are compacted to the front and their number is
-// written to *count (device int).
-hipError_t mgs_qr(int n, int m, double* Y, double drop, int* count, hipStream_t s);
-
 // Panel step of a blocked Gram-Schmidt: orthonormalise the n x b panel Y
 // (ld n, b <= 32) in place with `passes`-pass MGS; a column whose norm after
 // projection is <= drop * norm0[j] (norm0 null: drop * 1) is set to zero and
 // flagged 0 in keep[j].
 hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, int* keep,
                      int passes, hipStream_t s);
-// Move the kept columns (keep[j] != 0) of the n x m matrix Y to the front, in
-// order, and write their number to *count.  tmp: n x m scratch.
-hipError_t compact_cols(int n, int m, double* Y, const int* keep, double* tmp, int* count,
+// Move the kept columns (j < done, or keep[j] != 0) of the n x m matrix Y
+// (m <= 512) to the front, in order, in place, and write their number to
+// *count.
+hipError_t compact_cols(int n, int m, int done, double* Y, const int* keep, int* count,
                         hipStream_t s);
 
 // dst (cols x rows) = src^T, src rows x cols (ld lds), dst ld ldd

@@ -969,23 +969,6 @@ hipError_t axpby(long n, double a, const double* x, double b, double* y, hipStre
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void dot_kernel(long n, const double* __restrict__ x,
-                                                  const double* __restrict__ y, long stride,
-                                                  double* out) {
-    __shared__ double red[256];
-    const double* X = x + blockIdx.x * stride;
-    const double* Y = y + blockIdx.x * stride;
-    double acc = 0.0;
-    for (long i = threadIdx.x; i < n; i += 256) acc += X[i] * Y[i];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
-}
-
 __global__ __launch_bounds__(256) void dot_partial_kernel(long n, const double* __restrict__ x,
                                                           const double* __restrict__ y,
                                                           double* part) {
@@ -1010,38 +993,11 @@ __global__ __launch_bounds__(256) void dot_final_kernel(int parts, const double*
     if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
 }
 
-hipError_t dot_batched(long n, int batch, const double* x, const double* y, long stride,
-                       double* out, hipStream_t s) {
-    if (batch <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dot_kernel, dim3(batch), dim3(256), 0, s, n, x, y, stride, out);
-    return hipGetLastError();
-}
-
 hipError_t dot_long(long n, const double* x, const double* y, double* part, double* out,
                     hipStream_t s) {
     const int parts = (int)std::min<long>(256, std::max<long>(1, (n + 4095) / 4096));
     hipLaunchKernelGGL(dot_partial_kernel, dim3(parts), dim3(256), 0, s, n, x, y, part);
     hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(256), 0, s, parts, part, out);
-    return hipGetLastError();
-}
-
-__global__ void sum_strided_kernel(long n, int count, const double* __restrict__ coef,
-                                   const double* __restrict__ x, long stride,
-                                   double* __restrict__ y) {
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        double acc = 0.0;
-        for (int t = 0; t < count; ++t) acc += (coef ? coef[t] : 1.0) * x[i + t * stride];
-        y[i] = acc;
-    }
-}
-
-hipError_t sum_strided(long n, int count, const double* coef, const double* x, long stride,
-                       double* y, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(sum_strided_kernel, dim3(blocks), dim3(256), 0, s, n, count, coef, x,
-                       stride, y);
     return hipGetLastError();
 }
 
@@ -1109,19 +1065,6 @@ hipError_t fill_random(long n, unsigned seed, double* x, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(fill_random_kernel, dim3(blocks), dim3(256), 0, s, n, seed, x);
-    return hipGetLastError();
-}
-
-__global__ void zero_kernel(long n, double* x) {
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x)
-        x[i] = 0.0;
-}
-
-hipError_t zero(long n, double* x, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, s, n, x);
     return hipGetLastError();
 }
 
@@ -1197,17 +1140,6 @@ hipError_t scale_by_dot(int n, int K, const double* U, long ld, const double* v,
     return hipGetLastError();
 }
 
-__global__ void fill_int_kernel(int n, int* x, int v) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = v;
-}
-
-hipError_t fill_int(int n, int* x, int v, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const int blocks = std::min((n + 255) / 256, 256);
-    hipLaunchKernelGGL(fill_int_kernel, dim3(blocks), dim3(256), 0, s, n, x, v);
-    return hipGetLastError();
-}
-
 __global__ void copy2d_kernel(int rows, int cols, const double* __restrict__ src, long lds,
                               double* __restrict__ dst, long ldd) {
     const long total = (long)rows * cols;
@@ -1277,59 +1209,6 @@ __device__ inline double block_sum_1024(double v, double* red) {
     const double r = wave_sum((tid & 63) < 16 ? red[tid & 63] : 0.0);
     __syncthreads();
     return r;
-}
-
-__global__ __launch_bounds__(1024) void mgs_kernel(int n, int m, double* Y, double drop,
-                                                   int* count) {
-    __shared__ double red[32];
-    __shared__ double dots[1024];
-    const int tid = threadIdx.x;
-    int kept = 0;
-    for (int j = 0; j < m; ++j) {
-        double* y = Y + (long)j * n;
-        double s = 0.0;
-        for (int i = tid; i < n; i += 1024) s += y[i] * y[i];
-        const double nrm0 = sqrt(block_sum_1024(s, red));
-        // two projection passes against the kept columns 0..kept-1
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int c0 = 0; c0 < kept; c0 += 1024 / 64) {
-                // each wavefront computes one dot product
-                const int w = tid >> 6, lane = tid & 63;
-                const int c = c0 + w;
-                double acc = 0.0;
-                if (c < kept) {
-                    const double* q = Y + (long)c * n;
-                    for (int i = lane; i < n; i += 64) acc += q[i] * y[i];
-                }
-                acc = wave_sum(acc);
-                if (lane == 0) dots[w] = acc;
-                __syncthreads();
-                const int nc = min(16, kept - c0);
-                for (int i = tid; i < n; i += 1024) {
-                    double v = y[i];
-                    for (int t = 0; t < nc; ++t) v -= dots[t] * Y[(long)(c0 + t) * n + i];
-                    y[i] = v;
-                }
-                __syncthreads();
-            }
-        }
-        s = 0.0;
-        for (int i = tid; i < n; i += 1024) s += y[i] * y[i];
-        const double nrm = sqrt(block_sum_1024(s, red));
-        if (nrm > drop * nrm0 && nrm > 1e-300) {
-            double* dst = Y + (long)kept * n;
-            const double inv = 1.0 / nrm;
-            for (int i = tid; i < n; i += 1024) dst[i] = y[i] * inv;
-            ++kept;
-        }
-        __syncthreads();
-    }
-    if (tid == 0) *count = kept;
-}
-
-hipError_t mgs_qr(int n, int m, double* Y, double drop, int* count, hipStream_t s) {
-    hipLaunchKernelGGL(mgs_kernel, dim3(1), dim3(1024), 0, s, n, m, Y, drop, count);
-    return hipGetLastError();
 }
 
 __global__ void transpose_kernel(int rows, int cols, const double* __restrict__ src, long lds,
@@ -1415,42 +1294,46 @@ hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, 
     return hipGetLastError();
 }
 
-// Destination of every kept column: an exclusive prefix count of keep[],
-// one wavefront, 64 flags per step (ballot + popcount).
-__global__ void compact_pos_kernel(int m, const int* keep, int* pos, int* count) {
-    const int lane = threadIdx.x;
-    int carry = 0;
-    for (int base = 0; base < m; base += 64) {
-        const int j = base + lane;
-        const bool k = j < m && keep[j] != 0;
-        const unsigned long long mask = __ballot(k);
-        const int before = __popcll(mask & ((1ull << lane) - 1ull));
-        if (j < m) pos[j] = k ? carry + before : -1;
-        carry += __popcll(mask);
+// In-place compaction of the kept columns in one launch.  Every workgroup
+// first turns keep[] into destinations (an exclusive prefix count, one
+// wavefront, 64 flags per step by ballot + popcount; columns j < done count
+// as kept) in LDS, then each thread moves its own row: columns in increasing
+// order, column j to column pos[j] <= j.  A row is only ever touched by its
+// thread, and pos[j'] < j for every j' < j, so no source is overwritten
+// before it is read.
+__global__ __launch_bounds__(256) void compact_cols_kernel(int n, int m, int done,
+                                                           double* __restrict__ Y,
+                                                           const int* __restrict__ keep,
+                                                           int* __restrict__ count) {
+    __shared__ int pos[512];
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        int carry = 0;
+        for (int base = 0; base < m; base += 64) {
+            const int j = base + tid;
+            const bool k = j < m && (j < done || keep[j] != 0);
+            const unsigned long long mask = __ballot(k);
+            const int before = __popcll(mask & ((1ull << tid) - 1ull));
+            if (j < m) pos[j] = k ? carry + before : -1;
+            carry += __popcll(mask);
+        }
+        if (tid == 0 && blockIdx.x == 0) *count = carry;
     }
-    if (lane == 0) *count = carry;
-}
-
-__global__ void compact_copy_kernel(int n, int m, const double* __restrict__ src,
-                                    const int* __restrict__ pos, double* __restrict__ dst) {
-    const long total = (long)n * m;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
-        const int i = int(e % n), j = int(e / n);
+    __syncthreads();
+    const int i = blockIdx.x * 256 + tid;
+    if (i >= n) return;
+    for (int j = 0; j < m; ++j) {
         const int p = pos[j];
-        if (p >= 0) dst[i + (long)p * n] = src[e];
+        if (p >= 0 && p != j) Y[i + (long)p * n] = Y[i + (long)j * n];
     }
 }
 
-hipError_t compact_cols(int n, int m, double* Y, const int* keep, double* tmp, int* count,
+hipError_t compact_cols(int n, int m, int done, double* Y, const int* keep, int* count,
                         hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    int* pos = (int*)(tmp + (long)n * m);
-    hipLaunchKernelGGL(compact_pos_kernel, dim3(1), dim3(64), 0, s, m, keep, pos, count);
-    const long total = (long)n * m;
-    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(copy2d_kernel, dim3(blocks), dim3(256), 0, s, n, m, Y, (long)n, tmp, (long)n);
-    hipLaunchKernelGGL(compact_copy_kernel, dim3(blocks), dim3(256), 0, s, n, m, tmp, pos, Y);
+    if (m > 512) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(compact_cols_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, m, done, Y,
+                       keep, count);
     return hipGetLastError();
 }
 

@@ -148,7 +148,7 @@ struct fc_plan_s {
     int* icount = nullptr;
     double* jac = nullptr;
     WarmBasis warm[NSITES];
-    double *qrN = nullptr, *qrC = nullptr, *qrTmp = nullptr;
+    double *qrN = nullptr, *qrC = nullptr;
     double *Xs3[3] = {}, *HX3[3] = {}, *Bp3 = nullptr, *Ev3 = nullptr, *Evec3 = nullptr;
     int* qrKeep = nullptr;
     double* splitws = nullptr;
@@ -426,7 +426,6 @@ int orthonormalize(const Ctx& c, int m, double* Y, double drop, int done = 0, in
     double* norms = p->qrN;
     int* keep = p->qrKeep;
     HIPCHK(fc::col_norms(n, m, Y, n, norms, c.s));
-    HIPCHK(fc::fill_int(done, keep, 1, c.s));
     // panel width: the panel lives in LDS (<= 144 KiB)
     const int b = std::max(1, std::min(16, (int)((144L * 1024 / 8) / n)));
     // BCGS2: block projection, panel MGS, then a second block projection and
@@ -453,7 +452,7 @@ int orthonormalize(const Ctx& c, int m, double* Y, double drop, int done = 0, in
             }));
         }
     }
-    HIPCHK(fc::compact_cols(n, m, Y, keep, p->qrTmp, p->icount + 4 + slot, c.s));
+    HIPCHK(fc::compact_cols(n, m, done, Y, keep, p->icount + 4 + slot, c.s));
     int cnt = 0;
     d2h(c, &cnt, p->icount + 4 + slot, 1);
     return cnt;
@@ -1171,7 +1170,6 @@ void alloc_workspace(fc_plan_s* p) {
     p->icount = A.alloc_int(16);
     p->qrN = A.alloc(512);
     p->qrC = A.alloc(256 * 32);
-    p->qrTmp = A.alloc((size_t)n * 256 + 256);
     p->qrKeep = A.alloc_int(512);
     for (int l = 0; l < 3; ++l) {
         p->Xs3[l] = A.alloc((size_t)n * pc);
