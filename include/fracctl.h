@@ -189,7 +189,10 @@ fc_status fc_solve_state(fc_plan plan, int rank_y, const double* w_y, const doub
  * the environment variable FC_BATCH_STREAMS) each solve on a stream of their
  * own after the given stream's pending work; the call returns when all are
  * done.  The HIP runtime maps streams onto GPU_MAX_HW_QUEUES hardware queues
- * (4 unless set before the runtime starts), which bounds the concurrency. */
+ * (4 unless set before the runtime starts), which bounds the concurrency.
+ * Plans built with dims = 2 are solved as by fc_solve2d: their Y3[i] and
+ * U3[i] are not used (the arrays must still have `count` entries; those
+ * entries may be NULL). */
 fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
                            const double* const* w_y, const double* const* Y1,
                            const double* const* Y2, const double* const* Y3,

@@ -203,7 +203,8 @@ class Plan:
 def solve_batched(plans: Sequence["Plan"], problems: Sequence, cap_u: int = 4096, stream=None,
                   outs=None, raise_on_error: bool = True):
     """Concurrent solves (fc_solve_batched): problems[i] = (w_y, [Y1, Y2, Y3]) on
-    plans[i].  Returns a list of (w_u, [U1, U2, U3], info, status)."""
+    plans[i] ([Y1, Y2] for a dims=2 plan).  Returns a list of
+    (w_u, [U1, U2, U3] or [U1, U2], info, status)."""
     import torch
     from ._lib import Info, STATUS
     count = len(plans)
@@ -217,7 +218,7 @@ def solve_batched(plans: Sequence["Plan"], problems: Sequence, cap_u: int = 4096
             n = plans[i].n
             outs.append((torch.empty(cap_u, dtype=torch.float64, device=dev),
                          [torch.empty((cap_u, n), dtype=torch.float64, device=dev).t()
-                          for _ in range(3)]))
+                          for _ in range(len(Ys[i]))]))
     rank_y = (C.c_int * count)(*[Ys[i][0].shape[1] for i in range(count)])
     capa = (C.c_int * count)(*[outs[i][0].shape[0] for i in range(count)])
     rank_u = (C.c_int * count)()
@@ -227,9 +228,10 @@ def solve_batched(plans: Sequence["Plan"], problems: Sequence, cap_u: int = 4096
         count, arr([p.handle.value for p in plans]), rank_y,
         arr([_ptr(p[0]) for p in problems]),
         arr([_ptr(Ys[i][0]) for i in range(count)]), arr([_ptr(Ys[i][1]) for i in range(count)]),
-        arr([_ptr(Ys[i][2]) for i in range(count)]), capa, rank_u,
+        arr([_ptr(Ys[i][2]) if len(Ys[i]) > 2 else None for i in range(count)]), capa, rank_u,
         arr([_ptr(o[0]) for o in outs]), arr([_ptr(o[1][0]) for o in outs]),
-        arr([_ptr(o[1][1]) for o in outs]), arr([_ptr(o[1][2]) for o in outs]),
+        arr([_ptr(o[1][1]) for o in outs]),
+        arr([_ptr(o[1][2]) if len(o[1]) > 2 else None for o in outs]),
         status, infos, _stream_ptr(stream))
     res = []
     for i in range(count):

@@ -2186,9 +2186,13 @@ fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
             const int i = next.fetch_add(1);
             if (i >= count) break;
             std::lock_guard<std::mutex> lk(plans[i]->use_mu);
-            status[i] = fc_solve(plans[i], rank_y[i], w_y ? w_y[i] : nullptr, Y1[i], Y2[i], Y3[i],
-                                 cap_u[i], &rank_u[i], w_u[i], U1[i], U2[i], U3[i],
-                                 info ? &info[i] : nullptr, s);
+            const double* wy = w_y ? w_y[i] : nullptr;
+            fc_info* inf = info ? &info[i] : nullptr;
+            status[i] = plans[i]->dims == 2
+                            ? fc_solve2d(plans[i], rank_y[i], wy, Y1[i], Y2[i], cap_u[i],
+                                         &rank_u[i], w_u[i], U1[i], U2[i], inf, s)
+                            : fc_solve(plans[i], rank_y[i], wy, Y1[i], Y2[i], Y3[i], cap_u[i],
+                                       &rank_u[i], w_u[i], U1[i], U2[i], U3[i], inf, s);
             if (status[i] != FC_OK) errs[i] = g_last_error;
         }
         (void)hipStreamSynchronize(s);

@@ -99,3 +99,31 @@ def test_three_dimensional_entry_points_reject_2d_plans():
     w = torch.ones(1, dtype=torch.float64).cuda()
     with pytest.raises(FcError, match="two-dimensional"):
         plan.solve(w, [dev(prob.Y[0]), dev(prob.Y[1]), dev(prob.Y[1])])
+
+
+def test_batched_mixes_2d_and_3d_plans():
+    """fc_solve_batched with d = 2 and d = 3 plans in one call: each result
+    equals its single solve bit for bit."""
+    import torch
+    from paper_2006_09314_amd import api
+    from tests.gpu_util import dev, host, plan_for
+    p2 = [wl.workload_quadratic_2d(n=n, alpha=0.5, seed=s) for n, s in ((64, 1), (128, 2))]
+    p3 = [wl.workload_quadratic(n=48, alpha=0.5, seed=3)]
+    probs = [p2[0], p3[0], p2[1]]
+    plans = [plan_for(p, dims=len(p.a)) for p in probs]
+    inputs = [(torch.from_numpy(np.asarray(p.w, dtype=np.float64)).cuda(), [dev(y) for y in p.Y])
+              for p in probs]
+    res = api.solve_batched(plans, inputs, cap_u=256)
+    for i, (p, plan) in enumerate(zip(probs, plans)):
+        w_b, U_b, info_b, st = res[i]
+        assert st == "FC_OK", st
+        if len(p.a) == 2:
+            w_s, U_s, info_s = plan.solve2d(*inputs[i], cap_u=256)
+            rep = solve2d.rel_error_2d(p, host(w_b), [host(u) for u in U_b])
+            assert rep["rel_l2"] <= GATE * p.eps, rep
+        else:
+            w_s, U_s, info_s = plan.solve(*inputs[i], cap_u=256)
+        assert len(U_b) == len(p.a)
+        assert np.array_equal(host(w_b), host(w_s))
+        for a, b in zip(U_b, U_s):
+            assert np.array_equal(host(a), host(b))
