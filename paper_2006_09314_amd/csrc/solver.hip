@@ -593,7 +593,7 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
 template <class Apply>
 bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, double tail_budget,
                     int margin, int pk[3], const double* const* span = nullptr,
-                    const int* span_ortho = nullptr) {
+                    const int* span_ortho = nullptr, const int* cold = nullptr) {
     fc_plan_s* p = c.p;
     const int n = c.n;
     WarmBasis& wb = p->warm[site];
@@ -612,7 +612,7 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
             HIPCHK(fc::copy2d(n, have[l], wb.W[l], n, p->Xs3[l], n, c.s));
         } else {
             have[l] = 0;
-            kk[l] = kcap[l];
+            kk[l] = cold ? std::max(1, std::min(kcap[l], cold[l])) : kcap[l];
         }
     }
     std::vector<double> th(3 * KM);
@@ -874,8 +874,15 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
         gemm(c, false, true, n, r[l] * q, Q, 1.0, op.D[l], n, p->Ts, (long)r[l] * q, 0.0, p->F, n);
         HIPCHK(fc::rowcontract(n, r[l], q, P.Z[l], n, p->F, HXo, n, c.s));
     };
-    for (int l = 0; l < 3; ++l) kcap[l] = std::min({p->pcap, n, Q * r[l]});
-    if (!find_subspaces(c, site, kcap, apply, tau2_est / 3.0, 16, pk)) {
+    // a cold start (no basis from an earlier call at this site) begins with
+    // twice the input rank plus the margin; the search enlarges it when the
+    // Ritz tail needs more
+    int cold[3];
+    for (int l = 0; l < 3; ++l) {
+        kcap[l] = std::min({p->pcap, n, Q * r[l]});
+        cold[l] = 2 * r[l] + 32;
+    }
+    if (!find_subspaces(c, site, kcap, apply, tau2_est / 3.0, 16, pk, nullptr, nullptr, cold)) {
         out.r[0] = out.r[1] = out.r[2] = 0;
         return;
     }
