@@ -608,7 +608,9 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
             HIPCHK(fc::copy2d(n, kk[l], span[l], n, p->Xs3[l], n, c.s));
         } else if (wb.valid) {
             have[l] = std::min(wb.pk[l], kcap[l]);
-            kk[l] = std::min(kcap[l], have[l] + 2 * margin);
+            // the earlier basis plus padding, and at least the cold-start size
+            // (the input's rank may have grown since)
+            kk[l] = std::min(kcap[l], std::max(have[l] + 2 * margin, cold ? cold[l] : 0));
             HIPCHK(fc::copy2d(n, have[l], wb.W[l], n, p->Xs3[l], n, c.s));
         } else {
             have[l] = 0;
