@@ -110,14 +110,35 @@ hipError_t cp_inner_reduce(int ra, int rb, const double* G0, const double* G1, c
 // Panel step of a blocked Gram-Schmidt: orthonormalise the n x b panel Y
 // (ld n, b <= 32) in place with `passes`-pass MGS; a column whose norm after
 // projection is <= drop * norm0[j] (norm0 null: drop * 1) is set to zero and
-// flagged 0 in keep[j].
-hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, int* keep,
-                     int passes, hipStream_t s);
-// Move the kept columns (j < done, or keep[j] != 0) of the n x m matrix Y
+// flagged 0 in keep[j].  Up to kMaxPanelJobs panels (of different matrices)
+// per launch, one workgroup each.
+constexpr int kMaxPanelJobs = 3;
+struct PanelJob {
+    double* Y = nullptr;
+    const double* norm0 = nullptr;
+    double drop = 0.0;
+    int* keep = nullptr;
+    int b = 0;
+};
+struct PanelJobs {
+    int count = 0;
+    PanelJob job[kMaxPanelJobs];
+};
+hipError_t panel_mgs(int n, const PanelJobs& jobs, int passes, hipStream_t s);
+// Move the kept columns (j < done, or keep[j] != 0) of each n x m matrix Y
 // (m <= 512) to the front, in order, in place, and write their number to
-// *count.
-hipError_t compact_cols(int n, int m, int done, double* Y, const int* keep, int* count,
-                        hipStream_t s);
+// *count (device int); up to kMaxPanelJobs matrices per launch.
+struct CompactJob {
+    double* Y = nullptr;
+    int m = 0, done = 0;
+    const int* keep = nullptr;
+    int* count = nullptr;
+};
+struct CompactJobs {
+    int count = 0;
+    CompactJob job[kMaxPanelJobs];
+};
+hipError_t compact_cols(int n, const CompactJobs& jobs, hipStream_t s);
 
 // dst (cols x rows) = src^T, src rows x cols (ld lds), dst ld ldd
 hipError_t transpose(int rows, int cols, const double* src, long lds, double* dst, long ldd,

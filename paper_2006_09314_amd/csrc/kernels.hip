@@ -1234,13 +1234,17 @@ hipError_t transpose(int rows, int cols, const double* src, long lds, double* ds
 // Two-pass classical Gram-Schmidt inside a panel held in LDS: for column j,
 // all dot products against the kept panel columns are formed in one sweep
 // (one wavefront per column), then subtracted in one sweep.
-__global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, int b, double* Y,
-                                                         const double* norm0, double drop,
-                                                         int* keep, int passes) {
+__global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, PanelJobs jobs, int passes) {
     extern __shared__ double P[];   // n x b
     __shared__ double red[32];
     __shared__ double dots[32];
     __shared__ int kp[32];
+    const PanelJob& jb = jobs.job[blockIdx.x];
+    double* Y = jb.Y;
+    const double* norm0 = jb.norm0;
+    const double drop = jb.drop;
+    int* keep = jb.keep;
+    const int b = jb.b;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (long x = tid; x < (long)n * b; x += 1024) P[x] = Y[x];
     __syncthreads();
@@ -1278,10 +1282,15 @@ __global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, int b, double* Y
     for (long x = tid; x < (long)n * b; x += 1024) Y[x] = P[x];
 }
 
-hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, int* keep,
-                     int passes, hipStream_t s) {
-    if (b <= 0) return hipSuccess;
-    if ((long)n * b * sizeof(double) > 144L * 1024 || b > 32) return hipErrorInvalidValue;
+hipError_t panel_mgs(int n, const PanelJobs& jobs, int passes, hipStream_t s) {
+    if (jobs.count <= 0) return hipSuccess;
+    if (jobs.count > kMaxPanelJobs) return hipErrorInvalidValue;
+    int bmax = 0;
+    for (int i = 0; i < jobs.count; ++i) {
+        if (jobs.job[i].b <= 0 || jobs.job[i].b > 32) return hipErrorInvalidValue;
+        bmax = std::max(bmax, jobs.job[i].b);
+    }
+    if ((long)n * bmax * sizeof(double) > 144L * 1024) return hipErrorInvalidValue;
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
     std::call_once(once, [] {
@@ -1289,35 +1298,35 @@ hipError_t panel_mgs(int n, int b, double* Y, const double* norm0, double drop, 
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     });
     if (attr_err != hipSuccess) return attr_err;
-    hipLaunchKernelGGL(panel_mgs_kernel, dim3(1), dim3(1024), sizeof(double) * n * b, s, n, b, Y,
-                       norm0, drop, keep, passes);
+    hipLaunchKernelGGL(panel_mgs_kernel, dim3(jobs.count), dim3(1024), sizeof(double) * n * bmax, s,
+                       n, jobs, passes);
     return hipGetLastError();
 }
 
-// In-place compaction of the kept columns in one launch.  Every workgroup
-// first turns keep[] into destinations (an exclusive prefix count, one
-// wavefront, 64 flags per step by ballot + popcount; columns j < done count
-// as kept) in LDS, then each thread moves its own row: columns in increasing
-// order, column j to column pos[j] <= j.  A row is only ever touched by its
-// thread, and pos[j'] < j for every j' < j, so no source is overwritten
-// before it is read.
-__global__ __launch_bounds__(256) void compact_cols_kernel(int n, int m, int done,
-                                                           double* __restrict__ Y,
-                                                           const int* __restrict__ keep,
-                                                           int* __restrict__ count) {
+// In-place compaction of the kept columns in one launch (grid.y: one job per
+// matrix).  Every workgroup first turns keep[] into destinations (an
+// exclusive prefix count, one wavefront, 64 flags per step by ballot +
+// popcount; columns j < done count as kept) in LDS, then each thread moves
+// its own row: columns in increasing order, column j to column pos[j] <= j.
+// A row is only ever touched by its thread, and pos[j'] < j for every j' < j,
+// so no source is overwritten before it is read.
+__global__ __launch_bounds__(256) void compact_cols_kernel(int n, CompactJobs jobs) {
     __shared__ int pos[512];
+    const CompactJob& jb = jobs.job[blockIdx.y];
+    const int m = jb.m, done = jb.done;
+    double* __restrict__ Y = jb.Y;
     const int tid = threadIdx.x;
     if (tid < 64) {
         int carry = 0;
         for (int base = 0; base < m; base += 64) {
             const int j = base + tid;
-            const bool k = j < m && (j < done || keep[j] != 0);
+            const bool k = j < m && (j < done || jb.keep[j] != 0);
             const unsigned long long mask = __ballot(k);
             const int before = __popcll(mask & ((1ull << tid) - 1ull));
             if (j < m) pos[j] = k ? carry + before : -1;
             carry += __popcll(mask);
         }
-        if (tid == 0 && blockIdx.x == 0) *count = carry;
+        if (tid == 0 && blockIdx.x == 0) *jb.count = carry;
     }
     __syncthreads();
     const int i = blockIdx.x * 256 + tid;
@@ -1328,12 +1337,13 @@ __global__ __launch_bounds__(256) void compact_cols_kernel(int n, int m, int don
     }
 }
 
-hipError_t compact_cols(int n, int m, int done, double* Y, const int* keep, int* count,
-                        hipStream_t s) {
-    if (m <= 0) return hipSuccess;
-    if (m > 512) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(compact_cols_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, m, done, Y,
-                       keep, count);
+hipError_t compact_cols(int n, const CompactJobs& jobs, hipStream_t s) {
+    if (jobs.count <= 0) return hipSuccess;
+    if (jobs.count > kMaxPanelJobs) return hipErrorInvalidValue;
+    for (int i = 0; i < jobs.count; ++i)
+        if (jobs.job[i].m < 0 || jobs.job[i].m > 512) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(compact_cols_kernel, dim3((n + 255) / 256, jobs.count), dim3(256), 0, s, n,
+                       jobs);
     return hipGetLastError();
 }
 

@@ -418,44 +418,90 @@ double host_dot(const Ctx& c, long n, const double* x, const double* y) {
 // after projection drops below `drop` times their input norm are removed.
 // Returns the number of kept columns (compacted to the front).
 // `done` leading columns are already orthonormal and are kept as they are.
-int orthonormalize(const Ctx& c, int m, double* Y, double drop, int done = 0, int slot = 0) {
+// Rank-revealing orthonormalisation of up to three n x m_l blocks (one per
+// mode, in place; block l only when use[l]): BCGS2 with panels of b columns.
+// Per panel: block projection against the earlier columns, panel MGS (two
+// passes, drop test), a second block projection and panel pass.  The second
+// round removes what normalising a nearly dependent column magnified of its
+// rounding components along the earlier columns; a column with less than
+// half its length left after it was rounding noise and is dropped.  The
+// first done_l columns are already orthonormal.  The modes run in lockstep:
+// each panel step of the three modes is one launch (a workgroup per mode),
+// the compaction of the kept columns one launch, and the three counts one
+// read; m[l] receives the count.
+void orthonormalize3(const Ctx& c, int m[3], double* const Y[3], double drop, const int done_in[3],
+                     const bool use[3]) {
     fc_plan_s* p = c.p;
     const int n = c.n;
-    if (m <= 0) return 0;
-    done = std::max(0, std::min(done, m));
-    double* norms = p->qrN;
-    int* keep = p->qrKeep;
-    HIPCHK(fc::col_norms(n, m, Y, n, norms, c.s));
+    int done[3];
+    bool on[3];
+    for (int l = 0; l < 3; ++l) {
+        on[l] = use[l] && m[l] > 0;
+        done[l] = on[l] ? std::max(0, std::min(done_in[l], m[l])) : 0;
+        if (on[l]) HIPCHK(fc::col_norms(n, m[l], Y[l], n, p->qrN + l * 512L, c.s));
+    }
     // panel width: the panel lives in LDS (<= 144 KiB)
     const int b = std::max(1, std::min(16, (int)((144L * 1024 / 8) / n)));
-    // BCGS2: block projection, panel MGS, then a second block projection and
-    // panel pass.  The second round removes what normalising a nearly
-    // dependent column magnified of its rounding components along the earlier
-    // columns; a column with less than half its length left after it was
-    // rounding noise and is dropped.
-    for (int j0 = done; j0 < m; j0 += b) {
-        const int bw = std::min(b, m - j0);
-        double* P = Y + (long)j0 * n;
-        if (j0 > 0) {
-            gemm(c, true, false, j0, bw, n, 1.0, Y, n, P, n, 0.0, p->qrC, j0);
-            gemm(c, false, false, n, bw, j0, -1.0, Y, n, p->qrC, j0, 1.0, P, n);
+    for (int pi = 0;; ++pi) {
+        fc::PanelJobs first, second;
+        int j0s[3] = {0, 0, 0};
+        double flops1 = 0, bytes1 = 0, flops2 = 0, bytes2 = 0;
+        for (int l = 0; l < 3; ++l) {
+            if (!on[l]) continue;
+            const int j0 = done[l] + pi * b;
+            if (j0 >= m[l]) continue;
+            const int bw = std::min(b, m[l] - j0);
+            double* P = Y[l] + (long)j0 * n;
+            j0s[l] = j0;
+            if (j0 > 0) {
+                gemm(c, true, false, j0, bw, n, 1.0, Y[l], n, P, n, 0.0, p->qrC, j0);
+                gemm(c, false, false, n, bw, j0, -1.0, Y[l], n, p->qrC, j0, 1.0, P, n);
+            }
+            fc::PanelJob& J = first.job[first.count++];
+            J.Y = P; J.norm0 = p->qrN + l * 512L + j0; J.drop = drop;
+            J.keep = p->qrKeep + l * 512L + j0; J.b = bw;
+            // algorithmic work: the panel read and written once, two MGS passes
+            flops1 += 4.0 * n * bw * bw;
+            bytes1 += 16.0 * n * bw;
         }
-        // algorithmic work: the panel read and written once, two MGS passes
-        HIPCHK(timed_launch(1, c.s, 4.0 * n * bw * bw, 16.0 * n * bw, [&] {
-            return fc::panel_mgs(n, bw, P, norms + j0, drop, keep + j0, 2, c.s);
-        }));
-        if (j0 > 0) {
-            gemm(c, true, false, j0, bw, n, 1.0, Y, n, P, n, 0.0, p->qrC, j0);
-            gemm(c, false, false, n, bw, j0, -1.0, Y, n, p->qrC, j0, 1.0, P, n);
-            HIPCHK(timed_launch(1, c.s, 2.0 * n * bw * bw, 16.0 * n * bw, [&] {
-                return fc::panel_mgs(n, bw, P, nullptr, 0.5, keep + j0, 1, c.s);
-            }));
+        if (first.count == 0) break;
+        HIPCHK(timed_launch(1, c.s, flops1, bytes1,
+                            [&] { return fc::panel_mgs(n, first, 2, c.s); }));
+        for (int t = 0, l = 0; l < 3; ++l) {
+            if (!on[l] || done[l] + pi * b >= m[l]) continue;
+            const fc::PanelJob& J1 = first.job[t++];
+            const int j0 = j0s[l];
+            if (j0 == 0) continue;
+            gemm(c, true, false, j0, J1.b, n, 1.0, Y[l], n, J1.Y, n, 0.0, p->qrC, j0);
+            gemm(c, false, false, n, J1.b, j0, -1.0, Y[l], n, p->qrC, j0, 1.0, J1.Y, n);
+            fc::PanelJob& J = second.job[second.count++];
+            J = J1;
+            J.norm0 = nullptr; J.drop = 0.5;
+            flops2 += 2.0 * n * J1.b * J1.b;
+            bytes2 += 16.0 * n * J1.b;
         }
+        if (second.count > 0)
+            HIPCHK(timed_launch(1, c.s, flops2, bytes2,
+                                [&] { return fc::panel_mgs(n, second, 1, c.s); }));
     }
-    HIPCHK(fc::compact_cols(n, m, done, Y, keep, p->icount + 4 + slot, c.s));
-    int cnt = 0;
-    d2h(c, &cnt, p->icount + 4 + slot, 1);
-    return cnt;
+    fc::CompactJobs cj;
+    int slot[3] = {-1, -1, -1};
+    for (int l = 0; l < 3; ++l) {
+        if (!on[l]) continue;
+        fc::CompactJob& J = cj.job[cj.count];
+        J.Y = Y[l]; J.m = m[l]; J.done = done[l]; J.keep = p->qrKeep + l * 512L;
+        J.count = p->icount + 4 + cj.count;
+        slot[l] = cj.count++;
+    }
+    if (cj.count == 0) {
+        for (int l = 0; l < 3; ++l) if (use[l]) m[l] = 0;
+        return;
+    }
+    HIPCHK(fc::compact_cols(n, cj, c.s));
+    int cnt[3] = {0, 0, 0};
+    d2h(c, cnt, p->icount + 4, cj.count);
+    for (int l = 0; l < 3; ++l)
+        if (use[l]) m[l] = on[l] ? cnt[slot[l]] : 0;
 }
 
 // Diagnostic (environment variable FC_CHECK): largest deviation of M^T M
@@ -619,21 +665,34 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
     }
     std::vector<double> th(3 * KM);
     for (int round = 0;; ++round) {
+        // start bases of the active modes, orthonormalised together
+        int start_done[3] = {0, 0, 0};
         for (int l = 0; l < 3; ++l) {
             if (!active[l]) continue;
             if (kk[l] > have[l])
                 HIPCHK(fc::fill_random(n * (long)(kk[l] - have[l]),
                                        1234u + 7u * l + 101u * site + 7919u * round,
                                        p->Xs3[l] + (long)have[l] * n, c.s));
-            kk[l] = orthonormalize(c, kk[l], p->Xs3[l], 1e-13, exact[l] ? first_cols[l] : have[l]);
+            start_done[l] = exact[l] ? first_cols[l] : have[l];
+        }
+        orthonormalize3(c, kk, p->Xs3, 1e-13, start_done, active);
+        bool power[3] = {false, false, false};
+        int before[3] = {0, 0, 0};
+        for (int l = 0; l < 3; ++l) {
+            if (!active[l]) continue;
             if (kk[l] == 0) return false;
             check_cols(c, p->Xs3[l], n, n, kk[l], "start basis", l);
             if (exact[l]) continue;
             // one power step moves the start into the range of H_l
-            const int before = kk[l];
+            power[l] = true;
+            before[l] = kk[l];
             apply(l, p->Xs3[l], kk[l], p->HX3[l]);
-            kk[l] = orthonormalize(c, kk[l], p->HX3[l], 1e-13);
-            dropped[l] = kk[l] < before;
+        }
+        const int none[3] = {0, 0, 0};
+        orthonormalize3(c, kk, p->HX3, 1e-13, none, power);
+        for (int l = 0; l < 3; ++l) {
+            if (!power[l]) continue;
+            dropped[l] = kk[l] < before[l];
             if (kk[l] == 0) return false;
             std::swap(p->Xs3[l], p->HX3[l]);
             check_cols(c, p->Xs3[l], n, n, kk[l], "power-step basis", l);
@@ -970,8 +1029,12 @@ void canon_to_tucker(const Ctx& c, int m, const double* w, const double* const X
     for (int l = 0; l < 3; ++l) {
         HIPCHK(fc::copy2d(n, m, X[l], n, p->Phi[l], n, c.s));
     }
-    int cnt[3];
-    for (int l = 0; l < 3; ++l) cnt[l] = orthonormalize(c, m, p->Phi[l], 1e-13);
+    int cnt[3] = {m, m, m};
+    {
+        const int none[3] = {0, 0, 0};
+        const bool all[3] = {true, true, true};
+        orthonormalize3(c, cnt, p->Phi, 1e-13, none, all);
+    }
     for (int l = 0; l < 3; ++l) {
         k[l] = cnt[l];
         if (k[l] > KM) throw FcError(FC_ERR_INTERNAL, std::string(what) + ": input basis > 128");
@@ -1177,9 +1240,9 @@ void alloc_workspace(fc_plan_s* p) {
     p->tmpn = A.alloc((size_t)n * std::max<long>(rc, 256));
     p->tmpn2 = A.alloc((size_t)n * std::max<long>(rc, 256));
     p->icount = A.alloc_int(16);
-    p->qrN = A.alloc(512);
+    p->qrN = A.alloc(3 * 512);
     p->qrC = A.alloc(256 * 32);
-    p->qrKeep = A.alloc_int(512);
+    p->qrKeep = A.alloc_int(3 * 512);
     for (int l = 0; l < 3; ++l) {
         p->Xs3[l] = A.alloc((size_t)n * pc);
         p->HX3[l] = A.alloc((size_t)n * pc);
