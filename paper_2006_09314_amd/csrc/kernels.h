@@ -125,6 +125,19 @@ struct PanelJobs {
     PanelJob job[kMaxPanelJobs];
 };
 hipError_t panel_mgs(int n, const PanelJobs& jobs, int passes, hipStream_t s);
+// Block projection update P -= Y C of up to kMaxPanelJobs panels per launch:
+// P n x b (ld n, b <= 16), Y n x j0 (ld n, 1 <= j0 <= 256), C j0 x b (ld j0).
+struct UpdateJob {
+    const double* Y = nullptr;
+    const double* C = nullptr;
+    double* P = nullptr;
+    int j0 = 0, b = 0;
+};
+struct UpdateJobs {
+    int count = 0;
+    UpdateJob job[kMaxPanelJobs];
+};
+hipError_t panel_update(int n, const UpdateJobs& jobs, hipStream_t s);
 // Move the kept columns (j < done, or keep[j] != 0) of each n x m matrix Y
 // (m <= 512) to the front, in order, in place, and write their number to
 // *count (device int); up to kMaxPanelJobs matrices per launch.

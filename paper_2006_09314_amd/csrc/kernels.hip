@@ -1303,6 +1303,64 @@ hipError_t panel_mgs(int n, const PanelJobs& jobs, int passes, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Block projection update of a panel, P -= Y C (P n x b, Y n x j0, C j0 x b
+// with leading dimension j0, b <= 16), for up to kMaxPanelJobs panels per
+// launch (grid.y).  A workgroup covers 64 rows; its wavefront w handles the
+// columns w, w + 4, ... of those rows, streaming the rows of Y (coalesced
+// within the wavefront; the four wavefronts share them through the cache)
+// against C held in LDS.
+__global__ __launch_bounds__(256) void panel_update_kernel(int n, UpdateJobs jobs) {
+    __shared__ double Cs[256 * 16];
+    const UpdateJob& jb = jobs.job[blockIdx.y];
+    const int j0 = jb.j0, b = jb.b;
+    for (int x = threadIdx.x; x < j0 * b; x += 256) Cs[x] = jb.C[x];
+    __syncthreads();
+    const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + r;
+    if (i >= n) return;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* __restrict__ Y = jb.Y + i;
+    // eight rows of C per step: eight independent loads of Y in flight
+    int c = 0;
+    for (; c + 8 <= j0; c += 8) {
+        double y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y[u] = Y[(long)(c + u) * n];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = g + 4 * q;
+                if (j < b) acc[q] += y[u] * Cs[c + u + j * j0];
+            }
+    }
+    for (; c < j0; ++c) {
+        const double y = Y[(long)c * n];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = g + 4 * q;
+            if (j < b) acc[q] += y * Cs[c + j * j0];
+        }
+    }
+    double* __restrict__ P = jb.P + i;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = g + 4 * q;
+        if (j < b) P[(long)j * n] -= acc[q];
+    }
+}
+
+hipError_t panel_update(int n, const UpdateJobs& jobs, hipStream_t s) {
+    if (jobs.count <= 0) return hipSuccess;
+    if (jobs.count > kMaxPanelJobs) return hipErrorInvalidValue;
+    for (int t = 0; t < jobs.count; ++t)
+        if (jobs.job[t].b < 1 || jobs.job[t].b > 16 || jobs.job[t].j0 < 1 || jobs.job[t].j0 > 256)
+            return hipErrorInvalidValue;
+    hipLaunchKernelGGL(panel_update_kernel, dim3((n + 63) / 64, jobs.count), dim3(256), 0, s, n,
+                       jobs);
+    return hipGetLastError();
+}
+
 // In-place compaction of the kept columns in one launch (grid.y: one job per
 // matrix).  Every workgroup first turns keep[] into destinations (an
 // exclusive prefix count, one wavefront, 64 flags per step by ballot +

@@ -442,9 +442,24 @@ void orthonormalize3(const Ctx& c, int m[3], double* const Y[3], double drop, co
     }
     // panel width: the panel lives in LDS (<= 144 KiB)
     const int b = std::max(1, std::min(16, (int)((144L * 1024 / 8) / n)));
+    // block projection P -= Y (Y^T P) of the modes' current panels: the
+    // coefficients per mode (Gram-type product), the updates in one launch
+    auto project = [&](const fc::PanelJobs& pj, const int* j0s, const int* modes) {
+        fc::UpdateJobs uj;
+        for (int t = 0; t < pj.count; ++t) {
+            const int l = modes[t];
+            if (j0s[l] == 0) continue;
+            double* Cl = p->qrC + (long)l * 256 * 16;
+            gemm(c, true, false, j0s[l], pj.job[t].b, n, 1.0, Y[l], n, pj.job[t].Y, n, 0.0, Cl,
+                 j0s[l]);
+            fc::UpdateJob& U = uj.job[uj.count++];
+            U.Y = Y[l]; U.C = Cl; U.P = pj.job[t].Y; U.j0 = j0s[l]; U.b = pj.job[t].b;
+        }
+        HIPCHK(fc::panel_update(n, uj, c.s));
+    };
     for (int pi = 0;; ++pi) {
         fc::PanelJobs first, second;
-        int j0s[3] = {0, 0, 0};
+        int j0s[3] = {0, 0, 0}, modes[3] = {0, 0, 0};
         double flops1 = 0, bytes1 = 0, flops2 = 0, bytes2 = 0;
         for (int l = 0; l < 3; ++l) {
             if (!on[l]) continue;
@@ -453,10 +468,7 @@ void orthonormalize3(const Ctx& c, int m[3], double* const Y[3], double drop, co
             const int bw = std::min(b, m[l] - j0);
             double* P = Y[l] + (long)j0 * n;
             j0s[l] = j0;
-            if (j0 > 0) {
-                gemm(c, true, false, j0, bw, n, 1.0, Y[l], n, P, n, 0.0, p->qrC, j0);
-                gemm(c, false, false, n, bw, j0, -1.0, Y[l], n, p->qrC, j0, 1.0, P, n);
-            }
+            modes[first.count] = l;
             fc::PanelJob& J = first.job[first.count++];
             J.Y = P; J.norm0 = p->qrN + l * 512L + j0; J.drop = drop;
             J.keep = p->qrKeep + l * 512L + j0; J.b = bw;
@@ -465,21 +477,22 @@ void orthonormalize3(const Ctx& c, int m[3], double* const Y[3], double drop, co
             bytes1 += 16.0 * n * bw;
         }
         if (first.count == 0) break;
+        project(first, j0s, modes);
         HIPCHK(timed_launch(1, c.s, flops1, bytes1,
                             [&] { return fc::panel_mgs(n, first, 2, c.s); }));
-        for (int t = 0, l = 0; l < 3; ++l) {
-            if (!on[l] || done[l] + pi * b >= m[l]) continue;
-            const fc::PanelJob& J1 = first.job[t++];
-            const int j0 = j0s[l];
-            if (j0 == 0) continue;
-            gemm(c, true, false, j0, J1.b, n, 1.0, Y[l], n, J1.Y, n, 0.0, p->qrC, j0);
-            gemm(c, false, false, n, J1.b, j0, -1.0, Y[l], n, p->qrC, j0, 1.0, J1.Y, n);
+        int modes2[3] = {0, 0, 0};
+        for (int t = 0; t < first.count; ++t) {
+            const int l = modes[t];
+            if (j0s[l] == 0) continue;
+            const fc::PanelJob& J1 = first.job[t];
+            modes2[second.count] = l;
             fc::PanelJob& J = second.job[second.count++];
             J = J1;
             J.norm0 = nullptr; J.drop = 0.5;
             flops2 += 2.0 * n * J1.b * J1.b;
             bytes2 += 16.0 * n * J1.b;
         }
+        if (second.count > 0) project(second, j0s, modes2);
         if (second.count > 0)
             HIPCHK(timed_launch(1, c.s, flops2, bytes2,
                                 [&] { return fc::panel_mgs(n, second, 1, c.s); }));
@@ -1241,7 +1254,7 @@ void alloc_workspace(fc_plan_s* p) {
     p->tmpn2 = A.alloc((size_t)n * std::max<long>(rc, 256));
     p->icount = A.alloc_int(16);
     p->qrN = A.alloc(3 * 512);
-    p->qrC = A.alloc(256 * 32);
+    p->qrC = A.alloc(3 * 256 * 16);
     p->qrKeep = A.alloc_int(3 * 512);
     for (int l = 0; l < 3; ++l) {
         p->Xs3[l] = A.alloc((size_t)n * pc);
