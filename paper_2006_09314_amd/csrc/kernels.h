@@ -32,6 +32,14 @@ hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
 // truncations, one workgroup per 32 x 32 output tile, K split over its
 // wavefronts.
 hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
+// Up to kMaxGramJobs unbatched Gram-type products (each as in gram) in one
+// launch.
+constexpr int kMaxGramJobs = 3;
+struct GramJobs {
+    int count = 0;
+    GemmArgs g[kMaxGramJobs];
+};
+hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s);
 
 // Symmetric eigen-decomposition of a batch of k x k matrices (k <= 128),
 // cyclic Jacobi with the matrix in LDS.  A (column-major, leading dimension

@@ -272,12 +272,11 @@ constexpr int GR_WAVES = 16;
 constexpr int GR_DEPTH = 1;   // chunks loaded per wavefront before computing
 
 template <int L>
-__global__ __launch_bounds__(64 * GR_WAVES) void gram_kernel(GemmArgs g) {
+__device__ __forceinline__ void gram_tile(const GemmArgs& g, int tile, long b) {
     extern __shared__ double gram_red[];   // [GR_WAVES][4 blocks][4 regs][64 lanes]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tilesM = (g.M + 31) / 32;
-    const int i0 = (blockIdx.x % tilesM) * 32, j0 = (blockIdx.x / tilesM) * 32;
-    const long b = blockIdx.z;
+    const int i0 = (tile % tilesM) * 32, j0 = (tile / tilesM) * 32;
     const double* __restrict__ A = g.A + b * g.strideA;
     const double* __restrict__ B = g.B + b * g.strideB;
     double* __restrict__ C = g.C + b * g.strideC;
@@ -336,6 +335,21 @@ __global__ __launch_bounds__(64 * GR_WAVES) void gram_kernel(GemmArgs g) {
     }
 }
 
+template <int L>
+__global__ __launch_bounds__(64 * GR_WAVES) void gram_kernel(GemmArgs g) {
+    gram_tile<L>(g, blockIdx.x, blockIdx.z);
+}
+
+// Up to kMaxGramJobs independent products (each unbatched) in one launch:
+// grid.y picks the product, blocks beyond its tile count return at once.
+template <int L>
+__global__ __launch_bounds__(64 * GR_WAVES) void gram_multi_kernel(GramJobs jobs) {
+    const GemmArgs& g = jobs.g[blockIdx.y];
+    const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
+    if ((int)blockIdx.x >= tiles) return;
+    gram_tile<L>(g, blockIdx.x, 0);
+}
+
 hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     if (g.M > 128 || g.N > 128 || g.inner != 1 || g.d || g.lowp || g.K <= 0 || (transA && transB))
@@ -361,6 +375,40 @@ hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s) {
         hipLaunchKernelGGL(gram_kernel<1>, grid, block, lds, s, g);
     else
         hipLaunchKernelGGL(gram_kernel<2>, grid, block, lds, s, g);
+    return hipGetLastError();
+}
+
+hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s) {
+    if (jobs.count <= 0) return hipSuccess;
+    if (jobs.count > kMaxGramJobs || (transA && transB)) return hipErrorInvalidValue;
+    int tiles = 0;
+    for (int t = 0; t < jobs.count; ++t) {
+        const GemmArgs& g = jobs.g[t];
+        if (g.M <= 0 || g.N <= 0 || g.M > 128 || g.N > 128 || g.K <= 0 || g.batch != 1 ||
+            g.inner != 1 || g.d || g.lowp)
+            return hipErrorInvalidValue;
+        tiles = std::max(tiles, ((g.M + 31) / 32) * ((g.N + 31) / 32));
+    }
+    const size_t lds = sizeof(double) * GR_WAVES * 4 * 4 * 64;   // 128 KiB
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [lds] {
+        const void* fns[3] = {(const void*)gram_multi_kernel<0>, (const void*)gram_multi_kernel<1>,
+                              (const void*)gram_multi_kernel<2>};
+        for (const void* f : fns) {
+            const hipError_t e =
+                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) attr_err = e;
+        }
+    });
+    if (attr_err != hipSuccess) return attr_err;
+    const dim3 grid(tiles, jobs.count), block(64 * GR_WAVES);
+    if (transA)
+        hipLaunchKernelGGL(gram_multi_kernel<0>, grid, block, lds, s, jobs);
+    else if (transB)
+        hipLaunchKernelGGL(gram_multi_kernel<1>, grid, block, lds, s, jobs);
+    else
+        hipLaunchKernelGGL(gram_multi_kernel<2>, grid, block, lds, s, jobs);
     return hipGetLastError();
 }
 

@@ -335,6 +335,35 @@ void gemmb(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, co
          sBi, sCi, nullptr, 0, true);
 }
 
+// Up to three unbatched FP64 products A^T B (each M, N <= 128) in one launch
+// of the Gram kernel; timed like gemm when the GEMM profile is on.
+void gram3(const Ctx& c, fc::GramJobs& jobs) {
+    if (jobs.count == 0) return;
+    if (g_prof.on && !t_no_profile) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (g_prof.used + 2 > g_prof.ev.size()) {
+            for (int i = 0; i < 256; ++i) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                g_prof.ev.push_back(e);
+            }
+        }
+        HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], c.s));
+        HIPCHK(fc::gram_multi(true, false, jobs, c.s));
+        HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], c.s));
+        g_prof.used += 2;
+        for (int t = 0; t < jobs.count; ++t) {
+            const fc::GemmArgs& g = jobs.g[t];
+            g_prof.shapes.push_back({true, false, g.M, g.N, g.K, 1, 1, false});
+            g_prof.flops += 2.0 * g.M * g.N * (double)g.K;
+            g_prof.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
+        }
+        g_prof.launches += 1;
+        return;
+    }
+    HIPCHK(fc::gram_multi(true, false, jobs, c.s));
+}
+
 void sync(const Ctx& c) { HIPCHK(hipStreamSynchronize(c.s)); }
 
 // With FC_TRACE: wall time of one truncation, stream drained at both ends.
@@ -446,15 +475,24 @@ void orthonormalize3(const Ctx& c, int m[3], double* const Y[3], double drop, co
     // coefficients per mode (Gram-type product), the updates in one launch
     auto project = [&](const fc::PanelJobs& pj, const int* j0s, const int* modes) {
         fc::UpdateJobs uj;
+        fc::GramJobs gj;
         for (int t = 0; t < pj.count; ++t) {
             const int l = modes[t];
             if (j0s[l] == 0) continue;
             double* Cl = p->qrC + (long)l * 256 * 16;
-            gemm(c, true, false, j0s[l], pj.job[t].b, n, 1.0, Y[l], n, pj.job[t].Y, n, 0.0, Cl,
-                 j0s[l]);
+            if (j0s[l] <= 128) {
+                // coefficients of the short blocks: one Gram launch for the modes
+                fc::GemmArgs& g = gj.g[gj.count++];
+                g.M = j0s[l]; g.N = pj.job[t].b; g.K = n;
+                g.A = Y[l]; g.lda = n; g.B = pj.job[t].Y; g.ldb = n; g.C = Cl; g.ldc = j0s[l];
+            } else {
+                gemm(c, true, false, j0s[l], pj.job[t].b, n, 1.0, Y[l], n, pj.job[t].Y, n, 0.0,
+                     Cl, j0s[l]);
+            }
             fc::UpdateJob& U = uj.job[uj.count++];
             U.Y = Y[l]; U.C = Cl; U.P = pj.job[t].Y; U.j0 = j0s[l]; U.b = pj.job[t].b;
         }
+        gram3(c, gj);
         HIPCHK(fc::panel_update(n, uj, c.s));
     };
     for (int pi = 0;; ++pi) {
