@@ -335,9 +335,24 @@ void gemmb(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, co
          sBi, sCi, nullptr, 0, true);
 }
 
-// Up to three unbatched FP64 products A^T B (each M, N <= 128) in one launch
-// of the Gram kernel; timed like gemm when the GEMM profile is on.
-void gram3(const Ctx& c, fc::GramJobs& jobs) {
+// Up to three independent FP64 products of the same form (op(A) op(B) with
+// the given transposes) issued together: those that are Gram-type (the same
+// rule as run_gemm: M, N <= 128 and A^T B, or a reduction of at least 256)
+// share one launch of the Gram kernel, the others go through gemm.  Timed
+// like gemm when the GEMM profile is on.
+void gemm_group(const Ctx& c, bool ta, bool tb, const fc::GemmArgs* prods, int count) {
+    fc::GramJobs jobs;
+    for (int t = 0; t < count; ++t) {
+        const fc::GemmArgs& g = prods[t];
+        if (g.M <= 0 || g.N <= 0) continue;
+        const bool gram_type = g.M <= 128 && g.N <= 128 && !(ta && tb) && (ta || g.K >= 256) &&
+                               g.K > 0;
+        if (gram_type) {
+            jobs.g[jobs.count++] = g;
+        } else {
+            gemm(c, ta, tb, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc);
+        }
+    }
     if (jobs.count == 0) return;
     if (g_prof.on && !t_no_profile) {
         std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -349,19 +364,27 @@ void gram3(const Ctx& c, fc::GramJobs& jobs) {
             }
         }
         HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], c.s));
-        HIPCHK(fc::gram_multi(true, false, jobs, c.s));
+        HIPCHK(fc::gram_multi(ta, tb, jobs, c.s));
         HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], c.s));
         g_prof.used += 2;
         for (int t = 0; t < jobs.count; ++t) {
             const fc::GemmArgs& g = jobs.g[t];
-            g_prof.shapes.push_back({true, false, g.M, g.N, g.K, 1, 1, false});
+            g_prof.shapes.push_back({ta, tb, g.M, g.N, g.K, 1, 1, false});
             g_prof.flops += 2.0 * g.M * g.N * (double)g.K;
             g_prof.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
         }
         g_prof.launches += 1;
         return;
     }
-    HIPCHK(fc::gram_multi(true, false, jobs, c.s));
+    HIPCHK(fc::gram_multi(ta, tb, jobs, c.s));
+}
+
+fc::GemmArgs prod(int M, int N, int K, const double* A, long lda, const double* B, long ldb,
+                  double* C, long ldc) {
+    fc::GemmArgs g;
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+    return g;
 }
 
 void sync(const Ctx& c) { HIPCHK(hipStreamSynchronize(c.s)); }
@@ -475,24 +498,17 @@ void orthonormalize3(const Ctx& c, int m[3], double* const Y[3], double drop, co
     // coefficients per mode (Gram-type product), the updates in one launch
     auto project = [&](const fc::PanelJobs& pj, const int* j0s, const int* modes) {
         fc::UpdateJobs uj;
-        fc::GramJobs gj;
+        fc::GemmArgs coef[3];
+        int nc = 0;
         for (int t = 0; t < pj.count; ++t) {
             const int l = modes[t];
             if (j0s[l] == 0) continue;
             double* Cl = p->qrC + (long)l * 256 * 16;
-            if (j0s[l] <= 128) {
-                // coefficients of the short blocks: one Gram launch for the modes
-                fc::GemmArgs& g = gj.g[gj.count++];
-                g.M = j0s[l]; g.N = pj.job[t].b; g.K = n;
-                g.A = Y[l]; g.lda = n; g.B = pj.job[t].Y; g.ldb = n; g.C = Cl; g.ldc = j0s[l];
-            } else {
-                gemm(c, true, false, j0s[l], pj.job[t].b, n, 1.0, Y[l], n, pj.job[t].Y, n, 0.0,
-                     Cl, j0s[l]);
-            }
+            coef[nc++] = prod(j0s[l], pj.job[t].b, n, Y[l], n, pj.job[t].Y, n, Cl, j0s[l]);
             fc::UpdateJob& U = uj.job[uj.count++];
             U.Y = Y[l]; U.C = Cl; U.P = pj.job[t].Y; U.j0 = j0s[l]; U.b = pj.job[t].b;
         }
-        gram3(c, gj);
+        gemm_group(c, true, false, coef, nc);   // C_l = Y_l^T P_l
         HIPCHK(fc::panel_update(n, uj, c.s));
     };
     for (int pi = 0;; ++pi) {
@@ -586,17 +602,22 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
     if (csz == 0) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
     for (int l = 0; l < 3; ++l)
         if (k[l] > KM) throw FcError(FC_ERR_INTERNAL, std::string(what) + ": subspace > 128");
-    // unfolding Grams
-    for (int l = 0; l < 3; ++l) {
-        int pd[3];
-        perm_dims(k, l, pd);
-        const double* src = C;
-        if (l != 0) {
-            HIPCHK(fc::permute_core(k[0], k[1], k[2], l, 1, C, 0, p->Cp, 0, c.s));
-            src = p->Cp;
+    // unfolding Grams (modes 1 and 2 from permuted copies, one launch)
+    {
+        fc::GemmArgs grams[3];
+        double* perm[3] = {nullptr, p->Cp, p->Cn1};
+        for (int l = 0; l < 3; ++l) {
+            int pd[3];
+            perm_dims(k, l, pd);
+            const double* src = C;
+            if (l != 0) {
+                HIPCHK(fc::permute_core(k[0], k[1], k[2], l, 1, C, 0, perm[l], 0, c.s));
+                src = perm[l];
+            }
+            grams[l] = prod(pd[0], pd[0], pd[1] * pd[2], src, pd[0], src, pd[0],
+                            p->Cg + (long)l * KM * KM, pd[0]);
         }
-        gemm(c, false, true, pd[0], pd[0], pd[1] * pd[2], 1.0, src, pd[0], src, pd[0], 0.0,
-             p->Cg + (long)l * KM * KM, pd[0]);
+        gemm_group(c, false, true, grams, 3);
     }
     // per-mode share of the budget: the HOSVD bound sum_l tail_l <= thr2.  With
     // d = 2 the core is a matrix (third rank 1, no tail) and cutting both
@@ -750,11 +771,18 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
         }
         fc::EigJobs jobs;
         jobs.count = 0;
+        fc::GemmArgs rr_mats[3];
+        int nrr = 0;
         for (int l = 0; l < 3; ++l) {
             if (!active[l]) continue;
             apply(l, p->Xs3[l], kk[l], p->HX3[l]);
+            rr_mats[nrr++] = prod(kk[l], kk[l], n, p->Xs3[l], n, p->HX3[l], n,
+                                  p->Bp3 + (long)l * KM * KM, kk[l]);
+        }
+        gemm_group(c, true, false, rr_mats, nrr);   // Rayleigh-Ritz matrices X^T H X
+        for (int l = 0; l < 3; ++l) {
+            if (!active[l]) continue;
             double* Bl = p->Bp3 + (long)l * KM * KM;
-            gemm(c, true, false, kk[l], kk[l], n, 1.0, p->Xs3[l], n, p->HX3[l], n, 0.0, Bl, kk[l]);
             fc::EigJob& J = jobs.job[jobs.count++];
             J.A = Bl; J.lda = kk[l]; J.k = kk[l];
             J.evals = p->Ev3 + l * KM; J.V = p->Evec3 + (long)l * KM * KM; J.ldv = kk[l];
@@ -835,8 +863,13 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
         for (int t = 0; t < m; ++t)
             HIPCHK(fc::copy2d(n, terms[t].second->r[l], terms[t].second->Z[l], n,
                               p->Phi[l] + (long)off[t][l] * n, n, c.s));
-        // full Gram of the concatenated bases (k_l x k_l)
-        gemm(c, true, false, k[l], k[l], n, 1.0, p->Phi[l], n, p->Phi[l], n, 0.0, p->SG[l], k[l]);
+    }
+    {
+        // full Grams of the concatenated bases (k_l x k_l), the modes together
+        fc::GemmArgs grams[3];
+        for (int l = 0; l < 3; ++l)
+            grams[l] = prod(k[l], k[l], n, p->Phi[l], n, p->Phi[l], n, p->SG[l], k[l]);
+        gemm_group(c, true, false, grams, 3);
     }
     // block unfolding Grams M_l (k_l x k_l)
     for (int l = 0; l < 3; ++l) {
@@ -1093,9 +1126,13 @@ void canon_to_tucker(const Ctx& c, int m, const double* w, const double* const X
     }
     // coefficients M_l = Phi_l^T X_l  (k_l x m); scale M_2 columns by w
     double* Ml[3];
-    for (int l = 0; l < 3; ++l) {
-        Ml[l] = p->cf[l];
-        gemm(c, true, false, k[l], m, n, 1.0, p->Phi[l], n, X[l], n, 0.0, Ml[l], k[l]);
+    {
+        fc::GemmArgs coefs[3];
+        for (int l = 0; l < 3; ++l) {
+            Ml[l] = p->cf[l];
+            coefs[l] = prod(k[l], m, n, p->Phi[l], n, X[l], n, Ml[l], k[l]);
+        }
+        gemm_group(c, true, false, coefs, 3);
     }
     if (w) HIPCHK(fc::scale_cols(k[2], m, Ml[2], k[2], w, 0, c.s));
     // Khatri-Rao: KR[(i,j), s] = M0[i,s] M1[j,s]  -> use rowkron on transposes: build
