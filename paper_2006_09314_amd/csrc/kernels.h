@@ -160,6 +160,17 @@ struct CompactJobs {
     CompactJob job[kMaxPanelJobs];
 };
 hipError_t compact_cols(int n, const CompactJobs& jobs, hipStream_t s);
+// Column 2-norms of up to kMaxPanelJobs n x m matrices (ld n) in one launch.
+struct NormJob {
+    const double* X = nullptr;
+    int m = 0;
+    double* out = nullptr;
+};
+struct NormJobs {
+    int count = 0;
+    NormJob job[kMaxPanelJobs];
+};
+hipError_t col_norms(int n, const NormJobs& jobs, hipStream_t s);
 
 // dst (cols x rows) = src^T, src rows x cols (ld lds), dst ld ldd
 hipError_t transpose(int rows, int cols, const double* src, long lds, double* dst, long ldd,

@@ -1070,10 +1070,7 @@ hipError_t scale_cols(int n, int m, double* X, long ldx, const double* scale, in
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void col_norms_kernel(int n, const double* __restrict__ X,
-                                                        long ldx, double* out) {
-    __shared__ double red[256];
-    const double* x = X + blockIdx.x * ldx;
+__device__ void col_norm(int n, const double* __restrict__ x, double* out, double* red) {
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) acc += x[i] * x[i];
     red[threadIdx.x] = acc;
@@ -1082,12 +1079,36 @@ __global__ __launch_bounds__(256) void col_norms_kernel(int n, const double* __r
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(red[0]);
+    if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
+__global__ __launch_bounds__(256) void col_norms_kernel(int n, const double* __restrict__ X,
+                                                        long ldx, double* out) {
+    __shared__ double red[256];
+    col_norm(n, X + blockIdx.x * ldx, out + blockIdx.x, red);
+}
+
+// Column norms of up to kMaxPanelJobs matrices in one launch (grid.y).
+__global__ __launch_bounds__(256) void col_norms_multi_kernel(int n, NormJobs jobs) {
+    __shared__ double red[256];
+    const NormJob& jb = jobs.job[blockIdx.y];
+    if ((int)blockIdx.x >= jb.m) return;
+    col_norm(n, jb.X + (long)blockIdx.x * n, jb.out + blockIdx.x, red);
 }
 
 hipError_t col_norms(int n, int m, const double* X, long ldx, double* out, hipStream_t s) {
     if (m <= 0) return hipSuccess;
     hipLaunchKernelGGL(col_norms_kernel, dim3(m), dim3(256), 0, s, n, X, ldx, out);
+    return hipGetLastError();
+}
+
+hipError_t col_norms(int n, const NormJobs& jobs, hipStream_t s) {
+    if (jobs.count <= 0) return hipSuccess;
+    if (jobs.count > kMaxPanelJobs) return hipErrorInvalidValue;
+    int mmax = 0;
+    for (int t = 0; t < jobs.count; ++t) mmax = std::max(mmax, jobs.job[t].m);
+    if (mmax <= 0) return hipSuccess;
+    hipLaunchKernelGGL(col_norms_multi_kernel, dim3(mmax, jobs.count), dim3(256), 0, s, n, jobs);
     return hipGetLastError();
 }
 

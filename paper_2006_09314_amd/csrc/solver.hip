@@ -487,11 +487,16 @@ void orthonormalize3(const Ctx& c, int m[3], double* const Y[3], double drop, co
     const int n = c.n;
     int done[3];
     bool on[3];
+    fc::NormJobs nj;
     for (int l = 0; l < 3; ++l) {
         on[l] = use[l] && m[l] > 0;
         done[l] = on[l] ? std::max(0, std::min(done_in[l], m[l])) : 0;
-        if (on[l]) HIPCHK(fc::col_norms(n, m[l], Y[l], n, p->qrN + l * 512L, c.s));
+        if (on[l]) {
+            fc::NormJob& J = nj.job[nj.count++];
+            J.X = Y[l]; J.m = m[l]; J.out = p->qrN + l * 512L;
+        }
     }
+    HIPCHK(fc::col_norms(n, nj, c.s));
     // panel width: the panel lives in LDS (<= 144 KiB)
     const int b = std::max(1, std::min(16, (int)((144L * 1024 / 8) / n)));
     // block projection P -= Y (Y^T P) of the modes' current panels: the
