@@ -367,9 +367,12 @@ void gemm_group(const Ctx& c, bool ta, bool tb, const fc::GemmArgs* prods, int c
         HIPCHK(fc::gram_multi(ta, tb, jobs, c.s));
         HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], c.s));
         g_prof.used += 2;
+        // one shape entry per launch (the log pairs them with the events): the
+        // first product's shape, with the number of products as its batch
+        const fc::GemmArgs& g0 = jobs.g[0];
+        g_prof.shapes.push_back({ta, tb, g0.M, g0.N, g0.K, jobs.count, 1, false});
         for (int t = 0; t < jobs.count; ++t) {
             const fc::GemmArgs& g = jobs.g[t];
-            g_prof.shapes.push_back({ta, tb, g.M, g.N, g.K, 1, 1, false});
             g_prof.flops += 2.0 * g.M * g.N * (double)g.K;
             g_prof.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
         }
