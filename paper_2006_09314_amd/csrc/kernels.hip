@@ -538,13 +538,28 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double
 //  4. the eigenvectors move to LDS (one padded column each; the reflectors
 //     to global scratch) and vectors of clusters of close eigenvalues are
 //     re-orthogonalised against all their predecessors;
-//  5. back-transformation by the reflectors in LDS.
+//  5. back-transformation: each wavefront applies all reflectors to the
+//     columns it owns, with no barrier between reflectors.
+// The Sturm recurrence divides by a Newton-refined hardware reciprocal, and
+// the LU factors keep reciprocal pivots, so neither inner loop runs the full
+// division sequence.
 // Eigenvalues are returned in descending order.  Eigenvectors belonging to
 // eigenvalues at most 1e-17 of the largest in magnitude are neither refined
 // nor back-transformed (callers do not use them).  Scratch: 6 k^2 doubles.
 constexpr int TD_THREADS = 512;
 
 __device__ inline double td_wave_sum(double v) { return wave_sum(v); }
+
+// 1/q for the Sturm recurrence: the hardware reciprocal estimate refined by
+// two Newton steps (r <- r + r (1 - q r)), accurate to a few ulp; |q| is
+// kept at or above the pivot floor, so no operand scaling is needed
+__device__ inline double td_recip(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    double t = fma(-q, r, 1.0);
+    r = fma(r, t, r);
+    t = fma(-q, r, 1.0);
+    return fma(r, t, r);
+}
 
 __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
     extern __shared__ double sm[];
@@ -615,9 +630,23 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
             for (int r = lane; r < m; r += 64) pw[r] -= K * vv[r];
         }
         __syncthreads();
-        for (int x = tid; x < m * m; x += blockDim.x) {
-            const int r = x % m, c = x / m;
-            a[(j + 1 + r) + (j + 1 + c) * k] -= vv[r] * pw[c] + pw[r] * vv[c];
+        if (m > 64) {
+            // lane l updates rows l and l+64 (k <= 128), wavefront w columns
+            // w, w+8, ...: the row factors stay in registers
+            const bool in1 = lane + 64 < m;
+            const double vr0 = vv[lane], wr0 = pw[lane];
+            const double vr1 = in1 ? vv[lane + 64] : 0.0, wr1 = in1 ? pw[lane + 64] : 0.0;
+            for (int c = wv; c < m; c += TD_THREADS / 64) {
+                const double vc = vv[c], wc = pw[c];
+                double* col = a + (j + 1) + (long)(j + 1 + c) * k;
+                col[lane] -= vr0 * wc + wr0 * vc;
+                if (in1) col[lane + 64] -= vr1 * wc + wr1 * vc;
+            }
+        } else {
+            for (int x = tid; x < m * m; x += blockDim.x) {
+                const int r = x % m, c = x / m;
+                a[(j + 1 + r) + (j + 1 + c) * k] -= vv[r] * pw[c] + pw[r] * vv[c];
+            }
         }
         __syncthreads();
     }
@@ -659,8 +688,8 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
                 c2 = qb < 0;
                 for (int i = 1; i < k; ++i) {
                     const double di = d[i], ee = e2[i - 1];
-                    qa = (di - x1) - ee / qa;
-                    qb = (di - x2) - ee / qb;
+                    qa = (di - x1) - ee * td_recip(qa);
+                    qb = (di - x2) - ee * td_recip(qb);
                     if (fabs(qa) < pivmin) qa = -pivmin;
                     if (fabs(qb) < pivmin) qb = -pivmin;
                     c1 += qa < 0;
@@ -702,7 +731,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
     const int nvec = nvec_s;
     // 3. inverse iteration, thread i owns eigenvector i (coalesced scratch)
     double* X = J.scratch;                    // X[i + j k]: element j of vector i
-    double* U0 = X + (long)k * k;             // pivoted LU factors
+    double* U0 = X + (long)k * k;             // pivoted LU factors (U0: reciprocal pivots)
     double* U1 = U0 + (long)k * k;
     double* U2 = U1 + (long)k * k;
     double* ML = U2 + (long)k * k;            // multipliers, sign encodes the interchange
@@ -718,7 +747,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
             const double bn = (j + 2 < k) ? e[j + 1] : 0.0;
             if (fabs(ad) >= fabs(c)) {
                 const double mlt = (ad != 0.0) ? c / ad : 0.0;
-                U0[i + (long)j * k] = (fabs(ad) < smallpiv) ? copysign(smallpiv, ad) : ad;
+                U0[i + (long)j * k] = 1.0 / ((fabs(ad) < smallpiv) ? copysign(smallpiv, ad) : ad);
                 U1[i + (long)j * k] = bd;
                 U2[i + (long)j * k] = fd;
                 ML[i + (long)j * k] = mlt;
@@ -728,7 +757,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
                 fd = 0.0;
             } else {
                 const double mlt = ad / c;
-                U0[i + (long)j * k] = c;
+                U0[i + (long)j * k] = 1.0 / c;
                 U1[i + (long)j * k] = an;
                 U2[i + (long)j * k] = bn;
                 ML[i + (long)j * k] = mlt;
@@ -740,7 +769,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
                 fd = 0.0;
             }
         }
-        U0[i + (long)(k - 1) * k] = (fabs(ad) < smallpiv) ? copysign(smallpiv, ad) : ad;
+        U0[i + (long)(k - 1) * k] = 1.0 / ((fabs(ad) < smallpiv) ? copysign(smallpiv, ad) : ad);
         U1[i + (long)(k - 1) * k] = 0.0;
         U2[i + (long)(k - 1) * k] = 0.0;
         // start vector
@@ -784,7 +813,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
                     if (q < jn) {
-                        const double v = (rh[q] - u1[q] * x1 - u2[q] * x2) / u0[q];
+                        const double v = (rh[q] - u1[q] * x1 - u2[q] * x2) * u0[q];
                         X[i + (long)(j1 - q) * k] = v;
                         x2 = x1;
                         x1 = v;
@@ -854,34 +883,38 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
         }
         __syncthreads();
     }
-    // 5. back-transformation in LDS: V = H_0 ... H_{k-3} X; reflector j acts
-    //    on rows j+1..k-1
-    for (int j = k - 3; j >= 0; --j) {
-        const double t = tau[j];
-        if (t == 0.0) continue;
-        const int m = k - j - 1;
-        for (int r = tid; r < m; r += blockDim.x) vv[r] = Rf[(j + 1 + r) + j * k];
-        __syncthreads();
-        // s_i = t * v^T V[j+1:, i], four threads per column
-        for (int base = 0; base < 4 * nvec; base += blockDim.x) {
-            const int x = base + tid;
-            const int i = x >> 2, part = x & 3;
-            double acc = 0.0;
-            if (i < nvec && used[i] != 0.0) {
-                const double* col = Xl + (long)i * kp + (j + 1);
-                for (int r = part; r < m; r += 4) acc += vv[r] * col[r];
+    // 5. back-transformation V = H_0 ... H_{k-3} X (reflector j acts on rows
+    //    j+1..k-1).  Wavefront w owns columns w, w+8, ... and applies every
+    //    reflector to them in turn, so the wavefronts never wait for each
+    //    other; lane l holds rows l and l+64 of the reflector, loaded one
+    //    reflector ahead (k <= 128, so two rows per lane cover it).
+    {
+        auto refl = [&](int jj, int r) {
+            return r < k - jj - 1 ? Rf[(jj + 1 + r) + (long)jj * k] : 0.0;
+        };
+        double c0 = 0.0, c1 = 0.0;
+        if (k >= 3) { c0 = refl(k - 3, lane); c1 = refl(k - 3, lane + 64); }
+        for (int j = k - 3; j >= 0; --j) {
+            double n0 = 0.0, n1 = 0.0;
+            if (j > 0) { n0 = refl(j - 1, lane); n1 = refl(j - 1, lane + 64); }
+            const double t = tau[j];
+            if (t != 0.0) {
+                const int m = k - j - 1;
+                for (int i = wv; i < nvec; i += TD_THREADS / 64) {
+                    if (used[i] == 0.0) continue;
+                    double* col = Xl + (long)i * kp + (j + 1);
+                    const double x0 = lane < m ? col[lane] : 0.0;
+                    const double x1 = lane + 64 < m ? col[lane + 64] : 0.0;
+                    const double sj = t * td_wave_sum(c0 * x0 + c1 * x1);
+                    if (lane < m) col[lane] = x0 - sj * c0;
+                    if (lane + 64 < m) col[lane + 64] = x1 - sj * c1;
+                }
             }
-            acc += __shfl_xor(acc, 1, 64);
-            acc += __shfl_xor(acc, 2, 64);
-            if (i < nvec && part == 0) pw[i] = t * acc;
+            c0 = n0;
+            c1 = n1;
         }
-        __syncthreads();
-        for (int x = tid; x < m * nvec; x += blockDim.x) {
-            const int r = x % m, i = x / m;
-            Xl[(j + 1 + r) + (long)i * kp] -= pw[i] * vv[r];
-        }
-        __syncthreads();
     }
+    __syncthreads();
     for (int x = tid; x < k * nvec; x += blockDim.x) {
         const int r = x % k, i = x / k;
         J.V[r + (long)i * J.ldv] = Xl[r + (long)i * kp];
