@@ -85,10 +85,12 @@ hipError_t permute_core(int r0, int r1, int r2, int mode, int batch, const doubl
 
 // y[i] = a * x[i] (+ y[i] if accumulate)
 hipError_t axpby(long n, double a, const double* x, double b, double* y, hipStream_t s);
-// out[0] = x . y for a long vector: 256-thread partial sums in up to 256
-// blocks (part: 256 doubles of scratch), then one block sums them (fixed order)
-hipError_t dot_long(long n, const double* x, const double* y, double* part, double* out,
-                    hipStream_t s);
+// out[0] = x . y for a long vector in one launch: 256-thread partial sums in
+// up to 256 blocks (part: 256 doubles of scratch), summed in block order by
+// the last block to finish.  count: one unsigned that is zero before the call
+// and is zero again after it (calls sharing it must not overlap).
+hipError_t dot_long(long n, const double* x, const double* y, double* part, unsigned* count,
+                    double* out, hipStream_t s);
 // X[:, c] *= scale[c] (or /= if divide) for an n x m column-major matrix
 hipError_t scale_cols(int n, int m, double* X, long ldx, const double* scale, int divide,
                       hipStream_t s);
@@ -108,6 +110,33 @@ hipError_t normalize_factors(int n, int K, double* U0, double* U1, double* U2, l
 // copy a column-major m x n block
 hipError_t copy2d(int rows, int cols, const double* src, long lds, double* dst, long ldd,
                   hipStream_t s);
+// Up to kMaxCopyJobs column-major block copies in one launch.
+constexpr int kMaxCopyJobs = 12;
+struct CopyJob {
+    const double* src = nullptr; long lds = 0;
+    double* dst = nullptr; long ldd = 0;
+    int rows = 0, cols = 0;
+};
+struct CopyJobs {
+    int count = 0;
+    CopyJob job[kMaxCopyJobs];
+};
+hipError_t copy_multi(const CopyJobs& jobs, hipStream_t s);
+// Block-symmetric k x k matrices (ld k) split into nb diagonal blocks at
+// off[0] = 0 < off[1] < ... < off[nb] = k, with the blocks on and above the
+// diagonal filled: the blocks below are set to the transposes of their
+// mirror images.  Up to three matrices in one launch.
+constexpr int kMaxSymBlocks = 4;
+struct SymJob {
+    double* M = nullptr;
+    int k = 0, nb = 0;
+    int off[kMaxSymBlocks + 1] = {};
+};
+struct SymJobs {
+    int count = 0;
+    SymJob job[3];
+};
+hipError_t sym_blocks(const SymJobs& jobs, hipStream_t s);
 // nonfinite check: flag[0] = 1 if any of n values is NaN/Inf
 hipError_t check_finite(long n, const double* x, int* flag, hipStream_t s);
 

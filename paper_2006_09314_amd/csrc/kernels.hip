@@ -1050,35 +1050,47 @@ hipError_t axpby(long n, double a, const double* x, double b, double* y, hipStre
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void dot_partial_kernel(long n, const double* __restrict__ x,
-                                                          const double* __restrict__ y,
-                                                          double* part) {
+// x . y in one launch: each block writes its partial sum, and the block that
+// counts in last (device-scope fences around the counter) adds the partial
+// sums in block order, so the result does not depend on which block that is;
+// it then resets the counter for the next call.
+__global__ __launch_bounds__(256) void dot_kernel(long n, const double* __restrict__ x,
+                                                  const double* __restrict__ y, double* part,
+                                                  unsigned* count, double* out) {
     __shared__ double red[4];
+    __shared__ int last;
     double acc = 0.0;
     for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
         acc += x[i] * y[i];
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-__global__ __launch_bounds__(256) void dot_final_kernel(int parts, const double* part,
-                                                        double* out) {
-    __shared__ double red[4];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < parts; i += 256) acc += part[i];
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&part[blockIdx.x], red[0] + red[1] + red[2] + red[3], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        last = atomicAdd(count, 1u) == gridDim.x - 1;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
+    if (!last) return;
+    __threadfence();
+    double s = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += 256)   // gridDim.x <= 256: one each
+        s += __hip_atomic_load(&part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s = wave_sum(s);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = red[0] + red[1] + red[2] + red[3];
+        atomicExch(count, 0u);
+    }
 }
 
-hipError_t dot_long(long n, const double* x, const double* y, double* part, double* out,
-                    hipStream_t s) {
+hipError_t dot_long(long n, const double* x, const double* y, double* part, unsigned* count,
+                    double* out, hipStream_t s) {
     const int parts = (int)std::min<long>(256, std::max<long>(1, (n + 4095) / 4096));
-    hipLaunchKernelGGL(dot_partial_kernel, dim3(parts), dim3(256), 0, s, n, x, y, part);
-    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(256), 0, s, parts, part, out);
+    hipLaunchKernelGGL(dot_kernel, dim3(parts), dim3(256), 0, s, n, x, y, part, count, out);
     return hipGetLastError();
 }
 
@@ -1259,6 +1271,54 @@ hipError_t copy2d(int rows, int cols, const double* src, long lds, double* dst, 
     const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(copy2d_kernel, dim3(blocks), dim3(256), 0, s, rows, cols, src, lds, dst,
                        ldd);
+    return hipGetLastError();
+}
+
+__global__ void copy_multi_kernel(CopyJobs jobs) {
+    const CopyJob& J = jobs.job[blockIdx.y];
+    const long total = (long)J.rows * J.cols;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % J.rows), j = int(e / J.rows);
+        J.dst[i + J.ldd * j] = J.src[i + J.lds * j];
+    }
+}
+
+hipError_t copy_multi(const CopyJobs& jobs, hipStream_t s) {
+    long most = 0;
+    for (int t = 0; t < jobs.count; ++t)
+        most = std::max(most, (long)jobs.job[t].rows * jobs.job[t].cols);
+    if (jobs.count <= 0 || most <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((most + 255) / 256, 1024);
+    hipLaunchKernelGGL(copy_multi_kernel, dim3(blocks, jobs.count), dim3(256), 0, s, jobs);
+    return hipGetLastError();
+}
+
+__global__ void sym_blocks_kernel(SymJobs jobs) {
+    const SymJob& J = jobs.job[blockIdx.y];
+    const long total = (long)J.k * J.k;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % J.k), j = int(e / J.k);
+        int bi = 0, bj = 0;
+        for (int t = 1; t < J.nb; ++t) {
+            bi += i >= J.off[t];
+            bj += j >= J.off[t];
+        }
+        // element (j, i) lies in a block above the diagonal: never written here
+        if (bi > bj) J.M[i + (long)j * J.k] = J.M[j + (long)i * J.k];
+    }
+}
+
+hipError_t sym_blocks(const SymJobs& jobs, hipStream_t s) {
+    long most = 0;
+    for (int t = 0; t < jobs.count; ++t) {
+        if (jobs.job[t].nb < 1 || jobs.job[t].nb > kMaxSymBlocks) return hipErrorInvalidValue;
+        most = std::max(most, (long)jobs.job[t].k * jobs.job[t].k);
+    }
+    if (jobs.count <= 0 || most <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((most + 255) / 256, 1024);
+    hipLaunchKernelGGL(sym_blocks_kernel, dim3(blocks, jobs.count), dim3(256), 0, s, jobs);
     return hipGetLastError();
 }
 

@@ -157,6 +157,7 @@ struct fc_plan_s {
     long qchunk = 1;
     long cap_canon = 0;
     int* dflag = nullptr;
+    unsigned* dotcnt = nullptr;   // zero between calls of the device dot
     hipStream_t stream = nullptr;
     // statistics of the last solve
     int max_seen_rank = 0;
@@ -460,7 +461,7 @@ void perm_dims(const int r[3], int mode, int out[3]) {
 
 double host_dot(const Ctx& c, long n, const double* x, const double* y) {
     fc_plan_s* p = c.p;
-    HIPCHK(fc::dot_long(n, x, y, p->scal + 256, p->scal, c.s));
+    HIPCHK(fc::dot_long(n, x, y, p->scal + 256, p->dotcnt, p->scal, c.s));
     double v = 0;
     d2h(c, &v, p->scal, 1);
     return v;
@@ -868,9 +869,18 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
         for (int t = 0; t < m; ++t) { off[t][l] = tot; tot += terms[t].second->r[l]; }
         k[l] = tot;
         if (tot > 256) throw FcError(FC_ERR_INTERNAL, std::string(what) + ": too many columns");
-        for (int t = 0; t < m; ++t)
-            HIPCHK(fc::copy2d(n, terms[t].second->r[l], terms[t].second->Z[l], n,
-                              p->Phi[l] + (long)off[t][l] * n, n, c.s));
+    }
+    {
+        // concatenated bases, every mode and term in one launch
+        fc::CopyJobs cj;
+        for (int l = 0; l < 3; ++l)
+            for (int t = 0; t < m; ++t) {
+                fc::CopyJob& J = cj.job[cj.count++];
+                J.src = terms[t].second->Z[l]; J.lds = n;
+                J.dst = p->Phi[l] + (long)off[t][l] * n; J.ldd = n;
+                J.rows = n; J.cols = terms[t].second->r[l];
+            }
+        HIPCHK(fc::copy_multi(cj, c.s));
     }
     {
         // full Grams of the concatenated bases (k_l x k_l), the modes together
@@ -879,24 +889,38 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
             grams[l] = prod(k[l], k[l], n, p->Phi[l], n, p->Phi[l], n, p->SG[l], k[l]);
         gemm_group(c, true, false, grams, 3);
     }
-    // block unfolding Grams M_l (k_l x k_l)
+    // block unfolding Grams M_l (k_l x k_l), symmetric: the blocks M[t,u],
+    // u >= t, are computed and the ones below the diagonal are their
+    // transposes.  With two terms each term's core is permuted once per mode
+    // (into Cn2 and Cp); with more, per use.
+    const bool hoist = m <= 2;
     for (int l = 0; l < 3; ++l) {
         const int a = (l == 0) ? 1 : 0, b = (l == 2) ? 1 : 2;
+        const double* pcore[4] = {nullptr, nullptr, nullptr, nullptr};
+        for (int t = 0; t < m; ++t) {
+            const Tucker& Tt = *terms[t].second;
+            pcore[t] = Tt.core;
+            if (l != 0 && hoist) {
+                double* dst = (t == 0) ? p->Cn2 : p->Cp;
+                HIPCHK(fc::permute_core(Tt.r[0], Tt.r[1], Tt.r[2], l, 1, Tt.core, 0, dst, 0, c.s));
+                pcore[t] = dst;
+            }
+        }
         for (int t = 0; t < m; ++t) {
             const Tucker& Tt = *terms[t].second;
             int pt[3];
             perm_dims(Tt.r, l, pt);
-            const double* coret = Tt.core;
-            if (l != 0) {
+            const double* coret = pcore[t];
+            if (l != 0 && !hoist) {
                 HIPCHK(fc::permute_core(Tt.r[0], Tt.r[1], Tt.r[2], l, 1, Tt.core, 0, p->Cn2, 0, c.s));
                 coret = p->Cn2;
             }
-            for (int u = 0; u < m; ++u) {
+            for (int u = t; u < m; ++u) {
                 const Tucker& Tu = *terms[u].second;
                 int pu[3];
                 perm_dims(Tu.r, l, pu);
-                const double* coreu = Tu.core;
-                if (l != 0) {
+                const double* coreu = pcore[u];
+                if (l != 0 && !hoist) {
                     HIPCHK(fc::permute_core(Tu.r[0], Tu.r[1], Tu.r[2], l, 1, Tu.core, 0, p->Cp, 0, c.s));
                     coreu = p->Cp;
                 }
@@ -913,6 +937,18 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
                      k[l]);
             }
         }
+    }
+    if (m > 1) {
+        fc::SymJobs sj;
+        for (int l = 0; l < 3; ++l) {
+            fc::SymJob& J = sj.job[sj.count++];
+            J.M = p->SM[l];
+            J.k = k[l];
+            J.nb = m;
+            for (int t = 0; t < m; ++t) J.off[t] = off[t][l];
+            J.off[m] = k[l];
+        }
+        HIPCHK(fc::sym_blocks(sj, c.s));
     }
     const double n2 = host_dot(c, (long)k[0] * k[0], p->SM[0], p->SG[0]);
     if (!std::isfinite(n2)) throw FcError(FC_ERR_NUMERIC, std::string(what) + ": non-finite");
@@ -1351,6 +1387,10 @@ void alloc_workspace(fc_plan_s* p) {
     p->splitws_cap = 8L << 20;
     p->splitws = A.alloc((size_t)p->splitws_cap);
     p->dflag = A.alloc_int(4);
+    p->dotcnt = (unsigned*)A.alloc_int(1);
+    const unsigned zero = 0;
+    if (hipMemcpy(p->dotcnt, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+        throw FcError(FC_ERR_HIP, "hipMemcpy failed");
 }
 
 // Build the separable factors on the host and upload them.
