@@ -40,6 +40,10 @@ struct GramJobs {
     GemmArgs g[kMaxGramJobs];
 };
 hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s);
+// Up to three independent plain FP64 products C = alpha op(A) op(B) + beta C
+// (batch 1, no scaling vector, whole K per block) in one launch on the
+// matrix cores: 32 x 32 tiles, one wavefront each.
+hipError_t gemm_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s);
 
 // Symmetric eigen-decomposition of a batch of k x k matrices (k <= 128),
 // cyclic Jacobi with the matrix in LDS.  A (column-major, leading dimension

@@ -44,13 +44,13 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register v of
 // lane l holds C[l / 16 + 4 v][l % 16] (checked by the layout self-test).
 template <bool TA, bool TB, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g, int kchunk) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tile, int b, int kz, int kchunk,
+                                          bool split) {
     constexpr int BM = 32 * WM, BN = 32 * WN, BK = 16, NT = 64 * WM * WN;
     __shared__ double As[BK][BM + 1];
     __shared__ double Bs[BK][BN + 1];
     const int tilesM = (g.M + BM - 1) / BM;
-    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
-    const int b = blockIdx.y;
+    const int tm = tile % tilesM, tn = tile / tilesM;
     const long bo = b / g.inner, bi = b % g.inner;
     const double* __restrict__ A = g.A + bo * g.strideA + bi * g.strideAin;
     const double* __restrict__ B = g.B + bo * g.strideB + bi * g.strideBin;
@@ -58,9 +58,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g, int kchu
     double* __restrict__ C = g.C + bo * g.strideC + bi * g.strideCin;
     long ldc = g.ldc;
     double alpha = g.alpha, beta = g.beta;
-    const int kz = blockIdx.z;
     const int kbeg = kz * kchunk, kend = min(g.K, kbeg + kchunk);
-    if (gridDim.z > 1) {
+    if (split) {
         // partial product of this K slice -> part[kz][b] (M x N, ld M)
         C = g.part + ((long)kz * g.batch + b) * (long)g.M * g.N;
         ldc = g.M;
@@ -120,6 +119,43 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g, int kchu
                     C[i + (long)j * ldc] = r;
                 }
             }
+}
+
+template <bool TA, bool TB, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g, int kchunk) {
+    gemm_tile<TA, TB, WM, WN>(g, blockIdx.x, blockIdx.y, blockIdx.z, kchunk, gridDim.z > 1);
+}
+
+// Up to three independent plain products in one launch: grid.y picks the
+// product, grid.x runs over the largest product's tiles (blocks beyond a
+// product's own tiles return at once).  Whole K per block, no batching.
+template <bool TA, bool TB, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_multi_kernel(GramJobs jobs) {
+    const GemmArgs& g = jobs.g[blockIdx.y];
+    const int tiles = ((g.M + 32 * WM - 1) / (32 * WM)) * ((g.N + 32 * WN - 1) / (32 * WN));
+    if ((int)blockIdx.x >= tiles) return;
+    gemm_tile<TA, TB, WM, WN>(g, blockIdx.x, 0, 0, g.K, false);
+}
+
+hipError_t gemm_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s) {
+    int most = 0;
+    for (int t = 0; t < jobs.count; ++t) {
+        const GemmArgs& g = jobs.g[t];
+        if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch != 1 || g.inner != 1 || g.d || g.lowp)
+            return hipErrorInvalidValue;
+        most = std::max(most, ((g.M + 31) / 32) * ((g.N + 31) / 32));
+    }
+    if (jobs.count <= 0) return hipSuccess;
+    const dim3 grid(most, jobs.count), block(64);
+    if (!transA && !transB)
+        hipLaunchKernelGGL((gemm_multi_kernel<false, false, 1, 1>), grid, block, 0, s, jobs);
+    else if (!transA && transB)
+        hipLaunchKernelGGL((gemm_multi_kernel<false, true, 1, 1>), grid, block, 0, s, jobs);
+    else if (transA && !transB)
+        hipLaunchKernelGGL((gemm_multi_kernel<true, false, 1, 1>), grid, block, 0, s, jobs);
+    else
+        hipLaunchKernelGGL((gemm_multi_kernel<true, true, 1, 1>), grid, block, 0, s, jobs);
+    return hipGetLastError();
 }
 
 template <bool TA, bool TB, int WM, int WN>

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <exception>
 #include <string>
+#include <type_traits>
 #include <atomic>
 #include <cstdlib>
 #include <mutex>
@@ -158,6 +159,7 @@ struct fc_plan_s {
     long cap_canon = 0;
     int* dflag = nullptr;
     unsigned* dotcnt = nullptr;   // zero between calls of the device dot
+    long ys_cap = 0;              // doubles in Ys and in Ts
     hipStream_t stream = nullptr;
     // statistics of the last solve
     int max_seen_rank = 0;
@@ -339,22 +341,15 @@ void gemmb(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, co
 // Up to three independent FP64 products of the same form (op(A) op(B) with
 // the given transposes) issued together: those that are Gram-type (the same
 // rule as run_gemm: M, N <= 128 and A^T B, or a reduction of at least 256)
-// share one launch of the Gram kernel, the others go through gemm.  Timed
+// share one launch of the Gram kernel, two or more others with a short
+// reduction (K <= 256) share one launch of the grouped matrix-core GEMM, the
+// rest go through gemm one by one.  Timed
 // like gemm when the GEMM profile is on.
-void gemm_group(const Ctx& c, bool ta, bool tb, const fc::GemmArgs* prods, int count) {
-    fc::GramJobs jobs;
-    for (int t = 0; t < count; ++t) {
-        const fc::GemmArgs& g = prods[t];
-        if (g.M <= 0 || g.N <= 0) continue;
-        const bool gram_type = g.M <= 128 && g.N <= 128 && !(ta && tb) && (ta || g.K >= 256) &&
-                               g.K > 0;
-        if (gram_type) {
-            jobs.g[jobs.count++] = g;
-        } else {
-            gemm(c, ta, tb, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc);
-        }
-    }
+void launch_group(const Ctx& c, bool ta, bool tb, const fc::GramJobs& jobs, bool gram) {
     if (jobs.count == 0) return;
+    auto run = [&] {
+        return gram ? fc::gram_multi(ta, tb, jobs, c.s) : fc::gemm_multi(ta, tb, jobs, c.s);
+    };
     if (g_prof.on && !t_no_profile) {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         if (g_prof.used + 2 > g_prof.ev.size()) {
@@ -365,7 +360,7 @@ void gemm_group(const Ctx& c, bool ta, bool tb, const fc::GemmArgs* prods, int c
             }
         }
         HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], c.s));
-        HIPCHK(fc::gram_multi(ta, tb, jobs, c.s));
+        HIPCHK(run());
         HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], c.s));
         g_prof.used += 2;
         // one shape entry per launch (the log pairs them with the events): the
@@ -380,7 +375,30 @@ void gemm_group(const Ctx& c, bool ta, bool tb, const fc::GemmArgs* prods, int c
         g_prof.launches += 1;
         return;
     }
-    HIPCHK(fc::gram_multi(ta, tb, jobs, c.s));
+    HIPCHK(run());
+}
+
+void gemm_group(const Ctx& c, bool ta, bool tb, const fc::GemmArgs* prods, int count) {
+    fc::GramJobs grams, others;
+    for (int t = 0; t < count; ++t) {
+        const fc::GemmArgs& g = prods[t];
+        if (g.M <= 0 || g.N <= 0) continue;
+        const bool gram_type = g.M <= 128 && g.N <= 128 && !(ta && tb) && (ta || g.K >= 256) &&
+                               g.K > 0;
+        if (gram_type)
+            grams.g[grams.count++] = g;
+        else if (g.K > 0 && g.K <= 256)
+            others.g[others.count++] = g;
+        else
+            gemm(c, ta, tb, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc);
+    }
+    launch_group(c, ta, tb, grams, true);
+    if (others.count == 1) {
+        const fc::GemmArgs& g = others.g[0];
+        gemm(c, ta, tb, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc);
+    } else {
+        launch_group(c, ta, tb, others, false);
+    }
 }
 
 fc::GemmArgs prod(int M, int N, int K, const double* A, long lda, const double* B, long ldb,
@@ -692,13 +710,32 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
         cur[l] = r[l];
         src = dst;
     }
-    // bases: Z_l = B_l U_l[:, :r_l]
+    // bases: Z_l = B_l U_l[:, :r_l], the modes together
+    fc::GemmArgs bases[3];
     for (int l = 0; l < 3; ++l) {
-        gemm(c, false, false, n, r[l], k[l], 1.0, B[l], n, p->Cvec + (long)l * KM * KM, k[l], 0.0,
-             out.Z[l], n);
+        bases[l] = prod(n, r[l], k[l], B[l], n, p->Cvec + (long)l * KM * KM, k[l], out.Z[l], n);
         out.r[l] = r[l];
     }
+    gemm_group(c, false, false, bases, 3);
     p->max_seen_rank = std::max({p->max_seen_rank, r[0], r[1], r[2]});
+}
+
+// H_l X_l for the selected modes: through `apply.all` when the operator
+// offers it (its products then go out grouped over the modes), else mode by
+// mode.
+template <class A, class = void>
+struct has_all : std::false_type {};
+template <class A>
+struct has_all<A, std::void_t<decltype(&A::all)>> : std::true_type {};
+template <class Apply>
+void apply_modes(Apply& apply, const bool sel[3], double* const* X, const int q[3],
+                 double* const* HX) {
+    if constexpr (has_all<Apply>::value) {
+        apply.all(sel, X, q, HX);
+    } else {
+        for (int l = 0; l < 3; ++l)
+            if (sel[l]) apply(l, X[l], q[l], HX[l]);
+    }
 }
 
 // Dominant subspaces of the three mode Grams H_l (given by `apply`, which
@@ -726,24 +763,31 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
     WarmBasis& wb = p->warm[site];
     int kk[3], have[3], first_cols[3] = {0, 0, 0};
     bool exact[3], active[3], dropped[3] = {false, false, false};
+    fc::CopyJobs starts;   // the start bases of the three modes, copied in one launch
     for (int l = 0; l < 3; ++l) {
         exact[l] = span && span[l];
         active[l] = true;
+        const double* from = nullptr;
         if (exact[l]) {
             kk[l] = have[l] = kcap[l];
             first_cols[l] = span_ortho ? span_ortho[l] : 0;
-            HIPCHK(fc::copy2d(n, kk[l], span[l], n, p->Xs3[l], n, c.s));
+            from = span[l];
         } else if (wb.valid) {
             have[l] = std::min(wb.pk[l], kcap[l]);
             // the earlier basis plus padding, and at least the cold-start size
             // (the input's rank may have grown since)
             kk[l] = std::min(kcap[l], std::max(have[l] + 2 * margin, cold ? cold[l] : 0));
-            HIPCHK(fc::copy2d(n, have[l], wb.W[l], n, p->Xs3[l], n, c.s));
+            from = wb.W[l];
         } else {
             have[l] = 0;
             kk[l] = cold ? std::max(1, std::min(kcap[l], cold[l])) : kcap[l];
         }
+        if (from && have[l] > 0) {
+            fc::CopyJob& J = starts.job[starts.count++];
+            J.src = from; J.lds = n; J.dst = p->Xs3[l]; J.ldd = n; J.rows = n; J.cols = have[l];
+        }
     }
+    HIPCHK(fc::copy_multi(starts, c.s));
     std::vector<double> th(3 * KM);
     for (int round = 0;; ++round) {
         // start bases of the active modes, orthonormalised together
@@ -767,8 +811,8 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
             // one power step moves the start into the range of H_l
             power[l] = true;
             before[l] = kk[l];
-            apply(l, p->Xs3[l], kk[l], p->HX3[l]);
         }
+        apply_modes(apply, power, p->Xs3, kk, p->HX3);
         const int none[3] = {0, 0, 0};
         orthonormalize3(c, kk, p->HX3, 1e-13, none, power);
         for (int l = 0; l < 3; ++l) {
@@ -782,9 +826,9 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
         jobs.count = 0;
         fc::GemmArgs rr_mats[3];
         int nrr = 0;
+        apply_modes(apply, active, p->Xs3, kk, p->HX3);
         for (int l = 0; l < 3; ++l) {
             if (!active[l]) continue;
-            apply(l, p->Xs3[l], kk[l], p->HX3[l]);
             rr_mats[nrr++] = prod(kk[l], kk[l], n, p->Xs3[l], n, p->HX3[l], n,
                                   p->Bp3 + (long)l * KM * KM, kk[l]);
         }
@@ -803,6 +847,9 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
                             [&] { return fc::sym_eig_multi(jobs, c.s); }));
         d2h(c, th.data(), p->Ev3, 3 * KM);
         bool again = false;
+        fc::CopyJobs keep;   // the modes finished this round, saved for a warm start
+        fc::GemmArgs fin[3];   // their subspaces W_l = X_l V_l, formed together
+        int nfin = 0;
         for (int l = 0; l < 3; ++l) {
             if (!active[l]) continue;
             double tail = 0;
@@ -831,18 +878,65 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
             }
             const int use = std::min(std::max(numrank, 1), std::max(rr + margin, 1));
             check_cols(c, Vl, kk[l], kk[l], use, "Ritz vectors", l);
-            gemm(c, false, false, n, use, kk[l], 1.0, p->Xs3[l], n, Vl, kk[l], 0.0, p->W[l], n);
-            check_cols(c, p->W[l], n, n, use, "subspace W", l);
+            fin[nfin++] = prod(n, use, kk[l], p->Xs3[l], n, Vl, kk[l], p->W[l], n);
             pk[l] = use;
-            HIPCHK(fc::copy2d(n, use, p->W[l], n, wb.W[l], n, c.s));
+            fc::CopyJob& J = keep.job[keep.count++];
+            J.src = p->W[l]; J.lds = n; J.dst = wb.W[l]; J.ldd = n; J.rows = n; J.cols = use;
             wb.pk[l] = use;
             active[l] = false;
         }
+        gemm_group(c, false, false, fin, nfin);
+        for (int t = 0; t < nfin; ++t)
+            check_cols(c, fin[t].C, n, n, fin[t].N, "subspace W", t);
+        HIPCHK(fc::copy_multi(keep, c.s));
         if (!again) break;
     }
     wb.valid = true;
     return true;
 }
+
+// H_l X = B_l (M_l (B_l^T X)) for the sum truncation (B_l in Phi[l], M_l in
+// SM[l]); all() runs the three stages for the selected modes with one
+// grouped launch per stage (per-mode slices of Ys and Ts).
+struct SumGramApply {
+    const Ctx& c;
+    const int* k;
+    void operator()(int l, const double* X, int q, double* HXo) const {
+        fc_plan_s* p = c.p;
+        const int n = c.n;
+        gemm(c, true, false, k[l], q, n, 1.0, p->Phi[l], n, X, n, 0.0, p->Ys, k[l]);
+        gemm(c, false, false, k[l], q, k[l], 1.0, p->SM[l], k[l], p->Ys, k[l], 0.0, p->Ts, k[l]);
+        gemm(c, false, false, n, q, k[l], 1.0, p->Phi[l], n, p->Ts, k[l], 0.0, HXo, n);
+    }
+    void all(const bool sel[3], double* const* X, const int q[3], double* const* HX) const {
+        fc_plan_s* p = c.p;
+        const int n = c.n;
+        long need = 0;
+        for (int l = 0; l < 3; ++l)
+            if (sel[l]) need += (long)k[l] * q[l];
+        if (need > p->ys_cap) {
+            for (int l = 0; l < 3; ++l)
+                if (sel[l]) (*this)(l, X[l], q[l], HX[l]);
+            return;
+        }
+        fc::GemmArgs s1[3], s2[3], s3[3];
+        int cnt = 0;
+        long off = 0;
+        for (int l = 0; l < 3; ++l) {
+            if (!sel[l]) continue;
+            double* Ysl = p->Ys + off;
+            double* Tsl = p->Ts + off;
+            off += (long)k[l] * q[l];
+            s1[cnt] = prod(k[l], q[l], n, p->Phi[l], n, X[l], n, Ysl, k[l]);
+            s2[cnt] = prod(k[l], q[l], k[l], p->SM[l], k[l], Ysl, k[l], Tsl, k[l]);
+            s3[cnt] = prod(n, q[l], k[l], p->Phi[l], n, Tsl, k[l], HX[l], n);
+            ++cnt;
+        }
+        gemm_group(c, true, false, s1, cnt);
+        gemm_group(c, false, false, s2, cnt);
+        gemm_group(c, false, false, s3, cnt);
+    }
+};
 
 // ---- exact truncation of a short sum of Tucker tensors ---------------------
 // T = sum_t c_t T_t (t < 4).  With the concatenated bases B_l = [Z_l^0 ...]
@@ -956,11 +1050,7 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
     if (n2 <= thr2) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
     // dominant subspaces of H_l = B M B^T
     int pk[3], kcap[3];
-    auto apply = [&](int l, const double* X, int q, double* HXo) {
-        gemm(c, true, false, k[l], q, n, 1.0, p->Phi[l], n, X, n, 0.0, p->Ys, k[l]);
-        gemm(c, false, false, k[l], q, k[l], 1.0, p->SM[l], k[l], p->Ys, k[l], 0.0, p->Ts, k[l]);
-        gemm(c, false, false, n, q, k[l], 1.0, p->Phi[l], n, p->Ts, k[l], 0.0, HXo, n);
-    };
+    SumGramApply apply{c, k};
     const double* span[3] = {nullptr, nullptr, nullptr};
     for (int l = 0; l < 3; ++l) {
         kcap[l] = std::min({p->pcap, n, k[l]});
@@ -1341,8 +1431,9 @@ void alloc_workspace(fc_plan_s* p) {
     p->T2 = p->c2;
     p->Xs = A.alloc((size_t)n * pc);
     p->HX = A.alloc((size_t)n * pc);
-    p->Ys = A.alloc((size_t)std::max<long>(rc * pc * Q, 256L * KM));
-    p->Ts = A.alloc((size_t)std::max<long>(rc * pc * Q, 256L * KM));
+    p->ys_cap = std::max<long>(rc * pc * Q, 256L * KM);
+    p->Ys = A.alloc((size_t)p->ys_cap);
+    p->Ts = A.alloc((size_t)p->ys_cap);
     p->F = A.alloc((size_t)n * rc * pc);
     p->Bp = A.alloc((size_t)std::max<long>(pc * pc, rc * rc * rc));
     p->Ev = A.alloc((size_t)std::max<long>(pc, rc * rc));
