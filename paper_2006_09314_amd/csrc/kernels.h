@@ -41,8 +41,8 @@ struct GramJobs {
 };
 hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s);
 // Up to three independent plain FP64 products C = alpha op(A) op(B) + beta C
-// (batch 1, no scaling vector, whole K per block) in one launch on the
-// matrix cores: 32 x 32 tiles, one wavefront each.
+// (strided batches with inner = 1, no scaling vector, whole K per block) in
+// one launch on the matrix cores: 32 x 32 tiles, one wavefront each.
 hipError_t gemm_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s);
 
 // Symmetric eigen-decomposition of a batch of k x k matrices (k <= 128),
@@ -80,6 +80,22 @@ hipError_t rowkron(int n, int r, int p, const double* Z, long ldz, const double*
 // out[i + ldo*c] = sum_j Z[i + ldz*j] * F[i + n*(j + r*c)]   (row-wise contraction)
 hipError_t rowcontract(int n, int r, int p, const double* Z, long ldz, const double* F,
                        double* out, long ldo, hipStream_t s);
+
+// Up to three row-wise Kronecker products (out = E of rowkron, X the right
+// factor) or row-wise contractions (X = F, out the n x p result, ld ldo) in
+// one launch.
+struct RowJob {
+    int r = 0, p = 0;
+    const double* Z = nullptr; long ldz = 0;
+    const double* X = nullptr; long ldx = 0;
+    double* out = nullptr; long ldo = 0;
+};
+struct RowJobs {
+    int count = 0;
+    RowJob job[3];
+};
+hipError_t rowkron_multi(int n, const RowJobs& jobs, hipStream_t s);
+hipError_t rowcontract_multi(int n, const RowJobs& jobs, hipStream_t s);
 
 // dst = permutation of a dense r0 x r1 x r2 column-major core that brings
 // mode `mode` first: mode 0 -> identity copy, mode 1 -> (r1, r0, r2),

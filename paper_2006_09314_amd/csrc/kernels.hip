@@ -127,25 +127,27 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g, int kchu
 }
 
 // Up to three independent plain products in one launch: grid.y picks the
-// product, grid.x runs over the largest product's tiles (blocks beyond a
-// product's own tiles return at once).  Whole K per block, no batching.
+// product, grid.x runs over the largest product's tiles times its batch
+// (blocks beyond a product's own return at once).  Whole K per block; a
+// product may be a strided batch (inner = 1).
 template <bool TA, bool TB, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_multi_kernel(GramJobs jobs) {
     const GemmArgs& g = jobs.g[blockIdx.y];
     const int tiles = ((g.M + 32 * WM - 1) / (32 * WM)) * ((g.N + 32 * WN - 1) / (32 * WN));
-    if ((int)blockIdx.x >= tiles) return;
-    gemm_tile<TA, TB, WM, WN>(g, blockIdx.x, 0, 0, g.K, false);
+    if ((long)blockIdx.x >= (long)tiles * g.batch) return;
+    gemm_tile<TA, TB, WM, WN>(g, blockIdx.x % tiles, blockIdx.x / tiles, 0, g.K, false);
 }
 
 hipError_t gemm_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s) {
-    int most = 0;
+    long most = 0;
     for (int t = 0; t < jobs.count; ++t) {
         const GemmArgs& g = jobs.g[t];
-        if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch != 1 || g.inner != 1 || g.d || g.lowp)
+        if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch < 1 || g.inner != 1 || g.d || g.lowp)
             return hipErrorInvalidValue;
-        most = std::max(most, ((g.M + 31) / 32) * ((g.N + 31) / 32));
+        most = std::max(most, (long)((g.M + 31) / 32) * ((g.N + 31) / 32) * g.batch);
     }
     if (jobs.count <= 0) return hipSuccess;
+    if (most > 0x7fffffffL) return hipErrorInvalidValue;
     const dim3 grid(most, jobs.count), block(64);
     if (!transA && !transB)
         hipLaunchKernelGGL((gemm_multi_kernel<false, false, 1, 1>), grid, block, 0, s, jobs);
@@ -1041,6 +1043,50 @@ hipError_t rowcontract(int n, int r, int p, const double* Z, long ldz, const dou
     const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(rowcontract_kernel, dim3(blocks), dim3(256), 0, s, n, r, p, Z, ldz, F, out,
                        ldo);
+    return hipGetLastError();
+}
+
+__global__ void rowkron_multi_kernel(int n, RowJobs jobs) {
+    const RowJob& J = jobs.job[blockIdx.y];
+    const long total = (long)n * J.r * J.p;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % n);
+        const long jc = e / n;
+        const int j = int(jc % J.r), c = int(jc / J.r);
+        J.out[e] = J.Z[i + J.ldz * j] * J.X[i + J.ldx * c];
+    }
+}
+
+hipError_t rowkron_multi(int n, const RowJobs& jobs, hipStream_t s) {
+    long most = 0;
+    for (int t = 0; t < jobs.count; ++t) most = std::max(most, (long)n * jobs.job[t].r * jobs.job[t].p);
+    if (jobs.count <= 0 || most <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((most + 255) / 256, 8192);
+    hipLaunchKernelGGL(rowkron_multi_kernel, dim3(blocks, jobs.count), dim3(256), 0, s, n, jobs);
+    return hipGetLastError();
+}
+
+__global__ void rowcontract_multi_kernel(int n, RowJobs jobs) {
+    const RowJob& J = jobs.job[blockIdx.y];
+    const long total = (long)n * J.p;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % n), c = int(e / n);
+        double acc = 0.0;
+        for (int j = 0; j < J.r; ++j)
+            acc += J.Z[i + J.ldz * j] * J.X[i + (long)n * (j + (long)J.r * c)];
+        J.out[i + J.ldo * c] = acc;
+    }
+}
+
+hipError_t rowcontract_multi(int n, const RowJobs& jobs, hipStream_t s) {
+    long most = 0;
+    for (int t = 0; t < jobs.count; ++t) most = std::max(most, (long)n * jobs.job[t].p);
+    if (jobs.count <= 0 || most <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((most + 255) / 256, 8192);
+    hipLaunchKernelGGL(rowcontract_multi_kernel, dim3(blocks, jobs.count), dim3(256), 0, s, n,
+                       jobs);
     return hipGetLastError();
 }
 

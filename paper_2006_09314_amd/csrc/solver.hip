@@ -160,6 +160,7 @@ struct fc_plan_s {
     int* dflag = nullptr;
     unsigned* dotcnt = nullptr;   // zero between calls of the device dot
     long ys_cap = 0;              // doubles in Ys and in Ts
+    long e_cap = 0, f_cap = 0;    // doubles in E and in F
     hipStream_t stream = nullptr;
     // statistics of the last solve
     int max_seen_rank = 0;
@@ -342,8 +343,9 @@ void gemmb(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, co
 // the given transposes) issued together: those that are Gram-type (the same
 // rule as run_gemm: M, N <= 128 and A^T B, or a reduction of at least 256)
 // share one launch of the Gram kernel, two or more others with a short
-// reduction (K <= 256) share one launch of the grouped matrix-core GEMM, the
-// rest go through gemm one by one.  Timed
+// reduction (K <= 256, or any with long_k) share one launch of the grouped
+// matrix-core GEMM, the rest go through gemm one by one.  Products may be
+// strided batches (inner = 1; a batch is never Gram-type here).  Timed
 // like gemm when the GEMM profile is on.
 void launch_group(const Ctx& c, bool ta, bool tb, const fc::GramJobs& jobs, bool gram) {
     if (jobs.count == 0) return;
@@ -378,27 +380,30 @@ void launch_group(const Ctx& c, bool ta, bool tb, const fc::GramJobs& jobs, bool
     HIPCHK(run());
 }
 
-void gemm_group(const Ctx& c, bool ta, bool tb, const fc::GemmArgs* prods, int count) {
+void gemm_group(const Ctx& c, bool ta, bool tb, const fc::GemmArgs* prods, int count,
+                bool long_k = false) {
     fc::GramJobs grams, others;
+    auto one = [&](const fc::GemmArgs& g) {
+        gemm(c, ta, tb, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc,
+             g.batch, g.strideA, g.strideB, g.strideC);
+    };
     for (int t = 0; t < count; ++t) {
         const fc::GemmArgs& g = prods[t];
         if (g.M <= 0 || g.N <= 0) continue;
-        const bool gram_type = g.M <= 128 && g.N <= 128 && !(ta && tb) && (ta || g.K >= 256) &&
-                               g.K > 0;
+        const bool gram_type = g.batch == 1 && g.M <= 128 && g.N <= 128 && !(ta && tb) &&
+                               (ta || g.K >= 256) && g.K > 0;
         if (gram_type)
             grams.g[grams.count++] = g;
-        else if (g.K > 0 && g.K <= 256)
+        else if (g.K > 0 && (g.K <= 256 || long_k))
             others.g[others.count++] = g;
         else
-            gemm(c, ta, tb, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc);
+            one(g);
     }
     launch_group(c, ta, tb, grams, true);
-    if (others.count == 1) {
-        const fc::GemmArgs& g = others.g[0];
-        gemm(c, ta, tb, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc);
-    } else {
+    if (others.count == 1)
+        one(others.g[0]);
+    else
         launch_group(c, ta, tb, others, false);
-    }
 }
 
 fc::GemmArgs prod(int M, int N, int K, const double* A, long lda, const double* B, long ldb,
@@ -1093,6 +1098,77 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
 // T = D~ (.) P = sum_q P x_l diag(D_l[:,q]).  Subspace per mode from the
 // block reduced HOSVD (sum over q of the unfolding Grams of the terms),
 // exact projection of T onto it, then HOSVD of the projected core.
+// Hh_l X = sum_q D^q Z M^q Z^T D^q X for the Hadamard truncation: row-wise
+// Kronecker product E = Z (.) X, Y^q = E^T D^q (stack r q x Q), T^q = M^q Y^q,
+// F = D T^T, row-wise contraction with Z.  all() runs each stage for the
+// selected modes in one launch, on per-mode slices of E, F, Ys and Ts when
+// they fit (else mode by mode).
+struct HadGramApply {
+    const Ctx& c;
+    const Separable& op;
+    const Tucker& P;
+    double* const* Mq;
+    void operator()(int l, const double* X, int q, double* HXo) const {
+        fc_plan_s* p = c.p;
+        const int n = c.n, Q = op.Q;
+        const int* r = P.r;
+        HIPCHK(fc::rowkron(n, r[l], q, P.Z[l], n, X, n, p->E, c.s));
+        gemm(c, true, false, r[l] * q, Q, n, 1.0, p->E, n, op.D[l], n, 0.0, p->Ys, (long)r[l] * q);
+        gemm(c, false, false, r[l], q, r[l], 1.0, Mq[l], r[l], p->Ys, r[l], 0.0, p->Ts, r[l], Q,
+             (long)r[l] * r[l], (long)r[l] * q, (long)r[l] * q);
+        gemm(c, false, true, n, r[l] * q, Q, 1.0, op.D[l], n, p->Ts, (long)r[l] * q, 0.0, p->F, n);
+        HIPCHK(fc::rowcontract(n, r[l], q, P.Z[l], n, p->F, HXo, n, c.s));
+    }
+    void all(const bool sel[3], double* const* X, const int q[3], double* const* HX) const {
+        fc_plan_s* p = c.p;
+        const int n = c.n, Q = op.Q;
+        const int* r = P.r;
+        long ne = 0, ny = 0;
+        for (int l = 0; l < 3; ++l)
+            if (sel[l]) {
+                ne += (long)n * r[l] * q[l];
+                ny += (long)r[l] * q[l] * Q;
+            }
+        if (ne > p->e_cap || ne > p->f_cap || ny > p->ys_cap) {
+            for (int l = 0; l < 3; ++l)
+                if (sel[l]) (*this)(l, X[l], q[l], HX[l]);
+            return;
+        }
+        fc::RowJobs kr, rc;
+        fc::GemmArgs s1[3], s2[3], s3[3];
+        int cnt = 0;
+        long oe = 0, oy = 0;
+        for (int l = 0; l < 3; ++l) {
+            if (!sel[l]) continue;
+            const long rq = (long)r[l] * q[l];
+            double* El = p->E + oe;
+            double* Fl = p->F + oe;
+            double* Ysl = p->Ys + oy;
+            double* Tsl = p->Ts + oy;
+            oe += (long)n * rq;
+            oy += rq * Q;
+            fc::RowJob& K = kr.job[kr.count++];
+            K.r = r[l]; K.p = q[l]; K.Z = P.Z[l]; K.ldz = n; K.X = X[l]; K.ldx = n; K.out = El;
+            s1[cnt] = prod((int)rq, Q, n, El, n, op.D[l], n, Ysl, rq);
+            fc::GemmArgs g2 = prod(r[l], q[l], r[l], Mq[l], r[l], Ysl, r[l], Tsl, r[l]);
+            g2.batch = Q;
+            g2.strideA = (long)r[l] * r[l];
+            g2.strideB = rq;
+            g2.strideC = rq;
+            s2[cnt] = g2;
+            s3[cnt] = prod(n, (int)rq, Q, op.D[l], n, Tsl, rq, Fl, n);
+            fc::RowJob& C = rc.job[rc.count++];
+            C.r = r[l]; C.p = q[l]; C.Z = P.Z[l]; C.ldz = n; C.X = Fl; C.out = HX[l]; C.ldo = n;
+            ++cnt;
+        }
+        HIPCHK(fc::rowkron_multi(n, kr, c.s));
+        gemm_group(c, true, false, s1, cnt);
+        gemm_group(c, false, false, s2, cnt);
+        gemm_group(c, false, true, s3, cnt);
+        HIPCHK(fc::rowcontract_multi(n, rc, c.s));
+    }
+};
+
 void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_rel,
                double floor_abs, Tucker& out, const char* what, int site) {
     SiteClock clock(c, site);
@@ -1102,10 +1178,26 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     if (P.empty()) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
     const int* r = P.r;
     // 1. diagonal Grams Gd_l^q = Z_l^T diag(D_l[:,q]^2) Z_l  -> stack r_l^2 x Q
-    for (int l = 0; l < 3; ++l) {
-        HIPCHK(fc::rowkron(n, r[l], r[l], P.Z[l], n, P.Z[l], n, p->E, c.s));
-        gemm(c, true, false, r[l] * r[l], Q, n, 1.0, p->E, n, op.D2[l], n, 0.0, p->Gd[l],
-             (long)r[l] * r[l]);
+    if ((long)n * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) <= p->e_cap) {
+        // the three modes together, each in its own slice of E
+        fc::RowJobs kr;
+        fc::GemmArgs gd[3];
+        long oe = 0;
+        for (int l = 0; l < 3; ++l) {
+            double* El = p->E + oe;
+            oe += (long)n * r[l] * r[l];
+            fc::RowJob& J = kr.job[kr.count++];
+            J.r = r[l]; J.p = r[l]; J.Z = P.Z[l]; J.ldz = n; J.X = P.Z[l]; J.ldx = n; J.out = El;
+            gd[l] = prod(r[l] * r[l], Q, n, El, n, op.D2[l], n, p->Gd[l], (long)r[l] * r[l]);
+        }
+        HIPCHK(fc::rowkron_multi(n, kr, c.s));
+        gemm_group(c, true, false, gd, 3);
+    } else {
+        for (int l = 0; l < 3; ++l) {
+            HIPCHK(fc::rowkron(n, r[l], r[l], P.Z[l], n, P.Z[l], n, p->E, c.s));
+            gemm(c, true, false, r[l] * r[l], Q, n, 1.0, p->E, n, op.D2[l], n, 0.0, p->Gd[l],
+                 (long)r[l] * r[l]);
+        }
     }
     // 2. per-term unfolding Grams M_l^q = core_(l) (G_b^q (x) G_a^q) core_(l)^T
     double* Mq[3];
@@ -1142,17 +1234,7 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     const double tau2_est = std::max(tol_rel * tol_rel * trH, floor_abs * floor_abs);
     // 3. dominant subspaces of Hh_l = sum_q D^q Z M^q Z^T D^q
     int pk[3], kcap[3];
-    auto apply = [&](int l, const double* X, int q, double* HXo) {
-        // Y^q = Z^T D^q X  (stack: r*q x Q)
-        HIPCHK(fc::rowkron(n, r[l], q, P.Z[l], n, X, n, p->E, c.s));
-        gemm(c, true, false, r[l] * q, Q, n, 1.0, p->E, n, op.D[l], n, 0.0, p->Ys, (long)r[l] * q);
-        // T^q = M^q Y^q
-        gemm(c, false, false, r[l], q, r[l], 1.0, Mq[l], r[l], p->Ys, r[l], 0.0, p->Ts, r[l], Q,
-             (long)r[l] * r[l], (long)r[l] * q, (long)r[l] * q);
-        // F = D T^T : n x (r*q)
-        gemm(c, false, true, n, r[l] * q, Q, 1.0, op.D[l], n, p->Ts, (long)r[l] * q, 0.0, p->F, n);
-        HIPCHK(fc::rowcontract(n, r[l], q, P.Z[l], n, p->F, HXo, n, c.s));
-    };
+    HadGramApply apply{c, op, P, Mq};
     // a cold start (no basis from an earlier call at this site) begins with
     // twice the input rank plus the margin; the search enlarges it when the
     // Ritz tail needs more
@@ -1419,7 +1501,8 @@ void alloc_workspace(fc_plan_s* p) {
         p->slot[s].core = A.alloc((size_t)rc * rc * rc);
     }
     const long ecols = std::max(rc * rc, pc * rc);
-    p->E = A.alloc((size_t)std::max<long>((long)n * ecols, 256L * KM * KM));
+    p->e_cap = std::max<long>((long)n * ecols, 256L * KM * KM);
+    p->E = A.alloc((size_t)p->e_cap);
     for (int l = 0; l < 3; ++l) p->Gd[l] = A.alloc((size_t)Q * rc * rc);
     p->Mq = A.alloc((size_t)3 * Q * rc * rc);
     p->qchunk = std::max<long>(1, std::min<long>(Q, (8L << 20) / std::max<long>(1, rc * rc * rc)));
@@ -1434,7 +1517,8 @@ void alloc_workspace(fc_plan_s* p) {
     p->ys_cap = std::max<long>(rc * pc * Q, 256L * KM);
     p->Ys = A.alloc((size_t)p->ys_cap);
     p->Ts = A.alloc((size_t)p->ys_cap);
-    p->F = A.alloc((size_t)n * rc * pc);
+    p->f_cap = (long)n * rc * pc;
+    p->F = A.alloc((size_t)p->f_cap);
     p->Bp = A.alloc((size_t)std::max<long>(pc * pc, rc * rc * rc));
     p->Ev = A.alloc((size_t)std::max<long>(pc, rc * rc));
     p->Evec = A.alloc((size_t)std::max<long>(pc * pc, rc * rc * rc));
