@@ -156,6 +156,7 @@ struct fc_plan_s {
     long splitws_cap = 0;
     double *SG[3] = {}, *SM[3] = {};
     long qchunk = 1;
+    long cbig = 0;     // doubles in c1 (= T1) and in c2 (= T2)
     long cap_canon = 0;
     int* dflag = nullptr;
     unsigned* dotcnt = nullptr;   // zero between calls of the device dot
@@ -1212,8 +1213,10 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
             core = p->Cp;
         }
         const long csz = (long)r[0] * r[1] * r[2];
-        for (long q0 = 0; q0 < Q; q0 += p->qchunk) {
-            const int qc = (int)std::min<long>(p->qchunk, Q - q0);
+        // as many terms per pass as c1 and c2 hold at the actual core size
+        const long qstep = std::max<long>(1, std::min<long>(Q, p->cbig / std::max<long>(1, csz)));
+        for (long q0 = 0; q0 < Q; q0 += qstep) {
+            const int qc = (int)std::min<long>(qstep, Q - q0);
             // c1^q = core x_3 G_b^q : (pd0 pd1 x pd2) * G^T
             gemm(c, false, true, pd[0] * pd[1], pd[2], pd[2], 1.0, core, (long)pd[0] * pd[1],
                  p->Gd[b] + q0 * (long)r[b] * r[b], pd[2], 0.0, p->c1, (long)pd[0] * pd[1], qc, 0,
@@ -1257,8 +1260,10 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     const long csz = (long)r[0] * r[1] * r[2];
     const long t1sz = (long)pk[0] * r[1] * r[2];
     const long t2sz = (long)pk[0] * pk[1] * r[2];
-    for (long q0 = 0; q0 < Q; q0 += p->qchunk) {
-        const int qc = (int)std::min<long>(p->qchunk, Q - q0);
+    const long qstep =
+        std::max<long>(1, std::min<long>(Q, p->cbig / std::max<long>(1, std::max(t1sz, t2sz))));
+    for (long q0 = 0; q0 < Q; q0 += qstep) {
+        const int qc = (int)std::min<long>(qstep, Q - q0);
         // T1^q = A_0^q core_(1): (pk0 x r0)(r0 x r1 r2)
         gemmb(c, false, false, pk[0], r[1] * r[2], r[0], 1.0, p->As[0] + q0 * pk[0] * (long)r[0],
               pk[0], P.core, r[0], 0.0, p->T1, pk[0], qc, (long)pk[0] * r[0], 0, t1sz);
@@ -1508,6 +1513,7 @@ void alloc_workspace(fc_plan_s* p) {
     p->qchunk = std::max<long>(1, std::min<long>(Q, (8L << 20) / std::max<long>(1, rc * rc * rc)));
     // c1/c2 and T1/T2 need qchunk cores of up to pc*pc*rc
     const long big = p->qchunk * std::max(rc * rc * rc, pc * pc * rc);
+    p->cbig = big;
     p->c1 = A.alloc(big);
     p->c2 = A.alloc(big);
     p->T1 = p->c1;
