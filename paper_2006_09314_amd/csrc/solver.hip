@@ -1006,6 +1006,58 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
                 pcore[t] = dst;
             }
         }
+        if (hoist) {
+            // the pairs t <= u of this mode in three grouped stages, on
+            // per-pair slices of c1 and c2 when they fit
+            long n1 = 0, n2c = 0;
+            for (int t = 0; t < m; ++t)
+                for (int u = t; u < m; ++u) {
+                    int pt[3], pu[3];
+                    perm_dims(terms[t].second->r, l, pt);
+                    perm_dims(terms[u].second->r, l, pu);
+                    n1 += (long)pu[0] * pu[1] * pt[2];
+                    n2c += (long)pu[0] * pt[1] * pt[2];
+                }
+            if (n1 <= p->cbig && n2c <= p->cbig) {
+                fc::GemmArgs s1[3], s2[3], s3[3];
+                int np = 0;
+                long o1 = 0, o2 = 0;
+                for (int t = 0; t < m; ++t)
+                    for (int u = t; u < m; ++u) {
+                        int pt[3], pu[3];
+                        perm_dims(terms[t].second->r, l, pt);
+                        perm_dims(terms[u].second->r, l, pu);
+                        double* c1 = p->c1 + o1;
+                        double* c2 = p->c2 + o2;
+                        o1 += (long)pu[0] * pu[1] * pt[2];
+                        o2 += (long)pu[0] * pt[1] * pt[2];
+                        // c1 = core_u x_3 G_b^{tu}
+                        s1[np] = prod(pu[0] * pu[1], pt[2], pu[2], pcore[u], (long)pu[0] * pu[1],
+                                      p->SG[b] + off[t][b] + (long)off[u][b] * k[b], k[b], c1,
+                                      (long)pu[0] * pu[1]);
+                        // c2 = c1 x_2 G_a^{tu}, a batch over the third index
+                        fc::GemmArgs g2 = prod(pu[0], pt[1], pu[1], c1, pu[0],
+                                               p->SG[a] + off[t][a] + (long)off[u][a] * k[a], k[a],
+                                               c2, pu[0]);
+                        g2.batch = pt[2];
+                        g2.strideA = (long)pu[0] * pu[1];
+                        g2.strideB = 0;
+                        g2.strideC = (long)pu[0] * pt[1];
+                        s2[np] = g2;
+                        // M[t,u] = c_t c_u core_t,(1) c2_(1)^T
+                        fc::GemmArgs g3 = prod(pt[0], pu[0], pt[1] * pt[2], pcore[t], pt[0], c2,
+                                               pu[0], p->SM[l] + off[t][l] + (long)off[u][l] * k[l],
+                                               k[l]);
+                        g3.alpha = terms[t].first * terms[u].first;
+                        s3[np] = g3;
+                        ++np;
+                    }
+                gemm_group(c, false, true, s1, np);
+                gemm_group(c, false, true, s2, np);
+                gemm_group(c, false, true, s3, np);
+                continue;
+            }
+        }
         for (int t = 0; t < m; ++t) {
             const Tucker& Tt = *terms[t].second;
             int pt[3];
