@@ -41,7 +41,7 @@ struct GramJobs {
 };
 hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s);
 // Up to three independent plain FP64 products C = alpha op(A) op(B) + beta C
-// (strided batches with inner = 1, no scaling vector, whole K per block) in
+// (strided or two-level batches, no scaling vector, whole K per block) in
 // one launch on the matrix cores: 32 x 32 tiles, one wavefront each.
 hipError_t gemm_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s);
 

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmArgs g, int kchu
 // Up to three independent plain products in one launch: grid.y picks the
 // product, grid.x runs over the largest product's tiles times its batch
 // (blocks beyond a product's own return at once).  Whole K per block; a
-// product may be a strided batch (inner = 1).
+// product may be a strided (two-level) batch.
 template <bool TA, bool TB, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_multi_kernel(GramJobs jobs) {
     const GemmArgs& g = jobs.g[blockIdx.y];
@@ -142,7 +142,7 @@ hipError_t gemm_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_
     long most = 0;
     for (int t = 0; t < jobs.count; ++t) {
         const GemmArgs& g = jobs.g[t];
-        if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch < 1 || g.inner != 1 || g.d || g.lowp)
+        if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch < 1 || g.inner < 1 || g.d || g.lowp)
             return hipErrorInvalidValue;
         most = std::max(most, (long)((g.M + 31) / 32) * ((g.N + 31) / 32) * g.batch);
     }

@@ -346,7 +346,7 @@ void gemmb(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, co
 // share one launch of the Gram kernel, two or more others with a short
 // reduction (K <= 256, or any with long_k) share one launch of the grouped
 // matrix-core GEMM, the rest go through gemm one by one.  Products may be
-// strided batches (inner = 1; a batch is never Gram-type here).  Timed
+// strided or two-level batches (a batch is never Gram-type here).  Timed
 // like gemm when the GEMM profile is on.
 void launch_group(const Ctx& c, bool ta, bool tb, const fc::GramJobs& jobs, bool gram) {
     if (jobs.count == 0) return;
@@ -386,7 +386,8 @@ void gemm_group(const Ctx& c, bool ta, bool tb, const fc::GemmArgs* prods, int c
     fc::GramJobs grams, others;
     auto one = [&](const fc::GemmArgs& g) {
         gemm(c, ta, tb, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc,
-             g.batch, g.strideA, g.strideB, g.strideC);
+             g.batch, g.strideA, g.strideB, g.strideC, g.inner, g.strideAin, g.strideBin,
+             g.strideCin);
     };
     for (int t = 0; t < count; ++t) {
         const fc::GemmArgs& g = prods[t];
@@ -1255,7 +1256,54 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     // 2. per-term unfolding Grams M_l^q = core_(l) (G_b^q (x) G_a^q) core_(l)^T
     double* Mq[3];
     for (int l = 0; l < 3; ++l) Mq[l] = p->Mq + (long)l * Q * p->rcap * p->rcap;
-    for (int l = 0; l < 3; ++l) {
+    const long csz3 = (long)r[0] * r[1] * r[2];
+    const bool grouped = 3L * Q * csz3 <= p->cbig;
+    if (grouped) {
+        // all terms of the three modes at once, each mode on its own slices
+        // of c1 and c2 (the permuted cores of modes 1 and 2 in Cp and Cn2)
+        HIPCHK(fc::permute_core(r[0], r[1], r[2], 1, 1, P.core, 0, p->Cp, 0, c.s));
+        HIPCHK(fc::permute_core(r[0], r[1], r[2], 2, 1, P.core, 0, p->Cn2, 0, c.s));
+        const double* cores[3] = {P.core, p->Cp, p->Cn2};
+        fc::GemmArgs s1[3], s2[3], s3[3];
+        for (int l = 0; l < 3; ++l) {
+            int pd[3];
+            perm_dims(r, l, pd);
+            const int a = (l == 0) ? 1 : 0, b = (l == 2) ? 1 : 2;
+            double* c1 = p->c1 + (long)l * Q * csz3;
+            double* c2 = p->c2 + (long)l * Q * csz3;
+            // c1^q = core x_3 G_b^q
+            fc::GemmArgs g1 = prod(pd[0] * pd[1], pd[2], pd[2], cores[l], (long)pd[0] * pd[1],
+                                   p->Gd[b], pd[2], c1, (long)pd[0] * pd[1]);
+            g1.batch = Q;
+            g1.strideA = 0;
+            g1.strideB = (long)r[b] * r[b];
+            g1.strideC = csz3;
+            s1[l] = g1;
+            // c2^q = c1^q x_2 G_a^q: batch over (q, k)
+            fc::GemmArgs g2 = prod(pd[0], pd[1], pd[1], c1, pd[0], p->Gd[a], pd[1], c2, pd[0]);
+            g2.batch = Q * pd[2];
+            g2.inner = pd[2];
+            g2.strideA = csz3;
+            g2.strideB = (long)r[a] * r[a];
+            g2.strideC = csz3;
+            g2.strideAin = (long)pd[0] * pd[1];
+            g2.strideBin = 0;
+            g2.strideCin = (long)pd[0] * pd[1];
+            s2[l] = g2;
+            // M^q = core_(1) c2^q_(1)^T
+            fc::GemmArgs g3 = prod(pd[0], pd[0], pd[1] * pd[2], cores[l], pd[0], c2, pd[0], Mq[l],
+                                   pd[0]);
+            g3.batch = Q;
+            g3.strideA = 0;
+            g3.strideB = csz3;
+            g3.strideC = (long)pd[0] * pd[0];
+            s3[l] = g3;
+        }
+        gemm_group(c, false, true, s1, 3);
+        gemm_group(c, false, true, s2, 3);
+        gemm_group(c, false, true, s3, 3);
+    }
+    for (int l = 0; l < 3 && !grouped; ++l) {
         int pd[3];
         perm_dims(r, l, pd);
         const int a = (l == 0) ? 1 : 0, b = (l == 2) ? 1 : 2;   // other modes in order
@@ -1303,10 +1351,27 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
         return;
     }
     // 4. projection A_l^q = W_l^T D^q Z_l -> stack (pk*r x Q)
-    for (int l = 0; l < 3; ++l) {
-        HIPCHK(fc::rowkron(n, pk[l], r[l], p->W[l], n, P.Z[l], n, p->E, c.s));
-        gemmb(c, true, false, pk[l] * r[l], Q, n, 1.0, p->E, n, op.D[l], n, 0.0, p->As[l],
-              (long)pk[l] * r[l]);
+    if ((long)n * (pk[0] * r[0] + pk[1] * r[1] + pk[2] * r[2]) <= p->e_cap) {
+        fc::RowJobs kr;
+        double* El[3];
+        long oe = 0;
+        for (int l = 0; l < 3; ++l) {
+            El[l] = p->E + oe;
+            oe += (long)n * pk[l] * r[l];
+            fc::RowJob& J = kr.job[kr.count++];
+            J.r = pk[l]; J.p = r[l]; J.Z = p->W[l]; J.ldz = n; J.X = P.Z[l]; J.ldx = n;
+            J.out = El[l];
+        }
+        HIPCHK(fc::rowkron_multi(n, kr, c.s));
+        for (int l = 0; l < 3; ++l)
+            gemmb(c, true, false, pk[l] * r[l], Q, n, 1.0, El[l], n, op.D[l], n, 0.0, p->As[l],
+                  (long)pk[l] * r[l]);
+    } else {
+        for (int l = 0; l < 3; ++l) {
+            HIPCHK(fc::rowkron(n, pk[l], r[l], p->W[l], n, P.Z[l], n, p->E, c.s));
+            gemmb(c, true, false, pk[l] * r[l], Q, n, 1.0, p->E, n, op.D[l], n, 0.0, p->As[l],
+                  (long)pk[l] * r[l]);
+        }
     }
     // 5. C = sum_q core x_1 A_0^q x_2 A_1^q x_3 A_2^q
     const long csz = (long)r[0] * r[1] * r[2];
