@@ -102,6 +102,9 @@ hipError_t rowcontract_multi(int n, const RowJobs& jobs, hipStream_t s);
 // mode 2 -> (r2, r0, r1).  Batched with strides.
 hipError_t permute_core(int r0, int r1, int r2, int mode, int batch, const double* src,
                         long sstride, double* dst, long dstride, hipStream_t s);
+// the mode-1 and mode-2 permutations of one core (into dst1, dst2) in one launch
+hipError_t permute_core12(int r0, int r1, int r2, const double* src, double* dst1, double* dst2,
+                          hipStream_t s);
 
 // y[i] = a * x[i] (+ y[i] if accumulate)
 hipError_t axpby(long n, double a, const double* x, double b, double* y, hipStream_t s);
@@ -118,6 +121,17 @@ hipError_t scale_cols(int n, int m, double* X, long ldx, const double* scale, in
 hipError_t col_norms(int n, int m, const double* X, long ldx, double* out, hipStream_t s);
 // fill with a deterministic pseudo-random normal-like sequence (counter hash)
 hipError_t fill_random(long n, unsigned seed, double* x, hipStream_t s);
+// the same for up to three independent vectors in one launch
+struct FillJob {
+    long n = 0;
+    unsigned seed = 0;
+    double* x = nullptr;
+};
+struct FillJobs {
+    int count = 0;
+    FillJob job[3];
+};
+hipError_t fill_random_multi(const FillJobs& jobs, hipStream_t s);
 // out[:, j] = v for j < m (out n x m, leading dimension ld).
 hipError_t fill_columns(int n, int m, const double* v, double* out, long ld, hipStream_t s);
 // w[k] *= <U[:, k], v> for k < K (U n x K, leading dimension ld).

@@ -1108,6 +1108,32 @@ __global__ void permute_kernel(int r0, int r1, int r2, int mode, const double* _
     }
 }
 
+// modes 1 and 2 of one core in one launch (grid.y picks the mode)
+__global__ void permute12_kernel(int r0, int r1, int r2, const double* __restrict__ src,
+                                 double* __restrict__ dst1, double* __restrict__ dst2) {
+    const long total = (long)r0 * r1 * r2;
+    const bool m1 = blockIdx.y == 0;
+    double* D = m1 ? dst1 : dst2;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = int(e % r0);
+        const long t = e / r0;
+        const int j = int(t % r1), kk = int(t / r1);
+        const long o = m1 ? j + (long)r1 * (i + (long)r0 * kk) : kk + (long)r2 * (i + (long)r0 * j);
+        D[o] = src[e];
+    }
+}
+
+hipError_t permute_core12(int r0, int r1, int r2, const double* src, double* dst1, double* dst2,
+                          hipStream_t s) {
+    const long total = (long)r0 * r1 * r2;
+    if (total <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(permute12_kernel, dim3(blocks, 2), dim3(256), 0, s, r0, r1, r2, src, dst1,
+                       dst2);
+    return hipGetLastError();
+}
+
 hipError_t permute_core(int r0, int r1, int r2, int mode, int batch, const double* src,
                         long sstride, double* dst, long dstride, hipStream_t s) {
     const long total = (long)r0 * r1 * r2;
@@ -1255,6 +1281,27 @@ __global__ void fill_random_kernel(long n, unsigned seed, double* x) {
         const double u2 = ((h2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
         x[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
     }
+}
+
+__global__ void fill_random_multi_kernel(FillJobs jobs) {
+    const FillJob& J = jobs.job[blockIdx.y];
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < J.n;
+         i += (long)gridDim.x * blockDim.x) {
+        const uint64_t h1 = splitmix64(((uint64_t)J.seed << 40) ^ (uint64_t)(2 * i));
+        const uint64_t h2 = splitmix64(((uint64_t)J.seed << 40) ^ (uint64_t)(2 * i + 1));
+        const double u1 = ((h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        const double u2 = ((h2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        J.x[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    }
+}
+
+hipError_t fill_random_multi(const FillJobs& jobs, hipStream_t s) {
+    long most = 0;
+    for (int t = 0; t < jobs.count; ++t) most = std::max(most, jobs.job[t].n);
+    if (jobs.count <= 0 || most <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((most + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_random_multi_kernel, dim3(blocks, jobs.count), dim3(256), 0, s, jobs);
+    return hipGetLastError();
 }
 
 hipError_t fill_random(long n, unsigned seed, double* x, hipStream_t s) {

@@ -640,14 +640,11 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
     {
         fc::GemmArgs grams[3];
         double* perm[3] = {nullptr, p->Cp, p->Cn1};
+        HIPCHK(fc::permute_core12(k[0], k[1], k[2], C, perm[1], perm[2], c.s));
         for (int l = 0; l < 3; ++l) {
             int pd[3];
             perm_dims(k, l, pd);
-            const double* src = C;
-            if (l != 0) {
-                HIPCHK(fc::permute_core(k[0], k[1], k[2], l, 1, C, 0, perm[l], 0, c.s));
-                src = perm[l];
-            }
+            const double* src = (l == 0) ? C : perm[l];
             grams[l] = prod(pd[0], pd[0], pd[1] * pd[2], src, pd[0], src, pd[0],
                             p->Cg + (long)l * KM * KM, pd[0]);
         }
@@ -799,14 +796,18 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
     for (int round = 0;; ++round) {
         // start bases of the active modes, orthonormalised together
         int start_done[3] = {0, 0, 0};
+        fc::FillJobs fills;   // the random padding of the three modes, one launch
         for (int l = 0; l < 3; ++l) {
             if (!active[l]) continue;
-            if (kk[l] > have[l])
-                HIPCHK(fc::fill_random(n * (long)(kk[l] - have[l]),
-                                       1234u + 7u * l + 101u * site + 7919u * round,
-                                       p->Xs3[l] + (long)have[l] * n, c.s));
+            if (kk[l] > have[l]) {
+                fc::FillJob& F = fills.job[fills.count++];
+                F.n = n * (long)(kk[l] - have[l]);
+                F.seed = 1234u + 7u * l + 101u * site + 7919u * round;
+                F.x = p->Xs3[l] + (long)have[l] * n;
+            }
             start_done[l] = exact[l] ? first_cols[l] : have[l];
         }
+        HIPCHK(fc::fill_random_multi(fills, c.s));
         orthonormalize3(c, kk, p->Xs3, 1e-13, start_done, active);
         bool power[3] = {false, false, false};
         int before[3] = {0, 0, 0};
@@ -1261,8 +1262,7 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     if (grouped) {
         // all terms of the three modes at once, each mode on its own slices
         // of c1 and c2 (the permuted cores of modes 1 and 2 in Cp and Cn2)
-        HIPCHK(fc::permute_core(r[0], r[1], r[2], 1, 1, P.core, 0, p->Cp, 0, c.s));
-        HIPCHK(fc::permute_core(r[0], r[1], r[2], 2, 1, P.core, 0, p->Cn2, 0, c.s));
+        HIPCHK(fc::permute_core12(r[0], r[1], r[2], P.core, p->Cp, p->Cn2, c.s));
         const double* cores[3] = {P.core, p->Cp, p->Cn2};
         fc::GemmArgs s1[3], s2[3], s3[3];
         for (int l = 0; l < 3; ++l) {
