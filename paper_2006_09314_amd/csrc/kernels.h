@@ -117,11 +117,8 @@ hipError_t dot_long(long n, const double* x, const double* y, double* part, unsi
 // X[:, c] *= scale[c] (or /= if divide) for an n x m column-major matrix
 hipError_t scale_cols(int n, int m, double* X, long ldx, const double* scale, int divide,
                       hipStream_t s);
-// column 2-norms of an n x m matrix
-hipError_t col_norms(int n, int m, const double* X, long ldx, double* out, hipStream_t s);
-// fill with a deterministic pseudo-random normal-like sequence (counter hash)
-hipError_t fill_random(long n, unsigned seed, double* x, hipStream_t s);
-// the same for up to three independent vectors in one launch
+// fill up to three vectors with deterministic pseudo-random normal-like
+// sequences (counter hash of the seed and the index) in one launch
 struct FillJob {
     long n = 0;
     unsigned seed = 0;

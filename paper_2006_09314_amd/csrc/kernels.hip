@@ -1235,24 +1235,12 @@ __device__ void col_norm(int n, const double* __restrict__ x, double* out, doubl
     if (threadIdx.x == 0) *out = sqrt(red[0]);
 }
 
-__global__ __launch_bounds__(256) void col_norms_kernel(int n, const double* __restrict__ X,
-                                                        long ldx, double* out) {
-    __shared__ double red[256];
-    col_norm(n, X + blockIdx.x * ldx, out + blockIdx.x, red);
-}
-
 // Column norms of up to kMaxPanelJobs matrices in one launch (grid.y).
 __global__ __launch_bounds__(256) void col_norms_multi_kernel(int n, NormJobs jobs) {
     __shared__ double red[256];
     const NormJob& jb = jobs.job[blockIdx.y];
     if ((int)blockIdx.x >= jb.m) return;
     col_norm(n, jb.X + (long)blockIdx.x * n, jb.out + blockIdx.x, red);
-}
-
-hipError_t col_norms(int n, int m, const double* X, long ldx, double* out, hipStream_t s) {
-    if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(col_norms_kernel, dim3(m), dim3(256), 0, s, n, X, ldx, out);
-    return hipGetLastError();
 }
 
 hipError_t col_norms(int n, const NormJobs& jobs, hipStream_t s) {
@@ -1270,17 +1258,6 @@ __device__ inline uint64_t splitmix64(uint64_t x) {
     x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
     x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
     return x ^ (x >> 31);
-}
-
-__global__ void fill_random_kernel(long n, unsigned seed, double* x) {
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        const uint64_t h1 = splitmix64(((uint64_t)seed << 40) ^ (uint64_t)(2 * i));
-        const uint64_t h2 = splitmix64(((uint64_t)seed << 40) ^ (uint64_t)(2 * i + 1));
-        const double u1 = ((h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
-        const double u2 = ((h2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
-        x[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-    }
 }
 
 __global__ void fill_random_multi_kernel(FillJobs jobs) {
@@ -1301,13 +1278,6 @@ hipError_t fill_random_multi(const FillJobs& jobs, hipStream_t s) {
     if (jobs.count <= 0 || most <= 0) return hipSuccess;
     const int blocks = (int)std::min<long>((most + 255) / 256, 4096);
     hipLaunchKernelGGL(fill_random_multi_kernel, dim3(blocks, jobs.count), dim3(256), 0, s, jobs);
-    return hipGetLastError();
-}
-
-hipError_t fill_random(long n, unsigned seed, double* x, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(fill_random_kernel, dim3(blocks), dim3(256), 0, s, n, seed, x);
     return hipGetLastError();
 }
 
