@@ -608,6 +608,11 @@ void orthonormalize3(const Ctx& c, int m[3], double* const Y[3], double drop, co
 // Diagnostic (environment variable FC_CHECK): largest deviation of M^T M
 // from the identity for an m x k matrix, printed when above 1e-10.
 const bool g_check = std::getenv("FC_CHECK") != nullptr;
+// FC_UNGROUPED: the truncations issue their per-mode products, row-wise
+// products and term passes mode by mode instead of in grouped launches (the
+// paths taken when the grouped slices do not fit the plan's buffers), so
+// those paths can be checked on any problem
+const bool g_ungrouped = std::getenv("FC_UNGROUPED") != nullptr;
 void check_cols(const Ctx& c, const double* M, long ld, int m, int k, const char* what, int tag) {
     if (!g_check || k <= 0) return;
     fc_plan_s* p = c.p;
@@ -922,7 +927,7 @@ struct SumGramApply {
         long need = 0;
         for (int l = 0; l < 3; ++l)
             if (sel[l]) need += (long)k[l] * q[l];
-        if (need > p->ys_cap) {
+        if (g_ungrouped || need > p->ys_cap) {
             for (int l = 0; l < 3; ++l)
                 if (sel[l]) (*this)(l, X[l], q[l], HX[l]);
             return;
@@ -1020,7 +1025,7 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
                     n1 += (long)pu[0] * pu[1] * pt[2];
                     n2c += (long)pu[0] * pt[1] * pt[2];
                 }
-            if (n1 <= p->cbig && n2c <= p->cbig) {
+            if (!g_ungrouped && n1 <= p->cbig && n2c <= p->cbig) {
                 fc::GemmArgs s1[3], s2[3], s3[3];
                 int np = 0;
                 long o1 = 0, o2 = 0;
@@ -1184,7 +1189,7 @@ struct HadGramApply {
                 ne += (long)n * r[l] * q[l];
                 ny += (long)r[l] * q[l] * Q;
             }
-        if (ne > p->e_cap || ne > p->f_cap || ny > p->ys_cap) {
+        if (g_ungrouped || ne > p->e_cap || ne > p->f_cap || ny > p->ys_cap) {
             for (int l = 0; l < 3; ++l)
                 if (sel[l]) (*this)(l, X[l], q[l], HX[l]);
             return;
@@ -1233,7 +1238,7 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     if (P.empty()) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
     const int* r = P.r;
     // 1. diagonal Grams Gd_l^q = Z_l^T diag(D_l[:,q]^2) Z_l  -> stack r_l^2 x Q
-    if ((long)n * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) <= p->e_cap) {
+    if (!g_ungrouped && (long)n * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) <= p->e_cap) {
         // the three modes together, each in its own slice of E
         fc::RowJobs kr;
         fc::GemmArgs gd[3];
@@ -1258,7 +1263,7 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     double* Mq[3];
     for (int l = 0; l < 3; ++l) Mq[l] = p->Mq + (long)l * Q * p->rcap * p->rcap;
     const long csz3 = (long)r[0] * r[1] * r[2];
-    const bool grouped = 3L * Q * csz3 <= p->cbig;
+    const bool grouped = !g_ungrouped && 3L * Q * csz3 <= p->cbig;
     if (grouped) {
         // all terms of the three modes at once, each mode on its own slices
         // of c1 and c2 (the permuted cores of modes 1 and 2 in Cp and Cn2)
@@ -1351,7 +1356,7 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
         return;
     }
     // 4. projection A_l^q = W_l^T D^q Z_l -> stack (pk*r x Q)
-    if ((long)n * (pk[0] * r[0] + pk[1] * r[1] + pk[2] * r[2]) <= p->e_cap) {
+    if (!g_ungrouped && (long)n * (pk[0] * r[0] + pk[1] * r[1] + pk[2] * r[2]) <= p->e_cap) {
         fc::RowJobs kr;
         double* El[3];
         long oe = 0;
