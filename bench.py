@@ -15,10 +15,11 @@ solves/sec over the timed steps.  Also measured: the plain FP64 path one solve
 at a time, the mixed-precision path (single and batched), and a batch of
 uneven sizes (n from 64 to 2048).
 
-Prints one JSON line with the roofline of the dominant kernel (the FP64
-matrix-core GEMM, each launch timed with HIP events on its stream in the
-single-solve timed region), the CPU oracle timed on a bounded sample on this
-host, and the oracle error of sampled results.
+Prints one JSON line with the roofline of the dominant single kernel of a
+solve (the larger timed share of the Gram-Schmidt panel kernel and the
+symmetric eigensolver; the GEMM family beside it), each launch timed with HIP
+events on its stream in the single-solve timed region, the CPU oracle timed
+on a bounded sample on this host, and the oracle error of sampled results.
 """
 from __future__ import annotations
 
