@@ -125,23 +125,8 @@ class ErrorReport(dict):
     pass
 
 
-def rel_error(prob, w_u: np.ndarray, U_u: Sequence[np.ndarray], sp: Optional[Spectral] = None,
-              slabs: Optional[Iterable[int]] = None, block: int = 8) -> ErrorReport:
-    """Relative L2 error of a canonical candidate u = sum_t w_t U1 o U2 o U3
-    against the exact solution, and the exact-operator relative residual
-    ||y - F(A) u|| / ||y||.
-
-    Both are evaluated in eigen-coordinates (V orthogonal, so the norms are
-    unchanged), i1-slab by i1-slab.  With `slabs` given, only those mode-1
-    slabs enter both numerator and denominator (a sampled estimate); the
-    report says how many slabs were used."""
-    sp = sp or Spectral(prob)
-    n = prob.n
-    Uh = sp.to_eig(U_u)
-    w_u = np.asarray(w_u, dtype=np.float64)
-    idx = sorted(set(int(i) for i in slabs)) if slabs is not None else list(range(n))
-    num = den = rnum = rden = 0.0
-    # group consecutive indices into blocks
+def _slab_groups(idx, block):
+    """Consecutive runs of at most `block` mode-1 slab indices."""
     groups = []
     k = 0
     while k < len(idx):
@@ -150,15 +135,71 @@ def rel_error(prob, w_u: np.ndarray, U_u: Sequence[np.ndarray], sp: Optional[Spe
             j += 1
         groups.append((idx[k], idx[j] + 1))
         k = j + 1
-    for i0, i1 in groups:
+    return groups
+
+
+def slab_rows(w: np.ndarray, F: Sequence[np.ndarray], i0: int, i1: int) -> np.ndarray:
+    """Rows i0..i1 (mode 1) of sum_s w_s F1[:,s] o F2[:,s] o F3[:,s], slab by
+    slab: slab i is F2 diag(w * F1[i,:]) F3^T, one BLAS product per slab (the
+    same sum as cp_block, formed in another order)."""
+    w = np.asarray(w, dtype=np.float64)
+    A = F[0][i0:i1, :] * w[None, :]
+    return np.matmul(F[1][None, :, :] * A[:, None, :], F[2].T[None, :, :])
+
+
+def _parallel_sum(fn, groups, workers):
+    """Sum the tuples fn(i0, i1) returns over the slab groups, on a thread
+    pool (NumPy releases the GIL in its kernels) with single-threaded BLAS
+    inside, in group order (the result does not depend on the scheduling)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:   # pragma: no cover
+        threadpool_limits = None
+    if workers <= 1 or len(groups) <= 1:
+        parts = [fn(i0, i1) for i0, i1 in groups]
+    else:
+        import contextlib
+        limit = threadpool_limits(limits=1) if threadpool_limits else contextlib.nullcontext()
+        with limit, ThreadPoolExecutor(max_workers=workers) as ex:
+            parts = list(ex.map(lambda g: fn(*g), groups))
+    tot = [0.0] * len(parts[0]) if parts else []
+    for p in parts:
+        for k, v in enumerate(p):
+            tot[k] += v
+    return tot
+
+
+def rel_error(prob, w_u: np.ndarray, U_u: Sequence[np.ndarray], sp: Optional[Spectral] = None,
+              slabs: Optional[Iterable[int]] = None, block: int = 8,
+              workers: Optional[int] = None) -> ErrorReport:
+    """Relative L2 error of a canonical candidate u = sum_t w_t U1 o U2 o U3
+    against the exact solution, and the exact-operator relative residual
+    ||y - F(A) u|| / ||y||.
+
+    Both are evaluated in eigen-coordinates (V orthogonal, so the norms are
+    unchanged), i1-slab by i1-slab.  With `slabs` given, only those mode-1
+    slabs enter both numerator and denominator (a sampled estimate); the
+    report says how many slabs were used.  Slab groups are evaluated on a
+    thread pool and summed in slab order."""
+    sp = sp or Spectral(prob)
+    n = prob.n
+    Uh = sp.to_eig(U_u)
+    w_u = np.asarray(w_u, dtype=np.float64)
+    idx = sorted(set(int(i) for i in slabs)) if slabs is not None else list(range(n))
+
+    def part(i0, i1):
         D = sp.D_block(i0, i1)
-        Yb = cp_block(prob.w, sp.Yh, i0, i1)
-        Ub = cp_block(w_u, Uh, i0, i1)
+        Yb = slab_rows(prob.w, sp.Yh, i0, i1)
+        Ub = slab_rows(w_u, Uh, i0, i1)
         Ex = Yb / D
-        num += float(np.sum((Ub - Ex) ** 2))
-        den += float(np.sum(Ex ** 2))
-        rnum += float(np.sum((Yb - D * Ub) ** 2))
-        rden += float(np.sum(Yb ** 2))
+        return (float(np.sum((Ub - Ex) ** 2)), float(np.sum(Ex ** 2)),
+                float(np.sum((Yb - D * Ub) ** 2)), float(np.sum(Yb ** 2)))
+
+    num, den, rnum, rden = _parallel_sum(part, _slab_groups(idx, block), workers)
     rep = ErrorReport(rel_l2=float(np.sqrt(num / den)) if den > 0 else float("nan"),
                       rel_residual=float(np.sqrt(rnum / rden)) if rden > 0 else float("nan"),
                       slabs=len(idx), n=n)
@@ -194,7 +235,7 @@ def cost_from_factors(prob, w_u, U_u: Sequence[np.ndarray], w_y, Y_y: Sequence[n
 
 def state_rel_error(prob, w_y: np.ndarray, Y_y: Sequence[np.ndarray],
                     sp: Optional[Spectral] = None, slabs: Optional[Iterable[int]] = None,
-                    block: int = 8) -> ErrorReport:
+                    block: int = 8, workers: Optional[int] = None) -> ErrorReport:
     """Relative L2 error of a canonical candidate state y against the exact
     state beta A^-alpha u* of the exact control u* (eigen-coordinates, slab by
     slab; with `slabs` a sampled estimate)."""
@@ -203,16 +244,16 @@ def state_rel_error(prob, w_y: np.ndarray, Y_y: Sequence[np.ndarray],
     Yy = sp.to_eig(Y_y)
     w_y = np.asarray(w_y, dtype=np.float64)
     idx = sorted(set(int(i) for i in slabs)) if slabs is not None else list(range(n))
-    num = den = 0.0
-    for i0 in idx:
-        i1 = i0 + 1
+
+    def part(i0, i1):
         D = sp.D_block(i0, i1)
         s = (sp.lam[0][i0:i1, None, None] + sp.lam[1][None, :, None]
              + sp.lam[2][None, None, :])
-        Ex = f_state(s, prob.alpha, prob.beta) * cp_block(prob.w, sp.Yh, i0, i1) / D
-        Yb = cp_block(w_y, Yy, i0, i1)
-        num += float(np.sum((Yb - Ex) ** 2))
-        den += float(np.sum(Ex ** 2))
+        Ex = f_state(s, prob.alpha, prob.beta) * slab_rows(prob.w, sp.Yh, i0, i1) / D
+        Yb = slab_rows(w_y, Yy, i0, i1)
+        return float(np.sum((Yb - Ex) ** 2)), float(np.sum(Ex ** 2))
+
+    num, den = _parallel_sum(part, _slab_groups(idx, block), workers)
     return ErrorReport(rel_l2=float(np.sqrt(num / den)) if den > 0 else float("nan"),
                        slabs=len(idx), n=n)
 
