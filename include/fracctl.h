@@ -230,6 +230,26 @@ fc_status fc_cp_inner(fc_plan plan, int ra, const double* wa, const double* A1, 
                       const double* A3, int rb, const double* wb, const double* B1,
                       const double* B2, const double* B3, double* out, void* hip_stream);
 
+/* fc_cp_inner for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no plan, no allocation, no host synchronisation.
+ *   n                 rows of every factor (n >= 1)
+ *   ra, wa, A1..A3    as fc_cp_inner (DEVICE)
+ *   rb, wb, B1..B3    as fc_cp_inner (DEVICE)
+ *   out               DEVICE out: one double, <A, B>
+ * The three cross Grams A_l^T B_l live in a file-scope device array of the
+ * library (3 x 65536 doubles, 1.5 MiB per GPU, held until the process ends),
+ * so ra * rb <= 65536; larger ranks return FC_ERR_INVALID_ARG and enqueue
+ * nothing.  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU (different streams, or threads without ordering) race and give
+ * wrong results.  The result is enqueued on hip_stream and is ready when the
+ * stream reaches it.  For ra, rb <= 128 the result is bit-identical to
+ * fc_cp_inner's. */
+fc_status fc_cp_inner_noalloc(int n, int ra, const double* wa, const double* A1,
+                              const double* A2, const double* A3, int rb, const double* wb,
+                              const double* B1, const double* B2, const double* B3,
+                              double* out, void* hip_stream);
+
 /* Rank truncation of a canonical tensor (Appendix 1, C2T by reduced HOSVD
  * followed by the Tucker-to-canonical transform) to relative accuracy eps:
  * the result T' satisfies ||T - T'|| <= eps ||T|| (Euclidean norm).

@@ -95,6 +95,7 @@ PROTOTYPES = {
     "fc_plan_separable": (_I, [_VP, _I, _I, _PI, _PD, _PD]),
     "fc_mode_transform": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP]),
     "fc_cp_inner": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _I, _VP, _VP, _VP, _VP, _PD, _VP]),
+    "fc_cp_inner_noalloc": (_I, [_I, _I, _VP, _VP, _VP, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
     "fc_cp_truncate": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _D, _I, _PI, _VP, _VP, _VP, _VP, _VP]),
     "fc_apply_separable": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _D, _I, _PI, _VP, _VP, _VP,
                                 _VP, _VP]),

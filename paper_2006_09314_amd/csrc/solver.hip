@@ -2438,6 +2438,82 @@ fc_status fc_cp_inner(fc_plan p, int ra, const double* wa, const double* A1, con
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Scratch of fc_cp_inner_noalloc: the three cross Grams A_l^T B_l (ra x rb
+// each, ra * rb <= kNoAllocPairs).  A file-scope device array, so the entry
+// point needs no allocation; each GPU holds its own copy, found through
+// hipGetSymbolAddress once per device (the array's name in host code is not
+// a device address).
+constexpr long kNoAllocPairs = 256L * 256L;
+__device__ __align__(256) double scratch[3 * kNoAllocPairs];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (looked up on the first call on
+// that device).
+fc_status noalloc_scratch(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(FC_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FC_ERR_INTERNAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(FC_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fc_status fc_cp_inner_noalloc(int n, int ra, const double* wa, const double* A1, const double* A2,
+                              const double* A3, int rb, const double* wb, const double* B1,
+                              const double* B2, const double* B3, double* out, void* stream) {
+    if (n < 1 || ra < 1 || rb < 1 || !A1 || !A2 || !A3 || !B1 || !B2 || !B3 || !out)
+        return fail(FC_ERR_INVALID_ARG, "fc_cp_inner_noalloc: bad arguments");
+    if ((long)ra * rb > kNoAllocPairs)
+        return fail(FC_ERR_INVALID_ARG, "fc_cp_inner_noalloc: ra * rb = " +
+                                            std::to_string((long)ra * rb) +
+                                            " exceeds the scratch capacity of 65536 pairs");
+    double* ws = nullptr;
+    const fc_status st = noalloc_scratch(&ws);
+    if (st != FC_OK) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    const double* A[3] = {A1, A2, A3};
+    const double* B[3] = {B1, B2, B3};
+    double* G[3];
+    fc::GramJobs jobs;
+    for (int l = 0; l < 3; ++l) {
+        G[l] = ws + l * (long)ra * rb;
+        fc::GemmArgs& g = jobs.g[jobs.count++];
+        g.M = ra; g.N = rb; g.K = n;
+        g.A = A[l]; g.lda = n; g.B = B[l]; g.ldb = n; g.C = G[l]; g.ldc = ra;
+    }
+    hipError_t e;
+    if (ra <= 128 && rb <= 128) {
+        e = fc::gram_multi(true, false, jobs, s);
+    } else {
+        e = hipSuccess;
+        for (int l = 0; l < 3 && e == hipSuccess; ++l) e = fc::gemm(true, false, jobs.g[l], s);
+    }
+    if (e == hipSuccess) e = fc::cp_inner_reduce(ra, rb, G[0], G[1], G[2], wa, wb, out, s);
+    if (e != hipSuccess)
+        return fail(FC_ERR_HIP, std::string("fc_cp_inner_noalloc: ") + hipGetErrorString(e));
+    return FC_OK;
+}
+
 static fc_status canon_out(fc_plan p, const Ctx& c, const Tucker& T, double budget2, bool to_grid,
                            int cap, int* rank_out, double* w_out, double* O1, double* O2,
                            double* O3) {
