@@ -64,41 +64,95 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(prob, sample_slabs=8):
-    """The oracle's exact solve, timed on a bounded sample: full setup (three
-    LAPACK tridiagonal eigensolves and the entry transform), then the divide
-    and the mode-2/3 products for `sample_slabs` of the n mode-1 slabs and the
-    mode-1 product for the same share of columns; extrapolated to all n
-    slabs."""
-    import numpy as np
-    from oracle import solve as osolve
+def host_info():
+    """CPU model, logical CPUs and the BLAS the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    threads = os.cpu_count() or 1
     try:
         from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        info = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+        if info:
+            blas = f"{info[0].get('internal_api')} {info[0].get('version')}"
+            threads = max(d.get("num_threads", 1) for d in info)
     except Exception:
-        cores = os.cpu_count() or 1
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "blas": blas,
+            "blas_threads": int(threads)}
+
+
+def _median_iqr(xs):
+    q = np.percentile(np.asarray(xs), [25, 50, 75])
+    return float(q[1]), float(q[2] - q[0])
+
+
+def cpu_full_timings(repeats=5):
+    """The oracle's exact solve timed in full (setup: three LAPACK
+    tridiagonal eigensolves; solve: entry transform, divide over the n^3
+    grid, three mode products) at n = 32 and n = 256: median and IQR."""
+    import workloads as wl
+    from oracle import solve as osolve
+    out = {}
+    for name, prob in (("small_n32", wl.workload_small()),
+                       ("quadratic_n256", wl.workload_quadratic(n=256, alpha=0.5))):
+        ts, tt = [], []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            sp = osolve.Spectral(prob)
+            t1 = time.perf_counter()
+            osolve.solve_full(prob, sp)
+            t2 = time.perf_counter()
+            ts.append(t1 - t0)
+            tt.append(t2 - t0)
+        med, iqr = _median_iqr(tt)
+        smed, siqr = _median_iqr(ts)
+        out[name] = {"n": prob.n, "repeats": repeats, "s_per_solve_median": med, "s_iqr": iqr,
+                     "setup_s_median": smed, "setup_s_iqr": siqr, "solves_per_s": 1.0 / med}
+    return out
+
+
+def cpu_baseline(prob, sample_slabs=8, repeats=3):
+    """The oracle's exact solve at the headline size, timed on a bounded
+    sample: full setup (three LAPACK tridiagonal eigensolves and the entry
+    transform), then the divide and the mode-2/3 products for `sample_slabs`
+    of the n mode-1 slabs and the mode-1 product for the same share of
+    columns, extrapolated to all n slabs; median (and IQR) over `repeats`."""
+    from oracle import solve as osolve
+    hi = host_info()
     n = prob.n
-    t0 = time.perf_counter()
-    sp = osolve.Spectral(prob)
-    t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    blk = osolve.solve_eig_block(sp, 0, sample_slabs)
-    blk = np.tensordot(blk, sp.V[1], axes=(1, 1))          # (b, k, j) <- mode 2
-    blk = np.tensordot(blk, sp.V[2], axes=(1, 1))          # (b, j, k) <- mode 3
-    t_slabs = time.perf_counter() - t0
-    cols = blk.reshape(sample_slabs, -1)
-    W = np.ascontiguousarray(np.random.default_rng(0).standard_normal((n, sample_slabs)))
-    t0 = time.perf_counter()
-    _ = W @ cols                                           # mode-1 product share
-    t_mode1 = time.perf_counter() - t0
-    scale = n / sample_slabs
-    t_total = t_setup + scale * (t_slabs + t_mode1)
+    totals = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        sp = osolve.Spectral(prob)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        blk = osolve.solve_eig_block(sp, 0, sample_slabs)
+        blk = np.tensordot(blk, sp.V[1], axes=(1, 1))          # (b, k, j) <- mode 2
+        blk = np.tensordot(blk, sp.V[2], axes=(1, 1))          # (b, j, k) <- mode 3
+        t_slabs = time.perf_counter() - t0
+        cols = blk.reshape(sample_slabs, -1)
+        W = np.ascontiguousarray(np.random.default_rng(0).standard_normal((n, sample_slabs)))
+        t0 = time.perf_counter()
+        _ = W @ cols                                           # mode-1 product share
+        t_mode1 = time.perf_counter() - t0
+        scale = n / sample_slabs
+        totals.append(t_setup + scale * (t_slabs + t_mode1))
+    med, iqr = _median_iqr(totals)
     return {
-        "value": 1.0 / t_total, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-        "sample": (f"oracle exact solve at n={n}: setup timed in full ({t_setup:.2f}s), divide + "
-                   f"mode-2/3 products timed on {sample_slabs} of {n} mode-1 slabs and the mode-1 "
-                   f"product on the same share of columns, extrapolated x{scale:.0f}; "
-                   f"estimated {t_total:.1f}s per solve"),
+        "value": 1.0 / med, "unit": "solves/s", "cores": hi["blas_threads"], "kind": "oracle",
+        "sample": (f"oracle exact solve at n={n}: setup timed in full, divide + mode-2/3 products "
+                   f"timed on {sample_slabs} of {n} mode-1 slabs and the mode-1 product on the "
+                   f"same share of columns, extrapolated x{n / sample_slabs:.0f}; median "
+                   f"{med:.1f}s per solve (IQR {iqr:.2f}s over {repeats} repeats)"),
+        "s_per_solve_median": med, "s_iqr": iqr, "host": hi,
     }
 
 
@@ -136,28 +190,44 @@ def batch_io(api, torch, dev, probs, cap):
     return inputs, outs
 
 
-KERNELS = {0: "GEMM family (hand-written Gram-type and MFMA kernels, rocBLAS dgemm)",
+KERNELS = {0: "gemm_kernel / gemm_multi_kernel (short-reduction LDS-tiled FP64 MFMA GEMMs)",
            1: "panel_mgs_kernel (Gram-Schmidt panel, one workgroup)",
-           2: "tdeig_kernel (symmetric eigensolver, one workgroup per matrix)"}
+           2: "tdeig_kernel (symmetric eigensolver, one workgroup per matrix)",
+           3: "transform_kernel (mode transforms V^T Y, V Z on FP64 MFMA)",
+           4: "gram_kernel / gram_multi_kernel (long-reduction FP64 MFMA: Gram-type products, "
+              "scaled Grams Z^T diag(d) X, core contractions)",
+           5: "kron_apply_kernel (fused sum_q diag(D[:,q]) Z T^q on FP64 MFMA)"}
+# kernel names of each kind in rocprofv3 traces (for the traffic records)
+KERNEL_NAMES = {0: "gemm_family_short", 1: "panel_mgs_kernel", 2: "tdeig_kernel",
+                3: "transform_kernel", 4: "gram_family", 5: "kron_apply_kernel"}
+KIND_KEYS = {0: "short_gemm", 1: "gram_schmidt_panel", 2: "eigensolver", 3: "mode_transform",
+             4: "long_gram", 5: "kron_apply"}
 
 
 def kernel_profile(lib, check, kind):
+    """(launches, total ms, algorithmic flops, algorithmic bytes) of one
+    profile kind; kind -1: the whole product family (fc_profile_gemm_read)."""
     launches, ms, flops, byts = C.c_long(), C.c_double(), C.c_double(), C.c_double()
-    check(lib().fc_profile_kernel_read(kind, C.byref(launches), C.byref(ms), C.byref(flops),
-                                       C.byref(byts)), "fc_profile_kernel_read")
+    if kind < 0:
+        check(lib().fc_profile_gemm_read(C.byref(launches), C.byref(ms), C.byref(flops),
+                                         C.byref(byts)), "fc_profile_gemm_read")
+    else:
+        check(lib().fc_profile_kernel_read(kind, C.byref(launches), C.byref(ms), C.byref(flops),
+                                           C.byref(byts)), "fc_profile_kernel_read")
     return launches.value, ms.value, flops.value, byts.value
 
 
 def roofline(kind, launches, ms, flops, byts):
     """Roofline of one kernel family from HIP-event timings: the algorithmic
     work per launch over the mean launch duration, against the HBM roof when
-    the arithmetic intensity is below the FP64 ridge point, else the FP64
-    matrix-core roof."""
+    the arithmetic intensity is below the FP64 ridge point (always for the
+    mode transforms, whose V_l read dominates), else the FP64 matrix-core
+    roof."""
     per_launch_s = (ms / 1e3) / max(launches, 1)
     fl_launch = flops / max(launches, 1)
     by_launch = byts / max(launches, 1)
     ai = flops / max(byts, 1.0)
-    if ai >= PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
+    if ai >= PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9) and kind != 3:
         # above the ridge: the FP64 matrix cores for the GEMMs; the eigensolver
         # computes on the FP64 vector units (same 78.6 TFLOP/s peak)
         achieved = fl_launch / per_launch_s / 1e12
@@ -274,27 +344,32 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     check(lib().fc_profile_gemm(0), "fc_profile_gemm")
-    profs = {k: kernel_profile(lib, check, k) for k in (0, 1, 2)}
-    # the dominant single kernel of the solve: of the two single kernels
-    # timed (the Gram-Schmidt panel and the eigensolver; the GEMM family is a
-    # family of many kernels), the one with the larger share of the timed
-    # solves, as in the rocprofv3 trace
-    dom = 1 if profs[1][1] >= profs[2][1] else 2
+    kinds = sorted(KERNELS)
+    profs = {k: kernel_profile(lib, check, k) for k in kinds}
+    # the dominant kernel of the solve: the kernel family with the largest
+    # share of the timed solves (HIP events around every launch)
+    dom = max(kinds, key=lambda k: profs[k][1])
     roof = roofline(dom, *profs[dom])
     roof["measured_in"] = ("FP64 single-solve timed region, one stream (under concurrent streams "
                            "HIP events time queueing, not kernel duration)")
     roof["share_of_solve"] = (profs[dom][1] / 1e3) / el
-    roof["traffic"], roof["traffic_source"] = recorded_traffic(
-        "panel_mgs_kernel" if dom == 1 else "tdeig_kernel")
+    roof["traffic"], roof["traffic_source"] = recorded_traffic(KERNEL_NAMES[dom])
     others = {}
-    for k, name in ((0, "gemm_family"), (1, "gram_schmidt_panel"), (2, "eigensolver")):
+    for k in kinds:
         if k == dom:
             continue
         r = roofline(k, *profs[k])
         r["share_of_solve"] = (profs[k][1] / 1e3) / el
         r["per_solve_bytes"] = profs[k][3] / args.single_steps
-        others[name] = r
+        r["per_solve_flops"] = profs[k][2] / args.single_steps
+        r["traffic"], r["traffic_source"] = recorded_traffic(KERNEL_NAMES[k])
+        others[KIND_KEYS[k]] = r
     roof["other_kernels"] = others
+    # algorithmic work of one solve over all timed kernel families (for the
+    # roofline of the batched step)
+    solve_flops = sum(profs[k][2] for k in kinds) / args.single_steps
+    solve_bytes = sum(profs[k][3] for k in kinds) / args.single_steps
+    profs[0] = kernel_profile(lib, check, -1)   # the whole product family (kinds 0, 3, 4, 5)
     sl = profs[0][0]
     sms = profs[0][1]
     single = {"solves_per_s": args.single_steps / el, "ms_per_solve": 1e3 * el / args.single_steps,
@@ -341,10 +416,16 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = args.steps * len(probs) / elapsed
-    # GEMM bytes moved per second of the batched steps (all streams together),
-    # from the per-solve algorithmic GEMM bytes of the single-solve profile
-    roof["other_kernels"]["gemm_family"]["aggregate_gbs_batched"] = (
-        roof["other_kernels"]["gemm_family"]["per_solve_bytes"] * value / 1e9)
+    # the batched step as a whole: the algorithmic work of the timed kernel
+    # families per solve (single-solve profile) times the solves per second
+    # of the step, against the FP64 peak and the HBM roof
+    step_tflops = solve_flops * value / 1e12
+    step_gbs = solve_bytes * value / 1e9
+    roof["step"] = {"what": "timed batched step, all kernel families, algorithmic work per solve x "
+                            "solves/s",
+                    "flops_per_solve": solve_flops, "bytes_per_solve": solve_bytes,
+                    "achieved_tflops": step_tflops, "frac_fp64_peak": step_tflops / PEAK_FP64_TFLOPS,
+                    "achieved_gbs": step_gbs, "frac_hbm": step_gbs / PEAK_HBM_GBS}
     iters = [r[2]["iterations"] for r in res_b]
     batched = {"problems": len(probs), "setup_s": bsetup, "solves_per_s": value,
                "streams": int(os.environ.get("FC_BATCH_STREAMS", "16")),
@@ -416,6 +497,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
         cpu = cpu_baseline(prob)
+        cpu["full_solves"] = cpu_full_timings()
         log(f"[bench] cpu baseline {cpu}")
 
     rec = {

@@ -57,10 +57,16 @@ typedef enum {
 
 /* FC_FP64: every operation in FP64.  FC_MIXED_FP32: outer FP64 iterative
  * refinement of the true residual around an inner PCG whose bulk
- * contractions (mode transforms of the subspace iteration, Hadamard
- * projections, core contractions) run on the FP32 matrix cores with FP32
- * accumulation; Grams, eigensolves, PCG scalars and the refinement residual
- * stay FP64. */
+ * contractions (the Hadamard truncation's projections and core
+ * contractions) run on the FP32 matrix cores with FP32 accumulation; Grams,
+ * eigensolves, the short sums' projections, PCG scalars and the refinement
+ * residual stay FP64.  Stop rule of the mixed path: the refinement sweeps
+ * end when an error estimate, the preconditioned residual ratio
+ * ||D~_p (.) R|| / ||D~_p (.) B|| (formed to two digits), is <= tol; if it
+ * stops falling by half from one sweep to the next, the solve ends and counts
+ * as converged when the estimate is <= 3 tol (else FC_ERR_NOT_CONVERGED).
+ * The FP64 Euclidean residual ||R|| / ||Y|| of the last sweep is reported in
+ * fc_info.rel_residual. */
 typedef enum { FC_FP64 = 0, FC_MIXED_FP32 = 1 } fc_precision;
 
 /* Preconditioner (Section 3.5).
@@ -87,7 +93,8 @@ typedef struct {
     double tol;             /* stop when ||R|| <= tol ||Y||; 0 -> eps                          */
     double op_accuracy;     /* entrywise relative accuracy of the operator; 0 -> eps           */
     int max_iter;           /* 0 -> 100                                                        */
-    int max_rank;           /* Tucker rank capacity per mode; 0 -> 64, at most 96              */
+    int max_rank;           /* Tucker rank capacity per mode; 0 -> 96, at most 128 (the small
+                               eigenproblems of the truncations are at most 128 x 128)         */
     int precond_rank;       /* Kronecker rank of the preconditioner (the paper's tests use 6,
                                Section 4); 0 -> automatic: the first of 6, 8, ..., 16 whose
                                fit of 1/f reaches a relative error of 1e-3 (else the best)    */
@@ -118,6 +125,10 @@ typedef struct {
                                    case (A)) of |D~_p f - 1|                                   */
     int state_rank;         /* Kronecker rank of the state map beta A^-alpha                   */
     double state_max_rel_err; /* max over the spectrum of its relative error (setup gate)      */
+    double subspace_miss;   /* largest, over the Hadamard truncations of the solve, ratio of the
+                               energy their mode subspaces miss (twice an estimate from 8 rank-1
+                               Gaussian probes; charged to the truncation's budget) to that
+                               truncation's error budget: below 1 the error bound holds       */
 } fc_info;
 
 /* Plan with gamma = 1, FP64 and defaults; see fc_setup_ex.  a1..a3 are HOST. */
@@ -243,8 +254,8 @@ fc_status fc_cp_inner(fc_plan plan, int ra, const double* wa, const double* A1, 
  * nothing.  Every call on a GPU shares that GPU's array: calls that overlap
  * on one GPU (different streams, or threads without ordering) race and give
  * wrong results.  The result is enqueued on hip_stream and is ready when the
- * stream reaches it.  For ra, rb <= 128 the result is bit-identical to
- * fc_cp_inner's. */
+ * stream reaches it.  The cross Grams run on the same kernels as
+ * fc_cp_inner's, so the result is bit-identical to fc_cp_inner's. */
 fc_status fc_cp_inner_noalloc(int n, int ra, const double* wa, const double* A1,
                               const double* A2, const double* A3, int rb, const double* wb,
                               const double* B1, const double* B2, const double* B3,
@@ -312,11 +323,23 @@ fc_status fc_host_separable(const fc_setup_params* p, int which, int cap, int* r
 fc_status fc_profile_gemm(int enable);
 fc_status fc_profile_gemm_read(long* launches, double* total_ms, double* flops, double* bytes);
 
-/* The same for another kernel family timed while fc_profile_gemm is on:
- * kind 0 the GEMMs (as fc_profile_gemm_read), 1 the Gram-Schmidt panel kernel
- * (16 n b bytes: its n x b panel read and written once; 4 n b^2 flops per two
- * passes), 2 the symmetric eigensolver (16 k^2 bytes and (4/3 + 2) k^3 flops
- * per matrix). */
+/* The same for one kernel family timed while fc_profile_gemm is on (HIP
+ * events around each launch; algorithmic work as stated):
+ *   kind 0  the short-reduction LDS-tiled GEMMs (2 M N K flops; operands
+ *           read and the result written once, operands shared by a batch
+ *           counted once)
+ *   kind 1  the Gram-Schmidt panel kernel (16 n b bytes: its n x b panel
+ *           read and written once; 4 n b^2 flops per two passes)
+ *   kind 2  the symmetric eigensolver (16 k^2 bytes and (4/3 + 2) k^3 flops
+ *           per matrix)
+ *   kind 3  the mode transforms V^T Y, V Z (and case (A)'s sine-basis maps):
+ *           8 (n^2 + 2 n m) bytes and 2 n^2 m flops per mode
+ *   kind 4  the long-reduction Gram engine (Gram-type products, the scaled
+ *           Grams Z^T diag(d) X of the Hadamard truncation, the core
+ *           contractions over long reductions), counted as kind 0
+ *   kind 5  the fused Kronecker application sum_q diag(D[:,q]) Z T^q:
+ *           2 n p r Q flops; Z, D, T read and the n x p result written once
+ * fc_profile_gemm_read returns kinds 0, 3, 4 and 5 together. */
 fc_status fc_profile_kernel_read(int kind, long* launches, double* total_ms, double* flops,
                                  double* bytes);
 

@@ -58,6 +58,7 @@ class Info(C.Structure):
         ("precond_max_rel_err", C.c_double),
         ("state_rank", C.c_int),
         ("state_max_rel_err", C.c_double),
+        ("subspace_miss", C.c_double),
     ]
 
     def as_dict(self):
@@ -69,6 +70,7 @@ class Info(C.Structure):
             "rel_residual": self.rel_residual, "op_max_rel_err": self.op_max_rel_err,
             "precond_max_rel_err": self.precond_max_rel_err,
             "state_rank": self.state_rank, "state_max_rel_err": self.state_max_rel_err,
+            "subspace_miss": self.subspace_miss,
         }
 
 

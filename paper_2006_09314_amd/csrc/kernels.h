@@ -26,24 +26,68 @@ struct GemmArgs {
 };
 
 hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
-// C = alpha op(A) op(B) + beta C for M, N <= 128 and a long reduction
-// (op(A) op(B) = A^T B, A B^T or A B; batched over g.batch with strides;
-// inner == 1, no diagonal, FP64): the Gram-type products of the
-// truncations, one workgroup per 32 x 32 output tile, K split over its
-// wavefronts.
+// C = alpha op(A) diag(d) op(B) + beta C over a long reduction
+// (op(A) op(B) = A^T B, A B^T or A B; batched over g.batch with strides, d
+// advancing by strideD per batch entry; inner == 1, FP64): the Gram-type
+// products of the truncations and the diagonally scaled Grams Z^T diag(d) X
+// of the Hadamard truncation, one workgroup per 32 x 32 output tile, K split
+// over its wavefronts.
 hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
-// Up to kMaxGramJobs unbatched Gram-type products (each as in gram) in one
-// launch.
+// Up to kMaxGramJobs Gram-type products (each as in gram, batched or not) in
+// one launch.
 constexpr int kMaxGramJobs = 3;
 struct GramJobs {
     int count = 0;
     GemmArgs g[kMaxGramJobs];
 };
 hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s);
+// Streaming products C = alpha op(A) op(B) + beta C over a long reduction
+// with op(A) op(B) = A^T B (layout 0), A B^T (1) or A B (2), up to three
+// jobs (of any sizes) in one launch on the FP64 matrix cores: the mode
+// transforms (A an n x n eigenvector matrix, streamed once) and Gram-type
+// products with few output tiles.  K is split into chunks of kc (128 or 256)
+// values, one workgroup per chunk and 32-row block; with more than one
+// chunk the partial tiles go to `part` (jobs x chunks x max M N doubles,
+// part_cap available) and the last workgroup of a row block adds them in
+// chunk order, counting in through `counters` (one unsigned per job and
+// 32-row block of the largest job, counter_cap available; zero before the
+// call and zero again after it, so calls sharing them must not overlap).
+// stream_fits says whether partials and counters fit.
+struct StreamJob {
+    int M = 0, N = 0, K = 0;
+    double alpha = 1.0, beta = 0.0;
+    const double* A = nullptr; long lda = 0;
+    const double* B = nullptr; long ldb = 0;
+    double* C = nullptr; long ldc = 0;
+};
+struct StreamJobs {
+    int count = 0;
+    StreamJob job[3];
+};
+hipError_t stream_multi(int layout, const StreamJobs& jobs, int kc, double* part, long part_cap,
+                        unsigned* counters, long counter_cap, hipStream_t s);
+bool stream_fits(const StreamJobs& jobs, int kc, long part_cap, long counter_cap);
 // Up to three independent plain FP64 products C = alpha op(A) op(B) + beta C
 // (strided or two-level batches, no scaling vector, whole K per block) in
 // one launch on the matrix cores: 32 x 32 tiles, one wavefront each.
 hipError_t gemm_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s);
+
+// out = sum_q diag(D[:, q]) Z T^q for up to three jobs in one launch (one
+// per mode): Z n x r (ld ldz), D n x Q (ld n), T^q the r x p block at
+// T + q r p (ld r), out n x p (ld ldo).  The row-wise Kronecker product
+// Z (.) D is formed in registers (never stored); FP64 matrix cores.
+struct KronJob {
+    int r = 0, p = 0;
+    const double* Z = nullptr; long ldz = 0;
+    const double* D = nullptr;
+    const double* T = nullptr;
+    double* out = nullptr; long ldo = 0;
+};
+struct KronJobs {
+    int count = 0;
+    KronJob job[3];
+};
+hipError_t kron_apply_multi(int n, int Q, const KronJobs& jobs, hipStream_t s);
 
 // Symmetric eigen-decomposition of a batch of k x k matrices (k <= 128),
 // cyclic Jacobi with the matrix in LDS.  A (column-major, leading dimension
@@ -73,6 +117,41 @@ struct EigJobs {
     int kpmax = 0;
 };
 hipError_t sym_eig_multi(const EigJobs& jobs, hipStream_t s);
+
+// Tucker-to-canonical term selection on the device: N candidate terms
+// with energies sig2[e] (e = nu r1 + j); ordered by (energy, e) ascending,
+// the smallest are dropped while the cumulative dropped energy is <= budget2.
+// keep[t] (t < K) receives the kept term indices in descending order, *count
+// (device int) K.  N <= kT2cMaxTerms; scratch: 12 * N_pad bytes (N_pad the
+// next power of two) of device memory, used when N_pad > 8192.
+constexpr int kT2cMaxTerms = 1 << 16;
+hipError_t t2c_select(int N, const double* sig2, double budget2, void* scratch, int* keep,
+                      int* count, hipStream_t s);
+// The canonical factors of the K kept terms (see t2c_select): c0 r0 x K,
+// c1 r1 x K, c2 r2 x K (column-major, ld r0, r1, r2) and the weights w (K),
+// from the core (r0 x r1 x r2, r0 <= 128) and the slice-Gram eigenpairs
+// (values ev[nu r1 + j], vectors as columns of the r1 x r1 blocks at
+// V + nu r1 r1).
+hipError_t t2c_coef(int r0, int r1, int r2, int K, const double* core, const double* V,
+                    const double* ev, const int* keep, double* c0, double* c1, double* c2,
+                    double* w, hipStream_t s);
+
+// Probe sums of the projection check of the Hadamard truncation, for two
+// problems y = 0, 1 and S probes t:
+//   out[2 t + y] = sum_q sum_k U2_t[k, q] sum_j M_t[j + r1 k + r1 r2 q] U1_t[j, q]
+// with M_t at M + t mstride, U1_t (r1 x Q) at U1 + t r1 Q, U2_t (r2 x Q) at
+// U2 + t r2 Q, r1 <= 128.
+struct ProbeSum {
+    int r1 = 0, r2 = 0, Q = 0;
+    const double* M = nullptr; long mstride = 0;
+    const double* U1 = nullptr;
+    const double* U2 = nullptr;
+};
+struct ProbeSums {
+    ProbeSum p[2];
+    double* out = nullptr;
+};
+hipError_t probe_sums(const ProbeSums& a, int S, hipStream_t s);
 
 // E[i + n*(j + r*c)] = Z[i + ldz*j] * X[i + ldx*c]   (row-wise Kronecker product)
 hipError_t rowkron(int n, int r, int p, const double* Z, long ldz, const double* X, long ldx,

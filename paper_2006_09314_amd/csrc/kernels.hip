@@ -295,17 +295,17 @@ static hipError_t gemm_dispatch(const GemmArgs& g, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Products with a small result (M, N <= 128) and a long reduction:
-// C = alpha op(A) op(B) + beta C with op(A) op(B) = A^T B (L = 0), A B^T
-// (L = 1) or A B (L = 2), column-major operands.  One workgroup per 32 x 32
-// output tile; its sixteen wavefronts split K in interleaved chunks of 16 on
-// the FP64 matrix core (16x16x4), each loading the operands of a chunk
-// (four steps) before issuing their products, so that the sixteen
-// wavefronts keep sixteen chunks in flight; operands go straight from
-// memory into the
-// matrix-core lane layout (lane l: row/column l % 16, k = l / 16), and the
-// partial tiles are summed in LDS in a fixed order (deterministic).
-// Batched over blockIdx.z with strides.
+// Products with a long reduction: C = alpha op(A) diag(d) op(B) + beta C
+// with op(A) op(B) = A^T B (L = 0), A B^T (L = 1) or A B (L = 2),
+// column-major operands, d (length K, optional) scaling the reduction index.
+// One workgroup per 32 x 32 output tile; its sixteen wavefronts split K in
+// interleaved chunks of 16 on the FP64 matrix core (16x16x4), each loading
+// the operands of a chunk (four steps) before issuing their products, so
+// that the sixteen wavefronts keep sixteen chunks in flight; operands go
+// straight from memory into the matrix-core lane layout (lane l: row/column
+// l % 16, k = l / 16), and the partial tiles are summed in LDS in a fixed
+// order (deterministic).  Batched over blockIdx.z with strides (d advances
+// by strideD per batch entry).
 constexpr int GR_WAVES = 16;
 constexpr int GR_DEPTH = 1;   // chunks loaded per wavefront before computing
 
@@ -317,6 +317,7 @@ __device__ __forceinline__ void gram_tile(const GemmArgs& g, int tile, long b) {
     const int i0 = (tile % tilesM) * 32, j0 = (tile / tilesM) * 32;
     const double* __restrict__ A = g.A + b * g.strideA;
     const double* __restrict__ B = g.B + b * g.strideB;
+    const double* __restrict__ d = g.d ? g.d + b * g.strideD : nullptr;
     double* __restrict__ C = g.C + b * g.strideC;
     const int r16 = lane & 15, kq = lane >> 4;
     const int ia0 = i0 + r16, ia1 = i0 + 16 + r16;
@@ -343,6 +344,11 @@ __device__ __forceinline__ void gram_tile(const GemmArgs& g, int tile, long b) {
             a1[u] = (vk && va1) ? a1p[k * sa] : 0.0;
             b0[u] = (vk && vb0) ? b0p[k * sb] : 0.0;
             b1[u] = (vk && vb1) ? b1p[k * sb] : 0.0;
+            if (d) {
+                const double dk = vk ? d[k] : 0.0;
+                b0[u] *= dk;
+                b1[u] *= dk;
+            }
         }
 #pragma unroll
         for (int u = 0; u < 4 * GR_DEPTH; ++u) {
@@ -378,21 +384,198 @@ __global__ __launch_bounds__(64 * GR_WAVES) void gram_kernel(GemmArgs g) {
     gram_tile<L>(g, blockIdx.x, blockIdx.z);
 }
 
-// Up to kMaxGramJobs independent products (each unbatched) in one launch:
-// grid.y picks the product, blocks beyond its tile count return at once.
+// Up to kMaxGramJobs independent products (each possibly a strided batch)
+// in one launch: grid.y picks the product, grid.x runs over its tiles times
+// its batch; blocks beyond a product's own count return at once.
 template <int L>
 __global__ __launch_bounds__(64 * GR_WAVES) void gram_multi_kernel(GramJobs jobs) {
     const GemmArgs& g = jobs.g[blockIdx.y];
     const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
-    if ((int)blockIdx.x >= tiles) return;
-    gram_tile<L>(g, blockIdx.x, 0);
+    if ((long)blockIdx.x >= (long)tiles * g.batch) return;
+    gram_tile<L>(g, (int)(blockIdx.x % tiles), (long)(blockIdx.x / tiles));
+}
+
+// ---------------------------------------------------------------------------
+// Streaming products with a long reduction and a small right or output
+// side: C = alpha op(A) op(B) + beta C with op(A) op(B) = A^T B (L = 0),
+// A B^T (L = 1) or A B (L = 2), up to three jobs per launch.  This carries
+// the mode transforms (A the n x n eigenvector matrix of a mode, stored as
+// V or V^T so that A is read along its columns; B n x m) and the Gram-type
+// products whose few output tiles would leave the GPU idle.  A workgroup of
+// four wavefronts owns 32 rows of C and a chunk of KC values of K (every
+// wavefront KC / 4 of them): each lane loads all of its A operands of the
+// chunk (2 rows x STEPS steps of 4) before its first product, so the whole A
+// panel is requested at once; the products run on the FP64 matrix core
+// (16x16x4) for every 32-column block of C in turn (the upper 16 columns
+// only where C has them), with the A operands in registers.  The four
+// partial tiles are summed in LDS in a fixed order.  With K split over
+// several chunks the partial tiles go to `part`, and the last workgroup of a
+// row block to finish (a counter per row block, reset by that workgroup)
+// adds them in chunk order, so the result does not depend on the schedule.
+// One thread per workgroup issues the device-scope fence: a fence costs a
+// write-back of the XCD's L2, so one per thread would cost a launch's
+// worth of time.
+constexpr int TR_WAVES = 4;
+
+template <int L, int STEPS>
+__global__ __launch_bounds__(64 * TR_WAVES) void stream_kernel(StreamJobs jobs, int ksplit,
+                                                               double* part, long pstride,
+                                                               unsigned* counters, int rbmax) {
+    constexpr int KC = 4 * STEPS * TR_WAVES;
+    __shared__ double red[TR_WAVES][4][4][64];
+    __shared__ int last;
+    const StreamJob& J = jobs.job[blockIdx.y];
+    const int rblocks = (J.M + 31) / 32;
+    const int rb = blockIdx.x / ksplit, kz = blockIdx.x % ksplit;
+    if (rb >= rblocks) return;
+    const int i0 = rb * 32;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int ia0 = i0 + r16, ia1 = i0 + 16 + r16;
+    const bool va0 = ia0 < J.M, va1 = ia1 < J.M;
+    const int m = J.N;
+    const bool split = ksplit > 1;
+    double* __restrict__ out = split ? part + ((long)blockIdx.y * ksplit + kz) * pstride : J.C;
+    const long ldo = split ? J.M : J.ldc;
+    // element (i, k) of op(A) and (k, j) of op(B)
+    const long sa_i = (L == 0) ? J.lda : 1, sa_k = (L == 0) ? 1 : J.lda;
+    const long sb_k = (L == 1) ? J.ldb : 1, sb_j = (L == 1) ? 1 : J.ldb;
+    const int kend = min(J.K, (kz + 1) * KC);
+    const int kw = kz * KC + 4 * STEPS * wave;   // this wavefront's first k
+    double a0[STEPS], a1[STEPS];
+#pragma unroll
+    for (int u = 0; u < STEPS; ++u) {
+        const int k = kw + 4 * u + kq;
+        const bool vk = k < kend;
+        a0[u] = (vk && va0) ? J.A[ia0 * sa_i + k * sa_k] : 0.0;
+        a1[u] = (vk && va1) ? J.A[ia1 * sa_i + k * sa_k] : 0.0;
+    }
+    for (int c0 = 0; c0 < m; c0 += 32) {
+        const int jb0 = c0 + r16, jb1 = c0 + 16 + r16;
+        const bool vb0 = jb0 < m, vb1 = jb1 < m;
+        const bool hi = c0 + 16 < m;   // the block's upper 16 columns exist
+        dbl4 acc[2][2];
+        for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+        double b0[STEPS], b1[STEPS];
+#pragma unroll
+        for (int u = 0; u < STEPS; ++u) {
+            const int k = kw + 4 * u + kq;
+            const bool vk = k < kend;
+            b0[u] = (vk && vb0) ? J.B[k * sb_k + jb0 * sb_j] : 0.0;
+            b1[u] = (hi && vk && vb1) ? J.B[k * sb_k + jb1 * sb_j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < STEPS; ++u) {
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u], acc[0][0], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b0[u], acc[1][0], 0, 0, 0);
+        }
+        if (hi) {
+#pragma unroll
+            for (int u = 0; u < STEPS; ++u) {
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b1[u], acc[0][1], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u], acc[1][1], 0, 0, 0);
+            }
+        }
+        // sum the wavefronts' tiles in a fixed order
+        for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y)
+                for (int v = 0; v < 4; ++v) red[wave][2 * x + y][v][lane] = acc[x][y][v];
+        __syncthreads();
+        for (int e = threadIdx.x; e < 4 * 4 * 64; e += 64 * TR_WAVES) {
+            const int l = e & 63, v = (e >> 6) & 3, blk = e >> 8;
+            const int x = blk >> 1, y = blk & 1;
+            double sum = 0.0;
+            for (int w = 0; w < TR_WAVES; ++w) sum += red[w][blk][v][l];
+            const int i = i0 + 16 * x + (l >> 4) + 4 * v, c = c0 + 16 * y + (l & 15);
+            if (i < J.M && c < m) {
+                double* o = out + i + ldo * c;
+                *o = split ? sum : J.alpha * sum + (J.beta != 0.0 ? J.beta * *o : 0.0);
+            }
+        }
+        __syncthreads();
+    }
+    if (!split) return;
+    // the partial tile is written (and ordered for this workgroup by the
+    // barrier above); publish it and count in
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(counters + (long)blockIdx.y * rbmax + rb, 1u) == (unsigned)ksplit - 1;
+        if (last) __threadfence();
+    }
+    __syncthreads();
+    if (!last) return;
+    const double* pj = part + (long)blockIdx.y * ksplit * pstride;
+    for (int e = threadIdx.x; e < 32 * m; e += 64 * TR_WAVES) {
+        const int i = i0 + (e & 31), c = e >> 5;
+        if (i >= J.M) continue;
+        double sum = 0.0;
+        for (int z = 0; z < ksplit; ++z)
+            sum += __hip_atomic_load(pj + z * pstride + i + (long)J.M * c, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        double* o = J.C + i + J.ldc * c;
+        *o = J.alpha * sum + (J.beta != 0.0 ? J.beta * *o : 0.0);
+    }
+    if (threadIdx.x == 0) atomicExch(counters + (long)blockIdx.y * rbmax + rb, 0u);
+}
+
+template <int L>
+static void stream_launch(int kc, const StreamJobs& jobs, int rbmax, int ksplit, double* part,
+                          long pstride, unsigned* counters, hipStream_t s) {
+    const dim3 grid(rbmax * ksplit, jobs.count), block(64 * TR_WAVES);
+    if (kc == 128)
+        hipLaunchKernelGGL((stream_kernel<L, 8>), grid, block, 0, s, jobs, ksplit, part, pstride,
+                           counters, rbmax);
+    else
+        hipLaunchKernelGGL((stream_kernel<L, 16>), grid, block, 0, s, jobs, ksplit, part, pstride,
+                           counters, rbmax);
+}
+
+hipError_t stream_multi(int layout, const StreamJobs& jobs, int kc, double* part, long part_cap,
+                        unsigned* counters, long counter_cap, hipStream_t s) {
+    if (jobs.count <= 0) return hipSuccess;
+    if (jobs.count > 3 || layout < 0 || layout > 2 || (kc != 128 && kc != 256))
+        return hipErrorInvalidValue;
+    int kmax = 0, rbmax = 0;
+    long pmax = 0;
+    for (int t = 0; t < jobs.count; ++t) {
+        const StreamJob& J = jobs.job[t];
+        if (J.M <= 0 || J.N <= 0 || J.K <= 0 || !J.A || !J.B || !J.C) return hipErrorInvalidValue;
+        kmax = std::max(kmax, J.K);
+        rbmax = std::max(rbmax, (J.M + 31) / 32);
+        pmax = std::max(pmax, (long)J.M * J.N);
+    }
+    const int ksplit = (kmax + kc - 1) / kc;
+    if (ksplit > 1 && (!part || !counters || (long)jobs.count * ksplit * pmax > part_cap ||
+                       (long)jobs.count * rbmax > counter_cap))
+        return hipErrorInvalidValue;   // the caller checks stream_fits first
+    if (layout == 0)
+        stream_launch<0>(kc, jobs, rbmax, ksplit, part, pmax, counters, s);
+    else if (layout == 1)
+        stream_launch<1>(kc, jobs, rbmax, ksplit, part, pmax, counters, s);
+    else
+        stream_launch<2>(kc, jobs, rbmax, ksplit, part, pmax, counters, s);
+    return hipGetLastError();
+}
+
+bool stream_fits(const StreamJobs& jobs, int kc, long part_cap, long counter_cap) {
+    int kmax = 0, rbmax = 0;
+    long pmax = 0;
+    for (int t = 0; t < jobs.count; ++t) {
+        kmax = std::max(kmax, jobs.job[t].K);
+        rbmax = std::max(rbmax, (jobs.job[t].M + 31) / 32);
+        pmax = std::max(pmax, (long)jobs.job[t].M * jobs.job[t].N);
+    }
+    const int ksplit = (kmax + kc - 1) / kc;
+    return ksplit <= 1 ||
+           ((long)jobs.count * ksplit * pmax <= part_cap && (long)jobs.count * rbmax <= counter_cap);
 }
 
 hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    if (g.M > 128 || g.N > 128 || g.inner != 1 || g.d || g.lowp || g.K <= 0 || (transA && transB))
-        return hipErrorInvalidValue;
-    const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
+    if (g.inner != 1 || g.lowp || g.K <= 0 || (transA && transB)) return hipErrorInvalidValue;
+    const long tiles = (long)((g.M + 31) / 32) * ((g.N + 31) / 32);
+    if (tiles > 0x7fffffffL || g.batch > 65535) return hipErrorInvalidValue;
     const dim3 grid(tiles, 1, g.batch), block(64 * GR_WAVES);
     const size_t lds = sizeof(double) * GR_WAVES * 4 * 4 * 64;   // 128 KiB
     static std::once_flag once;
@@ -419,14 +602,14 @@ hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s) {
 hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s) {
     if (jobs.count <= 0) return hipSuccess;
     if (jobs.count > kMaxGramJobs || (transA && transB)) return hipErrorInvalidValue;
-    int tiles = 0;
+    long tiles = 0;
     for (int t = 0; t < jobs.count; ++t) {
         const GemmArgs& g = jobs.g[t];
-        if (g.M <= 0 || g.N <= 0 || g.M > 128 || g.N > 128 || g.K <= 0 || g.batch != 1 ||
-            g.inner != 1 || g.d || g.lowp)
+        if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch < 1 || g.inner != 1 || g.lowp)
             return hipErrorInvalidValue;
-        tiles = std::max(tiles, ((g.M + 31) / 32) * ((g.N + 31) / 32));
+        tiles = std::max(tiles, (long)((g.M + 31) / 32) * ((g.N + 31) / 32) * g.batch);
     }
+    if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * GR_WAVES * 4 * 4 * 64;   // 128 KiB
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
@@ -440,13 +623,111 @@ hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_
         }
     });
     if (attr_err != hipSuccess) return attr_err;
-    const dim3 grid(tiles, jobs.count), block(64 * GR_WAVES);
+    const dim3 grid((unsigned)tiles, jobs.count), block(64 * GR_WAVES);
     if (transA)
         hipLaunchKernelGGL(gram_multi_kernel<0>, grid, block, lds, s, jobs);
     else if (transB)
         hipLaunchKernelGGL(gram_multi_kernel<1>, grid, block, lds, s, jobs);
     else
         hipLaunchKernelGGL(gram_multi_kernel<2>, grid, block, lds, s, jobs);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused application of a separable diagonal scaling to the Tucker basis:
+//   out[i, c] = sum_q sum_j Z[i, j] D[i, q] T^q[j, c]
+// (i < n, c < p, j < r, q < Q; T^q the r x p block at T + q r p, ld r), i.e.
+// out = sum_q diag(D[:, q]) Z T^q: a product over the reduction index (q, j)
+// whose left operand, the row-wise Kronecker product Z[i, j] D[i, q], is
+// formed in registers and never stored.  Tiles and reduction as in
+// gram_tile: one workgroup per 32 x 32 output tile, the sixteen wavefronts
+// take the terms q in turn, partial tiles summed in LDS in a fixed order.
+__device__ __forceinline__ void kron_tile(int n, int Q, const KronJob& J, int tile) {
+    extern __shared__ double gram_red[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tilesM = (n + 31) / 32;
+    const int i0 = (tile % tilesM) * 32, c0 = (tile / tilesM) * 32;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int ia0 = i0 + r16, ia1 = i0 + 16 + r16;
+    const int cb0 = c0 + r16, cb1 = c0 + 16 + r16;
+    const bool va0 = ia0 < n, va1 = ia1 < n, vb0 = cb0 < J.p, vb1 = cb1 < J.p;
+    const int r = J.r;
+    const long rp = (long)r * J.p;
+    const double* __restrict__ z0p = J.Z + (va0 ? ia0 : 0);
+    const double* __restrict__ z1p = J.Z + (va1 ? ia1 : 0);
+    const double* __restrict__ t0p = J.T + (vb0 ? (long)r * cb0 : 0);
+    const double* __restrict__ t1p = J.T + (vb1 ? (long)r * cb1 : 0);
+    dbl4 acc[2][2];
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int steps = (r + 3) / 4;
+    for (int q = wave; q < Q; q += GR_WAVES) {
+        const double d0 = va0 ? J.D[ia0 + (long)n * q] : 0.0;
+        const double d1 = va1 ? J.D[ia1 + (long)n * q] : 0.0;
+        const double* __restrict__ tq0 = t0p + rp * q;
+        const double* __restrict__ tq1 = t1p + rp * q;
+        for (int s0 = 0; s0 < steps; s0 += 4) {
+            double a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = 4 * (s0 + u) + kq;
+                const bool vk = k < r;
+                a0[u] = vk ? z0p[(long)J.ldz * k] * d0 : 0.0;
+                a1[u] = vk ? z1p[(long)J.ldz * k] * d1 : 0.0;
+                b0[u] = (vk && vb0) ? tq0[k] : 0.0;
+                b1[u] = (vk && vb1) ? tq1[k] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u], acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b1[u], acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b0[u], acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u], acc[1][1], 0, 0, 0);
+            }
+        }
+    }
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y)
+            for (int v = 0; v < 4; ++v)
+                gram_red[((wave * 4 + 2 * x + y) * 4 + v) * 64 + lane] = acc[x][y][v];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * 2 * 4 * 64; e += 64 * GR_WAVES) {
+        const int l = e & 63, v = (e >> 6) & 3, blk = e >> 8;
+        const int x = blk >> 1, y = blk & 1;
+        double sum = 0.0;
+        for (int w = 0; w < GR_WAVES; ++w) sum += gram_red[((w * 4 + blk) * 4 + v) * 64 + l];
+        const int i = i0 + 16 * x + (l >> 4) + 4 * v, c = c0 + 16 * y + (l & 15);
+        if (i < n && c < J.p) J.out[i + J.ldo * c] = sum;
+    }
+}
+
+__global__ __launch_bounds__(64 * GR_WAVES) void kron_apply_kernel(int n, int Q, KronJobs jobs) {
+    const KronJob& J = jobs.job[blockIdx.y];
+    const int tiles = ((n + 31) / 32) * ((J.p + 31) / 32);
+    if ((int)blockIdx.x >= tiles) return;
+    kron_tile(n, Q, J, (int)blockIdx.x);
+}
+
+hipError_t kron_apply_multi(int n, int Q, const KronJobs& jobs, hipStream_t s) {
+    if (jobs.count <= 0) return hipSuccess;
+    if (jobs.count > kMaxPanelJobs || n <= 0 || Q <= 0) return hipErrorInvalidValue;
+    int tiles = 0;
+    for (int t = 0; t < jobs.count; ++t) {
+        const KronJob& J = jobs.job[t];
+        if (J.r <= 0 || J.p <= 0 || !J.Z || !J.D || !J.T || !J.out || J.ldz < n || J.ldo < n)
+            return hipErrorInvalidValue;
+        tiles = std::max(tiles, ((n + 31) / 32) * ((J.p + 31) / 32));
+    }
+    const size_t lds = sizeof(double) * GR_WAVES * 4 * 4 * 64;   // 128 KiB
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [lds] {
+        attr_err = hipFuncSetAttribute((const void*)kron_apply_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    });
+    if (attr_err != hipSuccess) return attr_err;
+    hipLaunchKernelGGL(kron_apply_kernel, dim3(tiles, jobs.count), dim3(64 * GR_WAVES), lds, s, n,
+                       Q, jobs);
     return hipGetLastError();
 }
 
@@ -996,6 +1277,217 @@ hipError_t sym_eig(int k, int batch, const double* A, long lda, long strideA, do
     if (attr_err != hipSuccess) return attr_err;
     hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(JAC_THREADS), shm, s, k, A, lda, strideA,
                        evals, V, ldv, strideV, scratch);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Tucker-to-canonical term selection (Appendix 1, the T2C step).  The
+// candidate terms are the (slice nu, singular value j) pairs of the mode-3
+// slices of an all-orthogonal core, with energies sig2[nu * r1 + j]
+// (negative rounding clamped to 0).  Ordered by (energy, nu, j) ascending,
+// the smallest are dropped while the cumulative dropped energy stays within
+// budget2; the kept ones go to keep[t], t < K, in descending order, and K to
+// *count.  One workgroup: a bitonic sort of (energy bits, index) pairs (the
+// bit pattern of a non-negative double orders like its value), in LDS up to
+// kT2cLds terms and in `scratch` beyond, then a block scan of the sorted
+// energies in a fixed order.
+constexpr int T2C_THREADS = 1024;
+constexpr int kT2cLds = 8192;
+
+__global__ __launch_bounds__(T2C_THREADS) void t2c_select_kernel(int N, int Np,
+                                                                 const double* __restrict__ sig2,
+                                                                 double budget2,
+                                                                 unsigned long long* gkey,
+                                                                 unsigned* gidx, int* keep,
+                                                                 int* count) {
+    extern __shared__ unsigned long long t2c_lds[];
+    __shared__ double part[T2C_THREADS];
+    __shared__ int cnt[T2C_THREADS];
+    const int tid = threadIdx.x;
+    unsigned long long* key = gkey ? gkey : t2c_lds;
+    unsigned* idx = gidx ? gidx : (unsigned*)(t2c_lds + Np);
+    for (int i = tid; i < Np; i += T2C_THREADS) {
+        if (i < N) {
+            const double v = sig2[i] > 0.0 ? sig2[i] : 0.0;
+            key[i] = (unsigned long long)__double_as_longlong(v);
+            idx[i] = (unsigned)i;
+        } else {
+            key[i] = ~0ULL;
+            idx[i] = 0xffffffffu;
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= Np; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < Np; i += T2C_THREADS) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const bool gt = key[i] > key[l] || (key[i] == key[l] && idx[i] > idx[l]);
+                    if (gt == up) {
+                        const unsigned long long tk = key[i];
+                        key[i] = key[l];
+                        key[l] = tk;
+                        const unsigned ti = idx[i];
+                        idx[i] = idx[l];
+                        idx[l] = ti;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // inclusive prefix sums of the sorted energies: contiguous chunks per
+    // thread, then a scan of the chunk sums; count the prefixes within budget
+    const int chunk = (N + T2C_THREADS - 1) / T2C_THREADS;
+    const int b0 = min(N, tid * chunk), b1 = min(N, b0 + chunk);
+    double loc = 0.0;
+    for (int i = b0; i < b1; ++i) loc += __longlong_as_double((long long)key[i]);
+    part[tid] = loc;
+    __syncthreads();
+    for (int off = 1; off < T2C_THREADS; off <<= 1) {
+        const double add = tid >= off ? part[tid - off] : 0.0;
+        __syncthreads();
+        part[tid] += add;
+        __syncthreads();
+    }
+    double run = tid > 0 ? part[tid - 1] : 0.0;
+    int dropped = 0;
+    for (int i = b0; i < b1; ++i) {
+        run += __longlong_as_double((long long)key[i]);
+        if (run <= budget2) ++dropped;
+    }
+    cnt[tid] = dropped;
+    __syncthreads();
+    for (int off = T2C_THREADS / 2; off > 0; off >>= 1) {
+        if (tid < off) cnt[tid] += cnt[tid + off];
+        __syncthreads();
+    }
+    const int K = N - cnt[0];
+    for (int t = tid; t < K; t += T2C_THREADS) keep[t] = (int)idx[N - 1 - t];
+    if (tid == 0) *count = K;
+}
+
+hipError_t t2c_select(int N, const double* sig2, double budget2, void* scratch, int* keep,
+                      int* count, hipStream_t s) {
+    if (N <= 0 || N > kT2cMaxTerms) return hipErrorInvalidValue;
+    int Np = 1;
+    while (Np < N) Np <<= 1;
+    size_t lds = 0;
+    unsigned long long* gkey = nullptr;
+    unsigned* gidx = nullptr;
+    if (Np <= kT2cLds) {
+        lds = (sizeof(unsigned long long) + sizeof(unsigned)) * (size_t)Np;
+    } else {
+        gkey = (unsigned long long*)scratch;
+        gidx = (unsigned*)(gkey + Np);
+    }
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [] {
+        attr_err = hipFuncSetAttribute((const void*)t2c_select_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)((sizeof(unsigned long long) + sizeof(unsigned)) * kT2cLds));
+    });
+    if (attr_err != hipSuccess) return attr_err;
+    hipLaunchKernelGGL(t2c_select_kernel, dim3(1), dim3(T2C_THREADS), lds, s, N, Np, sig2, budget2,
+                       gkey, gidx, keep, count);
+    return hipGetLastError();
+}
+
+// Canonical factors of the kept T2C terms: for term t = (nu, j), with v the
+// j-th eigenvector of the nu-th slice Gram (column j of the r1 x r1 block
+// at V + nu r1 r1), g = core[:, :, nu] v; c0[:, t] = g / |g|, c1[:, t] = v,
+// c2[:, t] = e_nu, w[t] = |g| (or the singular value when g vanishes).  One
+// wavefront per term.
+__global__ __launch_bounds__(256) void t2c_coef_kernel(int r0, int r1, int r2, int K,
+                                                       const double* __restrict__ core,
+                                                       const double* __restrict__ V,
+                                                       const double* __restrict__ ev,
+                                                       const int* __restrict__ keep,
+                                                       double* __restrict__ c0,
+                                                       double* __restrict__ c1,
+                                                       double* __restrict__ c2,
+                                                       double* __restrict__ w) {
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= K) return;
+    const int e = keep[t];
+    const int nu = e / r1, j = e % r1;
+    const double* v = V + (long)nu * r1 * r1 + (long)j * r1;
+    const double* cs = core + (long)r0 * r1 * nu;
+    double g[2] = {0.0, 0.0};
+    for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        if (i < r0) {
+            double acc = 0.0;
+            for (int jj = 0; jj < r1; ++jj) acc += cs[i + (long)r0 * jj] * v[jj];
+            g[h] = acc;
+        }
+    }
+    const double nrm = sqrt(wave_sum(g[0] * g[0] + g[1] * g[1]));
+    for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        if (i < r0) c0[(long)t * r0 + i] = nrm > 0.0 ? g[h] / nrm : 0.0;
+    }
+    for (int jj = lane; jj < r1; jj += 64) c1[(long)t * r1 + jj] = v[jj];
+    for (int q = lane; q < r2; q += 64) c2[(long)t * r2 + q] = q == nu ? 1.0 : 0.0;
+    if (lane == 0) {
+        const double s2 = ev[e] > 0.0 ? ev[e] : 0.0;
+        w[t] = nrm > 0.0 ? nrm : sqrt(s2);
+    }
+}
+
+hipError_t t2c_coef(int r0, int r1, int r2, int K, const double* core, const double* V,
+                    const double* ev, const int* keep, double* c0, double* c1, double* c2,
+                    double* w, hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    if (r0 > 128 || r0 <= 0 || r1 <= 0 || r2 <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(t2c_coef_kernel, dim3((K + 3) / 4), dim3(256), 0, s, r0, r1, r2, K, core, V,
+                       ev, keep, c0, c1, c2, w);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Probe sums of the projection check of the Hadamard truncation: for two
+// problems (blockIdx.y) and S probes (blockIdx.x),
+//   out[2 t + y] = sum_q sum_k U2_t[k, q] sum_j M_t[j + r1 k + r1 r2 q] U1_t[j, q]
+// (M_t at M + t mstride; U1_t r1 x Q at U1 + t r1 Q; U2_t r2 x Q at U2 + t r2 Q).
+// Wavefronts take the (q, k) pairs in turn, lanes the index j (r1 <= 128);
+// the lane sums are added in a fixed order at the end.
+constexpr int PB_THREADS = 1024;
+__global__ __launch_bounds__(PB_THREADS) void probe_sum_kernel(ProbeSums a) {
+    __shared__ double red[PB_THREADS / 64];
+    const ProbeSum& P = a.p[blockIdx.y];
+    const int t = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long rr = (long)P.r1 * P.r2;
+    const double* M = P.M + (long)t * P.mstride;
+    const double* U1 = P.U1 + (long)t * P.r1 * P.Q;
+    const double* U2 = P.U2 + (long)t * P.r2 * P.Q;
+    double acc = 0.0;
+    for (long qk = wave; qk < (long)P.r2 * P.Q; qk += PB_THREADS / 64) {
+        const int k = (int)(qk % P.r2), q = (int)(qk / P.r2);
+        const double u2 = U2[k + (long)P.r2 * q];
+        const double* Mc = M + (long)P.r1 * k + rr * q;
+        const double* u1 = U1 + (long)P.r1 * q;
+        for (int j = lane; j < P.r1; j += 64) acc += u2 * Mc[j] * u1[j];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) red[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < PB_THREADS / 64; ++w) sum += red[w];
+        a.out[2 * t + blockIdx.y] = sum;
+    }
+}
+
+hipError_t probe_sums(const ProbeSums& a, int S, hipStream_t s) {
+    if (S <= 0) return hipSuccess;
+    for (int y = 0; y < 2; ++y)
+        if (a.p[y].r1 <= 0 || a.p[y].r2 <= 0 || a.p[y].Q <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(probe_sum_kernel, dim3(S, 2), dim3(PB_THREADS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -121,6 +121,10 @@ struct fc_plan_s {
     std::vector<double> lam[3];   // host eigenvalues
     std::vector<double> Vh[3];    // host eigenvectors
     double* V[3] = {nullptr, nullptr, nullptr};
+    // V_l^T stored as well (n x n each), so that both transform directions
+    // read their matrix along columns (coalesced): HBM is plentiful, the
+    // transforms are bandwidth-bound
+    double* Vt[3] = {nullptr, nullptr, nullptr};
     Separable op, pc, st;   // operator ~ f, preconditioner ~ 1/f, state map ~ beta s^-alpha
     double op_err = 0, pc_err = 0, st_err = 0;
     // preconditioner case (A): 1/f on the spectrum of the anisotropic
@@ -135,18 +139,21 @@ struct fc_plan_s {
     Separable pcA;
     double pcA_err = 0;
     double* Wsin[3] = {nullptr, nullptr, nullptr};
+    double* WsinT[3] = {nullptr, nullptr, nullptr};   // W_l^T
     Arena arena;
     // workspace
     Tucker slot[14];
     fc_precision precision = FC_FP64;
     double *E = nullptr, *Gd[3] = {}, *Mq = nullptr, *c1 = nullptr, *c2 = nullptr;
-    double *Xs = nullptr, *HX = nullptr, *Ys = nullptr, *Ts = nullptr, *F = nullptr;
+    double *Xs = nullptr, *HX = nullptr, *Ys = nullptr, *Ts = nullptr;
     double *Bp = nullptr, *Ev = nullptr, *Evec = nullptr, *W[3] = {}, *As[3] = {};
     double *T1 = nullptr, *T2 = nullptr, *C = nullptr, *Cp = nullptr, *Cg = nullptr;
     double *Cev = nullptr, *Cvec = nullptr, *Cn1 = nullptr, *Cn2 = nullptr;
     double *Phi[3] = {}, *Map = nullptr, *scal = nullptr, *tmpn = nullptr, *tmpn2 = nullptr;
     double *cw = nullptr, *cf[3] = {}, *Yh[3] = {};
     int* icount = nullptr;
+    int* t2c_keep = nullptr;   // kept T2C term indices (rcap^2)
+    void* t2c_ws = nullptr;    // T2C sort scratch beyond the LDS capacity
     double* jac = nullptr;
     WarmBasis warm[NSITES];
     double *qrN = nullptr, *qrC = nullptr;
@@ -160,21 +167,22 @@ struct fc_plan_s {
     long cap_canon = 0;
     int* dflag = nullptr;
     unsigned* dotcnt = nullptr;   // zero between calls of the device dot
+    unsigned* trcount = nullptr;  // row-block counters of the streaming kernel (zero between calls)
+    long trcount_cap = 0;
     long ys_cap = 0;              // doubles in Ys and in Ts
-    long e_cap = 0, f_cap = 0;    // doubles in E and in F
+    long e_cap = 0;               // doubles in E
     hipStream_t stream = nullptr;
     // statistics of the last solve
     int max_seen_rank = 0;
+    double worst_missed = 0;   // largest missed-energy charge / budget of a Hadamard truncation
     double site_ms[16] = {};   // wall time per truncation site (with FC_TRACE)
     int site_calls[16] = {};
     std::mutex use_mu;   // one solve at a time per plan
-    rocblas_handle blas = nullptr;   // plain FP64 GEMMs (own workspace, no atomics)
     // pinned host landing area for the small device-to-host reads of a solve
     // (ranks, spectra, scalars): a direct copy, no pageable staging
     static constexpr size_t kPinnedBytes = 64 * 1024;
     void* pinned = nullptr;
     ~fc_plan_s() {
-        if (blas) rocblas_destroy_handle(blas);
         if (pinned) (void)hipHostFree(pinned);
     }
 };
@@ -200,6 +208,8 @@ struct GemmShape {
     bool ta, tb;
     int M, N, K, batch, inner;
     bool lowp;
+    int kind;   // profile kind of the launch (see KernelProfile)
+    double flops, bytes;
 };
 struct GemmProfile {
     bool on = false;
@@ -213,15 +223,48 @@ GemmProfile g_prof;
 std::mutex g_prof_mu;
 thread_local bool t_no_profile = false;   // set in batch workers
 
-// The same HIP-event timing for the Gram-Schmidt panel kernel (kind 1) and
-// the eigensolver (kind 2), enabled together with the GEMM timing.
+// Profile kinds: the products are split into the short-reduction LDS-tiled
+// GEMMs (0), the mode transforms V^T Y, V Z (3), the long-reduction Gram
+// engine (4: Gram-type products, scaled Grams, core contractions) and the
+// fused Kronecker application (5), all timed through the GEMM profile; the
+// Gram-Schmidt panel kernel (1) and the eigensolver (2) have event pairs of
+// their own, enabled together with the GEMM timing.
+constexpr int kProfKinds = 6;
+thread_local int t_tag = -1;   // kind override for the launches of a scope
+struct KindTag {
+    int saved;
+    explicit KindTag(int k) : saved(t_tag) { t_tag = k; }
+    ~KindTag() { t_tag = saved; }
+};
 struct KernelProfile {
     std::vector<hipEvent_t> ev;
     size_t used = 0;
     double flops = 0, bytes = 0;
     long launches = 0;
 };
-KernelProfile k_prof[3];
+KernelProfile k_prof[kProfKinds];
+
+// Event pair around one product-type launch, with its shape and work
+// (profile on, not a batch worker).
+template <class F>
+void record_product(hipStream_t s, const GemmShape& shape, F&& launch) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (g_prof.used + 2 > g_prof.ev.size()) {
+        for (int i = 0; i < 256; ++i) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            g_prof.ev.push_back(e);
+        }
+    }
+    HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], s));
+    HIPCHK(launch());
+    HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], s));
+    g_prof.used += 2;
+    g_prof.shapes.push_back(shape);
+    g_prof.flops += shape.flops;
+    g_prof.bytes += shape.bytes;
+    g_prof.launches += 1;
+}
 
 // algorithmic work of a batch of symmetric eigenproblems: Householder
 // tridiagonalisation 4/3 k^3 and back-transformation 2 k^2 k flops per
@@ -267,33 +310,96 @@ struct Ctx {
     bool clamp = false;  // search directions: cap HOSVD ranks at max_rank instead of failing
 };
 
-// Route one product: Gram-type (a small result: any A^T B, and A B^T or A B
-// over a long reduction) to the hand-written split-over-waves kernel, other
-// plain FP64 products to
-// rocBLAS, and the rest (diagonal scaling, two-level batches, FP32 cores)
-// to the library's MFMA GEMM.
+// Algorithmic work of one product: 2 M N K flops per batch entry; each
+// operand read once (once in all when shared by the batch, stride 0), the
+// result written once.
+double prod_flops(const GemmArgs& g) { return 2.0 * g.M * g.N * (double)g.K * g.batch; }
+double prod_bytes(const GemmArgs& g) {
+    const double nb = g.batch;
+    const bool two = g.inner > 1;
+    const double a = (double)g.M * g.K * ((g.strideA || (two && g.strideAin)) ? nb : 1.0);
+    const double b = (double)g.K * g.N * ((g.strideB || (two && g.strideBin)) ? nb : 1.0);
+    const double dd = g.d ? (double)g.K * (g.strideD ? nb : 1.0) : 0.0;
+    return 8.0 * (a + b + dd + (double)g.M * g.N * nb);
+}
+
+// Gram-type products go to the split-over-waves kernel: every FP64 product
+// over a reduction of at least 256 (the mode transforms V^T Y and V Z, the
+// diagonally scaled Grams Z^T diag(d) X of the Hadamard truncation, the
+// long contractions of the core), and the unbatched A^T B with a small
+// result (M, N <= 128).  Not A^T B^T, not two-level batches.
+bool gram_type(bool ta, bool tb, const GemmArgs& g) {
+    if (g.lowp || g.inner != 1 || g.K <= 0 || (ta && tb)) return false;
+    if (g.K >= 256) return true;
+    return !g.d && g.batch == 1 && g.M <= 128 && g.N <= 128 && ta;
+}
+
+// A mode transform: C = A B with A the n x n matrix of a mode (M = K = n),
+// FP64, unbatched, alpha = 1, beta = 0.
+bool is_transform(const Ctx& c, bool ta, bool tb, const GemmArgs& g) {
+    return !ta && !tb && !g.d && !g.lowp && g.inner == 1 && g.batch == 1 && g.M == c.n &&
+           g.K == c.n && g.alpha == 1.0 && g.beta == 0.0 && g.N > 0;
+}
+
+// Products for the streaming kernel: the mode transforms, and the unbatched
+// Gram-type products with at most 128 x 128 outputs (few output tiles: K is
+// split over workgroups instead).
+int stream_layout(bool ta, bool tb) { return ta ? 0 : (tb ? 1 : 2); }
+bool streamable(bool ta, bool tb, const GemmArgs& g) {
+    return gram_type(ta, tb, g) && !g.d && g.batch == 1 && (long)g.M * g.N <= 128L * 128;
+}
+
+// Up to three products in one launch of the streaming kernel (split-K
+// partials in the plan's GEMM workspace).
+hipError_t run_stream(const Ctx& c, bool ta, bool tb, const GemmArgs* g, int count) {
+    fc::StreamJobs sj;
+    for (int t = 0; t < count; ++t) {
+        fc::StreamJob& J = sj.job[sj.count++];
+        J.M = g[t].M; J.N = g[t].N; J.K = g[t].K;
+        J.alpha = g[t].alpha; J.beta = g[t].beta;
+        J.A = g[t].A; J.lda = g[t].lda;
+        J.B = g[t].B; J.ldb = g[t].ldb;
+        J.C = g[t].C; J.ldc = g[t].ldc;
+    }
+    fc_plan_s* p = c.p;
+    const int kc = fc::stream_fits(sj, 128, p->splitws_cap, p->trcount_cap) ? 128 : 256;
+    if (!fc::stream_fits(sj, kc, p->splitws_cap, p->trcount_cap)) {
+        // partials beyond the workspace: the Gram kernel, one product at a time
+        for (int t = 0; t < count; ++t) {
+            const hipError_t e = fc::gram(ta, tb, g[t], c.s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    return fc::stream_multi(stream_layout(ta, tb), sj, kc, p->splitws, p->splitws_cap, p->trcount,
+                            p->trcount_cap, c.s);
+}
+
+// Route one product: Gram-type ones to the split-over-waves kernel, the
+// rest (short reductions, two-level batches, FP32 cores) to the LDS-tiled
+// matrix-core GEMM.  Every product of a solve runs on the library's own
+// kernels.
 hipError_t run_gemm(const Ctx& c, bool ta, bool tb, const GemmArgs& g) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    const bool plain = !g.lowp && !g.d && g.inner == 1 && g.K > 0;
-    if (plain && g.M <= 128 && g.N <= 128 && !(ta && tb) && (ta || g.K >= 256))
-        return fc::gram(ta, tb, g, c.s);
-    if (plain && c.p->blas) {
-        rocblas_handle h = c.p->blas;
-        if (rocblas_set_stream(h, c.s) != rocblas_status_success) return hipErrorUnknown;
-        const rocblas_operation oa = ta ? rocblas_operation_transpose : rocblas_operation_none;
-        const rocblas_operation ob = tb ? rocblas_operation_transpose : rocblas_operation_none;
-        rocblas_status st;
-        if (g.batch == 1)
-            st = rocblas_dgemm(h, oa, ob, g.M, g.N, g.K, &g.alpha, g.A, (rocblas_int)g.lda, g.B,
-                               (rocblas_int)g.ldb, &g.beta, g.C, (rocblas_int)g.ldc);
-        else
-            st = rocblas_dgemm_strided_batched(h, oa, ob, g.M, g.N, g.K, &g.alpha, g.A,
-                                               (rocblas_int)g.lda, g.strideA, g.B,
-                                               (rocblas_int)g.ldb, g.strideB, &g.beta, g.C,
-                                               (rocblas_int)g.ldc, g.strideC, g.batch);
-        return st == rocblas_status_success ? hipSuccess : hipErrorUnknown;
-    }
+    if ((t_tag == 3 && is_transform(c, ta, tb, g)) || streamable(ta, tb, g))
+        return run_stream(c, ta, tb, &g, 1);
+    if (gram_type(ta, tb, g)) return fc::gram(ta, tb, g, c.s);
     return fc::gemm(ta, tb, g, c.s);
+}
+
+// One product given as GemmArgs (split-K workspace from the plan), timed
+// with HIP events when the GEMM profile is on.
+void gemm_args(const Ctx& c, bool ta, bool tb, GemmArgs g) {
+    g.part = c.p->splitws; g.part_cap = c.p->splitws_cap;
+    const int M = g.M, N = g.N, K = g.K, batch = g.batch;
+    if (g_prof.on && !t_no_profile && M > 0 && N > 0 && K > 0 && batch > 0) {
+        const int kind = t_tag >= 0 ? t_tag : (gram_type(ta, tb, g) ? 4 : 0);
+        record_product(c.s, {ta, tb, M, N, K, batch, g.inner, g.lowp, kind, prod_flops(g),
+                             prod_bytes(g)},
+                       [&] { return run_gemm(c, ta, tb, g); });
+        return;
+    }
+    HIPCHK(run_gemm(c, ta, tb, g));
 }
 
 void gemm(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
@@ -308,27 +414,7 @@ void gemm(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, con
     g.B = B; g.ldb = ldb; g.strideB = sB; g.strideBin = sBi;
     g.C = C; g.ldc = ldc; g.strideC = sC; g.strideCin = sCi;
     g.d = d; g.strideD = sD;
-    g.part = c.p->splitws; g.part_cap = c.p->splitws_cap;
-    if (g_prof.on && !t_no_profile && M > 0 && N > 0 && K > 0 && batch > 0) {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (g_prof.used + 2 > g_prof.ev.size()) {
-            for (int i = 0; i < 256; ++i) {
-                hipEvent_t e;
-                HIPCHK(hipEventCreate(&e));
-                g_prof.ev.push_back(e);
-            }
-        }
-        HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], c.s));
-        HIPCHK(run_gemm(c, ta, tb, g));
-        HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], c.s));
-        g_prof.used += 2;
-        g_prof.shapes.push_back({ta, tb, M, N, K, batch, inner, g.lowp});
-        g_prof.flops += 2.0 * M * N * (double)K * batch;
-        g_prof.bytes += 8.0 * ((double)M * K + (double)K * N + (double)M * N) * batch;
-        g_prof.launches += 1;
-        return;
-    }
-    HIPCHK(run_gemm(c, ta, tb, g));
+    gemm_args(c, ta, tb, g);
 }
 
 // bulk contraction: runs on the FP32 matrix cores when the context asks for it
@@ -350,32 +436,25 @@ void gemmb(const Ctx& c, bool ta, bool tb, int M, int N, int K, double alpha, co
 // like gemm when the GEMM profile is on.
 void launch_group(const Ctx& c, bool ta, bool tb, const fc::GramJobs& jobs, bool gram) {
     if (jobs.count == 0) return;
+    bool transform = gram && t_tag == 3 && !ta && !tb;
+    for (int t = 0; t < jobs.count && transform; ++t) transform = is_transform(c, ta, tb, jobs.g[t]);
+    bool stream = gram;
+    for (int t = 0; t < jobs.count && stream; ++t) stream = streamable(ta, tb, jobs.g[t]);
     auto run = [&] {
+        if (transform || stream) return run_stream(c, ta, tb, jobs.g, jobs.count);
         return gram ? fc::gram_multi(ta, tb, jobs, c.s) : fc::gemm_multi(ta, tb, jobs, c.s);
     };
     if (g_prof.on && !t_no_profile) {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (g_prof.used + 2 > g_prof.ev.size()) {
-            for (int i = 0; i < 256; ++i) {
-                hipEvent_t e;
-                HIPCHK(hipEventCreate(&e));
-                g_prof.ev.push_back(e);
-            }
-        }
-        HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], c.s));
-        HIPCHK(run());
-        HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], c.s));
-        g_prof.used += 2;
-        // one shape entry per launch (the log pairs them with the events): the
-        // first product's shape, with the number of products as its batch
+        // one shape entry per launch: the first product's shape, with the
+        // number of products as its batch; the work of all of them
         const fc::GemmArgs& g0 = jobs.g[0];
-        g_prof.shapes.push_back({ta, tb, g0.M, g0.N, g0.K, jobs.count, 1, false});
+        GemmShape sh{ta, tb, g0.M, g0.N, g0.K, jobs.count, 1, false,
+                     t_tag >= 0 ? t_tag : (gram ? 4 : 0), 0.0, 0.0};
         for (int t = 0; t < jobs.count; ++t) {
-            const fc::GemmArgs& g = jobs.g[t];
-            g_prof.flops += 2.0 * g.M * g.N * (double)g.K;
-            g_prof.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
+            sh.flops += prod_flops(jobs.g[t]);
+            sh.bytes += prod_bytes(jobs.g[t]);
         }
-        g_prof.launches += 1;
+        record_product(c.s, sh, run);
         return;
     }
     HIPCHK(run());
@@ -384,19 +463,13 @@ void launch_group(const Ctx& c, bool ta, bool tb, const fc::GramJobs& jobs, bool
 void gemm_group(const Ctx& c, bool ta, bool tb, const fc::GemmArgs* prods, int count,
                 bool long_k = false) {
     fc::GramJobs grams, others;
-    auto one = [&](const fc::GemmArgs& g) {
-        gemm(c, ta, tb, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc,
-             g.batch, g.strideA, g.strideB, g.strideC, g.inner, g.strideAin, g.strideBin,
-             g.strideCin);
-    };
+    auto one = [&](const fc::GemmArgs& g) { gemm_args(c, ta, tb, g); };
     for (int t = 0; t < count; ++t) {
         const fc::GemmArgs& g = prods[t];
         if (g.M <= 0 || g.N <= 0) continue;
-        const bool gram_type = g.batch == 1 && g.M <= 128 && g.N <= 128 && !(ta && tb) &&
-                               (ta || g.K >= 256) && g.K > 0;
-        if (gram_type)
+        if (gram_type(ta, tb, g))
             grams.g[grams.count++] = g;
-        else if (g.K > 0 && (g.K <= 256 || long_k))
+        else if (g.K > 0 && !g.d && !g.lowp && (g.K <= 256 || long_k))
             others.g[others.count++] = g;
         else
             one(g);
@@ -406,6 +479,27 @@ void gemm_group(const Ctx& c, bool ta, bool tb, const fc::GemmArgs* prods, int c
         one(others.g[0]);
     else
         launch_group(c, ta, tb, others, false);
+}
+
+// out_l = sum_q diag(D_l[:, q]) Z_l T_l^q for the jobs (fused row-wise
+// Kronecker product and contraction), timed with the GEMM family when the
+// GEMM profile is on: 2 n p r Q flops, Z, D, T read and out written once.
+void kron_apply(const Ctx& c, int Q, const fc::KronJobs& kj) {
+    if (kj.count == 0) return;
+    const int n = c.n;
+    if (g_prof.on && !t_no_profile) {
+        const fc::KronJob& J0 = kj.job[0];
+        GemmShape sh{false, false, n, J0.p, J0.r * Q, kj.count, 1, false, 5, 0.0, 0.0};
+        for (int t = 0; t < kj.count; ++t) {
+            const fc::KronJob& J = kj.job[t];
+            sh.flops += 2.0 * n * J.p * (double)J.r * Q;
+            sh.bytes += 8.0 * ((double)n * J.r + (double)n * Q + (double)J.r * J.p * Q +
+                               (double)n * J.p);
+        }
+        record_product(c.s, sh, [&] { return fc::kron_apply_multi(n, Q, kj, c.s); });
+        return;
+    }
+    HIPCHK(fc::kron_apply_multi(n, Q, kj, c.s));
 }
 
 fc::GemmArgs prod(int M, int N, int K, const double* A, long lda, const double* B, long ldb,
@@ -1127,10 +1221,12 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
         out.r[0] = out.r[1] = out.r[2] = 0;
         return;
     }
-    // exact projection C = sum_t c_t core_t x_l (W_l^T Z_l^t)
+    // exact projection C = sum_t c_t core_t x_l (W_l^T Z_l^t), in FP64 on
+    // every path: ||C||^2 decides the energy the subspace misses, which is
+    // charged to the tolerance
     for (int l = 0; l < 3; ++l)
-        gemmb(c, true, false, pk[l], k[l], n, 1.0, p->W[l], n, p->Phi[l], n, 0.0,
-              p->Map + (long)l * KM * 256, pk[l]);
+        gemm(c, true, false, pk[l], k[l], n, 1.0, p->W[l], n, p->Phi[l], n, 0.0,
+             p->Map + (long)l * KM * 256, pk[l]);
     const long Csz = (long)pk[0] * pk[1] * pk[2];
     for (int t = 0; t < m; ++t) {
         const Tucker& T = *terms[t].second;
@@ -1142,7 +1238,7 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
             double* dst = last ? p->C : bufs[l & 1];
             mode_product(c, src, cur, l, p->Map + (long)l * KM * 256 + (long)off[t][l] * pk[l], pk[l],
                          pk[l], dst, last ? terms[t].first : 1.0, (last && t > 0) ? 1.0 : 0.0, false,
-                         true);
+                         false);
             cur[l] = pk[l];
             src = dst;
         }
@@ -1154,15 +1250,29 @@ void sum_trunc(const Ctx& c, const std::vector<std::pair<double, const Tucker*>>
     hosvd_core(c, p->C, pk, B, thr_core, out, what);
 }
 
+// The Q diagonally scaled Grams C^q = A^T diag(D[:, q]) B (A n x M, B n x N,
+// D n x Q, all ld n) as one batched product: C^q is M x N with ld M at
+// C + q M N.  This is the row-wise Kronecker product of A and B contracted
+// with D (E^T D with E[i, (j, c)] = A[i, j] B[i, c]) without forming E.
+fc::GemmArgs scaled_gram(int M, int N, int n, int Q, const double* A, const double* B,
+                         const double* D, double* C) {
+    fc::GemmArgs g;
+    g.M = M; g.N = N; g.K = n; g.batch = Q;
+    g.A = A; g.lda = n; g.B = B; g.ldb = n; g.C = C; g.ldc = M; g.strideC = (long)M * N;
+    g.d = D; g.strideD = n;
+    return g;
+}
+
 // ---- truncation of a Hadamard product with a separable positive tensor ----
 // T = D~ (.) P = sum_q P x_l diag(D_l[:,q]).  Subspace per mode from the
 // block reduced HOSVD (sum over q of the unfolding Grams of the terms),
 // exact projection of T onto it, then HOSVD of the projected core.
-// Hh_l X = sum_q D^q Z M^q Z^T D^q X for the Hadamard truncation: row-wise
-// Kronecker product E = Z (.) X, Y^q = E^T D^q (stack r q x Q), T^q = M^q Y^q,
-// F = D T^T, row-wise contraction with Z.  all() runs each stage for the
-// selected modes in one launch, on per-mode slices of E, F, Ys and Ts when
-// they fit (else mode by mode).
+// Hh_l X = sum_q D^q Z M^q Z^T D^q X for the Hadamard truncation: the scaled
+// Grams Y^q = Z^T D^q X (stack r q x Q, one batched launch), T^q = M^q Y^q,
+// and sum_q D^q Z T^q in one fused launch (the row-wise Kronecker products
+// Z (.) X and Z (.) D are never stored).  all() runs each stage for the
+// selected modes in one launch, on per-mode slices of Ys and Ts when they
+// fit (else mode by mode).
 struct HadGramApply {
     const Ctx& c;
     const Separable& op;
@@ -1172,60 +1282,55 @@ struct HadGramApply {
         fc_plan_s* p = c.p;
         const int n = c.n, Q = op.Q;
         const int* r = P.r;
-        HIPCHK(fc::rowkron(n, r[l], q, P.Z[l], n, X, n, p->E, c.s));
-        gemm(c, true, false, r[l] * q, Q, n, 1.0, p->E, n, op.D[l], n, 0.0, p->Ys, (long)r[l] * q);
+        {
+            const fc::GemmArgs g1 = scaled_gram(r[l], q, n, Q, P.Z[l], X, op.D[l], p->Ys);
+            gemm_group(c, true, false, &g1, 1);
+        }
         gemm(c, false, false, r[l], q, r[l], 1.0, Mq[l], r[l], p->Ys, r[l], 0.0, p->Ts, r[l], Q,
              (long)r[l] * r[l], (long)r[l] * q, (long)r[l] * q);
-        gemm(c, false, true, n, r[l] * q, Q, 1.0, op.D[l], n, p->Ts, (long)r[l] * q, 0.0, p->F, n);
-        HIPCHK(fc::rowcontract(n, r[l], q, P.Z[l], n, p->F, HXo, n, c.s));
+        fc::KronJobs kj;
+        fc::KronJob& J = kj.job[kj.count++];
+        J.r = r[l]; J.p = q; J.Z = P.Z[l]; J.ldz = n; J.D = op.D[l]; J.T = p->Ts; J.out = HXo;
+        J.ldo = n;
+        kron_apply(c, Q, kj);
     }
     void all(const bool sel[3], double* const* X, const int q[3], double* const* HX) const {
         fc_plan_s* p = c.p;
         const int n = c.n, Q = op.Q;
         const int* r = P.r;
-        long ne = 0, ny = 0;
+        long ny = 0;
         for (int l = 0; l < 3; ++l)
-            if (sel[l]) {
-                ne += (long)n * r[l] * q[l];
-                ny += (long)r[l] * q[l] * Q;
-            }
-        if (g_ungrouped || ne > p->e_cap || ne > p->f_cap || ny > p->ys_cap) {
+            if (sel[l]) ny += (long)r[l] * q[l] * Q;
+        if (g_ungrouped || ny > p->ys_cap) {
             for (int l = 0; l < 3; ++l)
                 if (sel[l]) (*this)(l, X[l], q[l], HX[l]);
             return;
         }
-        fc::RowJobs kr, rc;
-        fc::GemmArgs s1[3], s2[3], s3[3];
+        fc::KronJobs kj;
+        fc::GemmArgs s1[3], s2[3];
         int cnt = 0;
-        long oe = 0, oy = 0;
+        long oy = 0;
         for (int l = 0; l < 3; ++l) {
             if (!sel[l]) continue;
             const long rq = (long)r[l] * q[l];
-            double* El = p->E + oe;
-            double* Fl = p->F + oe;
             double* Ysl = p->Ys + oy;
             double* Tsl = p->Ts + oy;
-            oe += (long)n * rq;
             oy += rq * Q;
-            fc::RowJob& K = kr.job[kr.count++];
-            K.r = r[l]; K.p = q[l]; K.Z = P.Z[l]; K.ldz = n; K.X = X[l]; K.ldx = n; K.out = El;
-            s1[cnt] = prod((int)rq, Q, n, El, n, op.D[l], n, Ysl, rq);
+            s1[cnt] = scaled_gram(r[l], q[l], n, Q, P.Z[l], X[l], op.D[l], Ysl);
             fc::GemmArgs g2 = prod(r[l], q[l], r[l], Mq[l], r[l], Ysl, r[l], Tsl, r[l]);
             g2.batch = Q;
             g2.strideA = (long)r[l] * r[l];
             g2.strideB = rq;
             g2.strideC = rq;
             s2[cnt] = g2;
-            s3[cnt] = prod(n, (int)rq, Q, op.D[l], n, Tsl, rq, Fl, n);
-            fc::RowJob& C = rc.job[rc.count++];
-            C.r = r[l]; C.p = q[l]; C.Z = P.Z[l]; C.ldz = n; C.X = Fl; C.out = HX[l]; C.ldo = n;
+            fc::KronJob& J = kj.job[kj.count++];
+            J.r = r[l]; J.p = q[l]; J.Z = P.Z[l]; J.ldz = n; J.D = op.D[l]; J.T = Tsl;
+            J.out = HX[l]; J.ldo = n;
             ++cnt;
         }
-        HIPCHK(fc::rowkron_multi(n, kr, c.s));
         gemm_group(c, true, false, s1, cnt);
         gemm_group(c, false, false, s2, cnt);
-        gemm_group(c, false, true, s3, cnt);
-        HIPCHK(fc::rowcontract_multi(n, rc, c.s));
+        kron_apply(c, Q, kj);
     }
 };
 
@@ -1237,27 +1342,16 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
     const int Q = op.Q;
     if (P.empty()) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
     const int* r = P.r;
-    // 1. diagonal Grams Gd_l^q = Z_l^T diag(D_l[:,q]^2) Z_l  -> stack r_l^2 x Q
-    if (!g_ungrouped && (long)n * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) <= p->e_cap) {
-        // the three modes together, each in its own slice of E
-        fc::RowJobs kr;
+    // 1. diagonal Grams Gd_l^q = Z_l^T diag(D_l[:,q]^2) Z_l  -> stack r_l^2 x Q,
+    //    the Q terms of the three modes as batched scaled Grams in one launch
+    {
         fc::GemmArgs gd[3];
-        long oe = 0;
-        for (int l = 0; l < 3; ++l) {
-            double* El = p->E + oe;
-            oe += (long)n * r[l] * r[l];
-            fc::RowJob& J = kr.job[kr.count++];
-            J.r = r[l]; J.p = r[l]; J.Z = P.Z[l]; J.ldz = n; J.X = P.Z[l]; J.ldx = n; J.out = El;
-            gd[l] = prod(r[l] * r[l], Q, n, El, n, op.D2[l], n, p->Gd[l], (long)r[l] * r[l]);
-        }
-        HIPCHK(fc::rowkron_multi(n, kr, c.s));
-        gemm_group(c, true, false, gd, 3);
-    } else {
-        for (int l = 0; l < 3; ++l) {
-            HIPCHK(fc::rowkron(n, r[l], r[l], P.Z[l], n, P.Z[l], n, p->E, c.s));
-            gemm(c, true, false, r[l] * r[l], Q, n, 1.0, p->E, n, op.D2[l], n, 0.0, p->Gd[l],
-                 (long)r[l] * r[l]);
-        }
+        for (int l = 0; l < 3; ++l)
+            gd[l] = scaled_gram(r[l], r[l], n, Q, P.Z[l], P.Z[l], op.D2[l], p->Gd[l]);
+        if (g_ungrouped)
+            for (int l = 0; l < 3; ++l) gemm_group(c, true, false, gd + l, 1);
+        else
+            gemm_group(c, true, false, gd, 3);
     }
     // 2. per-term unfolding Grams M_l^q = core_(l) (G_b^q (x) G_a^q) core_(l)^T
     double* Mq[3];
@@ -1355,8 +1449,20 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
         out.r[0] = out.r[1] = out.r[2] = 0;
         return;
     }
-    // 4. projection A_l^q = W_l^T D^q Z_l -> stack (pk*r x Q)
-    if (!g_ungrouped && (long)n * (pk[0] * r[0] + pk[1] * r[1] + pk[2] * r[2]) <= p->e_cap) {
+    // 4. projection A_l^q = W_l^T D^q Z_l -> stack (pk*r x Q): in FP64 the
+    //    scaled Grams of the three modes in one launch; on the FP32 matrix
+    //    cores (mixed inner solve) the row-wise Kronecker products contracted
+    //    with D
+    if (!c.lowp) {
+        fc::GemmArgs pa[3];
+        for (int l = 0; l < 3; ++l)
+            pa[l] = scaled_gram(pk[l], r[l], n, Q, p->W[l], P.Z[l], op.D[l], p->As[l]);
+        if (g_ungrouped)
+            for (int l = 0; l < 3; ++l) gemm_group(c, true, false, pa + l, 1);
+        else
+            gemm_group(c, true, false, pa, 3);
+    } else if (!g_ungrouped &&
+               (long)n * (pk[0] * r[0] + pk[1] * r[1] + pk[2] * r[2]) <= p->e_cap) {
         fc::RowJobs kr;
         double* El[3];
         long oe = 0;
@@ -1399,12 +1505,69 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
               (long)pk[0] * pk[1]);
     }
     const long Csz = (long)pk[0] * pk[1] * pk[2];
-    const double n2 = host_dot(c, Csz, p->C, p->C);
+    HIPCHK(fc::dot_long(Csz, p->C, p->C, p->scal + 256, p->dotcnt, p->scal, c.s));
+    // 6. a-posteriori check of the subspaces: the energy of T outside them,
+    //    ||T - PT||^2, estimated with S rank-1 Gaussian probes
+    //    g_t = g_0,t (x) g_1,t (x) g_2,t (E <X, g_t>^2 = ||X||^2), read back with
+    //    ||PT||^2 = ||C||^2 and charged to the core's budget
+    const long per_probe = (long)r[1] * r[2] * Q;
+    int S = (int)std::min<long>(8, p->cbig / std::max<long>(1, per_probe));
+    if ((long)S * Q * (r[0] + r[1] + r[2]) > p->ys_cap) S = 0;
+    if (S >= 2) {
+        fc::FillJobs fills;
+        for (int l = 0; l < 3; ++l) {
+            fc::FillJob& F = fills.job[fills.count++];
+            F.n = (long)n * S;
+            F.seed = 4099u + 7u * l + 101u * site;
+            F.x = p->Xs3[l];
+        }
+        HIPCHK(fc::fill_random_multi(fills, c.s));
+        fc::GemmArgs ug[3], vg[3];
+        double* Ul[3];
+        long ou = 0;
+        for (int l = 0; l < 3; ++l) {
+            Ul[l] = p->Ys + ou;
+            ou += (long)r[l] * Q * S;
+            // U_l,t = Z_l^T diag(g_l,t) D_l, the S probes as a batch
+            ug[l] = scaled_gram(r[l], Q, n, S, P.Z[l], op.D[l], p->Xs3[l], Ul[l]);
+            vg[l] = prod(pk[l], S, n, p->W[l], n, p->Xs3[l], n, p->Map + (long)l * KM * 256, pk[l]);
+        }
+        gemm_group(c, true, false, ug, 3);
+        gemm_group(c, true, false, vg, 3);
+        // Mb_t = core_(1)^T U_0,t  (r1 r2 x Q per probe)
+        gemm(c, true, false, r[1] * r[2], Q, r[0], 1.0, P.core, r[0], Ul[0], r[0], 0.0, p->T1,
+             (long)r[1] * r[2], S, 0, (long)r[0] * Q, per_probe);
+        // Yv_t = C_(1)^T v_0,t  (pk1 pk2 x 1 per probe)
+        const long ppk = (long)pk[1] * pk[2];
+        gemm(c, true, false, (int)ppk, S, pk[0], 1.0, p->C, pk[0], p->Map, pk[0], 0.0, p->T2, ppk);
+        fc::ProbeSums ps;
+        ps.p[0].r1 = r[1]; ps.p[0].r2 = r[2]; ps.p[0].Q = Q;
+        ps.p[0].M = p->T1; ps.p[0].mstride = per_probe;
+        ps.p[0].U1 = Ul[1]; ps.p[0].U2 = Ul[2];
+        ps.p[1].r1 = pk[1]; ps.p[1].r2 = pk[2]; ps.p[1].Q = 1;
+        ps.p[1].M = p->T2; ps.p[1].mstride = ppk;
+        ps.p[1].U1 = p->Map + (long)KM * 256; ps.p[1].U2 = p->Map + 2L * KM * 256;
+        ps.out = p->scal + 1;
+        HIPCHK(fc::probe_sums(ps, S, c.s));
+    }
+    double vals[1 + 2 * 8];
+    d2h(c, vals, p->scal, 1 + 2 * (S >= 2 ? S : 0));
+    const double n2 = vals[0];
     if (!std::isfinite(n2)) throw FcError(FC_ERR_NUMERIC, std::string(what) + ": non-finite");
+    double missed = 0.0;
+    for (int t = 0; S >= 2 && t < S; ++t) {
+        const double dlt = vals[1 + 2 * t] - vals[2 + 2 * t];
+        missed += dlt * dlt / S;
+    }
     const double thr2 = std::max(tol_rel * tol_rel * n2, floor_abs * floor_abs);
     if (n2 <= thr2) { out.r[0] = out.r[1] = out.r[2] = 0; return; }
+    // the estimate's spread over S probes: charge twice the estimate
+    const double charge = 2.0 * missed;
+    p->worst_missed = std::max(p->worst_missed, charge / thr2);
+    FC_TRACE_PRINT("%s: missed-energy estimate %.3e of budget %.3e (%d probes)\n", what, missed,
+                   thr2, S);
     double* B[3] = {p->W[0], p->W[1], p->W[2]};
-    hosvd_core(c, p->C, pk, B, thr2, out, what);
+    hosvd_core(c, p->C, pk, B, std::max(thr2 - charge, 0.0), out, what);
     (void)csz;
 }
 
@@ -1432,18 +1595,27 @@ void apply_precond(const Ctx& c, const Tucker& R, double tol_rel, Tucker& Z, con
     const int n = c.n;
     Tucker& tmp = p->slot[13];
     Tucker Rs;
-    for (int l = 0; l < 3; ++l) {
-        Rs.r[l] = R.r[l];
-        Rs.Z[l] = tmp.Z[l];
-        gemm(c, false, false, n, R.r[l], n, 1.0, p->Wsin[l], n, R.Z[l], n, 0.0, Rs.Z[l], n);
+    {
+        KindTag tag(3);
+        fc::GemmArgs to_sine[3];
+        for (int l = 0; l < 3; ++l) {
+            Rs.r[l] = R.r[l];
+            Rs.Z[l] = tmp.Z[l];
+            to_sine[l] = prod(n, R.r[l], n, p->Wsin[l], n, R.Z[l], n, Rs.Z[l], n);
+        }
+        gemm_group(c, false, false, to_sine, 3);
     }
     Rs.core = R.core;
     had_trunc(c, p->pcA, Rs, tol_rel, 0.0, Z, what, site);
     if (Z.empty()) return;
-    for (int l = 0; l < 3; ++l) {
-        gemm(c, true, false, n, Z.r[l], n, 1.0, p->Wsin[l], n, Z.Z[l], n, 0.0, tmp.Z[l], n);
-        std::swap(Z.Z[l], tmp.Z[l]);
+    {
+        KindTag tag(3);
+        fc::GemmArgs back[3];
+        for (int l = 0; l < 3; ++l)
+            back[l] = prod(n, Z.r[l], n, p->WsinT[l], n, Z.Z[l], n, tmp.Z[l], n);
+        gemm_group(c, false, false, back, 3);
     }
+    for (int l = 0; l < 3; ++l) std::swap(Z.Z[l], tmp.Z[l]);
 }
 
 // ---- canonical -> Tucker (exact unfolding spectra) ------------------------
@@ -1536,8 +1708,10 @@ void tucker_copy(const Ctx& c, const Tucker& src, Tucker& dst, double scale = 1.
 
 // ---- Tucker -> canonical (T2C) and output in grid coordinates -------------
 // The core of a HOSVD-truncated tensor is all-orthogonal; each mode-3 slice
-// core[:,:,nu] is split by its SVD, and (slice, singular value) terms are
-// dropped smallest first while the dropped energy stays within budget2.
+// core[:,:,nu] is split by its SVD (eigenpairs of the slice Gram), and
+// (slice, singular value) terms are dropped smallest first while the dropped
+// energy stays within budget2 (Appendix 1).  Selection and coefficient
+// assembly run on the device; the host reads the kept count only.
 // Returns the rank; writes nothing if the rank exceeds cap.
 int tucker_to_canon_out(const Ctx& c, const Tucker& X, double budget2, bool to_grid, int cap,
                         double* w_u, double* const U[3]) {
@@ -1549,65 +1723,28 @@ int tucker_to_canon_out(const Ctx& c, const Tucker& X, double budget2, bool to_g
     gemm(c, true, false, r1, r1, r0, 1.0, X.core, r0, X.core, r0, 0.0, p->Bp, r1, r2,
          (long)r0 * r1, (long)r0 * r1, (long)r1 * r1);
     HIPCHK(fc::sym_eig(r1, r2, p->Bp, r1, (long)r1 * r1, p->Ev, p->Evec, r1, (long)r1 * r1, p->jac, c.s));
-    std::vector<double> sig2((size_t)r1 * r2);
-    d2h(c, sig2.data(), p->Ev, sig2.size());
-    struct Term { double s2; int nu, j; };
-    std::vector<Term> terms;
-    for (int nu = 0; nu < r2; ++nu)
-        for (int j = 0; j < r1; ++j) terms.push_back({std::max(sig2[(size_t)nu * r1 + j], 0.0), nu, j});
-    std::stable_sort(terms.begin(), terms.end(), [](const Term& a, const Term& b) {
-        if (a.s2 != b.s2) return a.s2 < b.s2;
-        if (a.nu != b.nu) return a.nu < b.nu;
-        return a.j < b.j;
-    });
-    double dropped = 0;
-    size_t first = 0;
-    while (first < terms.size() && dropped + terms[first].s2 <= budget2) {
-        dropped += terms[first].s2;
-        ++first;
-    }
-    std::vector<Term> kept(terms.begin() + first, terms.end());
-    std::reverse(kept.begin(), kept.end());   // descending weight
-    const int K = (int)kept.size();
-    if (K > cap) return K;
-    if (K == 0) return 0;
-    // coefficient matrices: mode 1: core_nu v_j / sigma (r0 x K); mode 2: v_j (r1 x K);
-    // mode 3: e_nu (r2 x K)
-    std::vector<double> hv((size_t)r1 * r1 * r2);
-    d2h(c, hv.data(), p->Evec, hv.size());
-    std::vector<double> core_h((size_t)r0 * r1 * r2);
-    d2h(c, core_h.data(), X.core, core_h.size());
-    std::vector<double> c0((size_t)r0 * K), c1((size_t)r1 * K), c2((size_t)r2 * K, 0.0), wh(K);
-    for (int t = 0; t < K; ++t) {
-        const int nu = kept[t].nu, j = kept[t].j;
-        const double* v = hv.data() + (size_t)nu * r1 * r1 + (size_t)j * r1;
-        const double sg = std::sqrt(kept[t].s2);
-        double nrm = 0;
-        for (int i = 0; i < r0; ++i) {
-            double acc = 0;
-            for (int jj = 0; jj < r1; ++jj)
-                acc += core_h[i + (size_t)r0 * (jj + (size_t)r1 * nu)] * v[jj];
-            c0[(size_t)t * r0 + i] = acc;
-            nrm += acc * acc;
-        }
-        nrm = std::sqrt(nrm);
-        for (int i = 0; i < r0; ++i) c0[(size_t)t * r0 + i] = nrm > 0 ? c0[(size_t)t * r0 + i] / nrm : 0.0;
-        for (int jj = 0; jj < r1; ++jj) c1[(size_t)t * r1 + jj] = v[jj];
-        c2[(size_t)t * r2 + nu] = 1.0;
-        wh[t] = nrm > 0 ? nrm : sg;
-    }
-    const std::vector<double>* coef[3] = {&c0, &c1, &c2};
+    HIPCHK(fc::t2c_select(r1 * r2, p->Ev, budget2, p->t2c_ws, p->t2c_keep, p->icount + 8, c.s));
+    int K = 0;
+    d2h(c, &K, p->icount + 8, 1);
+    if (K > cap || K == 0) return K;
+    HIPCHK(fc::t2c_coef(r0, r1, r2, K, X.core, p->Evec, p->Ev, p->t2c_keep, p->cf[0], p->cf[1],
+                        p->cf[2], w_u, c.s));
     const int rr[3] = {r0, r1, r2};
-    for (int l = 0; l < 3; ++l) {
-        h2d(c, p->cf[l], coef[l]->data(), coef[l]->size());
-        const double* Zl = X.Z[l];
-        if (to_grid) {
-            gemm(c, false, false, n, rr[l], n, 1.0, p->V[l], n, X.Z[l], n, 0.0, p->tmpn, n);
-            Zl = p->tmpn;
+    const double* Zl[3] = {X.Z[0], X.Z[1], X.Z[2]};
+    if (to_grid) {
+        // exit transform V_l Z_l of the three bases in one launch
+        KindTag tag(3);
+        double* G[3] = {p->tmpn, p->tmpn2, p->Xs3[0]};
+        fc::GemmArgs tr[3];
+        for (int l = 0; l < 3; ++l) {
+            tr[l] = prod(n, rr[l], n, p->V[l], n, X.Z[l], n, G[l], n);
+            Zl[l] = G[l];
         }
-        gemm(c, false, false, n, K, rr[l], 1.0, Zl, n, p->cf[l], rr[l], 0.0, U[l], n);
+        gemm_group(c, false, false, tr, 3);
     }
-    h2d(c, w_u, wh.data(), K);
+    fc::GemmArgs outs[3];
+    for (int l = 0; l < 3; ++l) outs[l] = prod(n, K, rr[l], Zl[l], n, p->cf[l], rr[l], U[l], n);
+    gemm_group(c, false, false, outs, 3);
     // exact unit columns (the bases are orthonormal only to rounding)
     HIPCHK(fc::normalize_factors(n, K, U[0], U[1], U[2], n, w_u, c.s));
     sync(c);
@@ -1645,8 +1782,6 @@ void alloc_workspace(fc_plan_s* p) {
     p->ys_cap = std::max<long>(rc * pc * Q, 256L * KM);
     p->Ys = A.alloc((size_t)p->ys_cap);
     p->Ts = A.alloc((size_t)p->ys_cap);
-    p->f_cap = (long)n * rc * pc;
-    p->F = A.alloc((size_t)p->f_cap);
     p->Bp = A.alloc((size_t)std::max<long>(pc * pc, rc * rc * rc));
     p->Ev = A.alloc((size_t)std::max<long>(pc, rc * rc));
     p->Evec = A.alloc((size_t)std::max<long>(pc * pc, rc * rc * rc));
@@ -1675,6 +1810,12 @@ void alloc_workspace(fc_plan_s* p) {
     p->tmpn = A.alloc((size_t)n * std::max<long>(rc, 256));
     p->tmpn2 = A.alloc((size_t)n * std::max<long>(rc, 256));
     p->icount = A.alloc_int(16);
+    p->t2c_keep = A.alloc_int((size_t)rc * rc);
+    {
+        long np2 = 1;
+        while (np2 < rc * rc) np2 <<= 1;
+        p->t2c_ws = A.alloc((size_t)(12 * np2 + 7) / 8);
+    }
     p->qrN = A.alloc(3 * 512);
     p->qrC = A.alloc(3 * 256 * 16);
     p->qrKeep = A.alloc_int(3 * 512);
@@ -1691,6 +1832,10 @@ void alloc_workspace(fc_plan_s* p) {
     p->splitws = A.alloc((size_t)p->splitws_cap);
     p->dflag = A.alloc_int(4);
     p->dotcnt = (unsigned*)A.alloc_int(1);
+    p->trcount_cap = 3L * std::max(512, (n + 31) / 32);
+    p->trcount = (unsigned*)A.alloc_int((size_t)p->trcount_cap);
+    if (hipMemset(p->trcount, 0, sizeof(unsigned) * p->trcount_cap) != hipSuccess)
+        throw FcError(FC_ERR_HIP, "hipMemset failed");
     const unsigned zero = 0;
     if (hipMemcpy(p->dotcnt, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
         throw FcError(FC_ERR_HIP, "hipMemcpy failed");
@@ -1990,6 +2135,11 @@ void device_spectra(fc_plan_s* p, const fc_setup_params* prm) {
     p->arena.release(E);
     p->arena.release(info);
     for (int l = 0; l < 3; ++l) {
+        p->Vt[l] = p->arena.alloc((size_t)n * n);
+        HIPCHK(fc::transpose(n, n, p->V[l], n, p->Vt[l], n, p->stream));
+    }
+    HIPCHK(hipStreamSynchronize(p->stream));
+    for (int l = 0; l < 3; ++l) {
         p->lam[l].assign(dh.begin() + (long)l * n, dh.begin() + (long)(l + 1) * n);
         if (ih[l] != 0 || !(p->lam[l][0] > 0))
             throw FcError(FC_ERR_NUMERIC, "tridiagonal eigensolver failed (mode " +
@@ -2015,6 +2165,8 @@ void build_sine_maps(fc_plan_s* p) {
     for (int l = 0; l < 3; ++l) {
         p->Wsin[l] = p->arena.alloc((size_t)n * n);
         gemm(c, false, false, n, n, n, 1.0, Sd, n, p->V[l], n, 0.0, p->Wsin[l], n);
+        p->WsinT[l] = p->arena.alloc((size_t)n * n);
+        HIPCHK(fc::transpose(n, n, p->Wsin[l], n, p->WsinT[l], n, p->stream));
     }
     HIPCHK(hipStreamSynchronize(p->stream));
     p->arena.release(Sd);
@@ -2032,20 +2184,6 @@ void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
     upload_separable(p, p->st);
     if (p->pc_kind == FC_PRECOND_LAPLACE) upload_separable(p, p->pcA);
     alloc_workspace(p);
-    // rocBLAS for plain products: a fixed workspace from the plan (no device
-    // allocation during a solve), deterministic kernels only
-    if (rocblas_create_handle(&p->blas) != rocblas_status_success) {
-        p->blas = nullptr;
-        throw FcError(FC_ERR_HIP, "rocblas_create_handle failed");
-    }
-    if (rocblas_set_atomics_mode(p->blas, rocblas_atomics_not_allowed) != rocblas_status_success)
-        throw FcError(FC_ERR_HIP, "rocblas_set_atomics_mode failed");
-    {
-        const size_t wsz = size_t(32) << 20;
-        double* ws = p->arena.alloc(wsz / sizeof(double));
-        if (rocblas_set_workspace(p->blas, ws, wsz) != rocblas_status_success)
-            throw FcError(FC_ERR_HIP, "rocblas_set_workspace failed");
-    }
     if (p->pc_kind == FC_PRECOND_LAPLACE) build_sine_maps(p);
     HIPCHK(hipHostMalloc(&p->pinned, fc_plan_s::kPinnedBytes, hipHostMallocDefault));
     if (p->dims == 2) {
@@ -2319,7 +2457,7 @@ static fc_status validate_params(const fc_setup_params* prm) {
     if (prm->tol < 0 || prm->op_accuracy < 0 || prm->max_iter < 0 || prm->max_rank < 0 ||
         prm->precond_rank < 0)
         return fail(FC_ERR_INVALID_ARG, "negative option");
-    if (prm->max_rank > 96) return fail(FC_ERR_INVALID_ARG, "max_rank must be <= 96");
+    if (prm->max_rank > KM) return fail(FC_ERR_INVALID_ARG, "max_rank must be <= 128");
     if (prm->precond_rank > 32) return fail(FC_ERR_INVALID_ARG, "precond_rank must be <= 32");
     if (prm->precision != FC_FP64 && prm->precision != FC_MIXED_FP32)
         return fail(FC_ERR_INVALID_ARG, "unsupported precision");
@@ -2416,9 +2554,37 @@ fc_status fc_mode_transform(fc_plan p, int mode, int transpose, int m, const dou
     if (!p || mode < 0 || mode > 2 || m < 0 || !X || !out) return fail(FC_ERR_INVALID_ARG, "fc_mode_transform: bad arguments");
     Ctx c{p, (hipStream_t)stream, p->n};
     return guard([&] {
-        gemm(c, transpose != 0, false, p->n, m, p->n, 1.0, p->V[mode], p->n, X, p->n, 0.0, out, p->n);
+        KindTag tag(3);
+        const double* M = transpose ? p->Vt[mode] : p->V[mode];
+        gemm(c, false, false, p->n, m, p->n, 1.0, M, p->n, X, p->n, 0.0, out, p->n);
     });
 }
+
+}  // extern "C"
+
+namespace {
+
+// The three cross Grams G_l = A_l^T B_l (ra x rb, ld ra) of a canonical
+// inner product: one launch of the Gram kernel for ranks <= 128, else the
+// LDS-tiled GEMM (no split-K workspace).  Shared by fc_cp_inner and
+// fc_cp_inner_noalloc, so that both give the same bits.
+hipError_t cross_grams(int n, int ra, const double* const A[3], int rb, const double* const B[3],
+                       double* const G[3], hipStream_t s) {
+    fc::GramJobs jobs;
+    for (int l = 0; l < 3; ++l) {
+        fc::GemmArgs& g = jobs.g[jobs.count++];
+        g.M = ra; g.N = rb; g.K = n;
+        g.A = A[l]; g.lda = n; g.B = B[l]; g.ldb = n; g.C = G[l]; g.ldc = ra;
+    }
+    if (ra <= 128 && rb <= 128) return fc::gram_multi(true, false, jobs, s);
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < 3 && e == hipSuccess; ++l) e = fc::gemm(true, false, jobs.g[l], s);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
 
 fc_status fc_cp_inner(fc_plan p, int ra, const double* wa, const double* A1, const double* A2,
                       const double* A3, int rb, const double* wb, const double* B1,
@@ -2431,8 +2597,7 @@ fc_status fc_cp_inner(fc_plan p, int ra, const double* wa, const double* A1, con
     const double* B[3] = {B1, B2, B3};
     return guard([&] {
         double* G[3] = {p->C, p->Cp, p->Cn1};
-        for (int l = 0; l < 3; ++l)
-            gemm(c, true, false, ra, rb, p->n, 1.0, A[l], p->n, B[l], p->n, 0.0, G[l], ra);
+        HIPCHK(cross_grams(p->n, ra, A, rb, B, G, c.s));
         HIPCHK(fc::cp_inner_reduce(ra, rb, G[0], G[1], G[2], wa, wb, p->scal, c.s));
         d2h(c, out, p->scal, 1);
     });
@@ -2494,20 +2659,8 @@ fc_status fc_cp_inner_noalloc(int n, int ra, const double* wa, const double* A1,
     const double* A[3] = {A1, A2, A3};
     const double* B[3] = {B1, B2, B3};
     double* G[3];
-    fc::GramJobs jobs;
-    for (int l = 0; l < 3; ++l) {
-        G[l] = ws + l * (long)ra * rb;
-        fc::GemmArgs& g = jobs.g[jobs.count++];
-        g.M = ra; g.N = rb; g.K = n;
-        g.A = A[l]; g.lda = n; g.B = B[l]; g.ldb = n; g.C = G[l]; g.ldc = ra;
-    }
-    hipError_t e;
-    if (ra <= 128 && rb <= 128) {
-        e = fc::gram_multi(true, false, jobs, s);
-    } else {
-        e = hipSuccess;
-        for (int l = 0; l < 3 && e == hipSuccess; ++l) e = fc::gemm(true, false, jobs.g[l], s);
-    }
+    for (int l = 0; l < 3; ++l) G[l] = ws + l * (long)ra * rb;
+    hipError_t e = cross_grams(n, ra, A, rb, B, G, s);
     if (e == hipSuccess) e = fc::cp_inner_reduce(ra, rb, G[0], G[1], G[2], wa, wb, out, s);
     if (e != hipSuccess)
         return fail(FC_ERR_HIP, std::string("fc_cp_inner_noalloc: ") + hipGetErrorString(e));
@@ -2589,6 +2742,7 @@ fc_status solve_impl(fc_plan p, int rank_y, const double* w_y, const double* Y1,
     const int n = p->n;
     fc_status result = FC_OK;
     p->max_seen_rank = 0;
+    p->worst_missed = 0;
     reset_warm(p);
     for (int i = 0; i < 16; ++i) { p->site_ms[i] = 0; p->site_calls[i] = 0; }
     const auto t_solve = std::chrono::steady_clock::now();
@@ -2604,8 +2758,12 @@ fc_status solve_impl(fc_plan p, int rank_y, const double* w_y, const double* Y1,
         if (flag) throw FcError(FC_ERR_NUMERIC, "non-finite value in the design function");
         // entry transform Y_hat_l = V_l^T Y_l (into workspace tmp buffers)
         double* Yh[3] = {p->Yh[0], p->Yh[1], p->Yh[2]};
-        for (int l = 0; l < 3; ++l)
-            gemm(c, true, false, n, rank_y, n, 1.0, p->V[l], n, Y[l], n, 0.0, Yh[l], n);
+        {
+            KindTag tag(3);
+            fc::GemmArgs tr[3];
+            for (int l = 0; l < 3; ++l) tr[l] = prod(n, rank_y, n, p->Vt[l], n, Y[l], n, Yh[l], n);
+            gemm_group(c, false, false, tr, 3);
+        }
         Tucker& B = p->slot[0];
         const double* Yc[3] = {Yh[0], Yh[1], Yh[2]};
         canon_to_tucker(c, rank_y, w_y, Yc, 1e-2 * p->eps, B, "B = C2T(Y_hat)");
@@ -2662,6 +2820,7 @@ fc_status solve_impl(fc_plan p, int rank_y, const double* w_y, const double* Y1,
             info->precond_max_rel_err = active_pc_err(p);
             info->state_rank = p->st.Q;
             info->state_max_rel_err = p->st_err;
+            info->subspace_miss = p->worst_missed;
         }
         if (K > cap_u) result = fail(FC_ERR_RANK_OVERFLOW, "result rank exceeds cap_u");
         else if (so_out && Ks > so_out->cap) result = fail(FC_ERR_RANK_OVERFLOW, "state rank exceeds cap_s");
@@ -2713,11 +2872,18 @@ fc_status fc_solve2d(fc_plan p, int rank_y, const double* w_y, const double* Y1,
     const int cap = std::min(cap_u, 256);
     st = solve_impl(p, rank_y, w_y, Y1, Y2, p->Y3d, cap, rank_u, w_u, U1, U2, p->U3d, info, stream,
                     nullptr);
-    if (st != FC_OK) return st;
-    return guard([&] {
+    // the written iterate (a result, or the best iterate of a solve that did
+    // not converge) carries <U3[:, k], v1> = +-1 in its weights
+    if (st != FC_OK && st != FC_ERR_NOT_CONVERGED) return st;
+    if (*rank_u > cap) return st;
+    const std::string detail = st != FC_OK ? g_last_error : std::string();
+    const fc_status sc = guard([&] {
         HIPCHK(fc::scale_by_dot(p->n, *rank_u, p->U3d, p->n, v, w_u, s));
         HIPCHK(hipStreamSynchronize(s));
     });
+    if (sc != FC_OK) return sc;
+    if (st != FC_OK) g_last_error = detail;
+    return st;
 }
 
 fc_status fc_solve_state(fc_plan p, int rank_y, const double* w_y, const double* Y1,
@@ -2818,23 +2984,44 @@ fc_status fc_profile_gemm(int enable) {
 
 fc_status fc_profile_kernel_read(int kind, long* launches, double* total_ms, double* flops,
                                  double* bytes) {
-    if (kind == 0) return fc_profile_gemm_read(launches, total_ms, flops, bytes);
-    if (kind < 1 || kind > 2 || !launches || !total_ms || !flops || !bytes)
+    if (kind < 0 || kind >= kProfKinds || !launches || !total_ms || !flops || !bytes)
         return fail(FC_ERR_INVALID_ARG, "fc_profile_kernel_read: bad arguments");
-    KernelProfile& kp = k_prof[kind];
     double ms = 0;
-    for (size_t i = 0; i + 1 < kp.used; i += 2) {
-        if (hipEventSynchronize(kp.ev[i + 1]) != hipSuccess)
+    if (kind == 1 || kind == 2) {
+        KernelProfile& kp = k_prof[kind];
+        for (size_t i = 0; i + 1 < kp.used; i += 2) {
+            if (hipEventSynchronize(kp.ev[i + 1]) != hipSuccess)
+                return fail(FC_ERR_HIP, "hipEventSynchronize failed");
+            float t = 0;
+            if (hipEventElapsedTime(&t, kp.ev[i], kp.ev[i + 1]) != hipSuccess)
+                return fail(FC_ERR_HIP, "hipEventElapsedTime failed");
+            ms += t;
+        }
+        *launches = kp.launches;
+        *total_ms = ms;
+        *flops = kp.flops;
+        *bytes = kp.bytes;
+        return FC_OK;
+    }
+    long cnt = 0;
+    double fl = 0, by = 0;
+    for (size_t i = 0; i + 1 < g_prof.used && i / 2 < g_prof.shapes.size(); i += 2) {
+        const GemmShape& g = g_prof.shapes[i / 2];
+        if (g.kind != kind) continue;
+        if (hipEventSynchronize(g_prof.ev[i + 1]) != hipSuccess)
             return fail(FC_ERR_HIP, "hipEventSynchronize failed");
         float t = 0;
-        if (hipEventElapsedTime(&t, kp.ev[i], kp.ev[i + 1]) != hipSuccess)
+        if (hipEventElapsedTime(&t, g_prof.ev[i], g_prof.ev[i + 1]) != hipSuccess)
             return fail(FC_ERR_HIP, "hipEventElapsedTime failed");
         ms += t;
+        cnt += 1;
+        fl += g.flops;
+        by += g.bytes;
     }
-    *launches = kp.launches;
+    *launches = cnt;
     *total_ms = ms;
-    *flops = kp.flops;
-    *bytes = kp.bytes;
+    *flops = fl;
+    *bytes = by;
     return FC_OK;
 }
 
@@ -2852,13 +3039,14 @@ fc_status fc_profile_gemm_read(long* launches, double* total_ms, double* flops, 
     // diagnostic: per-launch shapes and times as CSV (environment FC_GEMMLOG = path)
     if (const char* path = std::getenv("FC_GEMMLOG")) {
         if (FILE* f = std::fopen(path, "w")) {
-            std::fprintf(f, "ta,tb,M,N,K,batch,inner,lowp,us\n");
+            std::fprintf(f, "kind,ta,tb,M,N,K,batch,inner,lowp,flops,bytes,us\n");
             for (size_t i = 0; i + 1 < g_prof.used && i / 2 < g_prof.shapes.size(); i += 2) {
                 float t = 0;
                 (void)hipEventElapsedTime(&t, g_prof.ev[i], g_prof.ev[i + 1]);
                 const GemmShape& g = g_prof.shapes[i / 2];
-                std::fprintf(f, "%d,%d,%d,%d,%d,%d,%d,%d,%.2f\n", g.ta, g.tb, g.M, g.N, g.K, g.batch,
-                             g.inner, g.lowp, 1000.0 * t);
+                std::fprintf(f, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%.6g,%.6g,%.2f\n", g.kind, g.ta, g.tb,
+                             g.M, g.N, g.K, g.batch, g.inner, g.lowp, g.flops, g.bytes,
+                             1000.0 * t);
             }
             std::fclose(f);
         }

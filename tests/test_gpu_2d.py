@@ -127,3 +127,32 @@ def test_batched_mixes_2d_and_3d_plans():
         assert np.array_equal(host(w_b), host(w_s))
         for a, b in zip(U_b, U_s):
             assert np.array_equal(host(a), host(b))
+
+
+def test_not_converged_iterate_keeps_its_sign():
+    """max_iter = 1: fc_solve2d reports FC_ERR_NOT_CONVERGED and still writes
+    the best iterate, with the third mode's <U3, v1> = +-1 folded into the
+    weights: the iterate approximates the solution (a flipped sign would give
+    a relative error of at least 1)."""
+    import ctypes as C
+    import torch
+    from paper_2006_09314_amd._lib import Info, lib
+    from tests.gpu_util import dev, host, plan_for
+    prob = wl.workload_paper_2d(128, 0.5)
+    plan = plan_for(prob, dims=2, max_iter=1, precond_rank=6)
+    w = torch.from_numpy(np.asarray(prob.w, dtype=np.float64)).cuda()
+    Y = [dev(y) for y in prob.Y]
+    cap = 256
+    w_u = torch.empty(cap, dtype=torch.float64, device="cuda")
+    U = [torch.empty((cap, prob.n), dtype=torch.float64, device="cuda").t() for _ in range(2)]
+    rank, info = C.c_int(), Info()
+    st = lib().fc_solve2d(plan.handle, prob.rank, w.data_ptr(), Y[0].data_ptr(), Y[1].data_ptr(),
+                          cap, C.byref(rank), w_u.data_ptr(), U[0].data_ptr(), U[1].data_ptr(),
+                          C.byref(info), None)
+    assert st == 3, st
+    k = rank.value
+    assert 0 < k <= cap
+    rep = solve2d.rel_error_2d(prob, host(w_u[:k]), [host(u[:, :k]) for u in U],
+                               sp=_spectral(prob))
+    print(f"[result] one iteration: rel_l2={rep['rel_l2']:.3e}", flush=True)
+    assert rep["rel_l2"] < 0.5, rep

@@ -196,6 +196,29 @@ def test_cp_truncate_nearly_dependent_columns():
             np.testing.assert_allclose(np.linalg.norm(host(o), axis=0), 1.0, rtol=1e-10)
 
 
+def test_cp_truncate_many_t2c_terms():
+    """Tucker ranks 96 in every mode: the Tucker-to-canonical step ranks
+    96 x 96 = 9216 candidate terms, more than its in-LDS sort holds, so the
+    device selection sorts in global memory; the result still meets the
+    error bound (measured with exact canonical inner products)."""
+    import torch
+    from tests.gpu_util import dev, host, plan_for
+    rng = np.random.default_rng(8)
+    n, m = 120, 96
+    F = [rng.standard_normal((n, m)) for _ in range(3)]
+    w = rng.uniform(0.5, 1.5, m)
+    plan = plan_for(wl.workload_small(n=n))
+    eps = 1e-6
+    wo, O = plan.cp_truncate(torch.from_numpy(w).cuda(), [dev(f) for f in F], eps, cap=9216)
+    wo, O = host(wo), [host(o) for o in O]
+    assert len(wo) > 96
+    tt = ot.cp_inner(w, F, w, F)
+    to = ot.cp_inner(w, F, wo, O)
+    oo = ot.cp_inner(wo, O, wo, O)
+    err = np.sqrt(max(tt - 2 * to + oo, 0.0) / tt)
+    assert err <= eps * (1 + 1e-3), err
+
+
 @pytest.mark.parametrize("which", [0, 1, 2])
 def test_apply_separable_matches_full_grid(which):
     import torch
@@ -223,6 +246,31 @@ def test_apply_separable_matches_full_grid(which):
     got = ot.cp_full(host(wo), [host(o) for o in O])
     want = Dt * T
     assert np.linalg.norm(got - want) <= 1.01 * eps * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("which", [0, 1, 2])
+def test_apply_separable_proper_subspace_n160(which):
+    """n = 160 > 128 subspace columns: the Hadamard truncation's mode
+    subspaces are proper subspaces of R^n (the input has Tucker rank 3, so
+    Q r > 128 candidate directions), and the result still meets the error
+    bound over the whole grid."""
+    import torch
+    from tests.gpu_util import dev, host, plan_for
+    n = 160
+    prob = wl.workload_quadratic(n=n, seed=9)
+    plan = plan_for(prob)
+    rng = np.random.default_rng(13)
+    F = [np.exp(-np.arange(n)[:, None] / 20.0) * rng.standard_normal((n, 3)) for _ in range(3)]
+    w = np.array([1.0, 0.3, -0.2])
+    eps = 1e-6
+    print(f"[case] apply_separable which={which} n={n}", flush=True)
+    wo, O = plan.apply_separable(which, torch.from_numpy(w).cuda(), [dev(f) for f in F], eps)
+    ws, Fs = plan.separable(which)
+    want = ot.cp_full(ws, Fs) * ot.cp_full(w, F)
+    got = ot.cp_full(host(wo), [host(o) for o in O])
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"[result] which={which}: rel err {err:.3e} rank {len(host(wo))}", flush=True)
+    assert err <= 1.01 * eps, err
 
 
 @pytest.mark.parametrize("maker", [lambda: wl.workload_sine(n=1024, seed=3),
