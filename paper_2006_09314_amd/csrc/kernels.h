@@ -48,11 +48,8 @@ hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_
 // products with few output tiles.  K is split into chunks of kc (128 or 256)
 // values, one workgroup per chunk and 32-row block; with more than one
 // chunk the partial tiles go to `part` (jobs x chunks x max M N doubles,
-// part_cap available) and the last workgroup of a row block adds them in
-// chunk order, counting in through `counters` (one unsigned per job and
-// 32-row block of the largest job, counter_cap available; zero before the
-// call and zero again after it, so calls sharing them must not overlap).
-// stream_fits says whether partials and counters fit.
+// part_cap available: stream_fits says whether they fit) and a second
+// kernel adds them in chunk order.
 struct StreamJob {
     int M = 0, N = 0, K = 0;
     double alpha = 1.0, beta = 0.0;
@@ -65,8 +62,8 @@ struct StreamJobs {
     StreamJob job[3];
 };
 hipError_t stream_multi(int layout, const StreamJobs& jobs, int kc, double* part, long part_cap,
-                        unsigned* counters, long counter_cap, hipStream_t s);
-bool stream_fits(const StreamJobs& jobs, int kc, long part_cap, long counter_cap);
+                        hipStream_t s);
+bool stream_fits(const StreamJobs& jobs, int kc, long part_cap);
 // Up to three independent plain FP64 products C = alpha op(A) op(B) + beta C
 // (strided or two-level batches, no scaling vector, whole K per block) in
 // one launch on the matrix cores: 32 x 32 tiles, one wavefront each.

@@ -409,21 +409,18 @@ __global__ __launch_bounds__(64 * GR_WAVES) void gram_multi_kernel(GramJobs jobs
 // (16x16x4) for every 32-column block of C in turn (the upper 16 columns
 // only where C has them), with the A operands in registers.  The four
 // partial tiles are summed in LDS in a fixed order.  With K split over
-// several chunks the partial tiles go to `part`, and the last workgroup of a
-// row block to finish (a counter per row block, reset by that workgroup)
-// adds them in chunk order, so the result does not depend on the schedule.
-// One thread per workgroup issues the device-scope fence: a fence costs a
-// write-back of the XCD's L2, so one per thread would cost a launch's
-// worth of time.
+// several chunks the partial tiles go to `part` and a second kernel adds
+// them in chunk order, so the result does not depend on the schedule.  (A
+// last-arriving workgroup could add them in the same launch, but the
+// device-scope fence each workgroup then needs writes back its XCD's L2:
+// measured, that costs more than the second launch.)
 constexpr int TR_WAVES = 4;
 
 template <int L, int STEPS>
 __global__ __launch_bounds__(64 * TR_WAVES) void stream_kernel(StreamJobs jobs, int ksplit,
-                                                               double* part, long pstride,
-                                                               unsigned* counters, int rbmax) {
+                                                               double* part, long pstride) {
     constexpr int KC = 4 * STEPS * TR_WAVES;
     __shared__ double red[TR_WAVES][4][4][64];
-    __shared__ int last;
     const StreamJob& J = jobs.job[blockIdx.y];
     const int rblocks = (J.M + 31) / 32;
     const int rb = blockIdx.x / ksplit, kz = blockIdx.x % ksplit;
@@ -495,44 +492,36 @@ __global__ __launch_bounds__(64 * TR_WAVES) void stream_kernel(StreamJobs jobs, 
         }
         __syncthreads();
     }
-    if (!split) return;
-    // the partial tile is written (and ordered for this workgroup by the
-    // barrier above); publish it and count in
-    if (threadIdx.x == 0) {
-        __threadfence();
-        last = atomicAdd(counters + (long)blockIdx.y * rbmax + rb, 1u) == (unsigned)ksplit - 1;
-        if (last) __threadfence();
-    }
-    __syncthreads();
-    if (!last) return;
+}
+
+// C = alpha sum_z part[z] + beta C for the jobs of a split streaming product
+__global__ void stream_reduce_kernel(StreamJobs jobs, int ksplit, const double* part,
+                                     long pstride) {
+    const StreamJob& J = jobs.job[blockIdx.y];
+    const long mn = (long)J.M * J.N;
     const double* pj = part + (long)blockIdx.y * ksplit * pstride;
-    for (int e = threadIdx.x; e < 32 * m; e += 64 * TR_WAVES) {
-        const int i = i0 + (e & 31), c = e >> 5;
-        if (i >= J.M) continue;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < mn;
+         e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % J.M), c = (int)(e / J.M);
         double sum = 0.0;
-        for (int z = 0; z < ksplit; ++z)
-            sum += __hip_atomic_load(pj + z * pstride + i + (long)J.M * c, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
+        for (int z = 0; z < ksplit; ++z) sum += pj[z * pstride + e];
         double* o = J.C + i + J.ldc * c;
         *o = J.alpha * sum + (J.beta != 0.0 ? J.beta * *o : 0.0);
     }
-    if (threadIdx.x == 0) atomicExch(counters + (long)blockIdx.y * rbmax + rb, 0u);
 }
 
 template <int L>
 static void stream_launch(int kc, const StreamJobs& jobs, int rbmax, int ksplit, double* part,
-                          long pstride, unsigned* counters, hipStream_t s) {
+                          long pstride, hipStream_t s) {
     const dim3 grid(rbmax * ksplit, jobs.count), block(64 * TR_WAVES);
     if (kc == 128)
-        hipLaunchKernelGGL((stream_kernel<L, 8>), grid, block, 0, s, jobs, ksplit, part, pstride,
-                           counters, rbmax);
+        hipLaunchKernelGGL((stream_kernel<L, 8>), grid, block, 0, s, jobs, ksplit, part, pstride);
     else
-        hipLaunchKernelGGL((stream_kernel<L, 16>), grid, block, 0, s, jobs, ksplit, part, pstride,
-                           counters, rbmax);
+        hipLaunchKernelGGL((stream_kernel<L, 16>), grid, block, 0, s, jobs, ksplit, part, pstride);
 }
 
 hipError_t stream_multi(int layout, const StreamJobs& jobs, int kc, double* part, long part_cap,
-                        unsigned* counters, long counter_cap, hipStream_t s) {
+                        hipStream_t s) {
     if (jobs.count <= 0) return hipSuccess;
     if (jobs.count > 3 || layout < 0 || layout > 2 || (kc != 128 && kc != 256))
         return hipErrorInvalidValue;
@@ -546,29 +535,31 @@ hipError_t stream_multi(int layout, const StreamJobs& jobs, int kc, double* part
         pmax = std::max(pmax, (long)J.M * J.N);
     }
     const int ksplit = (kmax + kc - 1) / kc;
-    if (ksplit > 1 && (!part || !counters || (long)jobs.count * ksplit * pmax > part_cap ||
-                       (long)jobs.count * rbmax > counter_cap))
+    if (ksplit > 1 && (!part || (long)jobs.count * ksplit * pmax > part_cap))
         return hipErrorInvalidValue;   // the caller checks stream_fits first
     if (layout == 0)
-        stream_launch<0>(kc, jobs, rbmax, ksplit, part, pmax, counters, s);
+        stream_launch<0>(kc, jobs, rbmax, ksplit, part, pmax, s);
     else if (layout == 1)
-        stream_launch<1>(kc, jobs, rbmax, ksplit, part, pmax, counters, s);
+        stream_launch<1>(kc, jobs, rbmax, ksplit, part, pmax, s);
     else
-        stream_launch<2>(kc, jobs, rbmax, ksplit, part, pmax, counters, s);
+        stream_launch<2>(kc, jobs, rbmax, ksplit, part, pmax, s);
+    if (ksplit > 1) {
+        const int blocks = (int)std::min<long>((pmax + 255) / 256, 1024);
+        hipLaunchKernelGGL(stream_reduce_kernel, dim3(blocks, jobs.count), dim3(256), 0, s, jobs,
+                           ksplit, part, pmax);
+    }
     return hipGetLastError();
 }
 
-bool stream_fits(const StreamJobs& jobs, int kc, long part_cap, long counter_cap) {
-    int kmax = 0, rbmax = 0;
+bool stream_fits(const StreamJobs& jobs, int kc, long part_cap) {
+    int kmax = 0;
     long pmax = 0;
     for (int t = 0; t < jobs.count; ++t) {
         kmax = std::max(kmax, jobs.job[t].K);
-        rbmax = std::max(rbmax, (jobs.job[t].M + 31) / 32);
         pmax = std::max(pmax, (long)jobs.job[t].M * jobs.job[t].N);
     }
     const int ksplit = (kmax + kc - 1) / kc;
-    return ksplit <= 1 ||
-           ((long)jobs.count * ksplit * pmax <= part_cap && (long)jobs.count * rbmax <= counter_cap);
+    return ksplit <= 1 || (long)jobs.count * ksplit * pmax <= part_cap;
 }
 
 hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s) {
@@ -880,7 +871,18 @@ __device__ inline double td_recip(double q) {
     return fma(r, t, r);
 }
 
-__global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
+// Scratch layout of one job (6 k^2 doubles): reflectors R (k x k, the lower
+// triangle of the reduced matrix), the eigenvectors X of the tridiagonal
+// matrix (element j of vector i at X[i + j k]), d, e, tau, the eigenvalues
+// (descending) and the number of vectors wanted.
+#define TD_X(k) ((long)(k) * (k))
+#define TD_D(k) (2L * (k) * (k))
+#define TD_E(k) (TD_D(k) + (k))
+#define TD_TAU(k) (TD_D(k) + 2L * (k))
+#define TD_LAM(k) (TD_D(k) + 3L * (k))
+#define TD_NV(k) (TD_D(k) + 4L * (k))
+
+__global__ __launch_bounds__(TD_THREADS) void tdeig_tri_kernel(EigJobs jobs) {
     extern __shared__ double sm[];
     __shared__ double sc[2];
     const EigJob& J = jobs.job[blockIdx.x];
@@ -904,6 +906,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
         if (tid == 0) { J.evals[0] = a[0]; J.V[0] = 1.0; }
         return;
     }
+    if (blockIdx.x >= (unsigned)jobs.count) return;
     // 1. tridiagonalisation; the first wavefront forms each reflector and the
     //    scalar products, so a step costs four barriers
     for (int j = 0; j + 2 < k; ++j) {
@@ -978,194 +981,233 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
     __syncthreads();
     for (int i = tid; i + 1 < k; i += blockDim.x) e2[i] = e[i] * e[i];
     __syncthreads();
-    // 2. eigenvalues by multisection: four lanes per eigenvalue, each
-    //    evaluating Sturm counts at two of eight interior points (two
-    //    independent recurrences per lane), so every step shrinks the bracket
-    //    nine-fold
-    double lo = 0.0, hi = 0.0, tnorm = 0.0;
+    // hand the reflectors (lower triangle of a), d, e and tau to the next phases
+    double* S = J.scratch;
+    for (int x = tid; x < k * k; x += blockDim.x) S[x] = a[x];
+    for (int i = tid; i < k; i += blockDim.x) {
+        S[TD_D(k) + i] = d[i];
+        S[TD_E(k) + i] = e[i];
+        S[TD_TAU(k) + i] = tau[i];
+    }
+}
+
+// Gershgorin bounds of the tridiagonal matrix (d, e): [lo, hi], and max |.|
+__device__ inline void td_bounds(int k, const double* d, const double* e, double& lo, double& hi,
+                                 double& tnorm) {
     for (int i = 0; i < k; ++i) {
         const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < k ? fabs(e[i]) : 0.0);
         lo = (i == 0) ? d[i] - r : fmin(lo, d[i] - r);
         hi = (i == 0) ? d[i] + r : fmax(hi, d[i] + r);
     }
     tnorm = fmax(fabs(lo), fabs(hi));
-    const double pivmin = fmax(1e-300, 1e-30 * tnorm * tnorm);
-    {
-        const int grp = tid >> 2, q = tid & 3;
-        const bool act = grp < k;
-        const int want = k - 1 - grp;   // number of eigenvalues below the target
-        double l = lo - 1e-14 * tnorm - 1e-300, h = hi + 1e-14 * tnorm + 1e-300;
-        for (int it = 0; it < 18; ++it) {   // 9^-18 of 2 |T| is below 1e-16 |T|
-            const double w = (h - l) / 9.0;
-            const double x1 = l + w * (2 * q + 1), x2 = l + w * (2 * q + 2);
-            int c1 = 0, c2 = 0;
-            if (act) {
-                double qa = d[0] - x1, qb = d[0] - x2;
-                if (fabs(qa) < pivmin) qa = -pivmin;
-                if (fabs(qb) < pivmin) qb = -pivmin;
-                c1 = qa < 0;
-                c2 = qb < 0;
-                for (int i = 1; i < k; ++i) {
-                    const double di = d[i], ee = e2[i - 1];
-                    qa = (di - x1) - ee * td_recip(qa);
-                    qb = (di - x2) - ee * td_recip(qb);
-                    if (fabs(qa) < pivmin) qa = -pivmin;
-                    if (fabs(qb) < pivmin) qb = -pivmin;
-                    c1 += qa < 0;
-                    c2 += qb < 0;
-                }
-            }
-            // Sturm counts are monotone in x: the first z of the eight points
-            // have at most `want` eigenvalues below them
-            int z = (c1 <= want) + (c2 <= want);
-            z += __shfl_xor(z, 1, 64);
-            z += __shfl_xor(z, 2, 64);
-            const double nl = (z == 0) ? l : l + w * z;
-            const double nh = (z == 8) ? h : l + w * (z + 1);
-            l = nl;
-            h = nh;
-        }
-        if (act && q == 0) lam[grp] = 0.5 * (l + h);
+}
+
+// 2. Eigenvalues by multisection on Sturm counts: one wavefront per
+//    eigenvalue, its 64 lanes counting at 64 interior points of the bracket,
+//    so every step shrinks the bracket 65-fold (10 steps: 65^-10 < 1e-18 of
+//    2 |T|).  Eight eigenvalues per workgroup, the workgroups of all jobs in
+//    one launch.
+__global__ __launch_bounds__(TD_THREADS) void tdeig_val_kernel(EigJobs jobs) {
+    __shared__ double d[128], e2[128], sb[4];
+    const EigJob& J = jobs.job[blockIdx.y];
+    const int k = J.k;
+    if (k <= 1 || (int)blockIdx.x * (TD_THREADS / 64) >= k) return;
+    const double* S = J.scratch;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int i = tid; i < k; i += blockDim.x) {
+        d[i] = S[TD_D(k) + i];
+        const double ee = S[TD_E(k) + i];
+        e2[i] = (i + 1 < k) ? ee * ee : 0.0;
     }
-    __syncthreads();
-    __shared__ int nvec_s;
     if (tid == 0) {
-        int nv = k;
-        if (J.budget >= 0.0) {
-            double tail = 0.0;
-            int rr = k;
-            for (int i = k - 1; i >= 0; --i) {
-                tail += fmax(lam[i], 0.0);
-                if (tail <= J.budget) rr = i; else break;
-            }
-            int numrank = 0;
-            const double tmax = fmax(lam[0], 0.0);
-            while (numrank < k && lam[numrank] > 1e-17 * tmax) ++numrank;
-            nv = min(max(numrank, 1), max(rr + J.margin, 1));
-            nv = min(nv, k);
-        }
-        nvec_s = nv;
+        double lo = 0, hi = 0, tn = 0;
+        td_bounds(k, S + TD_D(k), S + TD_E(k), lo, hi, tn);
+        sb[0] = lo; sb[1] = hi; sb[2] = tn;
     }
     __syncthreads();
-    const int nvec = nvec_s;
-    // 3. inverse iteration, thread i owns eigenvector i (coalesced scratch)
-    double* X = J.scratch;                    // X[i + j k]: element j of vector i
-    double* U0 = X + (long)k * k;             // pivoted LU factors (U0: reciprocal pivots)
-    double* U1 = U0 + (long)k * k;
-    double* U2 = U1 + (long)k * k;
-    double* ML = U2 + (long)k * k;            // multipliers, sign encodes the interchange
+    const int grp = blockIdx.x * (TD_THREADS / 64) + wv;
+    if (grp >= k) return;
+    const double tnorm = sb[2];
+    const double pivmin = fmax(1e-300, 1e-30 * tnorm * tnorm);
+    const int want = k - 1 - grp;   // number of eigenvalues below the target
+    double l = sb[0] - 1e-14 * tnorm - 1e-300, h = sb[1] + 1e-14 * tnorm + 1e-300;
+    for (int it = 0; it < 10; ++it) {
+        const double w = (h - l) / 65.0;
+        const double x = l + w * (lane + 1);
+        double q = d[0] - x;
+        if (fabs(q) < pivmin) q = -pivmin;
+        int c = q < 0;
+        for (int i = 1; i < k; ++i) {
+            q = (d[i] - x) - e2[i - 1] * td_recip(q);
+            if (fabs(q) < pivmin) q = -pivmin;
+            c += q < 0;
+        }
+        // counts are monotone in x: the first z points have at most `want`
+        // eigenvalues below them
+        const int z = __popcll(__ballot(c <= want));
+        const double nl = l + w * z;
+        const double nh = (z == 64) ? h : l + w * (z + 1);
+        l = nl;
+        h = nh;
+    }
+    if (lane == 0) J.scratch[TD_LAM(k) + grp] = 0.5 * (l + h);
+}
+
+// the rank rule of the truncations on the eigenvalues (descending): the
+// number of eigenvectors wanted
+__device__ inline int td_nvec(const EigJob& J, const double* lam) {
+    const int k = J.k;
+    if (J.budget < 0.0) return k;
+    double tail = 0.0;
+    int rr = k;
+    for (int i = k - 1; i >= 0; --i) {
+        tail += fmax(lam[i], 0.0);
+        if (tail <= J.budget) rr = i; else break;
+    }
+    int numrank = 0;
+    const double tmax = fmax(lam[0], 0.0);
+    while (numrank < k && lam[numrank] > 1e-17 * tmax) ++numrank;
+    return min(min(max(numrank, 1), max(rr + J.margin, 1)), k);
+}
+
+// 3. Eigenvectors of the tridiagonal matrix by inverse iteration with a
+//    partially pivoted LU (reciprocal pivots), one vector per thread,
+//    TD_VPB vectors per workgroup, the factors and the iterate in LDS.
+constexpr int TD_VPB = 16;
+__global__ __launch_bounds__(64) void tdeig_vec_kernel(EigJobs jobs) {
+    extern __shared__ double lu[];
+    __shared__ double dd[128], ee[128], sb[2];
+    __shared__ int nv_s;
+    const EigJob& J = jobs.job[blockIdx.y];
+    const int k = J.k;
+    if (k <= 1 || (int)blockIdx.x * TD_VPB >= k) return;
+    double* S = J.scratch;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < k; i += blockDim.x) {
+        dd[i] = S[TD_D(k) + i];
+        ee[i] = S[TD_E(k) + i];
+    }
+    if (tid == 0) {
+        const int nv = td_nvec(J, S + TD_LAM(k));
+        nv_s = nv;
+        if (blockIdx.x == 0) S[TD_NV(k)] = (double)nv;
+        double lo = 0, hi = 0, tn = 0;
+        td_bounds(k, S + TD_D(k), S + TD_E(k), lo, hi, tn);
+        sb[0] = tn;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * TD_VPB + tid;
+    if (tid >= TD_VPB || i >= nv_s) return;
+    const double tnorm = sb[0];
     const double smallpiv = 1e-15 * fmax(tnorm, 1e-300);
-    if (tid < nvec) {
-        const int i = tid;
-        const double lm = lam[i] + 4e-16 * tnorm * (1 + (i % 3));
-        // factor T - lm I (rows: sub c_j = e[j-1], diag, super e[j])
-        double ad = d[0] - lm, bd = (k > 1) ? e[0] : 0.0, fd = 0.0;
-        for (int j = 0; j + 1 < k; ++j) {
-            const double c = e[j];
-            const double an = d[j + 1] - lm;
-            const double bn = (j + 2 < k) ? e[j + 1] : 0.0;
-            if (fabs(ad) >= fabs(c)) {
-                const double mlt = (ad != 0.0) ? c / ad : 0.0;
-                U0[i + (long)j * k] = 1.0 / ((fabs(ad) < smallpiv) ? copysign(smallpiv, ad) : ad);
-                U1[i + (long)j * k] = bd;
-                U2[i + (long)j * k] = fd;
-                ML[i + (long)j * k] = mlt;
-                ML[i + (long)j * k + (long)k * k] = 0.0;
-                ad = an - mlt * bd;
-                bd = bn - mlt * fd;
-                fd = 0.0;
-            } else {
-                const double mlt = ad / c;
-                U0[i + (long)j * k] = 1.0 / c;
-                U1[i + (long)j * k] = an;
-                U2[i + (long)j * k] = bn;
-                ML[i + (long)j * k] = mlt;
-                ML[i + (long)j * k + (long)k * k] = 1.0;
-                const double na = bd - mlt * an;
-                const double nb = fd - mlt * bn;
-                ad = na;
-                bd = nb;
-                fd = 0.0;
-            }
-        }
-        U0[i + (long)(k - 1) * k] = 1.0 / ((fabs(ad) < smallpiv) ? copysign(smallpiv, ad) : ad);
-        U1[i + (long)(k - 1) * k] = 0.0;
-        U2[i + (long)(k - 1) * k] = 0.0;
-        // start vector
-        for (int j = 0; j < k; ++j) X[i + (long)j * k] = 1.0 + 0.37 * ((j * 7 + i * 13) % 11) / 11.0;
-        const long KK = (long)k * k;
-        for (int it = 0; it < 3; ++it) {
-            // forward: apply the row operations to the right-hand side
-            double carry = X[i];
-            for (int j0 = 0; j0 + 1 < k; j0 += 8) {
-                const int jn = min(8, k - 1 - j0);
-                double ml[8], sw[8], xs[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (q < jn) {
-                        ml[q] = ML[i + (long)(j0 + q) * k];
-                        sw[q] = ML[i + (long)(j0 + q) * k + KK];
-                        xs[q] = X[i + (long)(j0 + q + 1) * k];
-                    }
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (q < jn) {
-                        double r0 = carry, r1 = xs[q];
-                        if (sw[q] != 0.0) { const double t2 = r0; r0 = r1; r1 = t2; }
-                        r1 -= ml[q] * r0;
-                        X[i + (long)(j0 + q) * k] = r0;
-                        carry = r1;
-                    }
-            }
-            X[i + (long)(k - 1) * k] = carry;
-            // back substitution
-            double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-            for (int j1 = k - 1; j1 >= 0; j1 -= 8) {
-                const int jn = min(8, j1 + 1);
-                double u0[8], u1[8], u2[8], rh[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (q < jn) {
-                        const long o = i + (long)(j1 - q) * k;
-                        u0[q] = U0[o]; u1[q] = U1[o]; u2[q] = U2[o]; rh[q] = X[o];
-                    }
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (q < jn) {
-                        const double v = (rh[q] - u1[q] * x1 - u2[q] * x2) * u0[q];
-                        X[i + (long)(j1 - q) * k] = v;
-                        x2 = x1;
-                        x1 = v;
-                        nrm += v * v;
-                    }
-            }
-            const double inv = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
-            for (int j = 0; j < k; ++j) X[i + (long)j * k] *= inv;
+    // LDS arrays [j][TD_VPB]: U0 (reciprocal pivots), U1, U2, ML (multipliers),
+    // SW (row interchange), X (iterate)
+    double* U0 = lu;
+    double* U1 = U0 + k * TD_VPB;
+    double* U2 = U1 + k * TD_VPB;
+    double* ML = U2 + k * TD_VPB;
+    double* SW = ML + k * TD_VPB;
+    double* X = SW + k * TD_VPB;
+#define TDV(A, j) A[(j) * TD_VPB + tid]
+    const double lm = S[TD_LAM(k) + i] + 4e-16 * tnorm * (1 + (i % 3));
+    // factor T - lm I (rows: sub c_j = e[j-1], diag, super e[j])
+    double ad = dd[0] - lm, bd = (k > 1) ? ee[0] : 0.0, fd = 0.0;
+    for (int j = 0; j + 1 < k; ++j) {
+        const double c = ee[j];
+        const double an = dd[j + 1] - lm;
+        const double bn = (j + 2 < k) ? ee[j + 1] : 0.0;
+        if (fabs(ad) >= fabs(c)) {
+            const double mlt = (ad != 0.0) ? c / ad : 0.0;
+            TDV(U0, j) = 1.0 / ((fabs(ad) < smallpiv) ? copysign(smallpiv, ad) : ad);
+            TDV(U1, j) = bd;
+            TDV(U2, j) = fd;
+            TDV(ML, j) = mlt;
+            TDV(SW, j) = 0.0;
+            ad = an - mlt * bd;
+            bd = bn - mlt * fd;
+            fd = 0.0;
+        } else {
+            const double mlt = ad / c;
+            TDV(U0, j) = 1.0 / c;
+            TDV(U1, j) = an;
+            TDV(U2, j) = bn;
+            TDV(ML, j) = mlt;
+            TDV(SW, j) = 1.0;
+            const double na = bd - mlt * an;
+            const double nb = fd - mlt * bn;
+            ad = na;
+            bd = nb;
+            fd = 0.0;
         }
     }
+    TDV(U0, k - 1) = 1.0 / ((fabs(ad) < smallpiv) ? copysign(smallpiv, ad) : ad);
+    TDV(U1, k - 1) = 0.0;
+    TDV(U2, k - 1) = 0.0;
+    for (int j = 0; j < k; ++j) TDV(X, j) = 1.0 + 0.37 * ((j * 7 + i * 13) % 11) / 11.0;
+    for (int it = 0; it < 3; ++it) {
+        // forward: the row operations on the right-hand side
+        double carry = TDV(X, 0);
+        for (int j = 0; j + 1 < k; ++j) {
+            double r0 = carry, r1 = TDV(X, j + 1);
+            if (TDV(SW, j) != 0.0) { const double t2 = r0; r0 = r1; r1 = t2; }
+            r1 -= TDV(ML, j) * r0;
+            TDV(X, j) = r0;
+            carry = r1;
+        }
+        TDV(X, k - 1) = carry;
+        // back substitution
+        double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+        for (int j = k - 1; j >= 0; --j) {
+            const double v = (TDV(X, j) - TDV(U1, j) * x1 - TDV(U2, j) * x2) * TDV(U0, j);
+            TDV(X, j) = v;
+            x2 = x1;
+            x1 = v;
+            nrm += v * v;
+        }
+        const double inv = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
+        for (int j = 0; j < k; ++j) TDV(X, j) *= inv;
+    }
+    for (int j = 0; j < k; ++j) S[TD_X(k) + i + (long)j * k] = TDV(X, j);
+#undef TDV
+}
+
+// 4. Vectors of clusters of close eigenvalues (descending order) are
+//    re-orthogonalised against ALL their predecessors: inverse iteration
+//    returns nearly parallel vectors inside a cluster, and normalising what
+//    is left after removing the cluster alone would magnify their rounding
+//    components along the other eigenvectors.  Dot products one wavefront
+//    per predecessor, one subtraction sweep, two passes, then normalise.
+//    Vectors of eigenvalues at most 1e-17 of the largest in magnitude are
+//    not refined (callers never use them) and are skipped as predecessors.
+//    One workgroup per matrix; it returns at once when there is no cluster.
+__global__ __launch_bounds__(TD_THREADS) void tdeig_clu_kernel(EigJobs jobs) {
+    extern __shared__ double sm[];
+    __shared__ int any_s;
+    const EigJob& J = jobs.job[blockIdx.x];
+    const int k = J.k;
+    if (k <= 1) return;
+    double* S = J.scratch;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int kp = k + 1;
+    const double* lam = S + TD_LAM(k);
+    const int nvec = (int)S[TD_NV(k)];
+    const double lmax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
+    if (tid == 0) {
+        int any = 0;
+        for (int i = 1; i < nvec && !any; ++i)
+            any = fabs(lam[i]) > 1e-17 * lmax && lam[i - 1] - lam[i] < 1e-9 * lmax;
+        any_s = any;
+    }
     __syncthreads();
-    // The reflectors move to global scratch (the LU factors are no longer
-    // needed) and the eigenvectors of T into LDS, one contiguous column per
-    // vector (ld kp).
-    double* Rf = U0;
-    for (int x = tid; x < k * k; x += blockDim.x) Rf[x] = a[x];
-    __syncthreads();
-    double* Xl = a;
+    if (!any_s) return;
+    double* Xl = sm;                      // vector i at Xl + i kp
+    double* pw = sm + (long)k * kp;       // dot products
+    double* used = pw + k;                // 1 for a vector that is refined
+    double* X = S + TD_X(k);
     for (int x = tid; x < nvec * k; x += blockDim.x) {
         const int i = x % nvec, j = x / nvec;
         Xl[j + (long)i * kp] = X[i + (long)j * k];
     }
-    __syncthreads();
-    // 4. Vectors of clusters of close eigenvalues (descending order) are
-    //    re-orthogonalised against ALL their predecessors: inverse iteration
-    //    returns nearly parallel vectors inside a cluster, and normalising what
-    //    is left after removing the cluster alone would magnify their rounding
-    //    components along the other eigenvectors.  Dot products one wavefront
-    //    per predecessor, one subtraction sweep, two passes, then normalise.
-    //    Vectors of eigenvalues at most 1e-17 of the largest in magnitude are
-    //    not refined (callers never use them) and are skipped as predecessors.
-    const double lmax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
-    double* used = e2;   // no longer needed: 1 for a vector that is refined
     for (int i = tid; i < k; i += blockDim.x) used[i] = fabs(lam[i]) > 1e-17 * lmax ? 1.0 : 0.0;
     __syncthreads();
     for (int i = 1; i < nvec; ++i) {
@@ -1202,43 +1244,56 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_kernel(EigJobs jobs) {
         }
         __syncthreads();
     }
-    // 5. back-transformation V = H_0 ... H_{k-3} X (reflector j acts on rows
-    //    j+1..k-1).  Wavefront w owns columns w, w+8, ... and applies every
-    //    reflector to them in turn, so the wavefronts never wait for each
-    //    other; lane l holds rows l and l+64 of the reflector, loaded one
-    //    reflector ahead (k <= 128, so two rows per lane cover it).
-    {
-        auto refl = [&](int jj, int r) {
-            return r < k - jj - 1 ? Rf[(jj + 1 + r) + (long)jj * k] : 0.0;
-        };
+    for (int x = tid; x < nvec * k; x += blockDim.x) {
+        const int i = x % nvec, j = x / nvec;
+        X[i + (long)j * k] = Xl[j + (long)i * kp];
+    }
+}
+
+// 5. Back-transformation V = H_0 ... H_{k-3} X (reflector j acts on rows
+//    j+1..k-1): one wavefront per eigenvector, lane l holding rows l and
+//    l + 64 of the vector and of each reflector (read from scratch one
+//    reflector ahead), eight vectors per workgroup, all jobs in one launch.
+//    Vectors of eigenvalues at most 1e-17 of the largest in magnitude are
+//    written as they are.  The first workgroup of a job writes its
+//    eigenvalues.
+__global__ __launch_bounds__(TD_THREADS) void tdeig_back_kernel(EigJobs jobs) {
+    const EigJob& J = jobs.job[blockIdx.y];
+    const int k = J.k;
+    if (k <= 1) return;
+    const double* S = J.scratch;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double* lam = S + TD_LAM(k);
+    if (blockIdx.x == 0)
+        for (int i = tid; i < k; i += blockDim.x) J.evals[i] = lam[i];
+    const int nvec = (int)S[TD_NV(k)];
+    const int i = blockIdx.x * (TD_THREADS / 64) + wv;
+    if (i >= nvec) return;
+    const double lmax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
+    const double* X = S + TD_X(k);
+    const int r0 = lane, r1 = lane + 64;
+    double x0 = r0 < k ? X[i + (long)r0 * k] : 0.0;
+    double x1 = r1 < k ? X[i + (long)r1 * k] : 0.0;
+    if (fabs(lam[i]) > 1e-17 * lmax) {
+        const double* R = S;   // reflector j: R[rho + j k], rho > j
+        auto refl = [&](int jj, int rho) { return (rho > jj && rho < k) ? R[rho + (long)jj * k] : 0.0; };
         double c0 = 0.0, c1 = 0.0;
-        if (k >= 3) { c0 = refl(k - 3, lane); c1 = refl(k - 3, lane + 64); }
+        if (k >= 3) { c0 = refl(k - 3, r0); c1 = refl(k - 3, r1); }
         for (int j = k - 3; j >= 0; --j) {
             double n0 = 0.0, n1 = 0.0;
-            if (j > 0) { n0 = refl(j - 1, lane); n1 = refl(j - 1, lane + 64); }
-            const double t = tau[j];
+            if (j > 0) { n0 = refl(j - 1, r0); n1 = refl(j - 1, r1); }
+            const double t = S[TD_TAU(k) + j];
             if (t != 0.0) {
-                const int m = k - j - 1;
-                for (int i = wv; i < nvec; i += TD_THREADS / 64) {
-                    if (used[i] == 0.0) continue;
-                    double* col = Xl + (long)i * kp + (j + 1);
-                    const double x0 = lane < m ? col[lane] : 0.0;
-                    const double x1 = lane + 64 < m ? col[lane + 64] : 0.0;
-                    const double sj = t * td_wave_sum(c0 * x0 + c1 * x1);
-                    if (lane < m) col[lane] = x0 - sj * c0;
-                    if (lane + 64 < m) col[lane + 64] = x1 - sj * c1;
-                }
+                const double sj = t * td_wave_sum(c0 * x0 + c1 * x1);
+                x0 -= sj * c0;
+                x1 -= sj * c1;
             }
             c0 = n0;
             c1 = n1;
         }
     }
-    __syncthreads();
-    for (int x = tid; x < k * nvec; x += blockDim.x) {
-        const int r = x % k, i = x / k;
-        J.V[r + (long)i * J.ldv] = Xl[r + (long)i * kp];
-    }
-    for (int i = tid; i < k; i += blockDim.x) J.evals[i] = lam[i];
+    if (r0 < k) J.V[r0 + (long)i * J.ldv] = x0;
+    if (r1 < k) J.V[r1 + (long)i * J.ldv] = x1;
 }
 
 hipError_t sym_eig_multi(const EigJobs& jobs, hipStream_t s) {
@@ -1248,17 +1303,31 @@ hipError_t sym_eig_multi(const EigJobs& jobs, hipStream_t s) {
         kmax = std::max(kmax, jobs.job[i].k);
     }
     if (jobs.count <= 0 || kmax <= 0) return hipSuccess;
-    const int kp = kmax + (kmax & 1);
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
     std::call_once(once, [] {
-        attr_err = hipFuncSetAttribute((const void*)tdeig_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        hipError_t e = hipFuncSetAttribute((const void*)tdeig_tri_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)tdeig_clu_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)tdeig_vec_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 100 * 1024);
+        attr_err = e;
     });
     if (attr_err != hipSuccess) return attr_err;
-    (void)kp;
-    hipLaunchKernelGGL(tdeig_kernel, dim3(jobs.count), dim3(TD_THREADS),
+    const int per = TD_THREADS / 64;
+    hipLaunchKernelGGL(tdeig_tri_kernel, dim3(jobs.count), dim3(TD_THREADS),
                        sizeof(double) * ((size_t)kmax * (kmax + 1) + 7 * kmax), s, jobs);
+    hipLaunchKernelGGL(tdeig_val_kernel, dim3((kmax + per - 1) / per, jobs.count),
+                       dim3(TD_THREADS), 0, s, jobs);
+    hipLaunchKernelGGL(tdeig_vec_kernel, dim3((kmax + TD_VPB - 1) / TD_VPB, jobs.count), dim3(64),
+                       sizeof(double) * 6 * (size_t)kmax * TD_VPB, s, jobs);
+    hipLaunchKernelGGL(tdeig_clu_kernel, dim3(jobs.count), dim3(TD_THREADS),
+                       sizeof(double) * ((size_t)kmax * (kmax + 1) + 2 * kmax), s, jobs);
+    hipLaunchKernelGGL(tdeig_back_kernel, dim3((kmax + per - 1) / per, jobs.count),
+                       dim3(TD_THREADS), 0, s, jobs);
     return hipGetLastError();
 }
 

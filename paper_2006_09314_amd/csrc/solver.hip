@@ -167,8 +167,6 @@ struct fc_plan_s {
     long cap_canon = 0;
     int* dflag = nullptr;
     unsigned* dotcnt = nullptr;   // zero between calls of the device dot
-    unsigned* trcount = nullptr;  // row-block counters of the streaming kernel (zero between calls)
-    long trcount_cap = 0;
     long ys_cap = 0;              // doubles in Ys and in Ts
     long e_cap = 0;               // doubles in E
     hipStream_t stream = nullptr;
@@ -341,13 +339,11 @@ bool is_transform(const Ctx& c, bool ta, bool tb, const GemmArgs& g) {
            g.K == c.n && g.alpha == 1.0 && g.beta == 0.0 && g.N > 0;
 }
 
-// Products for the streaming kernel: the mode transforms, and the unbatched
-// Gram-type products with at most 128 x 128 outputs (few output tiles: K is
-// split over workgroups instead).
+// The mode transforms run on the streaming kernel (K split over workgroups,
+// partials added by a second kernel).  The small Gram-type products stay on
+// the Gram kernel: one launch each, where the split would need two (the
+// batched path is bound by the launch rate).
 int stream_layout(bool ta, bool tb) { return ta ? 0 : (tb ? 1 : 2); }
-bool streamable(bool ta, bool tb, const GemmArgs& g) {
-    return gram_type(ta, tb, g) && !g.d && g.batch == 1 && (long)g.M * g.N <= 128L * 128;
-}
 
 // Up to three products in one launch of the streaming kernel (split-K
 // partials in the plan's GEMM workspace).
@@ -362,8 +358,8 @@ hipError_t run_stream(const Ctx& c, bool ta, bool tb, const GemmArgs* g, int cou
         J.C = g[t].C; J.ldc = g[t].ldc;
     }
     fc_plan_s* p = c.p;
-    const int kc = fc::stream_fits(sj, 128, p->splitws_cap, p->trcount_cap) ? 128 : 256;
-    if (!fc::stream_fits(sj, kc, p->splitws_cap, p->trcount_cap)) {
+    const int kc = fc::stream_fits(sj, 128, p->splitws_cap) ? 128 : 256;
+    if (!fc::stream_fits(sj, kc, p->splitws_cap)) {
         // partials beyond the workspace: the Gram kernel, one product at a time
         for (int t = 0; t < count; ++t) {
             const hipError_t e = fc::gram(ta, tb, g[t], c.s);
@@ -371,8 +367,7 @@ hipError_t run_stream(const Ctx& c, bool ta, bool tb, const GemmArgs* g, int cou
         }
         return hipSuccess;
     }
-    return fc::stream_multi(stream_layout(ta, tb), sj, kc, p->splitws, p->splitws_cap, p->trcount,
-                            p->trcount_cap, c.s);
+    return fc::stream_multi(stream_layout(ta, tb), sj, kc, p->splitws, p->splitws_cap, c.s);
 }
 
 // Route one product: Gram-type ones to the split-over-waves kernel, the
@@ -381,8 +376,7 @@ hipError_t run_stream(const Ctx& c, bool ta, bool tb, const GemmArgs* g, int cou
 // kernels.
 hipError_t run_gemm(const Ctx& c, bool ta, bool tb, const GemmArgs& g) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    if ((t_tag == 3 && is_transform(c, ta, tb, g)) || streamable(ta, tb, g))
-        return run_stream(c, ta, tb, &g, 1);
+    if (t_tag == 3 && is_transform(c, ta, tb, g)) return run_stream(c, ta, tb, &g, 1);
     if (gram_type(ta, tb, g)) return fc::gram(ta, tb, g, c.s);
     return fc::gemm(ta, tb, g, c.s);
 }
@@ -438,10 +432,8 @@ void launch_group(const Ctx& c, bool ta, bool tb, const fc::GramJobs& jobs, bool
     if (jobs.count == 0) return;
     bool transform = gram && t_tag == 3 && !ta && !tb;
     for (int t = 0; t < jobs.count && transform; ++t) transform = is_transform(c, ta, tb, jobs.g[t]);
-    bool stream = gram;
-    for (int t = 0; t < jobs.count && stream; ++t) stream = streamable(ta, tb, jobs.g[t]);
     auto run = [&] {
-        if (transform || stream) return run_stream(c, ta, tb, jobs.g, jobs.count);
+        if (transform) return run_stream(c, ta, tb, jobs.g, jobs.count);
         return gram ? fc::gram_multi(ta, tb, jobs, c.s) : fc::gemm_multi(ta, tb, jobs, c.s);
     };
     if (g_prof.on && !t_no_profile) {
@@ -1832,10 +1824,6 @@ void alloc_workspace(fc_plan_s* p) {
     p->splitws = A.alloc((size_t)p->splitws_cap);
     p->dflag = A.alloc_int(4);
     p->dotcnt = (unsigned*)A.alloc_int(1);
-    p->trcount_cap = 3L * std::max(512, (n + 31) / 32);
-    p->trcount = (unsigned*)A.alloc_int((size_t)p->trcount_cap);
-    if (hipMemset(p->trcount, 0, sizeof(unsigned) * p->trcount_cap) != hipSuccess)
-        throw FcError(FC_ERR_HIP, "hipMemset failed");
     const unsigned zero = 0;
     if (hipMemcpy(p->dotcnt, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
         throw FcError(FC_ERR_HIP, "hipMemcpy failed");
