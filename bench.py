@@ -192,14 +192,17 @@ def batch_io(api, torch, dev, probs, cap):
 
 KERNELS = {0: "gemm_kernel / gemm_multi_kernel (short-reduction LDS-tiled FP64 MFMA GEMMs)",
            1: "panel_mgs_kernel (Gram-Schmidt panel, one workgroup)",
-           2: "tdeig_kernel (symmetric eigensolver, one workgroup per matrix)",
-           3: "transform_kernel (mode transforms V^T Y, V Z on FP64 MFMA)",
+           2: "tdeig_*_kernel (symmetric eigensolver: tridiagonalisation, multisection, inverse "
+              "iteration, clusters, back-transformation; five launches per call)",
+           3: "stream_kernel + stream_reduce_kernel (mode transforms V^T Y, V Z on FP64 MFMA)",
            4: "gram_kernel / gram_multi_kernel (long-reduction FP64 MFMA: Gram-type products, "
               "scaled Grams Z^T diag(d) X, core contractions)",
            5: "kron_apply_kernel (fused sum_q diag(D[:,q]) Z T^q on FP64 MFMA)"}
-# kernel names of each kind in rocprofv3 traces (for the traffic records)
-KERNEL_NAMES = {0: "gemm_family_short", 1: "panel_mgs_kernel", 2: "tdeig_kernel",
-                3: "transform_kernel", 4: "gram_family", 5: "kron_apply_kernel"}
+# names of the traffic records (profiles/*.md) of each kind: HBM bytes per
+# launch of the family (an eigensolver call is five dispatches, a transform
+# group two)
+KERNEL_NAMES = {0: "short_gemm", 1: "panel_mgs_kernel", 2: "eigensolver", 3: "mode_transform",
+                4: "long_gram", 5: "kron_apply_kernel"}
 KIND_KEYS = {0: "short_gemm", 1: "gram_schmidt_panel", 2: "eigensolver", 3: "mode_transform",
              4: "long_gram", 5: "kron_apply"}
 
@@ -335,7 +338,8 @@ def main():
     out = (torch.empty(cap, dtype=torch.float64, device=dev),
            [torch.empty((cap, prob.n), dtype=torch.float64, device=dev).t() for _ in range(3)])
     res = plan.solve(w, Y, cap_u=cap, out=out)
-    log(f"[bench] setup {setup_s:.2f}s; warm-up solve {res[2]}")
+    tuning = plan.tuning()
+    log(f"[bench] setup {setup_s:.2f}s; autotuner {tuning}; warm-up solve {res[2]}")
     torch.cuda.synchronize()
     check(lib().fc_profile_gemm(1), "fc_profile_gemm")
     t0 = time.perf_counter()
@@ -509,7 +513,7 @@ def main():
                    "step": f"one batched call solving {len(probs)} problems",
                    "n": 1024, "rank_y": 10, "alpha": 0.5, "beta": 1e-4, "gamma": 1.0,
                    "eps": 1e-6, "path": "fp64, concurrent streams"},
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "autotune": tuning,
         "fp64_single": single, "batched": batched, "mixed_single": mixed,
         "mixed_batched": mixed_batched, "batched_uneven": uneven,
     }

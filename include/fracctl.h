@@ -226,6 +226,17 @@ fc_status fc_plan_spectrum(fc_plan plan, double* lam, double* V);
  * (ascending mu_k), not by the eigenpairs of A_l. */
 fc_status fc_plan_separable(fc_plan plan, int which, int cap, int* rank, double* w, double* F);
 
+/* Launch choices the autotuner picked for the plan at setup (per device, n
+ * and operator rank; kept in a disk cache, environment FC_TUNE_CACHE, else
+ * $HOME/.cache/fracctl/tune_v1.txt; FC_TUNE=0 keeps the defaults).  HOST
+ * outputs: choices[0..5] = wavefronts per workgroup of the Gram kernel for
+ * batched and for single products (8 or 16), of the fused Kronecker
+ * application (8 or 16), K chunk of the streaming transform kernel (128 or
+ * 256), Gram-Schmidt panel width (8 or 16), 1 if tuned; us (may be NULL):
+ * the measured times of the ten candidates (us; two per choice, in that
+ * order, the panel widths per orthonormalisation of three n x 96 blocks). */
+fc_status fc_plan_tuning(fc_plan plan, int* choices, double* us);
+
 /* ---- building blocks of the path, exposed for testing (DEVICE buffers) ---- */
 
 /* Mode transform (Section 3.3): out = V_l^T X (transpose = 1, into

@@ -95,6 +95,7 @@ PROTOTYPES = {
     "fc_destroy": (None, [_VP]),
     "fc_plan_spectrum": (_I, [_VP, _PD, _PD]),
     "fc_plan_separable": (_I, [_VP, _I, _I, _PI, _PD, _PD]),
+    "fc_plan_tuning": (_I, [_VP, _PI, _PD]),
     "fc_mode_transform": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP]),
     "fc_cp_inner": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _I, _VP, _VP, _VP, _VP, _PD, _VP]),
     "fc_cp_inner_noalloc": (_I, [_I, _I, _VP, _VP, _VP, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP]),

@@ -100,6 +100,18 @@ class Plan:
                                       F.ctypes.data_as(C.POINTER(C.c_double))), "fc_plan_separable")
         return w, [F[l * n * cap:(l + 1) * n * cap].reshape(n, cap, order="F") for l in range(3)]
 
+    def tuning(self):
+        """The autotuner's choices for this plan and the measured candidate
+        times (fc_plan_tuning)."""
+        ch = (C.c_int * 6)()
+        us = (C.c_double * 10)()
+        check(lib().fc_plan_tuning(self.handle, ch, us), "fc_plan_tuning")
+        names = ("gram_batched_waves", "gram_single_waves", "kron_waves", "stream_kc", "panel_b")
+        out = {k: ch[i] for i, k in enumerate(names)}
+        out["tuned"] = bool(ch[5])
+        out["candidate_us"] = [us[i] for i in range(10)]
+        return out
+
     # ---- solve -----------------------------------------------------------
     def solve(self, w_y, Y: Sequence, cap_u: int = 4096, stream=None, out=None):
         """Y: three (n, rank) column-major device tensors (float64), i.e.

@@ -32,7 +32,7 @@ hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
 // products of the truncations and the diagonally scaled Grams Z^T diag(d) X
 // of the Hadamard truncation, one workgroup per 32 x 32 output tile, K split
 // over its wavefronts.
-hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
+hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s, int waves = 16);
 // Up to kMaxGramJobs Gram-type products (each as in gram, batched or not) in
 // one launch.
 constexpr int kMaxGramJobs = 3;
@@ -40,7 +40,8 @@ struct GramJobs {
     int count = 0;
     GemmArgs g[kMaxGramJobs];
 };
-hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s);
+hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s,
+                      int waves = 16);
 // Streaming products C = alpha op(A) op(B) + beta C over a long reduction
 // with op(A) op(B) = A^T B (layout 0), A B^T (1) or A B (2), up to three
 // jobs (of any sizes) in one launch on the FP64 matrix cores: the mode
@@ -84,7 +85,8 @@ struct KronJobs {
     int count = 0;
     KronJob job[3];
 };
-hipError_t kron_apply_multi(int n, int Q, const KronJobs& jobs, hipStream_t s);
+hipError_t kron_apply_multi(int n, int Q, const KronJobs& jobs, hipStream_t s,
+                            int waves = 16);
 
 // Symmetric eigen-decomposition of a batch of k x k matrices (k <= 128),
 // cyclic Jacobi with the matrix in LDS.  A (column-major, leading dimension

@@ -4,6 +4,8 @@
 
 #include <cstdint>
 #include <mutex>
+#include <utility>
+#include <vector>
 
 namespace fc {
 
@@ -306,10 +308,11 @@ static hipError_t gemm_dispatch(const GemmArgs& g, hipStream_t s) {
 // l % 16, k = l / 16), and the partial tiles are summed in LDS in a fixed
 // order (deterministic).  Batched over blockIdx.z with strides (d advances
 // by strideD per batch entry).
-constexpr int GR_WAVES = 16;
+// The number of wavefronts per workgroup (8 or 16) is chosen by the
+// autotuner per problem size.
 constexpr int GR_DEPTH = 1;   // chunks loaded per wavefront before computing
 
-template <int L>
+template <int L, int GR_WAVES>
 __device__ __forceinline__ void gram_tile(const GemmArgs& g, int tile, long b) {
     extern __shared__ double gram_red[];   // [GR_WAVES][4 blocks][4 regs][64 lanes]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -379,20 +382,20 @@ __device__ __forceinline__ void gram_tile(const GemmArgs& g, int tile, long b) {
     }
 }
 
-template <int L>
-__global__ __launch_bounds__(64 * GR_WAVES) void gram_kernel(GemmArgs g) {
-    gram_tile<L>(g, blockIdx.x, blockIdx.z);
+template <int L, int W>
+__global__ __launch_bounds__(64 * W) void gram_kernel(GemmArgs g) {
+    gram_tile<L, W>(g, blockIdx.x, blockIdx.z);
 }
 
 // Up to kMaxGramJobs independent products (each possibly a strided batch)
 // in one launch: grid.y picks the product, grid.x runs over its tiles times
 // its batch; blocks beyond a product's own count return at once.
-template <int L>
-__global__ __launch_bounds__(64 * GR_WAVES) void gram_multi_kernel(GramJobs jobs) {
+template <int L, int W>
+__global__ __launch_bounds__(64 * W) void gram_multi_kernel(GramJobs jobs) {
     const GemmArgs& g = jobs.g[blockIdx.y];
     const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
     if ((long)blockIdx.x >= (long)tiles * g.batch) return;
-    gram_tile<L>(g, (int)(blockIdx.x % tiles), (long)(blockIdx.x / tiles));
+    gram_tile<L, W>(g, (int)(blockIdx.x % tiles), (long)(blockIdx.x / tiles));
 }
 
 // ---------------------------------------------------------------------------
@@ -562,37 +565,55 @@ bool stream_fits(const StreamJobs& jobs, int kc, long part_cap) {
     return ksplit <= 1 || (long)jobs.count * ksplit * pmax <= part_cap;
 }
 
-hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s) {
-    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    if (g.inner != 1 || g.lowp || g.K <= 0 || (transA && transB)) return hipErrorInvalidValue;
-    const long tiles = (long)((g.M + 31) / 32) * ((g.N + 31) / 32);
-    if (tiles > 0x7fffffffL || g.batch > 65535) return hipErrorInvalidValue;
-    const dim3 grid(tiles, 1, g.batch), block(64 * GR_WAVES);
-    const size_t lds = sizeof(double) * GR_WAVES * 4 * 4 * 64;   // 128 KiB
-    static std::once_flag once;
-    static hipError_t attr_err = hipSuccess;
-    std::call_once(once, [lds] {
-        const void* fns[3] = {(const void*)gram_kernel<0>, (const void*)gram_kernel<1>,
-                              (const void*)gram_kernel<2>};
-        for (const void* f : fns) {
-            const hipError_t e =
-                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) attr_err = e;
+// dynamic LDS of the Gram-type kernels: the wavefronts' partial tiles
+static size_t gram_lds(int waves) { return sizeof(double) * (size_t)waves * 4 * 4 * 64; }
+
+template <class F>
+static hipError_t set_lds_once(std::once_flag& once, hipError_t& err, F&& fns) {
+    std::call_once(once, [&] {
+        for (const auto& fl : fns()) {
+            const hipError_t e = hipFuncSetAttribute(fl.first, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)fl.second);
+            if (e != hipSuccess) err = e;
         }
     });
-    if (attr_err != hipSuccess) return attr_err;
-    if (transA)
-        hipLaunchKernelGGL(gram_kernel<0>, grid, block, lds, s, g);
-    else if (transB)
-        hipLaunchKernelGGL(gram_kernel<1>, grid, block, lds, s, g);
-    else
-        hipLaunchKernelGGL(gram_kernel<2>, grid, block, lds, s, g);
+    return err;
+}
+
+hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s, int waves) {
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if (g.inner != 1 || g.lowp || g.K <= 0 || (transA && transB)) return hipErrorInvalidValue;
+    if (waves != 8 && waves != 16) return hipErrorInvalidValue;
+    const long tiles = (long)((g.M + 31) / 32) * ((g.N + 31) / 32);
+    if (tiles > 0x7fffffffL || g.batch > 65535) return hipErrorInvalidValue;
+    const dim3 grid(tiles, 1, g.batch), block(64 * waves);
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    const hipError_t ae = set_lds_once(once, attr_err, [] {
+        return std::vector<std::pair<const void*, size_t>>{
+            {(const void*)gram_kernel<0, 16>, gram_lds(16)}, {(const void*)gram_kernel<1, 16>, gram_lds(16)},
+            {(const void*)gram_kernel<2, 16>, gram_lds(16)}, {(const void*)gram_kernel<0, 8>, gram_lds(8)},
+            {(const void*)gram_kernel<1, 8>, gram_lds(8)}, {(const void*)gram_kernel<2, 8>, gram_lds(8)}};
+    });
+    if (ae != hipSuccess) return ae;
+    const size_t lds = gram_lds(waves);
+    const int L = transA ? 0 : (transB ? 1 : 2);
+    if (waves == 16) {
+        if (L == 0) hipLaunchKernelGGL((gram_kernel<0, 16>), grid, block, lds, s, g);
+        else if (L == 1) hipLaunchKernelGGL((gram_kernel<1, 16>), grid, block, lds, s, g);
+        else hipLaunchKernelGGL((gram_kernel<2, 16>), grid, block, lds, s, g);
+    } else {
+        if (L == 0) hipLaunchKernelGGL((gram_kernel<0, 8>), grid, block, lds, s, g);
+        else if (L == 1) hipLaunchKernelGGL((gram_kernel<1, 8>), grid, block, lds, s, g);
+        else hipLaunchKernelGGL((gram_kernel<2, 8>), grid, block, lds, s, g);
+    }
     return hipGetLastError();
 }
 
-hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s) {
+hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s, int waves) {
     if (jobs.count <= 0) return hipSuccess;
-    if (jobs.count > kMaxGramJobs || (transA && transB)) return hipErrorInvalidValue;
+    if (jobs.count > kMaxGramJobs || (transA && transB) || (waves != 8 && waves != 16))
+        return hipErrorInvalidValue;
     long tiles = 0;
     for (int t = 0; t < jobs.count; ++t) {
         const GemmArgs& g = jobs.g[t];
@@ -601,26 +622,30 @@ hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_
         tiles = std::max(tiles, (long)((g.M + 31) / 32) * ((g.N + 31) / 32) * g.batch);
     }
     if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
-    const size_t lds = sizeof(double) * GR_WAVES * 4 * 4 * 64;   // 128 KiB
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
-    std::call_once(once, [lds] {
-        const void* fns[3] = {(const void*)gram_multi_kernel<0>, (const void*)gram_multi_kernel<1>,
-                              (const void*)gram_multi_kernel<2>};
-        for (const void* f : fns) {
-            const hipError_t e =
-                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) attr_err = e;
-        }
+    const hipError_t ae = set_lds_once(once, attr_err, [] {
+        return std::vector<std::pair<const void*, size_t>>{
+            {(const void*)gram_multi_kernel<0, 16>, gram_lds(16)},
+            {(const void*)gram_multi_kernel<1, 16>, gram_lds(16)},
+            {(const void*)gram_multi_kernel<2, 16>, gram_lds(16)},
+            {(const void*)gram_multi_kernel<0, 8>, gram_lds(8)},
+            {(const void*)gram_multi_kernel<1, 8>, gram_lds(8)},
+            {(const void*)gram_multi_kernel<2, 8>, gram_lds(8)}};
     });
-    if (attr_err != hipSuccess) return attr_err;
-    const dim3 grid((unsigned)tiles, jobs.count), block(64 * GR_WAVES);
-    if (transA)
-        hipLaunchKernelGGL(gram_multi_kernel<0>, grid, block, lds, s, jobs);
-    else if (transB)
-        hipLaunchKernelGGL(gram_multi_kernel<1>, grid, block, lds, s, jobs);
-    else
-        hipLaunchKernelGGL(gram_multi_kernel<2>, grid, block, lds, s, jobs);
+    if (ae != hipSuccess) return ae;
+    const dim3 grid((unsigned)tiles, jobs.count), block(64 * waves);
+    const size_t lds = gram_lds(waves);
+    const int L = transA ? 0 : (transB ? 1 : 2);
+    if (waves == 16) {
+        if (L == 0) hipLaunchKernelGGL((gram_multi_kernel<0, 16>), grid, block, lds, s, jobs);
+        else if (L == 1) hipLaunchKernelGGL((gram_multi_kernel<1, 16>), grid, block, lds, s, jobs);
+        else hipLaunchKernelGGL((gram_multi_kernel<2, 16>), grid, block, lds, s, jobs);
+    } else {
+        if (L == 0) hipLaunchKernelGGL((gram_multi_kernel<0, 8>), grid, block, lds, s, jobs);
+        else if (L == 1) hipLaunchKernelGGL((gram_multi_kernel<1, 8>), grid, block, lds, s, jobs);
+        else hipLaunchKernelGGL((gram_multi_kernel<2, 8>), grid, block, lds, s, jobs);
+    }
     return hipGetLastError();
 }
 
@@ -633,6 +658,7 @@ hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_
 // formed in registers and never stored.  Tiles and reduction as in
 // gram_tile: one workgroup per 32 x 32 output tile, the sixteen wavefronts
 // take the terms q in turn, partial tiles summed in LDS in a fixed order.
+template <int GR_WAVES>
 __device__ __forceinline__ void kron_tile(int n, int Q, const KronJob& J, int tile) {
     extern __shared__ double gram_red[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -692,16 +718,18 @@ __device__ __forceinline__ void kron_tile(int n, int Q, const KronJob& J, int ti
     }
 }
 
-__global__ __launch_bounds__(64 * GR_WAVES) void kron_apply_kernel(int n, int Q, KronJobs jobs) {
+template <int W>
+__global__ __launch_bounds__(64 * W) void kron_apply_kernel(int n, int Q, KronJobs jobs) {
     const KronJob& J = jobs.job[blockIdx.y];
     const int tiles = ((n + 31) / 32) * ((J.p + 31) / 32);
     if ((int)blockIdx.x >= tiles) return;
-    kron_tile(n, Q, J, (int)blockIdx.x);
+    kron_tile<W>(n, Q, J, (int)blockIdx.x);
 }
 
-hipError_t kron_apply_multi(int n, int Q, const KronJobs& jobs, hipStream_t s) {
+hipError_t kron_apply_multi(int n, int Q, const KronJobs& jobs, hipStream_t s, int waves) {
     if (jobs.count <= 0) return hipSuccess;
-    if (jobs.count > kMaxPanelJobs || n <= 0 || Q <= 0) return hipErrorInvalidValue;
+    if (jobs.count > kMaxPanelJobs || n <= 0 || Q <= 0 || (waves != 8 && waves != 16))
+        return hipErrorInvalidValue;
     int tiles = 0;
     for (int t = 0; t < jobs.count; ++t) {
         const KronJob& J = jobs.job[t];
@@ -709,16 +737,20 @@ hipError_t kron_apply_multi(int n, int Q, const KronJobs& jobs, hipStream_t s) {
             return hipErrorInvalidValue;
         tiles = std::max(tiles, ((n + 31) / 32) * ((J.p + 31) / 32));
     }
-    const size_t lds = sizeof(double) * GR_WAVES * 4 * 4 * 64;   // 128 KiB
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
-    std::call_once(once, [lds] {
-        attr_err = hipFuncSetAttribute((const void*)kron_apply_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t ae = set_lds_once(once, attr_err, [] {
+        return std::vector<std::pair<const void*, size_t>>{
+            {(const void*)kron_apply_kernel<16>, gram_lds(16)},
+            {(const void*)kron_apply_kernel<8>, gram_lds(8)}};
     });
-    if (attr_err != hipSuccess) return attr_err;
-    hipLaunchKernelGGL(kron_apply_kernel, dim3(tiles, jobs.count), dim3(64 * GR_WAVES), lds, s, n,
-                       Q, jobs);
+    if (ae != hipSuccess) return ae;
+    if (waves == 16)
+        hipLaunchKernelGGL(kron_apply_kernel<16>, dim3(tiles, jobs.count), dim3(64 * 16), gram_lds(16),
+                           s, n, Q, jobs);
+    else
+        hipLaunchKernelGGL(kron_apply_kernel<8>, dim3(tiles, jobs.count), dim3(64 * 8), gram_lds(8), s,
+                           n, Q, jobs);
     return hipGetLastError();
 }
 
@@ -897,6 +929,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_tri_kernel(EigJobs jobs) {
     double* pw = vv + k;             // p / w / dot products
     double* lam = pw + k;            // eigenvalues, descending
     double* e2 = lam + k;            // squared off-diagonal
+    double* pw4 = e2 + k;            // partial sums of A22 v (4 x 128)
     for (int x = tid; x < k * k; x += blockDim.x) {
         const int i = x % k, j = x / k;
         a[x] = 0.5 * (J.A[i + (long)j * J.lda] + J.A[j + (long)i * J.lda]);
@@ -933,21 +966,25 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_tri_kernel(EigJobs jobs) {
         __syncthreads();
         const double t = sc[j & 1];
         if (t == 0.0) continue;
-        // p = t * A22 v, four threads per row
-        for (int base = 0; base < 4 * m; base += blockDim.x) {
-            const int x = base + tid;
-            const int r = x >> 2, part = x & 3;
+        // p = t * A22 v: thread (row r = tid % 128, part = tid / 128) sums over
+        // the columns c = part, part + 4, ..., so a wavefront reads 64
+        // consecutive rows of one column (no LDS bank conflicts); the first
+        // wavefront adds the four partial sums of each row
+        {
+            const int r = tid & 127, part = tid >> 7;
             double acc = 0.0;
             if (r < m)
                 for (int c = part; c < m; c += 4) acc += a[(j + 1 + r) + (j + 1 + c) * k] * vv[c];
-            acc += __shfl_xor(acc, 1, 64);
-            acc += __shfl_xor(acc, 2, 64);
-            if (r < m && part == 0) pw[r] = t * acc;
+            pw4[part * 128 + r] = acc;
         }
         __syncthreads();
         if (wv == 0) {
             double sp = 0.0;
-            for (int r = lane; r < m; r += 64) sp += vv[r] * pw[r];
+            for (int r = lane; r < m; r += 64) {
+                const double pr = t * ((pw4[r] + pw4[128 + r]) + (pw4[256 + r] + pw4[384 + r]));
+                pw[r] = pr;
+                sp += vv[r] * pr;
+            }
             const double K = 0.5 * t * td_wave_sum(sp);
             for (int r = lane; r < m; r += 64) pw[r] -= K * vv[r];
         }
@@ -1318,8 +1355,9 @@ hipError_t sym_eig_multi(const EigJobs& jobs, hipStream_t s) {
     });
     if (attr_err != hipSuccess) return attr_err;
     const int per = TD_THREADS / 64;
+    static_assert(TD_THREADS == 512, "the tridiagonalisation's matrix-vector step takes 4 x 128 threads");
     hipLaunchKernelGGL(tdeig_tri_kernel, dim3(jobs.count), dim3(TD_THREADS),
-                       sizeof(double) * ((size_t)kmax * (kmax + 1) + 7 * kmax), s, jobs);
+                       sizeof(double) * ((size_t)kmax * (kmax + 1) + 7 * kmax + 512), s, jobs);
     hipLaunchKernelGGL(tdeig_val_kernel, dim3((kmax + per - 1) / per, jobs.count),
                        dim3(TD_THREADS), 0, s, jobs);
     hipLaunchKernelGGL(tdeig_vec_kernel, dim3((kmax + TD_VPB - 1) / TD_VPB, jobs.count), dim3(64),

@@ -22,6 +22,7 @@
 #include <mutex>
 #include <thread>
 #include <vector>
+#include <sys/stat.h>
 
 #include "../../include/fracctl.h"
 #include "host_math.h"
@@ -108,6 +109,17 @@ enum {
     NSITES
 };
 
+// Launch choices picked by the autotuner for a plan's size (see autotune):
+// wavefronts per workgroup of the Gram kernel for batched (scaled) and for
+// unbatched products, of the fused Kronecker application, the K chunk of the
+// streaming transform kernel, the Gram-Schmidt panel width; and the measured
+// time (us) of every candidate.
+struct Tuning {
+    int gram_batched = 16, gram_single = 16, kron = 16, stream_kc = 128, panel_b = 16;
+    double us[10] = {};
+    bool tuned = false;
+};
+
 struct WarmBasis {
     double* W[3] = {nullptr, nullptr, nullptr};
     int pk[3] = {0, 0, 0};
@@ -156,6 +168,7 @@ struct fc_plan_s {
     void* t2c_ws = nullptr;    // T2C sort scratch beyond the LDS capacity
     double* jac = nullptr;
     WarmBasis warm[NSITES];
+    Tuning tune;
     double *qrN = nullptr, *qrC = nullptr;
     double *Xs3[3] = {}, *HX3[3] = {}, *Bp3 = nullptr, *Ev3 = nullptr, *Evec3 = nullptr;
     int* qrKeep = nullptr;
@@ -339,6 +352,12 @@ bool is_transform(const Ctx& c, bool ta, bool tb, const GemmArgs& g) {
            g.K == c.n && g.alpha == 1.0 && g.beta == 0.0 && g.N > 0;
 }
 
+// wavefronts per workgroup of the Gram kernel for a product: the tuned
+// choice for batched (the scaled Grams) and for single products
+int gram_waves(const Ctx& c, const GemmArgs& g) {
+    return g.batch > 1 ? c.p->tune.gram_batched : c.p->tune.gram_single;
+}
+
 // The mode transforms run on the streaming kernel (K split over workgroups,
 // partials added by a second kernel).  The small Gram-type products stay on
 // the Gram kernel: one launch each, where the split would need two (the
@@ -358,11 +377,11 @@ hipError_t run_stream(const Ctx& c, bool ta, bool tb, const GemmArgs* g, int cou
         J.C = g[t].C; J.ldc = g[t].ldc;
     }
     fc_plan_s* p = c.p;
-    const int kc = fc::stream_fits(sj, 128, p->splitws_cap) ? 128 : 256;
+    const int kc = fc::stream_fits(sj, p->tune.stream_kc, p->splitws_cap) ? p->tune.stream_kc : 256;
     if (!fc::stream_fits(sj, kc, p->splitws_cap)) {
         // partials beyond the workspace: the Gram kernel, one product at a time
         for (int t = 0; t < count; ++t) {
-            const hipError_t e = fc::gram(ta, tb, g[t], c.s);
+            const hipError_t e = fc::gram(ta, tb, g[t], c.s, gram_waves(c, g[t]));
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -377,7 +396,7 @@ hipError_t run_stream(const Ctx& c, bool ta, bool tb, const GemmArgs* g, int cou
 hipError_t run_gemm(const Ctx& c, bool ta, bool tb, const GemmArgs& g) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     if (t_tag == 3 && is_transform(c, ta, tb, g)) return run_stream(c, ta, tb, &g, 1);
-    if (gram_type(ta, tb, g)) return fc::gram(ta, tb, g, c.s);
+    if (gram_type(ta, tb, g)) return fc::gram(ta, tb, g, c.s, gram_waves(c, g));
     return fc::gemm(ta, tb, g, c.s);
 }
 
@@ -434,7 +453,8 @@ void launch_group(const Ctx& c, bool ta, bool tb, const fc::GramJobs& jobs, bool
     for (int t = 0; t < jobs.count && transform; ++t) transform = is_transform(c, ta, tb, jobs.g[t]);
     auto run = [&] {
         if (transform) return run_stream(c, ta, tb, jobs.g, jobs.count);
-        return gram ? fc::gram_multi(ta, tb, jobs, c.s) : fc::gemm_multi(ta, tb, jobs, c.s);
+        return gram ? fc::gram_multi(ta, tb, jobs, c.s, gram_waves(c, jobs.g[0]))
+                    : fc::gemm_multi(ta, tb, jobs, c.s);
     };
     if (g_prof.on && !t_no_profile) {
         // one shape entry per launch: the first product's shape, with the
@@ -488,10 +508,11 @@ void kron_apply(const Ctx& c, int Q, const fc::KronJobs& kj) {
             sh.bytes += 8.0 * ((double)n * J.r + (double)n * Q + (double)J.r * J.p * Q +
                                (double)n * J.p);
         }
-        record_product(c.s, sh, [&] { return fc::kron_apply_multi(n, Q, kj, c.s); });
+        record_product(c.s, sh,
+                       [&] { return fc::kron_apply_multi(n, Q, kj, c.s, c.p->tune.kron); });
         return;
     }
-    HIPCHK(fc::kron_apply_multi(n, Q, kj, c.s));
+    HIPCHK(fc::kron_apply_multi(n, Q, kj, c.s, c.p->tune.kron));
 }
 
 fc::GemmArgs prod(int M, int N, int K, const double* A, long lda, const double* B, long ldb,
@@ -613,7 +634,7 @@ void orthonormalize3(const Ctx& c, int m[3], double* const Y[3], double drop, co
     }
     HIPCHK(fc::col_norms(n, nj, c.s));
     // panel width: the panel lives in LDS (<= 144 KiB)
-    const int b = std::max(1, std::min(16, (int)((144L * 1024 / 8) / n)));
+    const int b = std::max(1, std::min(p->tune.panel_b, (int)((144L * 1024 / 8) / n)));
     // block projection P -= Y (Y^T P) of the modes' current panels: the
     // coefficients per mode (Gram-type product), the updates in one launch
     auto project = [&](const fc::PanelJobs& pj, const int* j0s, const int* modes) {
@@ -2160,6 +2181,213 @@ void build_sine_maps(fc_plan_s* p) {
     p->arena.release(Sd);
 }
 
+// ---- autotuner ------------------------------------------------------------
+// Picks, per device, grid size n and operator rank Q, the launch choices of
+// Tuning by timing every candidate on the plan's own buffers and operator:
+//   wavefronts per workgroup of the Gram kernel (8 or 16) on the scaled Grams
+//   Z^T diag(D_q) X (48 x 96, Q terms) and on three 32 x 16 products over n;
+//   wavefronts of the fused Kronecker application (8 or 16, r = 48, p = 96);
+//   the K chunk of the streaming transform kernel (128 or 256, three modes,
+//   m = 16); the Gram-Schmidt panel width (8 or 16, three n x 96 blocks).
+// Results are kept for the process and in a text cache on disk (environment
+// FC_TUNE_CACHE, else $HOME/.cache/fracctl/tune_v1.txt; one line per key),
+// so plans of the same size take the same choices and give the same bits.
+// FC_TUNE=0 keeps the defaults.
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, Tuning>> g_tune_table;
+
+std::string tune_cache_path() {
+    if (const char* e = std::getenv("FC_TUNE_CACHE")) return e;
+    const char* home = std::getenv("HOME");
+    if (!home || !*home) return std::string();
+    return std::string(home) + "/.cache/fracctl/tune_v1.txt";
+}
+
+bool tune_lookup_disk(const std::string& key, Tuning& t) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return false;
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        const char* bar = std::strchr(line, '|');
+        if (!bar || std::string(line, (size_t)(bar - line)) != key) continue;
+        Tuning x;
+        int got = std::sscanf(bar + 1, "%d %d %d %d %d | %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf",
+                              &x.gram_batched, &x.gram_single, &x.kron, &x.stream_kc, &x.panel_b,
+                              &x.us[0], &x.us[1], &x.us[2], &x.us[3], &x.us[4], &x.us[5], &x.us[6],
+                              &x.us[7], &x.us[8], &x.us[9]);
+        const bool ok = got == 15 && (x.gram_batched == 8 || x.gram_batched == 16) &&
+                        (x.gram_single == 8 || x.gram_single == 16) && (x.kron == 8 || x.kron == 16) &&
+                        (x.stream_kc == 128 || x.stream_kc == 256) &&
+                        (x.panel_b == 8 || x.panel_b == 16);
+        if (ok) {   // the last valid line for the key wins
+            x.tuned = true;
+            t = x;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_store_disk(const std::string& key, const Tuning& t) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0)
+        for (size_t i = 1; i <= slash; ++i)   // mkdir -p of the parent directory
+            if (path[i] == '/') (void)mkdir(path.substr(0, i).c_str(), 0755);
+    FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s|%d %d %d %d %d | %.2f %.2f %.2f %.2f %.2f %.2f %.2f %.2f %.2f %.2f\n",
+                 key.c_str(), t.gram_batched, t.gram_single, t.kron, t.stream_kc, t.panel_b, t.us[0],
+                 t.us[1], t.us[2], t.us[3], t.us[4], t.us[5], t.us[6], t.us[7], t.us[8], t.us[9]);
+    std::fclose(f);
+}
+
+// mean time (us) of `reps` launches after one warm-up, HIP events on s
+template <class F>
+double time_launches(hipStream_t s, int reps, F&& launch) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(launch());
+    HIPCHK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) HIPCHK(launch());
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return 1e3 * ms / reps;
+}
+
+void autotune(fc_plan_s* p) {
+    const char* off = std::getenv("FC_TUNE");
+    if (off && std::strcmp(off, "0") == 0) return;
+    const int n = p->n, Q = p->op.Q;
+    hipDeviceProp_t prop;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    const std::string key = std::string(prop.gcnArchName) + " n=" + std::to_string(n) +
+                            " Q=" + std::to_string(Q);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& e : g_tune_table)
+        if (e.first == key) { p->tune = e.second; return; }
+    Tuning t;
+    if (tune_lookup_disk(key, t)) {
+        g_tune_table.emplace_back(key, t);
+        p->tune = t;
+        return;
+    }
+    const hipStream_t s = p->stream;
+    Ctx c{p, s, n};
+    // random inputs in the subspace buffers
+    fc::FillJobs fills;
+    for (int l = 0; l < 3; ++l) {
+        fc::FillJob& F = fills.job[fills.count++];
+        F.n = (long)n * p->pcap;
+        F.seed = 97u + 13u * l;
+        F.x = p->Xs3[l];
+    }
+    HIPCHK(fc::fill_random_multi(fills, s));
+    const int reps = 5;
+    // 1. scaled Grams Z^T diag(D_q) X, 48 x 96 over Q terms
+    {
+        const int r = std::min(48, n), q = std::min(96, n);
+        const fc::GemmArgs g = scaled_gram(r, q, n, Q, p->Xs3[0], p->Xs3[1], p->op.D[0], p->Ys);
+        for (int w = 0; w < 2; ++w)
+            t.us[w] = time_launches(s, reps, [&] { return fc::gram(true, false, g, s, w ? 16 : 8); });
+        t.gram_batched = t.us[0] < t.us[1] ? 8 : 16;
+    }
+    // 2. three 32 x 16 Gram-type products over n (the panel coefficients)
+    {
+        fc::GramJobs jobs;
+        for (int l = 0; l < 3; ++l) {
+            fc::GemmArgs& g = jobs.g[jobs.count++];
+            g.M = std::min(32, n); g.N = std::min(16, n); g.K = n;
+            g.A = p->Xs3[l]; g.lda = n; g.B = p->Xs3[(l + 1) % 3]; g.ldb = n;
+            g.C = p->HX3[l]; g.ldc = g.M;
+        }
+        for (int w = 0; w < 2; ++w)
+            t.us[2 + w] = time_launches(s, reps, [&] {
+                return fc::gram_multi(true, false, jobs, s, w ? 16 : 8);
+            });
+        t.gram_single = t.us[2] < t.us[3] ? 8 : 16;
+    }
+    // 3. fused Kronecker application, r = 48, p = 96, Q terms
+    {
+        fc::KronJobs kj;
+        fc::KronJob& J = kj.job[kj.count++];
+        J.r = std::min(48, n); J.p = std::min(96, n); J.Z = p->Xs3[0]; J.ldz = n; J.D = p->op.D[0];
+        J.T = p->Ts; J.out = p->HX3[0]; J.ldo = n;
+        HIPCHK(fc::fill_random_multi(fc::FillJobs{1, {fc::FillJob{(long)J.r * J.p * Q, 5u, p->Ts}}}, s));
+        for (int w = 0; w < 2; ++w)
+            t.us[4 + w] = time_launches(s, reps, [&] {
+                return fc::kron_apply_multi(n, Q, kj, s, w ? 16 : 8);
+            });
+        t.kron = t.us[4] < t.us[5] ? 8 : 16;
+    }
+    // 4. streaming transforms of the three modes, m = 16
+    {
+        fc::StreamJobs sj;
+        for (int l = 0; l < 3; ++l) {
+            fc::StreamJob& J = sj.job[sj.count++];
+            J.M = n; J.N = std::min(16, n); J.K = n;
+            J.A = p->V[l]; J.lda = n; J.B = p->Xs3[l]; J.ldb = n; J.C = p->HX3[l]; J.ldc = n;
+        }
+        const int kcs[2] = {128, 256};
+        for (int w = 0; w < 2; ++w)
+            t.us[6 + w] = fc::stream_fits(sj, kcs[w], p->splitws_cap)
+                              ? time_launches(s, reps, [&] {
+                                    return fc::stream_multi(2, sj, kcs[w], p->splitws,
+                                                            p->splitws_cap, s);
+                                })
+                              : 1e30;
+        t.stream_kc = t.us[6] <= t.us[7] ? 128 : 256;
+    }
+    // 5. Gram-Schmidt panel width: three n x 96 blocks orthonormalised
+    if ((long)n * 16 * 8 <= 144L * 1024 && n >= 96) {
+        const int pw[2] = {8, 16};
+        for (int w = 0; w < 2; ++w) {
+            p->tune.panel_b = pw[w];
+            double best = 1e30;
+            for (int r = 0; r < 2; ++r) {
+                HIPCHK(fc::fill_random_multi(fills, s));
+                HIPCHK(hipStreamSynchronize(s));
+                const auto t0 = std::chrono::steady_clock::now();
+                int m[3] = {96, 96, 96};
+                const int none[3] = {0, 0, 0};
+                const bool all[3] = {true, true, true};
+                orthonormalize3(c, m, p->Xs3, 1e-13, none, all);
+                HIPCHK(hipStreamSynchronize(s));
+                best = std::min(best, std::chrono::duration<double, std::micro>(
+                                          std::chrono::steady_clock::now() - t0).count());
+            }
+            t.us[8 + w] = best;
+        }
+        t.panel_b = t.us[8] < t.us[9] ? 8 : 16;
+    } else {
+        t.us[8] = t.us[9] = 0.0;
+    }
+    // the times as the disk cache keeps them (two decimals), so that a plan
+    // reading the cache reports the same values
+    for (double& u : t.us) u = std::round(u * 100.0) / 100.0;
+    t.tuned = true;
+    p->tune = t;
+    g_tune_table.emplace_back(key, t);
+    tune_store_disk(key, t);
+    FC_TRACE_PRINT("autotune %s: gram %d/%d (%.1f %.1f | %.1f %.1f us) kron %d (%.1f %.1f) kc %d "
+                   "(%.1f %.1f) panel %d (%.0f %.0f)\n",
+                   key.c_str(), t.gram_batched, t.gram_single, t.us[0], t.us[1], t.us[2], t.us[3],
+                   t.kron, t.us[4], t.us[5], t.stream_kc, t.us[6], t.us[7], t.panel_b, t.us[8],
+                   t.us[9]);
+}
+
 void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
     const auto t0 = std::chrono::steady_clock::now();
     device_spectra(p, prm);
@@ -2174,6 +2402,7 @@ void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
     alloc_workspace(p);
     if (p->pc_kind == FC_PRECOND_LAPLACE) build_sine_maps(p);
     HIPCHK(hipHostMalloc(&p->pinned, fc_plan_s::kPinnedBytes, hipHostMallocDefault));
+    autotune(p);
     if (p->dims == 2) {
         p->Y3d = p->arena.alloc((size_t)p->n * 256);
         p->U3d = p->arena.alloc((size_t)p->n * 256);
@@ -2534,6 +2763,20 @@ fc_status fc_plan_separable(fc_plan p, int which, int cap, int* rank, double* w,
     if (F)
         for (int l = 0; l < 3; ++l)
             std::memcpy(F + (size_t)l * n * cap, S.F[l].data(), sizeof(double) * n * S.Q);
+    return FC_OK;
+}
+
+fc_status fc_plan_tuning(fc_plan p, int* choices, double* us) {
+    if (!p || !choices) return fail(FC_ERR_INVALID_ARG, "fc_plan_tuning: NULL argument");
+    const Tuning& t = p->tune;
+    choices[0] = t.gram_batched;
+    choices[1] = t.gram_single;
+    choices[2] = t.kron;
+    choices[3] = t.stream_kc;
+    choices[4] = t.panel_b;
+    choices[5] = t.tuned ? 1 : 0;
+    if (us)
+        for (int i = 0; i < 10; ++i) us[i] = t.us[i];
     return FC_OK;
 }
 

@@ -49,25 +49,25 @@ def test_traffic_records_follow_the_kernel_source(bench, tmp_path, monkeypatch):
     digest = hashlib.sha256(src.read_bytes()).hexdigest()
     prof = tmp_path / "profiles"
     prof.mkdir()
-    rec = {"kernel": "tdeig_kernel", "hbm_bytes_per_launch": 1234.5,
+    rec = {"kernel": "eigensolver", "hbm_bytes_per_launch": 1234.5,
            "kernel_source_sha256": digest}
     (prof / "traffic.md").write_text("summary\n\ntraffic-record: " + json.dumps(rec) + "\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.recorded_traffic("tdeig_kernel") == (1234.5, "traffic.md")
+    assert bench.recorded_traffic("eigensolver") == (1234.5, "traffic.md")
     assert bench.recorded_traffic("panel_mgs_kernel") == (None, "no counter record")
     src.write_text("// kernel source, changed\n")
-    value, note = bench.recorded_traffic("tdeig_kernel")
+    value, note = bench.recorded_traffic("eigensolver")
     assert value is None and "stale" in note
 
 
-def test_committed_profiles_carry_records():
+def test_committed_profiles_carry_records(bench):
     recs = []
     for name in os.listdir(os.path.join(ROOT, "profiles")):
         with open(os.path.join(ROOT, "profiles", name)) as f:
             recs += [json.loads(l[len("traffic-record: "):]) for l in f
                      if l.startswith("traffic-record: ")]
     kernels = {r["kernel"] for r in recs}
-    assert {"tdeig_kernel", "panel_mgs_kernel"} <= kernels
+    assert set(bench.KERNEL_NAMES.values()) <= kernels
     for r in recs:
         assert r["hbm_bytes_per_launch"] > 0 and len(r["kernel_source_sha256"]) == 64
 

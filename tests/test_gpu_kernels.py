@@ -299,3 +299,47 @@ def test_device_eigenpairs(maker):
         AV[:-1] += e[:, None] * V[l][1:]
         AV[1:] += e[:, None] * V[l][:-1]
         assert np.abs(AV - V[l] * lam[l][None, :]).max() <= 1e-12 * scale
+
+
+def test_autotuner_choices_cache_and_parity(tmp_path):
+    """The autotuner times its candidates at setup, keeps the choices for
+    the process (a second plan of the same size takes them) and on disk (a
+    fresh process reads them back unchanged), and a solve on the tuned plan
+    passes the oracle gate."""
+    import json
+    import os
+    import subprocess
+    import sys
+    from tests.gpu_util import plan_for, solve
+    cache = tmp_path / "tune.txt"
+    os.environ["FC_TUNE_CACHE"] = str(cache)
+    try:
+        prob = wl.workload_quadratic(n=200, alpha=0.5, rank=3)
+        plan = plan_for(prob)
+        t = plan.tuning()
+        print(f"[result] tuning {t}", flush=True)
+        assert t["tuned"]
+        assert t["gram_batched_waves"] in (8, 16) and t["gram_single_waves"] in (8, 16)
+        assert t["kron_waves"] in (8, 16) and t["stream_kc"] in (128, 256)
+        assert t["panel_b"] in (8, 16)
+        assert all(u > 0 for u in t["candidate_us"])
+        lines = cache.read_text().splitlines()
+        assert any(" n=200 " in ln for ln in lines), lines
+        assert plan_for(prob).tuning() == t
+        w_u, U, info = solve(plan, prob)
+        rep = osolve.rel_error(prob, w_u, U)
+        assert rep["rel_l2"] <= 10 * prob.eps, rep
+        code = ("import json, sys; sys.path.insert(0, %r); import workloads as wl; "
+                "from tests.gpu_util import plan_for; "
+                "print(json.dumps(plan_for(wl.workload_quadratic(n=200, alpha=0.5, rank=3)).tuning()))"
+                % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                             timeout=300, env=dict(os.environ))
+        assert out.returncode == 0, out.stderr[-2000:]
+        t2 = json.loads(out.stdout.strip().splitlines()[-1])
+        assert {k: v for k, v in t2.items() if k != "candidate_us"} == \
+            {k: v for k, v in t.items() if k != "candidate_us"}, (t2, t)
+        assert t2["candidate_us"] == pytest.approx(t["candidate_us"], abs=0.006)
+        assert len(cache.read_text().splitlines()) == len(lines)   # read, not tuned again
+    finally:
+        del os.environ["FC_TUNE_CACHE"]
