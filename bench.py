@@ -156,7 +156,7 @@ def cpu_baseline(prob, sample_slabs=8, repeats=3):
     }
 
 
-def build_plans(api, probs, precision=0, threads=8):
+def build_plans(api, probs, precision=0, threads=16):
     """Plans for `probs`, built concurrently on host threads."""
     import threading
     plans = [None] * len(probs)

@@ -96,8 +96,9 @@ typedef struct {
     int max_rank;           /* Tucker rank capacity per mode; 0 -> 96, at most 128 (the small
                                eigenproblems of the truncations are at most 128 x 128)         */
     int precond_rank;       /* Kronecker rank of the preconditioner (the paper's tests use 6,
-                               Section 4); 0 -> automatic: the first of 6, 8, ..., 16 whose
-                               fit of 1/f reaches a relative error of 1e-3 (else the best)    */
+                               Section 4), at most 16; 0 -> automatic: the first of 6, 8, ...,
+                               16 whose fit of 1/f reaches a relative error of 1e-3 (else the
+                               best)                                                          */
     fc_precision precision; /* FC_FP64 or FC_MIXED_FP32                                        */
     fc_precond_kind precond; /* FC_PRECOND_EIGEN (0, default) or FC_PRECOND_LAPLACE             */
     double precond_b0[3];   /* case (A) constants b0_l; <= 0 -> (max a_l + min a_l)/2 over the
@@ -135,16 +136,20 @@ typedef struct {
 fc_status fc_setup(int n, const double* a1, const double* a2, const double* a3,
                    double alpha, double beta, double eps, fc_plan* out);
 
-/* Build a plan (paper Sections 3.2-3.5): the three 1D FD matrices, their
- * eigenpairs (host, tridiagonal QL), the separable operator
- * D~ ~ f(lambda1+lambda2+lambda3), f(s) = beta s^-alpha + (gamma/beta) s^alpha, and
- * the rank-precond_rank preconditioner (case (B): D~_p ~ 1/f in the same
- * eigenbasis; case (A): 1/f on the spectrum of the anisotropic Laplacian in
- * the sine basis, see fc_precond_kind), both as exponential sums with positive weights (sinc-type
- * quadrature of the Laplace transform, Section 3.4, refined by least squares).
- * Uploads everything and allocates the solve workspace.  Fails with
- * FC_ERR_NUMERIC if the operator misses op_accuracy anywhere on
- * [s_min, s_max] or a separable factor is not positive. */
+/* Build a plan (paper Sections 3.2-3.5), on the device: the three 1D FD
+ * matrices (host, O(n)), their eigenpairs (divide and conquer on the
+ * device), the separable operator D~ ~ f(lambda1+lambda2+lambda3),
+ * f(s) = beta s^-alpha + (gamma/beta) s^alpha, the state map and the
+ * preconditioner (case (B): D~_p ~ 1/f in the same eigenbasis; case (A):
+ * 1/f on the spectrum of the anisotropic Laplacian in the sine basis, see
+ * fc_precond_kind), all as exponential sums with positive weights (Section
+ * 3.4: nonnegative least squares on a geometric node grid for the operator
+ * and the state map, free nodes for the preconditioner), fitted by one
+ * workgroup per candidate grid or rank on the device; then the factors
+ * exp(-t lambda) on the device, the solve workspace and the autotuner's
+ * launch choices.  Fails with FC_ERR_NUMERIC if the operator misses
+ * op_accuracy anywhere on [s_min, s_max] or a separable factor is not
+ * positive. */
 fc_status fc_setup_ex(const fc_setup_params* p, void* hip_stream, fc_plan* out);
 
 /* Solve F(A) u = y for one design function given in canonical format.
@@ -313,8 +318,11 @@ fc_status fc_host_expsum(int kind, double p1, double p2, double p3, double s_min
                          int terms, double* t, double* c, double* max_rel_err);
 
 /* Host-only construction of the setup phase (no device needed): the
- * eigenpairs and the separable operator (which = 0), preconditioner
- * (which = 1) or state map (which = 2) exactly as fc_setup_ex builds them, returned like
+ * eigenpairs (implicit QL) and the separable operator (which = 0),
+ * preconditioner (which = 1) or state map (which = 2) by the fits that
+ * fc_setup_ex runs on the device (the same algorithms, node grids, candidate
+ * ranks and selection rules; results agree to rounding, which may move a
+ * node of a nonnegative fit in or out of its active set), returned like
  * fc_plan_separable; *max_rel_err (may be NULL) receives the gate value
  * max over [s_min, s_max] of |D~/f - 1| (operator) or |D~_p f - 1|. */
 fc_status fc_host_separable(const fc_setup_params* p, int which, int cap, int* rank, double* w,

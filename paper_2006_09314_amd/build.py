@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfracctl.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "solver.hip", "host_math.cpp"]
+SOURCES = ["kernels.hip", "fit.hip", "solver.hip", "host_math.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

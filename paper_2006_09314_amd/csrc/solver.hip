@@ -26,6 +26,7 @@
 
 #include "../../include/fracctl.h"
 #include "host_math.h"
+#include "fit.h"
 #include "kernels.h"
 
 namespace {
@@ -101,7 +102,8 @@ struct Separable {
     double* D[3] = {nullptr, nullptr, nullptr};   // n x Q
     double* D2[3] = {nullptr, nullptr, nullptr};  // elementwise squares
     std::vector<double> w;                        // host copy of the weights (pre-folding)
-    std::vector<double> F[3];                     // host copies of unweighted factors n x Q
+    std::vector<double> F[3];                     // host-built plans: unweighted factors n x Q
+    double* Fd[3] = {nullptr, nullptr, nullptr};  // device-built plans: the same on the device
 };
 
 enum {
@@ -182,7 +184,7 @@ struct fc_plan_s {
     unsigned* dotcnt = nullptr;   // zero between calls of the device dot
     long ys_cap = 0;              // doubles in Ys and in Ts
     long e_cap = 0;               // doubles in E
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // the setup's stream (set during fc_setup_ex only)
     // statistics of the last solve
     int max_seen_rank = 0;
     double worst_missed = 0;   // largest missed-energy charge / budget of a Hadamard truncation
@@ -1850,25 +1852,6 @@ void alloc_workspace(fc_plan_s* p) {
         throw FcError(FC_ERR_HIP, "hipMemcpy failed");
 }
 
-// Build the separable factors on the host and upload them.
-void upload_separable(fc_plan_s* p, Separable& S) {
-    const int n = p->n;
-    for (int l = 0; l < 3; ++l) {
-        std::vector<double> D((size_t)n * S.Q), D2((size_t)n * S.Q);
-        for (int q = 0; q < S.Q; ++q) {
-            const double f = std::cbrt(S.w[q]);
-            for (int i = 0; i < n; ++i) {
-                const double v = f * S.F[l][(size_t)q * n + i];
-                D[(size_t)q * n + i] = v;
-                D2[(size_t)q * n + i] = v * v;
-            }
-        }
-        S.D[l] = p->arena.alloc(D.size());
-        S.D2[l] = p->arena.alloc(D2.size());
-        HIPCHK(hipMemcpy(S.D[l], D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(S.D2[l], D2.data(), D2.size() * sizeof(double), hipMemcpyHostToDevice));
-    }
-}
 
 double f_control(double s, double alpha, double beta, double gamma) {
     return beta * std::pow(s, -alpha) + (gamma / beta) * std::pow(s, alpha);
@@ -2047,7 +2030,9 @@ void build_state_map(fc_plan_s* p, double smin, double smax) {
 // The separable factors from the spectra (Sections 3.4, 3.5, 3.1): the
 // exponential-sum fits are independent host problems, run on threads of
 // their own.
-void build_separables(fc_plan_s* p, const fc_setup_params* prm) {
+// The spectra the fits run on: with d = 2 the third mode's eigenvalues are
+// shifted by the smallest one; case (A) adds the Laplacian's spectrum.
+void prepare_spectra(fc_plan_s* p, const fc_setup_params* prm) {
     if (p->dims == 2) {
         // A_3 - lambda_3,1 I: its first eigenvector spans a null space, so a
         // design y (x) v_1 has the solution u (x) v_1 with u the d = 2 control
@@ -2055,8 +2040,6 @@ void build_separables(fc_plan_s* p, const fc_setup_params* prm) {
         for (double& x : p->lam[2]) x -= sig;
         p->lam[2][0] = 0.0;
     }
-    double smin = 0, smax = 0;
-    for (int l = 0; l < 3; ++l) { smin += p->lam[l].front(); smax += p->lam[l].back(); }
     if (p->pc_kind == FC_PRECOND_LAPLACE) {
         laplace_spectrum(p, prm);
         if (p->dims == 2) {
@@ -2065,6 +2048,12 @@ void build_separables(fc_plan_s* p, const fc_setup_params* prm) {
             p->mu[2][0] = 0.0;
         }
     }
+}
+
+void build_separables(fc_plan_s* p, const fc_setup_params* prm) {
+    prepare_spectra(p, prm);
+    double smin = 0, smax = 0;
+    for (int l = 0; l < 3; ++l) { smin += p->lam[l].front(); smax += p->lam[l].back(); }
     auto now = [] { return std::chrono::steady_clock::now(); };
     const auto t0 = now();
     std::exception_ptr err[4];
@@ -2088,6 +2077,257 @@ void build_separables(fc_plan_s* p, const fc_setup_params* prm) {
         if (e) std::rethrow_exception(e);
     FC_TRACE_PRINT("setup fits: %.1f ms (operator Q %d)\n",
                    std::chrono::duration<double, std::milli>(now() - t0).count(), p->op.Q);
+}
+
+// ---- the separable factors on the device ----------------------------------
+// The same fits as build_separables (operator and state map: nonnegative
+// sums on the node grids of hstep 0.7 ... 0.35, the first grid meeting the
+// accuracy taken; preconditioner: the largest usable rank, automatic rank
+// the first of 6, 8, ..., 16 reaching 1e-3), every candidate an independent
+// workgroup of one launch (fit.hip); the host reads the results, applies the
+// same selection rules, and the factors exp(-t lam) are formed on the device.
+struct TermList {
+    std::vector<double> w, t;   // weight, node (< 0: no exponential)
+    std::vector<int> lm;        // mode whose factor carries the eigenvalue (-1: none)
+    void add(double wq, double tq, int m) { w.push_back(wq); t.push_back(tq); lm.push_back(m); }
+};
+
+// Stream-ordered temporaries of the setup: plans set up on concurrent host
+// threads must not wait for each other's kernels, which hipFree would do.
+// Freed on the plan's stream when the holder goes out of scope (also when
+// the setup throws).
+struct SetupTmp {
+    hipStream_t s;
+    std::vector<void*> held;
+    explicit SetupTmp(hipStream_t st) : s(st) {}
+    template <typename T>
+    T* get(size_t count) {
+        void* q = nullptr;
+        if (hipMallocAsync(&q, std::max<size_t>(count, 1) * sizeof(T), s) != hipSuccess)
+            throw FcError(FC_ERR_OUT_OF_MEMORY, "hipMallocAsync failed");
+        held.push_back(q);
+        return (T*)q;
+    }
+    ~SetupTmp() {
+        for (void* q : held) (void)hipFreeAsync(q, s);
+    }
+};
+
+void device_factors(fc_plan_s* p, const TermList& tl, const std::vector<double>* spec,
+                    Separable& S) {
+    const int n = p->n, Q = (int)tl.w.size();
+    S.Q = Q;
+    S.w = tl.w;
+    std::vector<double> lamh((size_t)3 * n), tw((size_t)2 * Q);
+    std::vector<int> lm(tl.lm);
+    for (int l = 0; l < 3; ++l) std::copy(spec[l].begin(), spec[l].end(), lamh.begin() + (long)l * n);
+    for (int q = 0; q < Q; ++q) { tw[q] = tl.w[q]; tw[Q + q] = tl.t[q]; }
+    SetupTmp tmp(p->stream);
+    double* lamd = tmp.get<double>(lamh.size());
+    double* twd = tmp.get<double>(tw.size());
+    int* lmd = tmp.get<int>(lm.size());
+    HIPCHK(hipMemcpyAsync(lamd, lamh.data(), sizeof(double) * lamh.size(), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipMemcpyAsync(twd, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipMemcpyAsync(lmd, lm.data(), sizeof(int) * lm.size(), hipMemcpyHostToDevice, p->stream));
+    for (int l = 0; l < 3; ++l) {
+        S.Fd[l] = p->arena.alloc((size_t)n * Q);
+        S.D[l] = p->arena.alloc((size_t)n * Q);
+        S.D2[l] = p->arena.alloc((size_t)n * Q);
+    }
+    HIPCHK(fc::expsum_factors(n, Q, lamd, twd, twd + Q, lmd, S.Fd, S.D, S.D2, p->stream));
+    // the host vectors are read by the copies above before they go out of scope
+    HIPCHK(hipStreamSynchronize(p->stream));
+}
+
+// A set of fit jobs run in one launch pair; results copied back per job.
+struct FitBatch {
+    fc::FitJobs jobs;
+    std::vector<std::vector<double>> out;
+    int add(const fc::FitJob& j) {
+        if (jobs.count >= fc::kMaxFitJobs) throw FcError(FC_ERR_INTERNAL, "too many fit jobs");
+        jobs.job[jobs.count] = j;
+        return jobs.count++;
+    }
+    void run(fc_plan_s* p) {
+        out.assign(jobs.count, {});
+        if (jobs.count == 0) return;
+        std::vector<long> woff(jobs.count), ooff(jobs.count + 1);
+        long wtot = 0;
+        ooff[0] = 0;
+        for (int k = 0; k < jobs.count; ++k) {
+            woff[k] = wtot;
+            wtot += fc::fit_work_doubles(jobs.job[k]);
+            ooff[k + 1] = ooff[k] + fc::fit_out_doubles(jobs.job[k]);
+        }
+        SetupTmp tmp(p->stream);
+        double* work = tmp.get<double>((size_t)wtot);
+        double* outd = tmp.get<double>((size_t)ooff[jobs.count]);
+        for (int k = 0; k < jobs.count; ++k) {
+            jobs.job[k].work = work + woff[k];
+            jobs.job[k].out = outd + ooff[k];
+        }
+        std::vector<double> h((size_t)ooff[jobs.count]);
+        HIPCHK(fc::fit_run(jobs, p->stream));
+        HIPCHK(hipMemcpyAsync(h.data(), outd, sizeof(double) * h.size(), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        for (int k = 0; k < jobs.count; ++k)
+            out[k].assign(h.begin() + ooff[k], h.begin() + ooff[k + 1]);
+    }
+};
+
+void device_separables(fc_plan_s* p, const fc_setup_params* prm) {
+    prepare_spectra(p, prm);
+    const auto t0 = std::chrono::steady_clock::now();
+    const double a = p->alpha, b = p->beta, gm = p->gamma;
+    double smin = 0, smax = 0, mmin = 0, mmax = 0;
+    for (int l = 0; l < 3; ++l) { smin += p->lam[l].front(); smax += p->lam[l].back(); }
+    const bool lap = p->pc_kind == FC_PRECOND_LAPLACE;
+    if (lap)
+        for (int l = 0; l < 3; ++l) { mmin += p->mu[l].front(); mmax += p->mu[l].back(); }
+    if (!(smin > 0) || !(smax >= smin) || (lap && (!(mmin > 0) || !(mmax >= mmin))))
+        throw FcError(FC_ERR_NUMERIC, "spectrum not positive");
+    const double hsteps[5] = {0.7, 0.6, 0.5, 0.42, 0.35};
+    const double t_hi = (std::log(1.0 / p->op_acc) + 10.0) / smin;
+    const double t_lo = std::pow(p->op_acc, 0.7) / smax;
+    const double cexact = (a == 1.0) ? gm / b : 0.0;
+    auto nonneg_job = [&](int target, double hs) {
+        fc::FitJob J;
+        J.target = target; J.alpha = a; J.beta = b; J.gamma = gm;
+        J.cexact = target == fc::FIT_OPERATOR ? cexact : 0.0;
+        J.smin = smin; J.smax = smax; J.log_tlo = std::log(t_lo); J.hstep = hs;
+        int cnt = 0;
+        for (double x = std::log(t_lo); x <= std::log(t_hi) + 1e-12; x += hs) ++cnt;
+        J.nodes = cnt;
+        J.with_constant = (target == fc::FIT_OPERATOR && a < 1.0) ? 1 : 0;
+        if (cnt < 1 || cnt + J.with_constant > fc::kFitMaxNodes)
+            throw FcError(FC_ERR_NUMERIC, "exponential-sum node grid out of range");
+        return J;
+    };
+    auto free_job = [&](double lo, double hi, int kmax) {
+        fc::FitJob J;
+        J.target = fc::FIT_PRECOND; J.alpha = a; J.beta = b; J.gamma = gm;
+        J.smin = lo; J.smax = hi; J.kmax = kmax;
+        return J;
+    };
+    // a nonnegative fit passes when it ran and its error meets the accuracy
+    auto passes = [&](const fc::FitJob& J, const std::vector<double>& o) {
+        const int N = J.nodes + J.with_constant;
+        return o[N + 2] == 1.0 && o[N] <= p->op_acc;
+    };
+    TermList op, st, pc, pcA;
+    int jobs_run = 0;
+    if (a == 0.0) {
+        op.add(b + gm / b, -1.0, -1);
+        p->op_err = 0.0;
+        st.add(b, -1.0, -1);
+        p->st_err = 0.0;
+        pc.add(1.0 / (b + gm / b), 0.0, -1);
+        p->pc_err = 0.0;
+        if (lap) { pcA.add(1.0 / (b + gm / b), 0.0, -1); p->pcA_err = 0.0; }
+    } else {
+        // stage 1: the three coarser node grids of both nonnegative fits and
+        // every preconditioner candidate; stage 2: the finer grids of a fit
+        // none of whose coarser grids met the accuracy (the selection takes
+        // the first grid that does, so the finer ones only matter then)
+        std::vector<int> kmaxes;
+        if (p->precond_rank > 0) kmaxes.push_back(p->precond_rank);
+        else
+            for (int K0 = 6; K0 <= 16; K0 += 2) kmaxes.push_back(K0);
+        FitBatch s1;
+        int opi[5], sti[5];
+        std::vector<int> pci, pai;
+        for (int h = 0; h < 3; ++h) {
+            opi[h] = s1.add(nonneg_job(fc::FIT_OPERATOR, hsteps[h]));
+            sti[h] = s1.add(nonneg_job(fc::FIT_STATE, hsteps[h]));
+        }
+        for (int K0 : kmaxes) pci.push_back(s1.add(free_job(smin, smax, K0)));
+        if (lap)
+            for (int K0 : kmaxes) pai.push_back(s1.add(free_job(mmin, mmax, K0)));
+        s1.run(p);
+        jobs_run += s1.jobs.count;
+        // chosen results: (job, outputs) per target
+        fc::FitJob opJ, stJ;
+        std::vector<double> opO, stO;
+        double op_last = 1e300, st_last = 1e300;
+        auto first_pass = [&](FitBatch& B, const int* idx, int from, int to, fc::FitJob& J,
+                              std::vector<double>& O, double& last) {
+            for (int h = from; h < to; ++h) {
+                const fc::FitJob& Jh = B.jobs.job[idx[h]];
+                const std::vector<double>& o = B.out[idx[h]];
+                const int N = Jh.nodes + Jh.with_constant;
+                if (o[N + 2] == 1.0) last = o[N];
+                if (passes(Jh, o)) { J = Jh; O = o; return true; }
+            }
+            return false;
+        };
+        bool opok = first_pass(s1, opi, 0, 3, opJ, opO, op_last);
+        bool stok = first_pass(s1, sti, 0, 3, stJ, stO, st_last);
+        if (!opok || !stok) {
+            FitBatch s2;
+            for (int h = 3; h < 5; ++h) {
+                if (!opok) opi[h] = s2.add(nonneg_job(fc::FIT_OPERATOR, hsteps[h]));
+                if (!stok) sti[h] = s2.add(nonneg_job(fc::FIT_STATE, hsteps[h]));
+            }
+            s2.run(p);
+            jobs_run += s2.jobs.count;
+            if (!opok) opok = first_pass(s2, opi, 3, 5, opJ, opO, op_last);
+            if (!stok) stok = first_pass(s2, sti, 3, 5, stJ, stO, st_last);
+        }
+        if (!opok)
+            throw FcError(FC_ERR_NUMERIC, "operator exponential sum misses the accuracy gate (err " +
+                                              std::to_string(op_last) + ")");
+        if (!stok)
+            throw FcError(FC_ERR_NUMERIC, "state-map exponential sum misses the accuracy gate (err " +
+                                              std::to_string(st_last) + ")");
+        {
+            const int N0 = opJ.nodes, N = N0 + opJ.with_constant;
+            const double* o = opO.data();
+            const double c0 = cexact + (opJ.with_constant ? o[N0] : 0.0);
+            if (c0 > 0.0)
+                for (int m = 0; m < 3; ++m) op.add(c0, -1.0, m);
+            for (int j = 0; j < N0; ++j)
+                if (o[j] > 0)
+                    for (int m = 0; m < 3; ++m) op.add(o[j], o[N + 3 + j], m);
+            p->op_err = o[N + 1];
+            if (!(p->op_err <= p->op_acc))
+                throw FcError(FC_ERR_NUMERIC, "operator gate failed: max rel err " + std::to_string(p->op_err));
+        }
+        {
+            const int N = stJ.nodes;
+            const double* o = stO.data();
+            for (int j = 0; j < N; ++j)
+                if (o[j] > 0) st.add(o[j], o[N + 3 + j], -1);
+            p->st_err = o[N];
+        }
+        // preconditioner: fixed rank, or the automatic rule over the candidates
+        auto pick_free = [&](const std::vector<int>& idx, TermList& tl, double& err_out) {
+            int kbest = -1;
+            double best = 1e300;
+            for (size_t c = 0; c < idx.size(); ++c) {
+                const std::vector<double>& o = s1.out[idx[c]];
+                const int K = (int)o[2 * fc::kFitMaxK + 1];
+                const double e = o[2 * fc::kFitMaxK];
+                if (K > 0 && e < best) { best = e; kbest = idx[c]; }
+                if (best <= 1e-3) break;
+            }
+            if (kbest < 0) throw FcError(FC_ERR_NUMERIC, "preconditioner fit failed");
+            const std::vector<double>& o = s1.out[kbest];
+            const int K = (int)o[2 * fc::kFitMaxK + 1];
+            for (int k = 0; k < K; ++k) tl.add(o[K + k], o[k], -1);
+            err_out = best;
+        };
+        pick_free(pci, pc, p->pc_err);
+        if (lap) pick_free(pai, pcA, p->pcA_err);
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    device_factors(p, op, p->lam, p->op);
+    device_factors(p, st, p->lam, p->st);
+    device_factors(p, pc, p->lam, p->pc);
+    if (lap) device_factors(p, pcA, p->mu, p->pcA);
+    FC_TRACE_PRINT("setup fits on the device: %.1f ms (%d jobs), factors %.1f ms (operator Q %d)\n",
+                   std::chrono::duration<double, std::milli>(t1 - t0).count(), jobs_run,
+                   std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count(),
+                   p->op.Q);
 }
 
 // Host construction (no device): implicit-QL eigenpairs, then the fits.
@@ -2116,18 +2356,33 @@ void device_spectra(fc_plan_s* p, const fc_setup_params* prm) {
     const int n = p->n;
     std::vector<double> dh((size_t)3 * n), eh((size_t)3 * n, 0.0);
     for (int l = 0; l < 3; ++l) fc::fd_tridiag(n, prm->a[l], &dh[(size_t)l * n], &eh[(size_t)l * n]);
-    double* D = p->arena.alloc((size_t)3 * n);
-    double* E = p->arena.alloc((size_t)3 * n);
-    int* info = p->arena.alloc_int(3);
-    HIPCHK(hipMemcpy(D, dh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(E, eh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice));
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success)
-        throw FcError(FC_ERR_HIP, "rocblas_create_handle failed");
-    struct HandleGuard {
-        rocblas_handle h;
-        ~HandleGuard() { rocblas_destroy_handle(h); }
-    } guard_h{h};
+    SetupTmp tmp(p->stream);
+    double* D = tmp.get<double>((size_t)3 * n);
+    double* E = tmp.get<double>((size_t)3 * n);
+    int* info = tmp.get<int>(3);
+    HIPCHK(hipMemcpyAsync(D, dh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipMemcpyAsync(E, eh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, p->stream));
+    // a library handle from a process-wide pool: creating and destroying one
+    // per plan frees its device workspace, which waits for the whole device
+    // (plans set up on concurrent threads would wait for each other)
+    struct HandleLease {
+        rocblas_handle h = nullptr;
+        HandleLease() {
+            {
+                std::lock_guard<std::mutex> lk(pool_mutex());
+                if (!pool().empty()) { h = pool().back(); pool().pop_back(); }
+            }
+            if (!h && rocblas_create_handle(&h) != rocblas_status_success)
+                throw FcError(FC_ERR_HIP, "rocblas_create_handle failed");
+        }
+        ~HandleLease() {
+            std::lock_guard<std::mutex> lk(pool_mutex());
+            pool().push_back(h);
+        }
+        static std::vector<rocblas_handle>& pool() { static std::vector<rocblas_handle> v; return v; }
+        static std::mutex& pool_mutex() { static std::mutex m; return m; }
+    } lease;
+    rocblas_handle h = lease.h;
     if (rocblas_set_stream(h, p->stream) != rocblas_status_success)
         throw FcError(FC_ERR_HIP, "rocblas_set_stream failed");
     for (int l = 0; l < 3; ++l) {
@@ -2140,9 +2395,6 @@ void device_spectra(fc_plan_s* p, const fc_setup_params* prm) {
     HIPCHK(hipMemcpyAsync(dh.data(), D, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, p->stream));
     HIPCHK(hipMemcpyAsync(ih, info, sizeof(int) * 3, hipMemcpyDeviceToHost, p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
-    p->arena.release(D);
-    p->arena.release(E);
-    p->arena.release(info);
     for (int l = 0; l < 3; ++l) {
         p->Vt[l] = p->arena.alloc((size_t)n * n);
         HIPCHK(fc::transpose(n, n, p->V[l], n, p->Vt[l], n, p->stream));
@@ -2168,8 +2420,9 @@ void build_sine_maps(fc_plan_s* p) {
             const long m = ((long)i * k) % (2L * (n + 1));
             S[(size_t)(k - 1) * n + (i - 1)] = sc * std::sin(M_PI * (double)m / (n + 1));
         }
-    double* Sd = p->arena.alloc((size_t)n * n);
-    HIPCHK(hipMemcpy(Sd, S.data(), sizeof(double) * n * n, hipMemcpyHostToDevice));
+    SetupTmp tmp(p->stream);
+    double* Sd = tmp.get<double>((size_t)n * n);
+    HIPCHK(hipMemcpyAsync(Sd, S.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, p->stream));
     Ctx c{p, p->stream, n};
     for (int l = 0; l < 3; ++l) {
         p->Wsin[l] = p->arena.alloc((size_t)n * n);
@@ -2178,7 +2431,6 @@ void build_sine_maps(fc_plan_s* p) {
         HIPCHK(fc::transpose(n, n, p->Wsin[l], n, p->WsinT[l], n, p->stream));
     }
     HIPCHK(hipStreamSynchronize(p->stream));
-    p->arena.release(Sd);
 }
 
 // ---- autotuner ------------------------------------------------------------
@@ -2392,13 +2644,9 @@ void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
     const auto t0 = std::chrono::steady_clock::now();
     device_spectra(p, prm);
     const auto t1 = std::chrono::steady_clock::now();
-    build_separables(p, prm);
     FC_TRACE_PRINT("setup eigenpairs on the device: %.1f ms\n",
                    std::chrono::duration<double, std::milli>(t1 - t0).count());
-    upload_separable(p, p->op);
-    upload_separable(p, p->pc);
-    upload_separable(p, p->st);
-    if (p->pc_kind == FC_PRECOND_LAPLACE) upload_separable(p, p->pcA);
+    device_separables(p, prm);
     alloc_workspace(p);
     if (p->pc_kind == FC_PRECOND_LAPLACE) build_sine_maps(p);
     HIPCHK(hipHostMalloc(&p->pinned, fc_plan_s::kPinnedBytes, hipHostMallocDefault));
@@ -2407,7 +2655,7 @@ void setup_plan(fc_plan_s* p, const fc_setup_params* prm) {
         p->Y3d = p->arena.alloc((size_t)p->n * 256);
         p->U3d = p->arena.alloc((size_t)p->n * 256);
     }
-    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipStreamSynchronize(p->stream));
 }
 
 // The rank-truncated PCG (Algorithm 1) on Tucker iterates in eigen-coordinates.
@@ -2675,7 +2923,7 @@ static fc_status validate_params(const fc_setup_params* prm) {
         prm->precond_rank < 0)
         return fail(FC_ERR_INVALID_ARG, "negative option");
     if (prm->max_rank > KM) return fail(FC_ERR_INVALID_ARG, "max_rank must be <= 128");
-    if (prm->precond_rank > 32) return fail(FC_ERR_INVALID_ARG, "precond_rank must be <= 32");
+    if (prm->precond_rank > 16) return fail(FC_ERR_INVALID_ARG, "precond_rank must be <= 16");
     if (prm->precision != FC_FP64 && prm->precision != FC_MIXED_FP32)
         return fail(FC_ERR_INVALID_ARG, "unsupported precision");
     if (prm->precond != FC_PRECOND_EIGEN && prm->precond != FC_PRECOND_LAPLACE)
@@ -2719,10 +2967,25 @@ fc_status fc_setup_ex(const fc_setup_params* prm, void* hip_stream, fc_plan* out
     if (v != FC_OK) return v;
     fc_plan_s* p = new fc_plan_s();
     apply_defaults(p, prm);
-    p->stream = (hipStream_t)hip_stream;
+    // without a caller stream the setup runs on a stream of its own: plans set
+    // up on concurrent threads must not queue behind each other on the NULL
+    // stream (their fits run for hundreds of milliseconds)
+    hipStream_t own = nullptr;
+    if (!hip_stream) {
+        if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) {
+            delete p;
+            return fail(FC_ERR_HIP, "hipStreamCreateWithFlags failed");
+        }
+    }
+    p->stream = own ? own : (hipStream_t)hip_stream;
     std::vector<double> ones;
     const fc_setup_params q = effective_params(prm, ones);
     fc_status st = guard([&] { setup_plan(p, &q); });
+    if (own) {
+        (void)hipStreamSynchronize(own);
+        (void)hipStreamDestroy(own);
+        p->stream = nullptr;
+    }
     if (st != FC_OK) { delete p; return st; }
     *out = p;
     return FC_OK;
@@ -2761,8 +3024,11 @@ fc_status fc_plan_separable(fc_plan p, int which, int cap, int* rank, double* w,
     const int n = p->n;
     if (w) std::memcpy(w, S.w.data(), sizeof(double) * S.Q);
     if (F)
-        for (int l = 0; l < 3; ++l)
-            std::memcpy(F + (size_t)l * n * cap, S.F[l].data(), sizeof(double) * n * S.Q);
+        return guard([&] {
+            for (int l = 0; l < 3; ++l)
+                HIPCHK(hipMemcpy(F + (size_t)l * n * cap, S.Fd[l], sizeof(double) * n * S.Q,
+                                 hipMemcpyDeviceToHost));
+        });
     return FC_OK;
 }
 

@@ -100,13 +100,16 @@ def test_solve_with_case_a_mixed():
 def test_case_a_equals_case_b_for_constant_coefficients():
     """With a_l = c_l constant the sine basis is the eigenbasis of A_l and the
     Laplacian's spectrum is A's, so both preconditioners are the same symbol:
-    the same iteration count and both within the gate."""
+    the same iteration count and both within the gate.  A fixed rank (8)
+    keeps the comparison on one fit: the automatic rule takes the best of
+    ranks up to 16, whose free-node fits can settle in different local
+    optima when the interval moves by eigensolver rounding."""
     n = 48
     base = wl.workload_quadratic(n=n, alpha=0.5)
     base.a = [np.full(n + 1, c) for c in (0.6, 1.7, 2.9)]
     base.name = "const_n48"
-    repA, infoA = _check(base, precond=1)
-    repB, infoB = _check(base)
+    repA, infoA = _check(base, precond=1, precond_rank=8)
+    repB, infoB = _check(base, precond_rank=8)
     assert abs(infoA["iterations"] - infoB["iterations"]) <= 1
     # the two fits see the same interval up to eigensolver rounding
     assert infoA["precond_max_rel_err"] == pytest.approx(infoB["precond_max_rel_err"], rel=1e-3)

@@ -52,7 +52,7 @@ def _params(prob, **kw):
 @pytest.mark.parametrize("field,value", [
     ("n", 1), ("alpha", -0.1), ("alpha", 1.5), ("beta", 0.0), ("gamma", -1.0),
     ("eps", 0.0), ("eps", 1.0), ("max_rank", 200), ("precision", 3), ("precond", 2),
-    ("precond", -1),
+    ("precond", -1), ("precond_rank", 17),
 ])
 def test_setup_rejects_invalid_arguments(field, value):
     h = _lib()
