@@ -233,7 +233,7 @@ fc_status fc_plan_separable(fc_plan plan, int which, int cap, int* rank, double*
 
 /* Launch choices the autotuner picked for the plan at setup (per device, n
  * and operator rank; kept in a disk cache, environment FC_TUNE_CACHE, else
- * $HOME/.cache/fracctl/tune_v1.txt; FC_TUNE=0 keeps the defaults).  HOST
+ * $HOME/.cache/fracctl/tune_v2.txt; FC_TUNE=0 keeps the defaults).  HOST
  * outputs: choices[0..5] = wavefronts per workgroup of the Gram kernel for
  * batched and for single products (8 or 16), of the fused Kronecker
  * application (8 or 16), K chunk of the streaming transform kernel (128 or

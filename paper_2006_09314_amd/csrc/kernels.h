@@ -30,9 +30,13 @@ hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
 // (op(A) op(B) = A^T B, A B^T or A B; batched over g.batch with strides, d
 // advancing by strideD per batch entry; inner == 1, FP64): the Gram-type
 // products of the truncations and the diagonally scaled Grams Z^T diag(d) X
-// of the Hadamard truncation, one workgroup per 32 x 32 output tile, K split
-// over its wavefronts.
-hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s, int waves = 16);
+// of the Hadamard truncation, one workgroup per 32 x 32 output tile.
+// staged: the workgroup stages K chunks of both operands in LDS with
+// coalesced loads (the next chunk fetched while the current one is used);
+// direct: each wavefront loads its K slice straight into the matrix-core
+// layout, with no barrier in the K loop.
+hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s, int waves = 16,
+                bool staged = false);
 // Up to kMaxGramJobs Gram-type products (each as in gram, batched or not) in
 // one launch.
 constexpr int kMaxGramJobs = 3;
@@ -41,7 +45,7 @@ struct GramJobs {
     GemmArgs g[kMaxGramJobs];
 };
 hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s,
-                      int waves = 16);
+                      int waves = 16, bool staged = false);
 // Streaming products C = alpha op(A) op(B) + beta C over a long reduction
 // with op(A) op(B) = A^T B (layout 0), A B^T (1) or A B (2), up to three
 // jobs (of any sizes) in one launch on the FP64 matrix cores: the mode

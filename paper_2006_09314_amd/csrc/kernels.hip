@@ -300,20 +300,118 @@ static hipError_t gemm_dispatch(const GemmArgs& g, hipStream_t s) {
 // Products with a long reduction: C = alpha op(A) diag(d) op(B) + beta C
 // with op(A) op(B) = A^T B (L = 0), A B^T (L = 1) or A B (L = 2),
 // column-major operands, d (length K, optional) scaling the reduction index.
-// One workgroup per 32 x 32 output tile; its sixteen wavefronts split K in
-// interleaved chunks of 16 on the FP64 matrix core (16x16x4), each loading
-// the operands of a chunk (four steps) before issuing their products, so
-// that the sixteen wavefronts keep sixteen chunks in flight; operands go
-// straight from memory into the matrix-core lane layout (lane l: row/column
-// l % 16, k = l / 16), and the partial tiles are summed in LDS in a fixed
-// order (deterministic).  Batched over blockIdx.z with strides (d advances
-// by strideD per batch entry).
-// The number of wavefronts per workgroup (8 or 16) is chosen by the
-// autotuner per problem size.
+// One workgroup per 32 x 32 output tile.  K is taken in chunks of GR_KC:
+// the workgroup stages the chunk's 32 rows of op(A) and 32 columns of
+// op(B) (the latter already scaled by d) in LDS with coalesced loads, along
+// whichever index is contiguous in memory, and fetches the next chunk into
+// registers while its wavefronts run the current one on the FP64 matrix
+// core (16x16x4; the wavefronts take the chunk's k-steps in turn, reading
+// their operands from LDS in the matrix-core lane layout: lane l row/column
+// l % 16, k = l / 16).  The wavefronts' partial tiles are summed in LDS in
+// a fixed order (deterministic).  Batched over blockIdx.z with strides (d
+// advances by strideD per batch entry).  The number of wavefronts per
+// workgroup (8 or 16) is chosen by the autotuner per problem size.
+constexpr int GR_KC = 128;          // K chunk staged in LDS
+constexpr int GR_LD = GR_KC + 4;    // padded row of a staged chunk (doubles)
+
+template <int L, int W>
+__device__ __forceinline__ void gram_tile_staged(const GemmArgs& g, int tile, long b) {
+    extern __shared__ double gram_sm[];   // As, Bs [32][GR_LD]; after the K loop: partial tiles
+    constexpr int T = 64 * W;
+    constexpr int PER = 32 * GR_KC / T;  // values per thread and operand per chunk
+    constexpr bool a_kfast = (L == 0);   // op(A) row i is contiguous in k
+    constexpr bool b_kfast = (L != 1);   // op(B) column j is contiguous in k
+    double* As = gram_sm;
+    double* Bs = gram_sm + 32 * GR_LD;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tilesM = (g.M + 31) / 32;
+    const int i0 = (tile % tilesM) * 32, j0 = (tile / tilesM) * 32;
+    const double* __restrict__ A = g.A + b * g.strideA;
+    const double* __restrict__ B = g.B + b * g.strideB;
+    const double* __restrict__ d = g.d ? g.d + b * g.strideD : nullptr;
+    double* __restrict__ C = g.C + b * g.strideC;
+    const int r16 = lane & 15, kq = lane >> 4;
+    double pa[PER], pb[PER];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * T;
+            {
+                const int c = a_kfast ? e / GR_KC : e % 32, kk = kc + (a_kfast ? e % GR_KC : e / 32);
+                const int i = i0 + c;
+                pa[u] = (kk < g.K && i < g.M)
+                            ? (a_kfast ? A[kk + (long)i * g.lda] : A[i + (long)kk * g.lda]) : 0.0;
+            }
+            {
+                const int c = b_kfast ? e / GR_KC : e % 32, kk = kc + (b_kfast ? e % GR_KC : e / 32);
+                const int j = j0 + c;
+                double v = (kk < g.K && j < g.N)
+                               ? (b_kfast ? B[kk + (long)j * g.ldb] : B[j + (long)kk * g.ldb]) : 0.0;
+                if (d) v *= (kk < g.K) ? d[kk] : 0.0;
+                pb[u] = v;
+            }
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * T;
+            As[(a_kfast ? e / GR_KC : e % 32) * GR_LD + (a_kfast ? e % GR_KC : e / 32)] = pa[u];
+            Bs[(b_kfast ? e / GR_KC : e % 32) * GR_LD + (b_kfast ? e % GR_KC : e / 32)] = pb[u];
+        }
+    };
+    dbl4 acc[2][2];
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    for (int kc = 0; kc < g.K; kc += GR_KC) {
+        __syncthreads();   // the previous chunk has been read
+        put();
+        __syncthreads();
+        if (kc + GR_KC < g.K) fetch(kc + GR_KC);
+        for (int st = wave; st < GR_KC / 4; st += W) {
+            const int k = 4 * st + kq;
+            const double a0 = As[r16 * GR_LD + k], a1 = As[(16 + r16) * GR_LD + k];
+            const double b0 = Bs[r16 * GR_LD + k], b1 = Bs[(16 + r16) * GR_LD + k];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    }
+    __syncthreads();   // the LDS now takes the partial tiles
+    double* red = gram_sm;   // [W][4 blocks][4 regs][64 lanes]
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y)
+            for (int v = 0; v < 4; ++v)
+                red[((wave * 4 + 2 * x + y) * 4 + v) * 64 + lane] = acc[x][y][v];
+    __syncthreads();
+    // 32 x 32 outputs; accumulator v of lane l holds row (l >> 4) + 4 v,
+    // column l & 15 of its 16 x 16 block
+    for (int e = threadIdx.x; e < 2 * 2 * 4 * 64; e += T) {
+        const int l = e & 63, v = (e >> 6) & 3, blk = e >> 8;
+        const int x = blk >> 1, y = blk & 1;
+        double sum = 0.0;
+        for (int w = 0; w < W; ++w) sum += red[((w * 4 + blk) * 4 + v) * 64 + l];
+        const int i = i0 + 16 * x + (l >> 4) + 4 * v, j = j0 + 16 * y + (l & 15);
+        if (i < g.M && j < g.N) {
+            double r = g.alpha * sum;
+            if (g.beta != 0.0) r += g.beta * C[i + (long)j * g.ldc];
+            C[i + (long)j * g.ldc] = r;
+        }
+    }
+}
+
+// The direct variant: no staging; its wavefronts split K in interleaved
+// chunks of 16 and load their operands straight from memory into the
+// matrix-core lane layout (lane l: row/column l % 16, k = l / 16), with no
+// barrier in the K loop.  It keeps the edge where K is long and the tiles
+// few (unfolding Grams of cores, K = r^2), where the staged variant spends
+// a barrier pair per chunk.
 constexpr int GR_DEPTH = 1;   // chunks loaded per wavefront before computing
 
 template <int L, int GR_WAVES>
-__device__ __forceinline__ void gram_tile(const GemmArgs& g, int tile, long b) {
+__device__ __forceinline__ void gram_tile_direct(const GemmArgs& g, int tile, long b) {
     extern __shared__ double gram_red[];   // [GR_WAVES][4 blocks][4 regs][64 lanes]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tilesM = (g.M + 31) / 32;
@@ -382,20 +480,26 @@ __device__ __forceinline__ void gram_tile(const GemmArgs& g, int tile, long b) {
     }
 }
 
-template <int L, int W>
+template <int L, int W, bool S>
+__device__ __forceinline__ void gram_tile(const GemmArgs& g, int tile, long b) {
+    if constexpr (S) gram_tile_staged<L, W>(g, tile, b);
+    else gram_tile_direct<L, W>(g, tile, b);
+}
+
+template <int L, int W, bool S>
 __global__ __launch_bounds__(64 * W) void gram_kernel(GemmArgs g) {
-    gram_tile<L, W>(g, blockIdx.x, blockIdx.z);
+    gram_tile<L, W, S>(g, blockIdx.x, blockIdx.z);
 }
 
 // Up to kMaxGramJobs independent products (each possibly a strided batch)
 // in one launch: grid.y picks the product, grid.x runs over its tiles times
 // its batch; blocks beyond a product's own count return at once.
-template <int L, int W>
+template <int L, int W, bool S>
 __global__ __launch_bounds__(64 * W) void gram_multi_kernel(GramJobs jobs) {
     const GemmArgs& g = jobs.g[blockIdx.y];
     const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
     if ((long)blockIdx.x >= (long)tiles * g.batch) return;
-    gram_tile<L, W>(g, (int)(blockIdx.x % tiles), (long)(blockIdx.x / tiles));
+    gram_tile<L, W, S>(g, (int)(blockIdx.x % tiles), (long)(blockIdx.x / tiles));
 }
 
 // ---------------------------------------------------------------------------
@@ -566,7 +670,9 @@ bool stream_fits(const StreamJobs& jobs, int kc, long part_cap) {
 }
 
 // dynamic LDS of the Gram-type kernels: the wavefronts' partial tiles
-static size_t gram_lds(int waves) { return sizeof(double) * (size_t)waves * 4 * 4 * 64; }
+static size_t gram_lds(int waves) {
+    return sizeof(double) * std::max((size_t)2 * 32 * GR_LD, (size_t)waves * 4 * 4 * 64);
+}
 
 template <class F>
 static hipError_t set_lds_once(std::once_flag& once, hipError_t& err, F&& fns) {
@@ -580,37 +686,45 @@ static hipError_t set_lds_once(std::once_flag& once, hipError_t& err, F&& fns) {
     return err;
 }
 
-hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s, int waves) {
+// the kernel for (layout, wavefronts, staging) as a table index
+static int gram_index(int L, int waves, bool staged) { return (L * 2 + (waves == 16)) * 2 + staged; }
+
+#define FC_GRAM_TABLE(kern)                                                                        \
+    {(const void*)kern<0, 8, false>, (const void*)kern<0, 8, true>, (const void*)kern<0, 16, false>, \
+     (const void*)kern<0, 16, true>, (const void*)kern<1, 8, false>, (const void*)kern<1, 8, true>,   \
+     (const void*)kern<1, 16, false>, (const void*)kern<1, 16, true>, (const void*)kern<2, 8, false>, \
+     (const void*)kern<2, 8, true>, (const void*)kern<2, 16, false>, (const void*)kern<2, 16, true>}
+
+static const void* const kGramKernels[12] = FC_GRAM_TABLE(gram_kernel);
+static const void* const kGramMultiKernels[12] = FC_GRAM_TABLE(gram_multi_kernel);
+
+static hipError_t gram_attrs(const void* const* table, std::once_flag& once, hipError_t& err) {
+    return set_lds_once(once, err, [table] {
+        std::vector<std::pair<const void*, size_t>> v;
+        for (int i = 0; i < 12; ++i) v.push_back({table[i], gram_lds(((i >> 1) & 1) ? 16 : 8)});
+        return v;
+    });
+}
+
+hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s, int waves, bool staged) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     if (g.inner != 1 || g.lowp || g.K <= 0 || (transA && transB)) return hipErrorInvalidValue;
     if (waves != 8 && waves != 16) return hipErrorInvalidValue;
     const long tiles = (long)((g.M + 31) / 32) * ((g.N + 31) / 32);
     if (tiles > 0x7fffffffL || g.batch > 65535) return hipErrorInvalidValue;
-    const dim3 grid(tiles, 1, g.batch), block(64 * waves);
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
-    const hipError_t ae = set_lds_once(once, attr_err, [] {
-        return std::vector<std::pair<const void*, size_t>>{
-            {(const void*)gram_kernel<0, 16>, gram_lds(16)}, {(const void*)gram_kernel<1, 16>, gram_lds(16)},
-            {(const void*)gram_kernel<2, 16>, gram_lds(16)}, {(const void*)gram_kernel<0, 8>, gram_lds(8)},
-            {(const void*)gram_kernel<1, 8>, gram_lds(8)}, {(const void*)gram_kernel<2, 8>, gram_lds(8)}};
-    });
+    const hipError_t ae = gram_attrs(kGramKernels, once, attr_err);
     if (ae != hipSuccess) return ae;
-    const size_t lds = gram_lds(waves);
     const int L = transA ? 0 : (transB ? 1 : 2);
-    if (waves == 16) {
-        if (L == 0) hipLaunchKernelGGL((gram_kernel<0, 16>), grid, block, lds, s, g);
-        else if (L == 1) hipLaunchKernelGGL((gram_kernel<1, 16>), grid, block, lds, s, g);
-        else hipLaunchKernelGGL((gram_kernel<2, 16>), grid, block, lds, s, g);
-    } else {
-        if (L == 0) hipLaunchKernelGGL((gram_kernel<0, 8>), grid, block, lds, s, g);
-        else if (L == 1) hipLaunchKernelGGL((gram_kernel<1, 8>), grid, block, lds, s, g);
-        else hipLaunchKernelGGL((gram_kernel<2, 8>), grid, block, lds, s, g);
-    }
-    return hipGetLastError();
+    GemmArgs a = g;
+    void* args[] = {&a};
+    return hipLaunchKernel(kGramKernels[gram_index(L, waves, staged)], dim3(tiles, 1, g.batch),
+                           dim3(64 * waves), args, gram_lds(waves), s);
 }
 
-hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s, int waves) {
+hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s, int waves,
+                      bool staged) {
     if (jobs.count <= 0) return hipSuccess;
     if (jobs.count > kMaxGramJobs || (transA && transB) || (waves != 8 && waves != 16))
         return hipErrorInvalidValue;
@@ -624,29 +738,13 @@ hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_
     if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
-    const hipError_t ae = set_lds_once(once, attr_err, [] {
-        return std::vector<std::pair<const void*, size_t>>{
-            {(const void*)gram_multi_kernel<0, 16>, gram_lds(16)},
-            {(const void*)gram_multi_kernel<1, 16>, gram_lds(16)},
-            {(const void*)gram_multi_kernel<2, 16>, gram_lds(16)},
-            {(const void*)gram_multi_kernel<0, 8>, gram_lds(8)},
-            {(const void*)gram_multi_kernel<1, 8>, gram_lds(8)},
-            {(const void*)gram_multi_kernel<2, 8>, gram_lds(8)}};
-    });
+    const hipError_t ae = gram_attrs(kGramMultiKernels, once, attr_err);
     if (ae != hipSuccess) return ae;
-    const dim3 grid((unsigned)tiles, jobs.count), block(64 * waves);
-    const size_t lds = gram_lds(waves);
     const int L = transA ? 0 : (transB ? 1 : 2);
-    if (waves == 16) {
-        if (L == 0) hipLaunchKernelGGL((gram_multi_kernel<0, 16>), grid, block, lds, s, jobs);
-        else if (L == 1) hipLaunchKernelGGL((gram_multi_kernel<1, 16>), grid, block, lds, s, jobs);
-        else hipLaunchKernelGGL((gram_multi_kernel<2, 16>), grid, block, lds, s, jobs);
-    } else {
-        if (L == 0) hipLaunchKernelGGL((gram_multi_kernel<0, 8>), grid, block, lds, s, jobs);
-        else if (L == 1) hipLaunchKernelGGL((gram_multi_kernel<1, 8>), grid, block, lds, s, jobs);
-        else hipLaunchKernelGGL((gram_multi_kernel<2, 8>), grid, block, lds, s, jobs);
-    }
-    return hipGetLastError();
+    GramJobs j = jobs;
+    void* args[] = {&j};
+    return hipLaunchKernel(kGramMultiKernels[gram_index(L, waves, staged)],
+                           dim3((unsigned)tiles, jobs.count), dim3(64 * waves), args, gram_lds(waves), s);
 }
 
 // ---------------------------------------------------------------------------

@@ -360,6 +360,21 @@ int gram_waves(const Ctx& c, const GemmArgs& g) {
     return g.batch > 1 ? c.p->tune.gram_batched : c.p->tune.gram_single;
 }
 
+// staged or direct Gram tile for a product (see fc::gram): staged for
+// A^T B, whose operands are contiguous along the reduction (measured per
+// shape on the n = 1024 workload: 0.7-0.9 of the direct tile's time), direct
+// for A B^T (1.4-2.1x faster than staged there); FC_GRAM_MODE = staged |
+// direct forces one (a diagnostic)
+const int g_gram_mode = [] {
+    const char* m = std::getenv("FC_GRAM_MODE");
+    if (!m) return -1;
+    return std::strcmp(m, "staged") == 0 ? 1 : std::strcmp(m, "direct") == 0 ? 0 : -1;
+}();
+bool gram_staged(bool ta) {
+    if (g_gram_mode >= 0) return g_gram_mode == 1;
+    return ta;
+}
+
 // The mode transforms run on the streaming kernel (K split over workgroups,
 // partials added by a second kernel).  The small Gram-type products stay on
 // the Gram kernel: one launch each, where the split would need two (the
@@ -383,7 +398,7 @@ hipError_t run_stream(const Ctx& c, bool ta, bool tb, const GemmArgs* g, int cou
     if (!fc::stream_fits(sj, kc, p->splitws_cap)) {
         // partials beyond the workspace: the Gram kernel, one product at a time
         for (int t = 0; t < count; ++t) {
-            const hipError_t e = fc::gram(ta, tb, g[t], c.s, gram_waves(c, g[t]));
+            const hipError_t e = fc::gram(ta, tb, g[t], c.s, gram_waves(c, g[t]), gram_staged(ta));
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -398,7 +413,7 @@ hipError_t run_stream(const Ctx& c, bool ta, bool tb, const GemmArgs* g, int cou
 hipError_t run_gemm(const Ctx& c, bool ta, bool tb, const GemmArgs& g) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     if (t_tag == 3 && is_transform(c, ta, tb, g)) return run_stream(c, ta, tb, &g, 1);
-    if (gram_type(ta, tb, g)) return fc::gram(ta, tb, g, c.s, gram_waves(c, g));
+    if (gram_type(ta, tb, g)) return fc::gram(ta, tb, g, c.s, gram_waves(c, g), gram_staged(ta));
     return fc::gemm(ta, tb, g, c.s);
 }
 
@@ -455,7 +470,7 @@ void launch_group(const Ctx& c, bool ta, bool tb, const fc::GramJobs& jobs, bool
     for (int t = 0; t < jobs.count && transform; ++t) transform = is_transform(c, ta, tb, jobs.g[t]);
     auto run = [&] {
         if (transform) return run_stream(c, ta, tb, jobs.g, jobs.count);
-        return gram ? fc::gram_multi(ta, tb, jobs, c.s, gram_waves(c, jobs.g[0]))
+        return gram ? fc::gram_multi(ta, tb, jobs, c.s, gram_waves(c, jobs.g[0]), gram_staged(ta))
                     : fc::gemm_multi(ta, tb, jobs, c.s);
     };
     if (g_prof.on && !t_no_profile) {
@@ -2442,7 +2457,7 @@ void build_sine_maps(fc_plan_s* p) {
 //   the K chunk of the streaming transform kernel (128 or 256, three modes,
 //   m = 16); the Gram-Schmidt panel width (8 or 16, three n x 96 blocks).
 // Results are kept for the process and in a text cache on disk (environment
-// FC_TUNE_CACHE, else $HOME/.cache/fracctl/tune_v1.txt; one line per key),
+// FC_TUNE_CACHE, else $HOME/.cache/fracctl/tune_v2.txt; one line per key),
 // so plans of the same size take the same choices and give the same bits.
 // FC_TUNE=0 keeps the defaults.
 std::mutex g_tune_mu;
@@ -2452,7 +2467,7 @@ std::string tune_cache_path() {
     if (const char* e = std::getenv("FC_TUNE_CACHE")) return e;
     const char* home = std::getenv("HOME");
     if (!home || !*home) return std::string();
-    return std::string(home) + "/.cache/fracctl/tune_v1.txt";
+    return std::string(home) + "/.cache/fracctl/tune_v2.txt";
 }
 
 bool tune_lookup_disk(const std::string& key, Tuning& t) {
@@ -2553,7 +2568,7 @@ void autotune(fc_plan_s* p) {
         const int r = std::min(48, n), q = std::min(96, n);
         const fc::GemmArgs g = scaled_gram(r, q, n, Q, p->Xs3[0], p->Xs3[1], p->op.D[0], p->Ys);
         for (int w = 0; w < 2; ++w)
-            t.us[w] = time_launches(s, reps, [&] { return fc::gram(true, false, g, s, w ? 16 : 8); });
+            t.us[w] = time_launches(s, reps, [&] { return fc::gram(true, false, g, s, w ? 16 : 8, gram_staged(true)); });
         t.gram_batched = t.us[0] < t.us[1] ? 8 : 16;
     }
     // 2. three 32 x 16 Gram-type products over n (the panel coefficients)
@@ -2567,7 +2582,7 @@ void autotune(fc_plan_s* p) {
         }
         for (int w = 0; w < 2; ++w)
             t.us[2 + w] = time_launches(s, reps, [&] {
-                return fc::gram_multi(true, false, jobs, s, w ? 16 : 8);
+                return fc::gram_multi(true, false, jobs, s, w ? 16 : 8, gram_staged(true));
             });
         t.gram_single = t.us[2] < t.us[3] ? 8 : 16;
     }
@@ -3073,7 +3088,7 @@ hipError_t cross_grams(int n, int ra, const double* const A[3], int rb, const do
         g.M = ra; g.N = rb; g.K = n;
         g.A = A[l]; g.lda = n; g.B = B[l]; g.ldb = n; g.C = G[l]; g.ldc = ra;
     }
-    if (ra <= 128 && rb <= 128) return fc::gram_multi(true, false, jobs, s);
+    if (ra <= 128 && rb <= 128) return fc::gram_multi(true, false, jobs, s, 16, gram_staged(true));
     hipError_t e = hipSuccess;
     for (int l = 0; l < 3 && e == hipSuccess; ++l) e = fc::gemm(true, false, jobs.g[l], s);
     return e;
