@@ -987,6 +987,8 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int k, const double
 // eigenvalues at most 1e-17 of the largest in magnitude are neither refined
 // nor back-transformed (callers do not use them).  Scratch: 6 k^2 doubles.
 constexpr int TD_THREADS = 512;
+constexpr int TRI_THREADS = 1024;   // the tridiagonalisation's workgroup
+constexpr int TRI_PARTS = TRI_THREADS / 128;   // column groups of its matrix-vector step
 
 __device__ inline double td_wave_sum(double v) { return wave_sum(v); }
 
@@ -1012,7 +1014,7 @@ __device__ inline double td_recip(double q) {
 #define TD_LAM(k) (TD_D(k) + 3L * (k))
 #define TD_NV(k) (TD_D(k) + 4L * (k))
 
-__global__ __launch_bounds__(TD_THREADS) void tdeig_tri_kernel(EigJobs jobs) {
+__global__ __launch_bounds__(TRI_THREADS) void tdeig_tri_kernel(EigJobs jobs) {
     extern __shared__ double sm[];
     __shared__ double sc[2];
     const EigJob& J = jobs.job[blockIdx.x];
@@ -1027,7 +1029,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_tri_kernel(EigJobs jobs) {
     double* pw = vv + k;             // p / w / dot products
     double* lam = pw + k;            // eigenvalues, descending
     double* e2 = lam + k;            // squared off-diagonal
-    double* pw4 = e2 + k;            // partial sums of A22 v (4 x 128)
+    double* pw4 = e2 + k;            // partial sums of A22 v (TRI_PARTS x 128)
     for (int x = tid; x < k * k; x += blockDim.x) {
         const int i = x % k, j = x / k;
         a[x] = 0.5 * (J.A[i + (long)j * J.lda] + J.A[j + (long)i * J.lda]);
@@ -1065,21 +1067,24 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_tri_kernel(EigJobs jobs) {
         const double t = sc[j & 1];
         if (t == 0.0) continue;
         // p = t * A22 v: thread (row r = tid % 128, part = tid / 128) sums over
-        // the columns c = part, part + 4, ..., so a wavefront reads 64
+        // the columns c = part, part + TRI_PARTS, ..., so a wavefront reads 64
         // consecutive rows of one column (no LDS bank conflicts); the first
-        // wavefront adds the four partial sums of each row
+        // wavefront adds the partial sums of each row in a fixed order
         {
             const int r = tid & 127, part = tid >> 7;
             double acc = 0.0;
             if (r < m)
-                for (int c = part; c < m; c += 4) acc += a[(j + 1 + r) + (j + 1 + c) * k] * vv[c];
+                for (int c = part; c < m; c += TRI_PARTS) acc += a[(j + 1 + r) + (j + 1 + c) * k] * vv[c];
             pw4[part * 128 + r] = acc;
         }
         __syncthreads();
         if (wv == 0) {
             double sp = 0.0;
             for (int r = lane; r < m; r += 64) {
-                const double pr = t * ((pw4[r] + pw4[128 + r]) + (pw4[256 + r] + pw4[384 + r]));
+                double s8 = 0.0;
+#pragma unroll
+                for (int q = 0; q < TRI_PARTS; q += 2) s8 += pw4[q * 128 + r] + pw4[(q + 1) * 128 + r];
+                const double pr = t * s8;
                 pw[r] = pr;
                 sp += vv[r] * pr;
             }
@@ -1093,7 +1098,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_tri_kernel(EigJobs jobs) {
             const bool in1 = lane + 64 < m;
             const double vr0 = vv[lane], wr0 = pw[lane];
             const double vr1 = in1 ? vv[lane + 64] : 0.0, wr1 = in1 ? pw[lane + 64] : 0.0;
-            for (int c = wv; c < m; c += TD_THREADS / 64) {
+            for (int c = wv; c < m; c += TRI_THREADS / 64) {
                 const double vc = vv[c], wc = pw[c];
                 double* col = a + (j + 1) + (long)(j + 1 + c) * k;
                 col[lane] -= vr0 * wc + wr0 * vc;
@@ -1453,9 +1458,10 @@ hipError_t sym_eig_multi(const EigJobs& jobs, hipStream_t s) {
     });
     if (attr_err != hipSuccess) return attr_err;
     const int per = TD_THREADS / 64;
-    static_assert(TD_THREADS == 512, "the tridiagonalisation's matrix-vector step takes 4 x 128 threads");
-    hipLaunchKernelGGL(tdeig_tri_kernel, dim3(jobs.count), dim3(TD_THREADS),
-                       sizeof(double) * ((size_t)kmax * (kmax + 1) + 7 * kmax + 512), s, jobs);
+    static_assert(TRI_THREADS % 128 == 0 && TRI_PARTS % 2 == 0,
+                  "the tridiagonalisation's matrix-vector step takes whole groups of 128 threads");
+    hipLaunchKernelGGL(tdeig_tri_kernel, dim3(jobs.count), dim3(TRI_THREADS),
+                       sizeof(double) * ((size_t)kmax * (kmax + 1) + 7 * kmax + 128 * TRI_PARTS), s, jobs);
     hipLaunchKernelGGL(tdeig_val_kernel, dim3((kmax + per - 1) / per, jobs.count),
                        dim3(TD_THREADS), 0, s, jobs);
     hipLaunchKernelGGL(tdeig_vec_kernel, dim3((kmax + TD_VPB - 1) / TD_VPB, jobs.count), dim3(64),
