@@ -41,14 +41,16 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 //
 // A workgroup of WM x WN wavefronts owns a (32 WM) x (32 WN) tile of C; each
 // wavefront owns a 32 x 32 sub-tile held as 2 x 2 MFMA 16x16 accumulators.
-// K is consumed in chunks of 16 staged through LDS (coalesced global reads in
-// the operand's storage order).  MFMA 16x16x4 f64 operand layout: lane l
+// K is consumed in chunks of 32 staged through LDS (coalesced global reads in
+// the operand's storage order), the next chunk fetched into registers while
+// the current one is used.  MFMA 16x16x4 f64 operand layout: lane l
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register v of
 // lane l holds C[l / 16 + 4 v][l % 16] (checked by the layout self-test).
 template <bool TA, bool TB, int WM, int WN>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tile, int b, int kz, int kchunk,
                                           bool split) {
-    constexpr int BM = 32 * WM, BN = 32 * WN, BK = 16, NT = 64 * WM * WN;
+    constexpr int BM = 32 * WM, BN = 32 * WN, BK = 32, NT = 64 * WM * WN;
+    constexpr int PA = BM * BK / NT, PB = BK * BN / NT;   // staged values per thread
     __shared__ double As[BK][BM + 1];
     __shared__ double Bs[BK][BN + 1];
     const int tilesM = (g.M + BM - 1) / BM;
@@ -74,28 +76,53 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tile, int b, in
     dbl4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        for (int e = tid; e < BM * BK; e += NT) {
+    // chunks of BK staged in LDS along the index contiguous in memory; the
+    // next chunk is fetched into registers while the current one is used
+    double pa[PA], pb[PB];
+    auto a_ik = [&](int e, int& i, int& k) {
+        if (!TA) { i = e % BM; k = e / BM; } else { k = e % BK; i = e / BK; }
+    };
+    auto b_kj = [&](int e, int& k, int& j) {
+        if (!TB) { k = e % BK; j = e / BK; } else { j = e % BN; k = e / BN; }
+    };
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < PA; ++u) {
             int i, k;
-            if (!TA) { i = e % BM; k = e / BM; } else { k = e % BK; i = e / BK; }
+            a_ik(tid + u * NT, i, k);
             const int gi = row0 + i, gk = k0 + k;
             double v = 0.0;
             if (gi < g.M && gk < kend) {
                 v = TA ? A[gk + (long)gi * g.lda] : A[gi + (long)gk * g.lda];
                 if (d) v *= d[gk];
             }
-            As[k][i] = v;
+            pa[u] = v;
         }
-        for (int e = tid; e < BK * BN; e += NT) {
-            int j, k;
-            if (!TB) { k = e % BK; j = e / BK; } else { j = e % BN; k = e / BN; }
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+            int k, j;
+            b_kj(tid + u * NT, k, j);
             const int gj = col0 + j, gk = k0 + k;
-            double v = 0.0;
-            if (gj < g.N && gk < kend) v = TB ? B[gj + (long)gk * g.ldb] : B[gk + (long)gj * g.ldb];
-            Bs[k][j] = v;
+            pb[u] = (gj < g.N && gk < kend) ? (TB ? B[gj + (long)gk * g.ldb] : B[gk + (long)gj * g.ldb]) : 0.0;
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PA; ++u) {
+            int i, k;
+            a_ik(tid + u * NT, i, k);
+            As[k][i] = pa[u];
+        }
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+            int k, j;
+            b_kj(tid + u * NT, k, j);
+            Bs[k][j] = pb[u];
         }
         __syncthreads();
+        if (k0 + BK < kend) fetch(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
             const int k = kk * 4 + (lane >> 4);
@@ -108,7 +135,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tile, int b, in
             acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
-        __syncthreads();
     }
     for (int mi = 0; mi < 2; ++mi)
         for (int ni = 0; ni < 2; ++ni)
