@@ -1056,9 +1056,20 @@ __global__ __launch_bounds__(TRI_THREADS) void tdeig_tri_kernel(EigJobs jobs) {
     double* lam = pw + k;            // eigenvalues, descending
     double* e2 = lam + k;            // squared off-diagonal
     double* pw4 = e2 + k;            // partial sums of A22 v (TRI_PARTS x 128)
-    for (int x = tid; x < k * k; x += blockDim.x) {
-        const int i = x % k, j = x / k;
-        a[x] = 0.5 * (J.A[i + (long)j * J.lda] + J.A[j + (long)i * J.lda]);
+    // the symmetrised matrix into LDS, eight elements per thread in flight
+    for (int x0 = 0; x0 < k * k; x0 += 8 * TRI_THREADS) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int x = x0 + tid + u * TRI_THREADS;
+            const int i = x % k, j = x / k;
+            v[u] = x < k * k ? 0.5 * (J.A[i + (long)j * J.lda] + J.A[j + (long)i * J.lda]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int x = x0 + tid + u * TRI_THREADS;
+            if (x < k * k) a[x] = v[u];
+        }
     }
     __syncthreads();
     if (k == 1) {
@@ -1370,9 +1381,20 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_clu_kernel(EigJobs jobs) {
     double* pw = sm + (long)k * kp;       // dot products
     double* used = pw + k;                // 1 for a vector that is refined
     double* X = S + TD_X(k);
-    for (int x = tid; x < nvec * k; x += blockDim.x) {
-        const int i = x % nvec, j = x / nvec;
-        Xl[j + (long)i * kp] = X[i + (long)j * k];
+    for (int x0 = 0; x0 < nvec * k; x0 += 8 * TD_THREADS) {   // eight loads in flight
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int x = x0 + tid + u * TD_THREADS;
+            const int i = x % nvec, j = x / nvec;
+            v[u] = x < nvec * k ? X[i + (long)j * k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int x = x0 + tid + u * TD_THREADS;
+            const int i = x % nvec, j = x / nvec;
+            if (x < nvec * k) Xl[j + (long)i * kp] = v[u];
+        }
     }
     for (int i = tid; i < k; i += blockDim.x) used[i] = fabs(lam[i]) > 1e-17 * lmax ? 1.0 : 0.0;
     __syncthreads();
@@ -2236,7 +2258,21 @@ __global__ __launch_bounds__(1024) void panel_mgs_kernel(int n, PanelJobs jobs, 
     int* keep = jb.keep;
     const int b = jb.b;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (long x = tid; x < (long)n * b; x += 1024) P[x] = Y[x];
+    // the panel into LDS, eight loads per thread in flight
+    const long total = (long)n * b;
+    for (long x0 = 0; x0 < total; x0 += 8 * 1024) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const long x = x0 + tid + (long)u * 1024;
+            v[u] = x < total ? Y[x] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const long x = x0 + tid + (long)u * 1024;
+            if (x < total) P[x] = v[u];
+        }
+    }
     __syncthreads();
     for (int j = 0; j < b; ++j) {
         double* y = P + (long)j * n;
