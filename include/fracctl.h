@@ -28,8 +28,12 @@
  * by the caller; HOST pointers are ordinary host memory.  The plan owns all
  * of its device state and workspace; fc_solve performs no device allocation.
  * Streams: `hip_stream` is a hipStream_t (NULL = the default stream); all
- * device work of a call is enqueued on it.  A plan must not be used by two
- * threads at once; distinct plans may run concurrently on distinct streams.
+ * device work of a call is enqueued on it.  fc_setup_ex is the exception: a
+ * NULL stream there means a private non-blocking stream that the setup
+ * creates, and with any stream the plan is complete when it returns.  A plan
+ * must not be used by two threads at once; distinct plans may run
+ * concurrently on distinct streams, and plans may be built concurrently on
+ * several threads.
  *
  * Errors: every entry point returns an fc_status; no exception crosses the
  * boundary.  fc_last_error() returns a thread-local text describing the last
@@ -147,7 +151,10 @@ fc_status fc_setup(int n, const double* a1, const double* a2, const double* a3,
  * and the state map, free nodes for the preconditioner), fitted by one
  * workgroup per candidate grid or rank on the device; then the factors
  * exp(-t lambda) on the device, the solve workspace and the autotuner's
- * launch choices.  Fails with FC_ERR_NUMERIC if the operator misses
+ * launch choices.  The device work runs on hip_stream, or on a private
+ * non-blocking stream when it is NULL (so that setups on several threads do
+ * not serialise on the default stream); the stream is synchronised before
+ * the call returns.  Fails with FC_ERR_NUMERIC if the operator misses
  * op_accuracy anywhere on [s_min, s_max] or a separable factor is not
  * positive. */
 fc_status fc_setup_ex(const fc_setup_params* p, void* hip_stream, fc_plan* out);

@@ -131,3 +131,95 @@ def test_device_fits_full_size_and_setup_time():
     # device fit keeps the host's support (up to a node)
     assert abs(len(w) - len(hw)) <= 3
     assert t_dev < 1.0
+
+
+def _plan_record(plan, prob, stream=None):
+    """Everything a plan decides at setup, and one solve with it."""
+    import torch
+    from tests.gpu_util import dev, host
+    rec = {"lam": np.concatenate(plan.spectrum()), "tuning": plan.tuning()}
+    for which in range(3):
+        w, F = plan.separable(which)
+        rec[f"w{which}"] = w
+        rec[f"F{which}"] = np.concatenate([f[:, :len(w)] for f in F], axis=1)
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        wy = torch.from_numpy(np.asarray(prob.w, dtype=np.float64)).cuda()
+        Y = [dev(y) for y in prob.Y]
+        w_u, U, info = plan.solve(wy, Y, stream=stream)
+        rec["w_u"] = host(w_u)
+        rec["U"] = [host(u) for u in U]
+    rec["iterations"] = info["iterations"]
+    return rec
+
+
+class _nullctx:
+    def __enter__(self):
+        return None
+
+    def __exit__(self, *a):
+        return False
+
+
+@pytest.mark.timeout(600)
+def test_concurrent_setups_match_sequential_ones():
+    """Plans built on several host threads at once (each setup on a private
+    stream, temporaries stream-ordered, handles from a shared pool) decide
+    exactly what the same plans built one after another decide: spectra,
+    all three separables, the autotuner's choices, and the solve's bits."""
+    import threading
+    import torch
+    from tests.gpu_util import plan_for
+    probs = [wl.workload_sine(n=256, seed=s) for s in (1, 2, 3)] + [
+        wl.workload_quadratic(n=128, alpha=0.25),
+        wl.workload_paper_shaped(128, 0.5),
+        wl.workload_sine(n=512, seed=4),
+    ]
+    seq = []
+    for prob in probs:
+        plan = plan_for(prob)
+        seq.append(_plan_record(plan, prob))
+        del plan
+    plans = [None] * len(probs)
+    errors = []
+    start = threading.Barrier(len(probs))
+
+    def build(i):
+        try:
+            start.wait()
+            plans[i] = plan_for(probs[i])
+        except Exception as e:   # reported on the main thread
+            errors.append((i, repr(e)))
+
+    threads = [threading.Thread(target=build, args=(i,)) for i in range(len(probs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    # solves of the concurrently built plans, concurrently on streams of their own
+    streams = [torch.cuda.Stream() for _ in probs]
+    recs = [None] * len(probs)
+
+    def run(i):
+        try:
+            recs[i] = _plan_record(plans[i], probs[i], streams[i])
+        except Exception as e:
+            errors.append((i, repr(e)))
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(len(probs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for i, (a, b) in enumerate(zip(seq, recs)):
+        assert a["tuning"] == b["tuning"], i
+        for key in ("lam", "w0", "F0", "w1", "F1", "w2", "F2", "w_u"):
+            assert a[key].shape == b[key].shape, (i, key)
+            assert np.array_equal(a[key], b[key]), (i, key)
+        for u, v in zip(a["U"], b["U"]):
+            assert np.array_equal(u, v), i
+        assert a["iterations"] == b["iterations"]
+    print(f"[setup] {len(probs)} concurrent setups and solves bit-identical to sequential ones",
+          flush=True)
