@@ -35,8 +35,12 @@ hipError_t gemm(bool transA, bool transB, const GemmArgs& g, hipStream_t s);
 // coalesced loads (the next chunk fetched while the current one is used);
 // direct: each wavefront loads its K slice straight into the matrix-core
 // layout, with no barrier in the K loop.
+// group (1, 2 or 4): batches of scaled Grams A^T diag(d_q) B with A and B
+// shared by the batch (strideA = strideB = 0) run with that many terms per
+// workgroup, their operand chunks staged once for the group (16 wavefronts
+// take two terms at most); other products ignore it.
 hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s, int waves = 16,
-                bool staged = false);
+                bool staged = false, int group = 1);
 // Up to kMaxGramJobs Gram-type products (each as in gram, batched or not) in
 // one launch.
 constexpr int kMaxGramJobs = 3;
@@ -45,7 +49,7 @@ struct GramJobs {
     GemmArgs g[kMaxGramJobs];
 };
 hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s,
-                      int waves = 16, bool staged = false);
+                      int waves = 16, bool staged = false, int group = 1);
 // Streaming products C = alpha op(A) op(B) + beta C over a long reduction
 // with op(A) op(B) = A^T B (layout 0), A B^T (1) or A B (2), up to three
 // jobs (of any sizes) in one launch on the FP64 matrix cores: the mode

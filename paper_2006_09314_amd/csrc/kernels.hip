@@ -528,6 +528,129 @@ __global__ __launch_bounds__(64 * W) void gram_multi_kernel(GramJobs jobs) {
     gram_tile<L, W, S>(g, (int)(blockIdx.x % tiles), (long)(blockIdx.x / tiles));
 }
 
+// Batches of diagonally scaled Grams C_q = alpha A^T diag(d_q) B + beta C_q
+// that share A and B (strideA = strideB = 0; d_q at d + q strideD, C_q at
+// C + q strideC): one workgroup per 32 x 32 output tile and group of QG
+// consecutive terms.  The K chunks of A and B are staged in LDS once for
+// the group (coalesced, the next chunk fetched into registers while the
+// current one is used) with the group's QG chunks of d; every wavefront
+// takes its k-steps for all QG terms, scaling its B operand by d_q in
+// registers.  The group shares its operand loads and its barriers, so a
+// batch runs on a quarter (QG = 4) or half of the workgroups, each doing
+// QG times the matrix-core work: fewer compute units held for the batch,
+// which leaves room for the kernels of concurrent solves.  Partial tiles
+// are summed in LDS term by term in a fixed wavefront order (deterministic).
+template <int W, int QG>
+__device__ __forceinline__ void sgram_tile(const GemmArgs& g, int tile, int q0) {
+    extern __shared__ double gram_sm[];   // As, Bs [32][GR_LD], Ds [QG][GR_KC]; then partial tiles
+    constexpr int T = 64 * W;
+    constexpr int PER = 32 * GR_KC / T;
+    constexpr int PERD = (QG * GR_KC + T - 1) / T;
+    double* As = gram_sm;
+    double* Bs = gram_sm + 32 * GR_LD;
+    double* Ds = gram_sm + 64 * GR_LD;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tilesM = (g.M + 31) / 32;
+    const int i0 = (tile % tilesM) * 32, j0 = (tile / tilesM) * 32;
+    const int nq = min(QG, g.batch - q0);
+    const double* __restrict__ A = g.A;
+    const double* __restrict__ B = g.B;
+    const double* __restrict__ d = g.d + (long)q0 * g.strideD;
+    const int r16 = lane & 15, kq = lane >> 4;
+    double pa[PER], pb[PER], pd[PERD];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * T;
+            const int c = e / GR_KC, kk = kc + e % GR_KC;
+            const bool vk = kk < g.K;
+            pa[u] = (vk && i0 + c < g.M) ? A[kk + (long)(i0 + c) * g.lda] : 0.0;
+            pb[u] = (vk && j0 + c < g.N) ? B[kk + (long)(j0 + c) * g.ldb] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PERD; ++u) {
+            const int e = threadIdx.x + u * T;
+            const int t = e / GR_KC, kk = kc + e % GR_KC;
+            pd[u] = (e < QG * GR_KC && t < nq && kk < g.K) ? d[kk + (long)t * g.strideD] : 0.0;
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * T;
+            As[(e / GR_KC) * GR_LD + e % GR_KC] = pa[u];
+            Bs[(e / GR_KC) * GR_LD + e % GR_KC] = pb[u];
+        }
+#pragma unroll
+        for (int u = 0; u < PERD; ++u) {
+            const int e = threadIdx.x + u * T;
+            if (e < QG * GR_KC) Ds[e] = pd[u];
+        }
+    };
+    dbl4 acc[QG][2][2];
+#pragma unroll
+    for (int t = 0; t < QG; ++t)
+        for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y) acc[t][x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    for (int kc = 0; kc < g.K; kc += GR_KC) {
+        __syncthreads();   // the previous chunk has been read
+        put();
+        __syncthreads();
+        if (kc + GR_KC < g.K) fetch(kc + GR_KC);
+        for (int st = wave; st < GR_KC / 4; st += W) {
+            const int k = 4 * st + kq;
+            const double a0 = As[r16 * GR_LD + k], a1 = As[(16 + r16) * GR_LD + k];
+            const double b0 = Bs[r16 * GR_LD + k], b1 = Bs[(16 + r16) * GR_LD + k];
+#pragma unroll
+            for (int t = 0; t < QG; ++t) {
+                const double dk = Ds[t * GR_KC + k];
+                const double c0 = b0 * dk, c1 = b1 * dk;
+                acc[t][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, c0, acc[t][0][0], 0, 0, 0);
+                acc[t][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, c1, acc[t][0][1], 0, 0, 0);
+                acc[t][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, c0, acc[t][1][0], 0, 0, 0);
+                acc[t][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, c1, acc[t][1][1], 0, 0, 0);
+            }
+        }
+    }
+    double* red = gram_sm;   // [W][4 blocks][4 regs][64 lanes], one term at a time
+#pragma unroll
+    for (int t = 0; t < QG; ++t) {
+        __syncthreads();   // the LDS is free (staged chunks, or the previous term's partials)
+        for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y)
+                for (int v = 0; v < 4; ++v)
+                    red[((wave * 4 + 2 * x + y) * 4 + v) * 64 + lane] = acc[t][x][y][v];
+        __syncthreads();
+        if (t < nq) {
+            double* __restrict__ C = g.C + (long)(q0 + t) * g.strideC;
+            for (int e = threadIdx.x; e < 2 * 2 * 4 * 64; e += T) {
+                const int l = e & 63, v = (e >> 6) & 3, blk = e >> 8;
+                const int x = blk >> 1, y = blk & 1;
+                double sum = 0.0;
+                for (int w = 0; w < W; ++w) sum += red[((w * 4 + blk) * 4 + v) * 64 + l];
+                const int i = i0 + 16 * x + (l >> 4) + 4 * v, j = j0 + 16 * y + (l & 15);
+                if (i < g.M && j < g.N) {
+                    double r = g.alpha * sum;
+                    if (g.beta != 0.0) r += g.beta * C[i + (long)j * g.ldc];
+                    C[i + (long)j * g.ldc] = r;
+                }
+            }
+        }
+    }
+}
+
+// Up to kMaxGramJobs such batches in one launch: grid.y picks the batch,
+// grid.x runs over its tiles times its term groups.
+template <int W, int QG>
+__global__ __launch_bounds__(64 * W) void sgram_multi_kernel(GramJobs jobs) {
+    const GemmArgs& g = jobs.g[blockIdx.y];
+    const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
+    const int groups = (g.batch + QG - 1) / QG;
+    if ((long)blockIdx.x >= (long)tiles * groups) return;
+    sgram_tile<W, QG>(g, (int)(blockIdx.x % tiles), (int)(blockIdx.x / tiles) * QG);
+}
+
 // ---------------------------------------------------------------------------
 // Streaming products with a long reduction and a small right or output
 // side: C = alpha op(A) op(B) + beta C with op(A) op(B) = A^T B (L = 0),
@@ -699,7 +822,6 @@ bool stream_fits(const StreamJobs& jobs, int kc, long part_cap) {
 static size_t gram_lds(int waves) {
     return sizeof(double) * std::max((size_t)2 * 32 * GR_LD, (size_t)waves * 4 * 4 * 64);
 }
-
 template <class F>
 static hipError_t set_lds_once(std::once_flag& once, hipError_t& err, F&& fns) {
     std::call_once(once, [&] {
@@ -710,6 +832,52 @@ static hipError_t set_lds_once(std::once_flag& once, hipError_t& err, F&& fns) {
         }
     });
     return err;
+}
+
+static size_t sgram_lds(int waves, int group) {
+    return sizeof(double) * std::max((size_t)2 * 32 * GR_LD + (size_t)group * GR_KC,
+                                     (size_t)waves * 4 * 4 * 64);
+}
+
+// a launch of scaled-Gram batches that the grouped kernel takes: A^T diag(d_q) B
+// with A and B shared by the batch
+static bool sgram_fits(bool transA, bool transB, const GramJobs& jobs) {
+    if (!transA || transB || jobs.count <= 0) return false;
+    for (int t = 0; t < jobs.count; ++t) {
+        const GemmArgs& g = jobs.g[t];
+        if (!g.d || g.strideA != 0 || g.strideB != 0 || g.batch < 2 || g.inner != 1 || g.lowp)
+            return false;
+    }
+    return true;
+}
+
+static hipError_t sgram_launch(const GramJobs& jobs, hipStream_t s, int waves, int group) {
+    // (waves, terms per group): (8, 2), (8, 4), (16, 2); 16 wavefronts hold
+    // at most 128 registers per lane, too few for four terms' accumulators
+    if (waves == 16) group = 2;
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    const void* const kern[3] = {(const void*)sgram_multi_kernel<8, 2>,
+                                 (const void*)sgram_multi_kernel<8, 4>,
+                                 (const void*)sgram_multi_kernel<16, 2>};
+    const hipError_t ae = set_lds_once(once, attr_err, [&kern] {
+        return std::vector<std::pair<const void*, size_t>>{
+            {kern[0], sgram_lds(8, 2)}, {kern[1], sgram_lds(8, 4)}, {kern[2], sgram_lds(16, 2)}};
+    });
+    if (ae != hipSuccess) return ae;
+    long blocks = 0;
+    for (int t = 0; t < jobs.count; ++t) {
+        const GemmArgs& g = jobs.g[t];
+        if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
+        blocks = std::max(blocks, (long)((g.M + 31) / 32) * ((g.N + 31) / 32) *
+                                      ((g.batch + group - 1) / group));
+    }
+    if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    const int idx = waves == 16 ? 2 : (group == 4 ? 1 : 0);
+    GramJobs j = jobs;
+    void* args[] = {&j};
+    return hipLaunchKernel(kern[idx], dim3((unsigned)blocks, jobs.count), dim3(64 * waves), args,
+                           sgram_lds(waves, group), s);
 }
 
 // the kernel for (layout, wavefronts, staging) as a table index
@@ -732,10 +900,18 @@ static hipError_t gram_attrs(const void* const* table, std::once_flag& once, hip
     });
 }
 
-hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s, int waves, bool staged) {
+hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s, int waves, bool staged,
+                int group) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     if (g.inner != 1 || g.lowp || g.K <= 0 || (transA && transB)) return hipErrorInvalidValue;
     if (waves != 8 && waves != 16) return hipErrorInvalidValue;
+    if (group != 1 && group != 2 && group != 4) return hipErrorInvalidValue;
+    if (group > 1) {
+        GramJobs one;
+        one.count = 1;
+        one.g[0] = g;
+        if (sgram_fits(transA, transB, one)) return sgram_launch(one, s, waves, group);
+    }
     const long tiles = (long)((g.M + 31) / 32) * ((g.N + 31) / 32);
     if (tiles > 0x7fffffffL || g.batch > 65535) return hipErrorInvalidValue;
     static std::once_flag once;
@@ -750,10 +926,12 @@ hipError_t gram(bool transA, bool transB, const GemmArgs& g, hipStream_t s, int 
 }
 
 hipError_t gram_multi(bool transA, bool transB, const GramJobs& jobs, hipStream_t s, int waves,
-                      bool staged) {
+                      bool staged, int group) {
     if (jobs.count <= 0) return hipSuccess;
     if (jobs.count > kMaxGramJobs || (transA && transB) || (waves != 8 && waves != 16))
         return hipErrorInvalidValue;
+    if (group != 1 && group != 2 && group != 4) return hipErrorInvalidValue;
+    if (group > 1 && sgram_fits(transA, transB, jobs)) return sgram_launch(jobs, s, waves, group);
     long tiles = 0;
     for (int t = 0; t < jobs.count; ++t) {
         const GemmArgs& g = jobs.g[t];

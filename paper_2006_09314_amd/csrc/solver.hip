@@ -389,6 +389,26 @@ bool gram_staged(bool ta) {
     return ta;
 }
 
+// terms per workgroup of the batched scaled Grams (fc::gram's group): two.
+// A workgroup then stages its A and B chunks once for two terms; a batch
+// holds half the compute units, which the concurrent solves of a batched
+// call use (64 solves at n = 1024: 151 -> 166 solves/s; one solve alone
+// unchanged).  FC_GRAM_GROUP = 1 | 2 | 4 overrides it (a diagnostic).
+const int g_gram_group = [] {
+    const char* m = std::getenv("FC_GRAM_GROUP");
+    const int v = m ? std::atoi(m) : 2;
+    return (v == 1 || v == 2 || v == 4) ? v : 2;
+}();
+// FC_KRON_WAVES = 8 | 16 overrides the tuned wavefronts of the fused
+// Kronecker application (a diagnostic)
+const int g_kron_waves = [] {
+    const char* m = std::getenv("FC_KRON_WAVES");
+    const int v = m ? std::atoi(m) : 0;
+    return (v == 8 || v == 16) ? v : 0;
+}();
+int kron_waves(const Ctx& c) { return g_kron_waves ? g_kron_waves : c.p->tune.kron; }
+int gram_group(const GemmArgs& g) { return g.batch > 1 ? g_gram_group : 1; }
+
 // The mode transforms run on the streaming kernel (K split over workgroups,
 // partials added by a second kernel).  The small Gram-type products stay on
 // the Gram kernel: one launch each, where the split would need two (the
@@ -412,7 +432,8 @@ hipError_t run_stream(const Ctx& c, bool ta, bool tb, const GemmArgs* g, int cou
     if (!fc::stream_fits(sj, kc, p->splitws_cap)) {
         // partials beyond the workspace: the Gram kernel, one product at a time
         for (int t = 0; t < count; ++t) {
-            const hipError_t e = fc::gram(ta, tb, g[t], c.s, gram_waves(c, g[t]), gram_staged(ta));
+            const hipError_t e = fc::gram(ta, tb, g[t], c.s, gram_waves(c, g[t]), gram_staged(ta),
+                                          gram_group(g[t]));
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -427,7 +448,8 @@ hipError_t run_stream(const Ctx& c, bool ta, bool tb, const GemmArgs* g, int cou
 hipError_t run_gemm(const Ctx& c, bool ta, bool tb, const GemmArgs& g) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     if (t_tag == 3 && is_transform(c, ta, tb, g)) return run_stream(c, ta, tb, &g, 1);
-    if (gram_type(ta, tb, g)) return fc::gram(ta, tb, g, c.s, gram_waves(c, g), gram_staged(ta));
+    if (gram_type(ta, tb, g))
+        return fc::gram(ta, tb, g, c.s, gram_waves(c, g), gram_staged(ta), gram_group(g));
     return fc::gemm(ta, tb, g, c.s);
 }
 
@@ -484,7 +506,8 @@ void launch_group(const Ctx& c, bool ta, bool tb, const fc::GramJobs& jobs, bool
     for (int t = 0; t < jobs.count && transform; ++t) transform = is_transform(c, ta, tb, jobs.g[t]);
     auto run = [&] {
         if (transform) return run_stream(c, ta, tb, jobs.g, jobs.count);
-        return gram ? fc::gram_multi(ta, tb, jobs, c.s, gram_waves(c, jobs.g[0]), gram_staged(ta))
+        return gram ? fc::gram_multi(ta, tb, jobs, c.s, gram_waves(c, jobs.g[0]), gram_staged(ta),
+                                     gram_group(jobs.g[0]))
                     : fc::gemm_multi(ta, tb, jobs, c.s);
     };
     if (g_prof.on && !t_no_profile) {
@@ -540,10 +563,10 @@ void kron_apply(const Ctx& c, int Q, const fc::KronJobs& kj) {
                                (double)n * J.p);
         }
         record_product(c.s, sh,
-                       [&] { return fc::kron_apply_multi(n, Q, kj, c.s, c.p->tune.kron); });
+                       [&] { return fc::kron_apply_multi(n, Q, kj, c.s, kron_waves(c)); });
         return;
     }
-    HIPCHK(fc::kron_apply_multi(n, Q, kj, c.s, c.p->tune.kron));
+    HIPCHK(fc::kron_apply_multi(n, Q, kj, c.s, kron_waves(c)));
 }
 
 fc::GemmArgs prod(int M, int N, int K, const double* A, long lda, const double* B, long ldb,
