@@ -195,8 +195,8 @@ KERNELS = {0: "gemm_kernel / gemm_multi_kernel (short-reduction LDS-tiled FP64 M
            2: "tdeig_*_kernel (symmetric eigensolver: tridiagonalisation, multisection, inverse "
               "iteration, clusters, back-transformation; five launches per call)",
            3: "stream_kernel + stream_reduce_kernel (mode transforms V^T Y, V Z on FP64 MFMA)",
-           4: "gram_kernel / gram_multi_kernel (long-reduction FP64 MFMA: Gram-type products, "
-              "scaled Grams Z^T diag(d) X, core contractions)",
+           4: "gram_kernel / gram_multi_kernel / sgram_multi_kernel (long-reduction FP64 MFMA: "
+              "Gram-type products, scaled Grams Z^T diag(d) X, core contractions)",
            5: "kron_apply_kernel (fused sum_q diag(D[:,q]) Z T^q on FP64 MFMA)"}
 # names of the traffic records (profiles/*.md) of each kind: HBM bytes per
 # launch of the family (an eigensolver call is five dispatches, a transform
