@@ -1224,6 +1224,7 @@ __device__ inline double td_recip(double q) {
 #define TD_TAU(k) (TD_D(k) + 2L * (k))
 #define TD_LAM(k) (TD_D(k) + 3L * (k))
 #define TD_NV(k) (TD_D(k) + 4L * (k))
+#define TD_BND(k) (TD_NV(k) + 1)   // Gershgorin lo, hi and max(|lo|, |hi|) of (d, e)
 
 __global__ __launch_bounds__(TRI_THREADS) void tdeig_tri_kernel(EigJobs jobs) {
     extern __shared__ double sm[];
@@ -1345,23 +1346,31 @@ __global__ __launch_bounds__(TRI_THREADS) void tdeig_tri_kernel(EigJobs jobs) {
     __syncthreads();
     // hand the reflectors (lower triangle of a), d, e and tau to the next phases
     double* S = J.scratch;
+    if (tid < 64) {
+        // Gershgorin bounds: min and max over the rows, two rows per lane
+        // (exact operations, so any order gives the same values)
+        double lo = INFINITY, hi = -INFINITY;
+        for (int i = tid; i < k; i += 64) {
+            const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < k ? fabs(e[i]) : 0.0);
+            lo = fmin(lo, d[i] - r);
+            hi = fmax(hi, d[i] + r);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, off, 64));
+            hi = fmax(hi, __shfl_xor(hi, off, 64));
+        }
+        if (tid == 0) {
+            S[TD_BND(k)] = lo;
+            S[TD_BND(k) + 1] = hi;
+            S[TD_BND(k) + 2] = fmax(fabs(lo), fabs(hi));
+        }
+    }
     for (int x = tid; x < k * k; x += blockDim.x) S[x] = a[x];
     for (int i = tid; i < k; i += blockDim.x) {
         S[TD_D(k) + i] = d[i];
         S[TD_E(k) + i] = e[i];
         S[TD_TAU(k) + i] = tau[i];
     }
-}
-
-// Gershgorin bounds of the tridiagonal matrix (d, e): [lo, hi], and max |.|
-__device__ inline void td_bounds(int k, const double* d, const double* e, double& lo, double& hi,
-                                 double& tnorm) {
-    for (int i = 0; i < k; ++i) {
-        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < k ? fabs(e[i]) : 0.0);
-        lo = (i == 0) ? d[i] - r : fmin(lo, d[i] - r);
-        hi = (i == 0) ? d[i] + r : fmax(hi, d[i] + r);
-    }
-    tnorm = fmax(fabs(lo), fabs(hi));
 }
 
 // 2. Eigenvalues by multisection on Sturm counts: one wavefront per
@@ -1381,11 +1390,7 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_val_kernel(EigJobs jobs) {
         const double ee = S[TD_E(k) + i];
         e2[i] = (i + 1 < k) ? ee * ee : 0.0;
     }
-    if (tid == 0) {
-        double lo = 0, hi = 0, tn = 0;
-        td_bounds(k, S + TD_D(k), S + TD_E(k), lo, hi, tn);
-        sb[0] = lo; sb[1] = hi; sb[2] = tn;
-    }
+    if (tid < 3) sb[tid] = S[TD_BND(k) + tid];
     __syncthreads();
     const int grp = blockIdx.x * (TD_THREADS / 64) + wv;
     if (grp >= k) return;
@@ -1438,7 +1443,7 @@ __device__ inline int td_nvec(const EigJob& J, const double* lam) {
 constexpr int TD_VPB = 16;
 __global__ __launch_bounds__(64) void tdeig_vec_kernel(EigJobs jobs) {
     extern __shared__ double lu[];
-    __shared__ double dd[128], ee[128], sb[2];
+    __shared__ double dd[128], ee[128], lams[128], sb[2];
     __shared__ int nv_s;
     const EigJob& J = jobs.job[blockIdx.y];
     const int k = J.k;
@@ -1448,14 +1453,15 @@ __global__ __launch_bounds__(64) void tdeig_vec_kernel(EigJobs jobs) {
     for (int i = tid; i < k; i += blockDim.x) {
         dd[i] = S[TD_D(k) + i];
         ee[i] = S[TD_E(k) + i];
+        lams[i] = S[TD_LAM(k) + i];
     }
+    if (tid == 0) sb[0] = S[TD_BND(k) + 2];
+    __syncthreads();
     if (tid == 0) {
-        const int nv = td_nvec(J, S + TD_LAM(k));
+        // the rank rule's scan runs on the LDS copy of the eigenvalues
+        const int nv = td_nvec(J, lams);
         nv_s = nv;
         if (blockIdx.x == 0) S[TD_NV(k)] = (double)nv;
-        double lo = 0, hi = 0, tn = 0;
-        td_bounds(k, S + TD_D(k), S + TD_E(k), lo, hi, tn);
-        sb[0] = tn;
     }
     __syncthreads();
     const int i = blockIdx.x * TD_VPB + tid;
@@ -1554,12 +1560,10 @@ __global__ __launch_bounds__(TD_THREADS) void tdeig_clu_kernel(EigJobs jobs) {
     const double* lam = S + TD_LAM(k);
     const int nvec = (int)S[TD_NV(k)];
     const double lmax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
-    if (tid == 0) {
-        int any = 0;
-        for (int i = 1; i < nvec && !any; ++i)
-            any = fabs(lam[i]) > 1e-17 * lmax && lam[i - 1] - lam[i] < 1e-9 * lmax;
-        any_s = any;
-    }
+    if (tid == 0) any_s = 0;
+    __syncthreads();
+    for (int i = 1 + tid; i < nvec; i += blockDim.x)
+        if (fabs(lam[i]) > 1e-17 * lmax && lam[i - 1] - lam[i] < 1e-9 * lmax) any_s = 1;
     __syncthreads();
     if (!any_s) return;
     double* Xl = sm;                      // vector i at Xl + i kp
