@@ -285,9 +285,9 @@ def sampled_parity(prob, w_u, U, k, seed):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2,
+    ap.add_argument("--steps", type=int, default=6,
                     help="timed batched steps (one step = one batched call over --batch problems)")
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--workload", default="sine1024", help="single-solve workload")
     ap.add_argument("--single-steps", type=int, default=5)
@@ -415,8 +415,11 @@ def main():
         res_b = api.solve_batched(plans, inputs, cap_u=1024, outs=outs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_s = []
     for _ in range(args.steps):
-        res_b = api.solve_batched(plans, inputs, cap_u=1024, outs=outs)
+        ts = time.perf_counter()
+        res_b = api.solve_batched(plans, inputs, cap_u=1024, outs=outs)   # returns when all are done
+        step_s.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = args.steps * len(probs) / elapsed
@@ -435,6 +438,7 @@ def main():
                "streams": int(os.environ.get("FC_BATCH_STREAMS", "16")),
                "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                "iterations_min_max": [min(iters), max(iters)],
+               "step_s": [round(x, 4) for x in step_s],
                "vs_fp64_single": value / single["solves_per_s"]}
     log(f"[bench] batched FP64: {args.steps} x {len(probs)} solves in {elapsed:.2f}s -> "
         f"{value:.2f} solves/s")
