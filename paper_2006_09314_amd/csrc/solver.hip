@@ -190,8 +190,9 @@ struct fc_plan_s {
     double site_ms[16] = {};   // wall time per truncation site (with FC_TRACE)
     int site_calls[16] = {};
     std::mutex use_mu;   // one solve at a time per plan
-    // pinned host landing area for the small device-to-host reads of a solve
-    // (ranks, spectra, scalars): a direct copy, no pageable staging
+    // pinned host landing area for the device-to-host copies that remain
+    // (the standalone canonical inner product, flags, check mode): a direct
+    // copy, no pageable staging
     static constexpr size_t kPinnedBytes = 64 * 1024;
     void* pinned = nullptr;
     // results that only the host reads (inner products, probe sums, the
