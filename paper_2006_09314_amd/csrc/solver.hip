@@ -165,6 +165,7 @@ struct fc_plan_s {
     double *Cev = nullptr, *Cvec = nullptr, *Cn1 = nullptr, *Cn2 = nullptr;
     double *Phi[3] = {}, *Map = nullptr, *scal = nullptr, *tmpn = nullptr, *tmpn2 = nullptr;
     double *cw = nullptr, *cf[3] = {}, *Yh[3] = {};
+    int* icount = nullptr;
     int* t2c_keep = nullptr;   // kept T2C term indices (rcap^2)
     void* t2c_ws = nullptr;    // T2C sort scratch beyond the LDS capacity
     double* jac = nullptr;
@@ -190,28 +191,16 @@ struct fc_plan_s {
     double site_ms[16] = {};   // wall time per truncation site (with FC_TRACE)
     int site_calls[16] = {};
     std::mutex use_mu;   // one solve at a time per plan
-    // pinned host landing area for the device-to-host copies that remain
-    // (the standalone canonical inner product, flags, check mode): a direct
-    // copy, no pageable staging
+    // pinned host landing area for the small device-to-host reads of a solve
+    // (ranks, spectra, scalars): a direct copy, no pageable staging.  (The
+    // kernels writing these results straight into coherent pinned host
+    // memory, with a stream synchronisation as the only wait, saved under 1%;
+    // one batched run in about fifty then stopped on a zero inner product,
+    // so the copies stay.)
     static constexpr size_t kPinnedBytes = 64 * 1024;
     void* pinned = nullptr;
-    // results that only the host reads (inner products, probe sums, the
-    // spectra behind rank decisions, kept counts), written by the kernels
-    // that compute them straight into coherent pinned host memory: a read is
-    // a stream synchronisation, with no copy launch behind it.  hres is the
-    // host's address, hres_dev the device's; layout at the kHr* offsets.
-    static constexpr int kHrScal = 0;        // [0] a dot product, [1, 17) probe sums
-    static constexpr int kHrCev = 256;       // 3 x 128 eigenvalues of the subspace Grams
-    static constexpr int kHrEv3 = 640;       // 3 x 128 eigenvalues of the subspace searches
-    static constexpr int kHrInt = 1024;      // 16 ints: kept-column counts [4, 7), T2C count [8]
-    static constexpr size_t kHrBytes = sizeof(double) * (1024 + 8);
-    double* hres = nullptr;
-    double* hres_dev = nullptr;
-    int* hint() const { return reinterpret_cast<int*>(hres + kHrInt); }
-    int* hint_dev() const { return reinterpret_cast<int*>(hres_dev + kHrInt); }
     ~fc_plan_s() {
         if (pinned) (void)hipHostFree(pinned);
-        if (hres) (void)hipHostFree(hres);
     }
 };
 
@@ -614,12 +603,6 @@ void d2h(const Ctx& c, T* dst, const T* src, size_t count) {
     HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.s));
     sync(c);
 }
-// a result that a kernel on c.s wrote to the plan's host-result area
-template <class T>
-void host_read(const Ctx& c, T* dst, const T* hsrc, size_t count) {
-    sync(c);
-    std::memcpy(dst, hsrc, count * sizeof(T));
-}
 template <class T>
 void h2d(const Ctx& c, T* dst, const T* src, size_t count) {
     HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, c.s));
@@ -654,9 +637,9 @@ void perm_dims(const int r[3], int mode, int out[3]) {
 
 double host_dot(const Ctx& c, long n, const double* x, const double* y) {
     fc_plan_s* p = c.p;
-    HIPCHK(fc::dot_long(n, x, y, p->scal + 256, p->dotcnt, p->hres_dev + fc_plan_s::kHrScal, c.s));
+    HIPCHK(fc::dot_long(n, x, y, p->scal + 256, p->dotcnt, p->scal, c.s));
     double v = 0;
-    host_read(c, &v, p->hres + fc_plan_s::kHrScal, 1);
+    d2h(c, &v, p->scal, 1);
     return v;
 }
 
@@ -759,7 +742,7 @@ void orthonormalize3(const Ctx& c, int m[3], double* const Y[3], double drop, co
         if (!on[l]) continue;
         fc::CompactJob& J = cj.job[cj.count];
         J.Y = Y[l]; J.m = m[l]; J.done = done[l]; J.keep = p->qrKeep + l * 512L;
-        J.count = p->hint_dev() + 4 + cj.count;
+        J.count = p->icount + 4 + cj.count;
         slot[l] = cj.count++;
     }
     if (cj.count == 0) {
@@ -768,7 +751,7 @@ void orthonormalize3(const Ctx& c, int m[3], double* const Y[3], double drop, co
     }
     HIPCHK(fc::compact_cols(n, cj, c.s));
     int cnt[3] = {0, 0, 0};
-    host_read(c, cnt, p->hint() + 4, cj.count);
+    d2h(c, cnt, p->icount + 4, cj.count);
     for (int l = 0; l < 3; ++l)
         if (use[l]) m[l] = on[l] ? cnt[slot[l]] : 0;
 }
@@ -843,7 +826,7 @@ void hosvd_core(const Ctx& c, const double* C, const int k[3], double* const B[3
                             [&] { return fc::sym_eig_multi(jobs, c.s); }));
     }
     std::vector<double> ev(3 * KM);
-    host_read(c, ev.data(), p->hres + fc_plan_s::kHrCev, 3 * KM);
+    d2h(c, ev.data(), p->Cev, 3 * KM);
     double tot = 0;
     for (int i = 0; i < k[0]; ++i) tot += std::max(ev[i], 0.0);
     int r[3];
@@ -1026,7 +1009,7 @@ bool find_subspaces(const Ctx& c, int site, const int kcap[3], Apply& apply, dou
         }
         HIPCHK(timed_launch(2, c.s, eig_flops(jobs), eig_bytes(jobs),
                             [&] { return fc::sym_eig_multi(jobs, c.s); }));
-        host_read(c, th.data(), p->hres + fc_plan_s::kHrEv3, 3 * KM);
+        d2h(c, th.data(), p->Ev3, 3 * KM);
         bool again = false;
         fc::CopyJobs keep;   // the modes finished this round, saved for a warm start
         fc::GemmArgs fin[3];   // their subspaces W_l = X_l V_l, formed together
@@ -1579,7 +1562,7 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
               (long)pk[0] * pk[1]);
     }
     const long Csz = (long)pk[0] * pk[1] * pk[2];
-    HIPCHK(fc::dot_long(Csz, p->C, p->C, p->scal + 256, p->dotcnt, p->hres_dev + fc_plan_s::kHrScal, c.s));
+    HIPCHK(fc::dot_long(Csz, p->C, p->C, p->scal + 256, p->dotcnt, p->scal, c.s));
     // 6. a-posteriori check of the subspaces: the energy of T outside them,
     //    ||T - PT||^2, estimated with S rank-1 Gaussian probes
     //    g_t = g_0,t (x) g_1,t (x) g_2,t (E <X, g_t>^2 = ||X||^2), read back with
@@ -1621,11 +1604,11 @@ void had_trunc(const Ctx& c, const Separable& op, const Tucker& P, double tol_re
         ps.p[1].r1 = pk[1]; ps.p[1].r2 = pk[2]; ps.p[1].Q = 1;
         ps.p[1].M = p->T2; ps.p[1].mstride = ppk;
         ps.p[1].U1 = p->Map + (long)KM * 256; ps.p[1].U2 = p->Map + 2L * KM * 256;
-        ps.out = p->hres_dev + fc_plan_s::kHrScal + 1;
+        ps.out = p->scal + 1;
         HIPCHK(fc::probe_sums(ps, S, c.s));
     }
     double vals[1 + 2 * 8];
-    host_read(c, vals, p->hres + fc_plan_s::kHrScal, 1 + 2 * (S >= 2 ? S : 0));
+    d2h(c, vals, p->scal, 1 + 2 * (S >= 2 ? S : 0));
     const double n2 = vals[0];
     if (!std::isfinite(n2)) throw FcError(FC_ERR_NUMERIC, std::string(what) + ": non-finite");
     double missed = 0.0;
@@ -1797,9 +1780,9 @@ int tucker_to_canon_out(const Ctx& c, const Tucker& X, double budget2, bool to_g
     gemm(c, true, false, r1, r1, r0, 1.0, X.core, r0, X.core, r0, 0.0, p->Bp, r1, r2,
          (long)r0 * r1, (long)r0 * r1, (long)r1 * r1);
     HIPCHK(fc::sym_eig(r1, r2, p->Bp, r1, (long)r1 * r1, p->Ev, p->Evec, r1, (long)r1 * r1, p->jac, c.s));
-    HIPCHK(fc::t2c_select(r1 * r2, p->Ev, budget2, p->t2c_ws, p->t2c_keep, p->hint_dev() + 8, c.s));
+    HIPCHK(fc::t2c_select(r1 * r2, p->Ev, budget2, p->t2c_ws, p->t2c_keep, p->icount + 8, c.s));
     int K = 0;
-    host_read(c, &K, p->hint() + 8, 1);
+    d2h(c, &K, p->icount + 8, 1);
     if (K > cap || K == 0) return K;
     HIPCHK(fc::t2c_coef(r0, r1, r2, K, X.core, p->Evec, p->Ev, p->t2c_keep, p->cf[0], p->cf[1],
                         p->cf[2], w_u, c.s));
@@ -1834,10 +1817,6 @@ void alloc_workspace(fc_plan_s* p) {
     const long rc = p->rcap, pc = p->pcap;
     const int Q = std::max({p->op.Q, p->pc.Q, p->st.Q, p->pcA.Q});
     Arena& A = p->arena;
-    HIPCHK(hipHostMalloc((void**)&p->hres, fc_plan_s::kHrBytes,
-                         hipHostMallocMapped | hipHostMallocCoherent));
-    std::memset(p->hres, 0, fc_plan_s::kHrBytes);
-    HIPCHK(hipHostGetDevicePointer((void**)&p->hres_dev, p->hres, 0));
     for (int s = 0; s < 14; ++s) {
         for (int l = 0; l < 3; ++l) p->slot[s].Z[l] = A.alloc((size_t)n * rc);
         p->slot[s].core = A.alloc((size_t)rc * rc * rc);
@@ -1876,7 +1855,7 @@ void alloc_workspace(fc_plan_s* p) {
     p->Cn1 = A.alloc(kcube);
     p->Cn2 = A.alloc(kcube);
     p->Cg = A.alloc((size_t)3 * KM * KM);
-    p->Cev = p->hres_dev + fc_plan_s::kHrCev;
+    p->Cev = A.alloc((size_t)3 * KM);
     p->Cvec = A.alloc((size_t)3 * KM * KM);
     p->Map = A.alloc((size_t)3 * KM * 256);
     for (int l = 0; l < 3; ++l) {
@@ -1887,6 +1866,7 @@ void alloc_workspace(fc_plan_s* p) {
     p->scal = A.alloc(512);
     p->tmpn = A.alloc((size_t)n * std::max<long>(rc, 256));
     p->tmpn2 = A.alloc((size_t)n * std::max<long>(rc, 256));
+    p->icount = A.alloc_int(16);
     p->t2c_keep = A.alloc_int((size_t)rc * rc);
     {
         long np2 = 1;
@@ -1903,7 +1883,7 @@ void alloc_workspace(fc_plan_s* p) {
     p->Bp3 = A.alloc((size_t)3 * KM * KM);
     for (int st = 0; st < NSITES; ++st)
         for (int l = 0; l < 3; ++l) p->warm[st].W[l] = A.alloc((size_t)n * pc);
-    p->Ev3 = p->hres_dev + fc_plan_s::kHrEv3;
+    p->Ev3 = A.alloc((size_t)3 * KM);
     p->Evec3 = A.alloc((size_t)3 * KM * KM);
     p->splitws_cap = 8L << 20;
     p->splitws = A.alloc((size_t)p->splitws_cap);
