@@ -379,15 +379,17 @@ bool gram_staged(bool ta) {
     return ta;
 }
 
-// terms per workgroup of the batched scaled Grams (fc::gram's group): two.
-// A workgroup then stages its A and B chunks once for two terms; a batch
-// holds half the compute units, which the concurrent solves of a batched
-// call use (64 solves at n = 1024: 151 -> 166 solves/s; one solve alone
-// unchanged).  FC_GRAM_GROUP = 1 | 2 | 4 overrides it (a diagnostic).
+// terms per workgroup of the batched scaled Grams (fc::gram's group): four
+// (two at sixteen wavefronts).  A workgroup then stages its A and B chunks
+// once for the group; a batch holds a fraction of the compute units, which
+// the concurrent solves of a batched call use (64 solves at n = 1024, six
+// timed steps: one term 151-154, two 164-165, four 166-167 solves/s; one
+// solve alone unchanged).  FC_GRAM_GROUP = 1 | 2 | 4 overrides it (a
+// diagnostic); the results do not depend on it.
 const int g_gram_group = [] {
     const char* m = std::getenv("FC_GRAM_GROUP");
-    const int v = m ? std::atoi(m) : 2;
-    return (v == 1 || v == 2 || v == 4) ? v : 2;
+    const int v = m ? std::atoi(m) : 4;
+    return (v == 1 || v == 2 || v == 4) ? v : 4;
 }();
 // FC_KRON_WAVES = 8 | 16 overrides the tuned wavefronts of the fused
 // Kronecker application (a diagnostic)
