@@ -239,7 +239,8 @@ def test_full_size_batched_64x1024():
     """The batched benchmark configuration: 64 sine problems at n = 1024
     (seeds 100..163) in one fc_solve_batched call.  Eight of them, spread
     over the batch, are compared with the oracle over the whole grid, the
-    rest on sampled slabs, and two equal their single solves bit for bit."""
+    rest on sampled slabs, two equal their single solves bit for bit, and
+    three more calls on the same plans reproduce every result bit for bit."""
     import torch
     from paper_2006_09314_amd import api
     from tests.gpu_util import dev, host, plan_for, solve
@@ -265,8 +266,25 @@ def test_full_size_batched_64x1024():
         w1, U1, _ = solve(plans[i], probs[i])
         assert np.array_equal(host(res[i][0]), w1)
         assert all(np.array_equal(host(a), b) for a, b in zip(res[i][1], U1))
+    # repeated calls on the same plans (as the benchmark makes them): every
+    # problem converges again, to the same bits
+    first = [_result_digest(r) for r in res]
+    for rep_i in range(3):
+        print(f"[case] batched 64 x n=1024 repeat {rep_i}", flush=True)
+        again = api.solve_batched(plans, inputs, cap_u=1024)
+        assert all(r[3] == "FC_OK" for r in again)
+        assert [_result_digest(r) for r in again] == first, rep_i
     for plan in plans:
         plan.close()
+
+
+def _result_digest(r):
+    import hashlib
+    from tests.gpu_util import host
+    h = hashlib.sha256()
+    for a in [r[0]] + list(r[1]):
+        h.update(np.ascontiguousarray(host(a)).tobytes())
+    return h.hexdigest()
 
 
 @pytest.mark.timeout(600)
