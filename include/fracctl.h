@@ -209,9 +209,12 @@ fc_status fc_solve_state(fc_plan plan, int rank_y, const double* w_y, const doub
  * per-problem pointers follow fc_solve.  status[i] receives each problem's
  * own status; the return value is FC_OK if every problem succeeded, else the
  * first failing status.  Problems run concurrently: worker threads (16, or
- * the environment variable FC_BATCH_STREAMS) each solve on a stream of their
- * own after the given stream's pending work; the call returns when all are
- * done.  The HIP runtime maps streams onto GPU_MAX_HW_QUEUES hardware queues
+ * the environment variable FC_BATCH_STREAMS, at most 64) each solve on a
+ * stream of their own after the given stream's pending work; the call
+ * returns when all are done.  The workers and their streams are created by
+ * the first batched call on a device and kept for the process; batched calls
+ * made at the same time on one device run one after the other.  The HIP
+ * runtime maps streams onto GPU_MAX_HW_QUEUES hardware queues
  * (4 unless set before the runtime starts), which bounds the concurrency.
  * Plans built with dims = 2 are solved as by fc_solve2d: their Y3[i] and
  * U3[i] are not used (the arrays must still have `count` entries; those

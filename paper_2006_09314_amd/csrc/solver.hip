@@ -18,7 +18,9 @@
 #include <string>
 #include <type_traits>
 #include <atomic>
+#include <condition_variable>
 #include <cstdlib>
+#include <functional>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -3385,6 +3387,72 @@ fc_status solve_impl(fc_plan p, int rank_y, const double* w_y, const double* Y1,
 
 }  // namespace
 
+// Workers of the batched call, one pool per device and worker count: the
+// threads and their non-blocking streams (default priority) live for the
+// process, created by the first batched call, so a call neither starts
+// threads nor creates streams.  One batched call at a time runs on a pool
+// (concurrent calls queue on call_mu).  Pools are never freed: their threads
+// wait on the condition variable until the process ends.
+struct BatchPool {
+    int dev = 0;
+    int size = 0;
+    std::mutex call_mu;
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::function<void(int, hipStream_t)> job;
+    unsigned long generation = 0;
+    int pending = 0;
+    int ready = 0;
+    bool failed = false;   // a worker could not select the device or create its stream
+};
+
+void batch_worker(BatchPool* P, int t) {
+    hipStream_t s = nullptr;
+    const bool ok = hipSetDevice(P->dev) == hipSuccess &&
+                    hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    unsigned long seen = 0;
+    {
+        std::lock_guard<std::mutex> lk(P->mu);
+        if (!ok) P->failed = true;
+        ++P->ready;
+    }
+    P->done_cv.notify_all();
+    for (;;) {
+        std::function<void(int, hipStream_t)> job;
+        {
+            std::unique_lock<std::mutex> lk(P->mu);
+            P->cv.wait(lk, [&] { return P->generation != seen; });
+            seen = P->generation;
+            job = P->job;
+        }
+        if (ok && job) job(t, s);
+        bool last = false;
+        {
+            std::lock_guard<std::mutex> lk(P->mu);
+            last = --P->pending == 0;
+        }
+        if (last) P->done_cv.notify_all();
+    }
+}
+
+BatchPool* batch_pool(int dev, int size) {
+    static std::mutex m;
+    static std::vector<BatchPool*> pools;
+    std::lock_guard<std::mutex> lk(m);
+    for (BatchPool* p : pools)
+        if (p->dev == dev && p->size == size) return p;
+    BatchPool* p = new BatchPool();
+    p->dev = dev;
+    p->size = size;
+    for (int t = 0; t < size; ++t) std::thread(batch_worker, p, t).detach();
+    {
+        std::unique_lock<std::mutex> l2(p->mu);
+        p->done_cv.wait(l2, [&] { return p->ready == size; });
+    }
+    pools.push_back(p);
+    return p;
+}
+
 extern "C" {
 
 fc_status fc_solve(fc_plan p, int rank_y, const double* w_y, const double* Y1, const double* Y2,
@@ -3458,24 +3526,26 @@ fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
     for (int i = 0; i < count; ++i)
         if (!plans[i]) return fail(FC_ERR_INVALID_ARG, "fc_solve_batched: NULL plan");
     if (count == 0) return FC_OK;
-    // Problems run concurrently: worker threads, each with its own stream,
-    // take problems in order from a shared counter.  The caller's stream is
-    // joined at the start (its pending work completes before any solve
-    // starts); every solve synchronises its own stream before it returns.
+    // Problems run concurrently: the pool's worker threads, each with its own
+    // stream, take problems in order from a shared counter.  The caller's
+    // stream is joined at the start (its pending work completes before any
+    // solve starts); every solve synchronises its own stream before it
+    // returns.
     int workers = 16;
     if (const char* env = std::getenv("FC_BATCH_STREAMS")) workers = std::max(1, std::atoi(env));
-    workers = std::min(workers, count);
+    workers = std::min(workers, 64);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(FC_ERR_HIP, "hipGetDevice failed");
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
         return fail(FC_ERR_HIP, "hipStreamSynchronize failed");
+    BatchPool* P = batch_pool(dev, workers);
+    if (P->failed) return fail(FC_ERR_HIP, "fc_solve_batched: a worker stream could not be created");
+    std::lock_guard<std::mutex> call(P->call_mu);
     std::atomic<int> next(0);
     std::vector<std::string> errs(count);
-    auto work = [&](int t) {
+    for (int i = 0; i < count; ++i) status[i] = FC_ERR_INTERNAL;
+    auto work = [&](int t, hipStream_t s) {
         t_no_profile = (t != 0);   // GEMM timing (when enabled) samples worker 0
-        if (hipSetDevice(dev) != hipSuccess) return;
-        hipStream_t s = nullptr;
-        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
         for (;;) {
             const int i = next.fetch_add(1);
             if (i >= count) break;
@@ -3490,12 +3560,20 @@ fc_status fc_solve_batched(int count, const fc_plan* plans, const int* rank_y,
             if (status[i] != FC_OK) errs[i] = g_last_error;
         }
         (void)hipStreamSynchronize(s);
-        (void)hipStreamDestroy(s);
+        t_no_profile = false;
     };
-    for (int i = 0; i < count; ++i) status[i] = FC_ERR_INTERNAL;
-    std::vector<std::thread> pool;
-    for (int t = 0; t < workers; ++t) pool.emplace_back(work, t);
-    for (auto& t : pool) t.join();
+    {
+        std::lock_guard<std::mutex> lk(P->mu);
+        P->job = work;
+        P->pending = P->size;
+        ++P->generation;
+    }
+    P->cv.notify_all();
+    {
+        std::unique_lock<std::mutex> lk(P->mu);
+        P->done_cv.wait(lk, [&] { return P->pending == 0; });
+        P->job = nullptr;   // it refers to this call's locals
+    }
     fc_status first = FC_OK;
     for (int i = 0; i < count; ++i)
         if (status[i] != FC_OK && first == FC_OK) {
