@@ -125,6 +125,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tile, int b, in
         if (k0 + BK < kend) fetch(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
+            // a reduction that ends inside the chunk stops at its last step
+            // of four (the rest of the chunk holds zeros)
+            if (k0 + 4 * kk >= kend) break;
             const int k = kk * 4 + (lane >> 4);
             const double a0 = As[k][wm * 32 + (lane & 15)];
             const double a1 = As[k][wm * 32 + 16 + (lane & 15)];
